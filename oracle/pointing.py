@@ -80,29 +80,29 @@ class Pointing:
 def invert_blocks(W: np.ndarray, hits: np.ndarray, rcond_min: float = 1e-8):
     """Invert the per-pixel blocks of P^T T^-1 P.
 
-    A pixel is solvable when it has hits and, for 3x3 blocks, its reciprocal
-    1-norm condition number 1 / (||W||_1 ||W^-1||_1) is at least ``rcond_min``.
-    Unsolvable pixels get a zero block (their map values are held at zero).
-    Returns (W_inv, solvable).
+    A pixel is solvable when it has hits and, for 3x3 blocks, the determinant of
+    the block normalised by its diagonal, det(W) / (W_00 W_11 W_22), is at least
+    ``rcond_min``.  (With weights (1, cos 2psi, sin 2psi), W_11 + W_22 = W_00, so
+    this number measures how well the pixel's angles separate Q from U; it is 1
+    for evenly spread angles and 0 for a single angle.  Unlike a condition number
+    computed from the inverse it stays near 0 for exactly singular blocks whose
+    determinant is rounding noise.)  Unsolvable pixels get a zero block (their map
+    values are held at zero).  Returns (W_inv, solvable).
     """
     npix, nc, _ = W.shape
     solvable = hits > 0
     Winv = np.zeros_like(W)
     if nc == 1:
+        solvable = solvable & (W[:, 0, 0] > 0)
         Winv[solvable, 0, 0] = 1.0 / W[solvable, 0, 0]
         return Winv, solvable
     idx = np.nonzero(solvable)[0]
     blocks = W[idx]
+    diag = blocks[:, 0, 0] * blocks[:, 1, 1] * blocks[:, 2, 2]
     dets = np.linalg.det(blocks)
-    ok = dets > 0
-    inv = np.zeros_like(blocks)
-    inv[ok] = np.linalg.inv(blocks[ok])
-    n1 = np.abs(blocks).sum(axis=1).max(axis=1)        # max column sum
-    n1i = np.abs(inv).sum(axis=1).max(axis=1)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        rc = np.where(ok, 1.0 / (n1 * n1i), 0.0)
-    good = ok & (rc >= rcond_min)
+    good = diag > 0
+    good[good] = dets[good] / diag[good] >= rcond_min
     solvable = np.zeros(npix, dtype=bool)
     solvable[idx[good]] = True
-    Winv[idx[good]] = inv[good]
+    Winv[idx[good]] = np.linalg.inv(blocks[good])
     return Winv, solvable
