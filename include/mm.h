@@ -1,0 +1,225 @@
+/*
+ * mm.h -- messenger-field CMB mapmaking on one MI355X (gfx950).
+ *
+ * C ABI of libmm.so.  The library solves the minimum-variance mapmaking
+ * equation (P^T N^-1 P) m = P^T N^-1 d of Huffenberger & Naess, "Cosmic
+ * Microwave Background Mapmaking with a Messenger Field":
+ *   - Section 2: data model d = P m + n, eqn. (mapmaking), eqn. (chi2);
+ *   - Section 2.1: the messenger iteration, compact form eqn. (mcompact),
+ *     the cooling parameter lambda and chi^2(m, lambda);
+ *   - Section 3.1: the cooling schedule and the diagonal-preconditioned
+ *     conjugate-gradient comparison;
+ *   - Section 4.2: a messenger variance tau per detector chunk.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Samples      The time-ordered data (TOD) of all detector chunks are
+ *               concatenated; chunk c holds samples [chunk_off[c], chunk_off[c+1]).
+ *               A chunk is one stationary stretch of one detector; its noise
+ *               covariance is circulant (diagonal in the chunk's discrete
+ *               Fourier basis).  Every chunk length must be even and half of it
+ *               must factor into 2, 3 and 5 only (MM_E_LEN otherwise).
+ *  Pointing     pix[j] is the map pixel of sample j (int32); a negative value
+ *               means the sample is off the map (its row of P is zero but it
+ *               still enters the noise filter and chi^2).  With three Stokes
+ *               components sample j sees I + Q cos 2psi_j + U sin 2psi_j.
+ *  Noise        Chunk c has N(f) = sigma_c^2 (1 + (f / fknee_c)^alpha_c) at the
+ *               rfft frequencies f_k = k fsample_c / n_c; the f = 0 bin takes the
+ *               value at f_1.  The messenger covariance is T = tau_c I on chunk c
+ *               (default tau_c = sigma_c^2, the minimum of the spectrum).
+ *  Maps         float64, layout [ncomp][npix], pixel p = y * nx + x.
+ *  Memory       Arguments documented "device" are device pointers on the
+ *               current HIP device; "host" are host pointers.  All are
+ *               borrowed: the library never frees or keeps them past the
+ *               call, except pix / psi, which a plan reads at every iteration
+ *               and which must stay valid and unchanged until mm_plan_destroy.
+ *               A plan allocates and owns its own device tables
+ *               (mm_plan_workspace_bytes reports how much).
+ *  Streams      Every call is ordered on the given stream and returns without
+ *               waiting for it, except mm_plan (waits for its precompute),
+ *               mm_chi2 (returns a host scalar) and mm_cg_solve when rtol > 0.
+ *               Pass 0 for the default stream.  A plan is not thread-safe; use
+ *               it from one host thread and one stream at a time.
+ *  Errors       Every entry point returns an mm_status.  On error nothing is
+ *               written to the output arguments and mm_last_error() gives a
+ *               thread-local description.  Errors of earlier asynchronous work
+ *               surface as MM_E_HIP at a later call.
+ *  Determinism  Pixel binning is a fixed-order segmented reduction over
+ *               samples sorted by pixel: results are bitwise reproducible run
+ *               to run on the same device.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_plan_s* mm_plan_t;
+typedef void* mm_stream_t; /* a hipStream_t */
+
+typedef enum {
+  MM_OK = 0,
+  MM_E_ARG = 1,       /* invalid argument or descriptor field */
+  MM_E_LEN = 2,       /* a chunk length the transforms do not support */
+  MM_E_NOMEM = 3,     /* device or host allocation failed */
+  MM_E_HIP = 4,       /* a HIP runtime error (possibly from earlier asynchronous work) */
+  MM_E_SINGULAR = 5,  /* no pixel has a solvable weight block */
+  MM_E_NONFINITE = 6  /* a non-finite chi^2 (NaN or Inf in the data or the map) */
+} mm_status;
+
+enum { MM_FP64 = 0, MM_MIXED = 1 };                              /* precision */
+enum { MM_PSI_NONE = 0, MM_PSI_F64 = 1, MM_PSI_F32 = 2, MM_PSI_U16 = 3 }; /* psi storage */
+
+/*
+ * Problem description (Section 2 data model; Section 4.2 per-chunk tau).
+ *  ncomp        1 (temperature) or 3 (I, Q, U).
+ *  precision    MM_FP64: TOD, transforms and filter in float64 (d is double*).
+ *               MM_MIXED: TOD, transforms and filter in float32 (d is float*);
+ *               map, weight blocks, binning sums, chi^2 and CG scalars stay float64.
+ *  npix, nx     map size; nx > 0 is the row length used to form square pixel
+ *               tiles for binning (0 treats the map as one long row).
+ *  nchunk       number of chunks; chunk_off (host, nchunk+1 int64, increasing,
+ *               chunk_off[0] = 0) gives their extents.
+ *  fsample, sigma, fknee, alpha   host, nchunk doubles: the noise law above.
+ *  tau          host, nchunk doubles, or NULL for sigma^2; must satisfy
+ *               0 < tau_c <= sigma_c^2 so that N - T stays positive semidefinite.
+ *  pix          device, N_s int32 (N_s = chunk_off[nchunk]).
+ *  psi          device, N_s angles (radians) of type psi_kind: MM_PSI_F64
+ *               (double), MM_PSI_F32 (float) or MM_PSI_U16 (uint16 index into
+ *               psi_table); NULL / MM_PSI_NONE when ncomp == 1.
+ *  psi_table    host, psi_table_len floats (only for MM_PSI_U16).
+ */
+typedef struct {
+  int32_t ncomp;
+  int32_t precision;
+  int64_t npix;
+  int64_t nx;
+  int64_t nchunk;
+  const int64_t* chunk_off;
+  const double* fsample;
+  const double* sigma;
+  const double* fknee;
+  const double* alpha;
+  const double* tau;
+  const int32_t* pix;
+  const void* psi;
+  int32_t psi_kind;
+  int32_t reserved0;
+  const float* psi_table;
+  int64_t psi_table_len;
+} mm_plan_desc;
+
+/* Cooling schedule (Section 3.1): optionally one lambda = inf step, then
+ * nlevel levels, level l running iters[l] iterations at lambda[l] (host arrays). */
+typedef struct {
+  int32_t nlevel;
+  int32_t first_inf;
+  const double* lambda;
+  const int32_t* iters;
+} mm_schedule;
+
+/*
+ * Build a plan: validates the descriptor, sorts the pointing by pixel tile for
+ * deterministic binning (host), selects transform splits, and runs the
+ * precompute kernels on `stream`: hit counts, the weight blocks
+ * W_p = sum_{j at p} a_j a_j^T / tau_c (P^T T^-1 P of Section 2.1) and their
+ * inverses.  A pixel is solvable when it has hits and, for 3x3 blocks,
+ * det(W_p) / (W_p,00 W_p,11 W_p,22) >= 1e-8 (its angles separate Q from U);
+ * unsolvable pixels are held at 0.
+ * Waits for the stream.  MM_E_SINGULAR if no pixel is solvable.
+ */
+mm_status mm_plan(const mm_plan_desc* desc, mm_stream_t stream, mm_plan_t* out);
+mm_status mm_plan_destroy(mm_plan_t plan);
+/* Device bytes held by the plan (tables, sorted pointing, one TOD-sized work buffer). */
+mm_status mm_plan_workspace_bytes(mm_plan_t plan, size_t* bytes);
+/* Copy the bit-exact hit counts (int32 [npix]) into hits_dev (device). */
+mm_status mm_plan_hits(mm_plan_t plan, int32_t* hits_dev, mm_stream_t stream);
+/* Copy the solvable mask (uint8 [npix]) into mask_dev (device). */
+mm_status mm_plan_solvable(mm_plan_t plan, uint8_t* mask_dev, mm_stream_t stream);
+/* Number of solvable pixels (host). */
+mm_status mm_plan_nsolvable(mm_plan_t plan, int64_t* count);
+
+/*
+ * One messenger iteration, eqn. (mcompact) of Section 2.1:
+ *   m_out = m_in + W^-1 P^T (lambda^-1 (N - T) + T)^-1 (d - P m_in)
+ * on solvable pixels (0 elsewhere).  lambda >= 1 or INFINITY; lambda = inf
+ * gives the binned map W^-1 P^T T^-1 d directly (no transforms).
+ * d: device TOD (double* for MM_FP64, float* for MM_MIXED).  m_in, m_out:
+ * device maps (may be the same buffer).  chi2_dev: device double or NULL;
+ * receives chi^2(m_in) of eqn. (chi2) (computed from the same transform).
+ */
+mm_status mm_messenger_iter(mm_plan_t plan, const void* d, double lambda, const double* m_in,
+                            double* m_out, double* chi2_dev, mm_stream_t stream);
+
+/*
+ * Full cooled messenger solve (Section 3.1).  Captures the whole schedule in
+ * one HIP graph and launches it on `stream`.  m0: device start map or NULL for
+ * zero.  m_out: device result.  chi2_hist_dev: device array of
+ * (first_inf + sum(iters) + 1) doubles or NULL; entry i is chi^2(m_i) of the
+ * map entering iteration i, the last entry chi^2 of the final map.
+ */
+mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, const double* m0,
+                   double* m_out, double* chi2_hist_dev, mm_stream_t stream);
+
+/*
+ * Geometric cooling levels (Section 3.1): lambda_l = lambda_max^((nlevel-1-l)/(nlevel-1)),
+ * ending at exactly 1.  lambda_max <= 0 selects the rule lambda_max = max_c N_c(f_0) / tau_c
+ * (lambda tau spans the noise power).  out: host array of nlevel doubles.
+ */
+mm_status mm_cooling_levels(mm_plan_t plan, int32_t nlevel, double lambda_max, double* out);
+
+/*
+ * Diagonal-preconditioned conjugate gradients on (P^T N^-1 P) m = P^T N^-1 d
+ * (Sections 1, 2 and 3.1), preconditioner W^-1 = (P^T T^-1 P)^-1 per pixel.
+ * d: device TOD, or NULL when rhs_map (device map) gives P^T N^-1 d directly.
+ * m0: device start map or NULL (zero, as in Section 3.1).  Runs maxiter
+ * iterations, or stops when r^T W^-1 r <= rtol^2 r_0^T W^-1 r_0 (checked on
+ * the host every 10 iterations, which waits for the stream) if rtol > 0.
+ * chi2_hist_dev (device, maxiter+1 doubles, or NULL) gets chi^2 of each iterate
+ * from the recursion chi^2(x) = d^T N^-1 d - x^T b - x^T r (needs d).
+ * rz_hist_dev (device, maxiter+1 doubles, or NULL) gets r^T W^-1 r.
+ * iters_done (host, or NULL) gets the number of iterations run.
+ */
+mm_status mm_cg_solve(mm_plan_t plan, const void* d, const double* rhs_map, int32_t maxiter,
+                      double rtol, const double* m0, double* m_out, double* chi2_hist_dev,
+                      double* rz_hist_dev, int32_t* iters_done, mm_stream_t stream);
+
+/*
+ * chi^2(m, lambda) = (d - P m)^T N'(lambda)^-1 (d - P m), N' = N + (lambda - 1) T
+ * (eqn. chi2 for lambda = 1; Section 2.1 otherwise), summed over the Fourier
+ * modes of every chunk.  chi2_host: host double (the call waits for the
+ * stream).  per_chunk_dev: device array of nchunk doubles or NULL.
+ * MM_E_NONFINITE if the sum is not finite.
+ */
+mm_status mm_chi2(mm_plan_t plan, const void* d, const double* m, double lambda, double* chi2_host,
+                  double* per_chunk_dev, mm_stream_t stream);
+
+/*
+ * Apply the map-space operators once (building blocks for adjoint solves and
+ * tests): out = P^T G P x or P^T G d with G = N^-1 (which == 0) or
+ * G = (lambda^-1 (N - T) + T)^-1 (which == 1).  x: device map, d: device TOD
+ * (exactly one of them non-NULL).  out: device map.
+ */
+mm_status mm_apply(mm_plan_t plan, int32_t which, double lambda, const double* x, const void* d,
+                   double* out, mm_stream_t stream);
+
+/*
+ * Lift a map-space vector g to TOD space: out = N T^-1 P W^-1 g, so that
+ * P^T N^-1 out = g on solvable pixels.  Running mm_solve on `out` then solves
+ * (P^T N^-1 P) z = g with the messenger iteration (the adjoint solve of the
+ * map gradient).  out: device TOD of the plan's TOD type.
+ */
+mm_status mm_lift_rhs(mm_plan_t plan, const double* g, void* out, mm_stream_t stream);
+
+const char* mm_status_str(mm_status s);
+const char* mm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

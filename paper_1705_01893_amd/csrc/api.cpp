@@ -1,0 +1,337 @@
+// C entry points of libmm (declared in include/mm.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mm.h"
+#include "plan.h"
+
+using namespace mm;
+
+namespace {
+
+#define MM_TRY_HIP(expr)                                                                           \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return fail(MM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define MM_TRY(expr)               \
+  do {                             \
+    mm_status s_ = (expr);         \
+    if (s_ != MM_OK) return s_;    \
+  } while (0)
+
+inline hipStream_t S(mm_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+int64_t mapn(const mm_plan_s* pl) { return (int64_t)pl->ncomp * pl->npix; }
+
+// r = src(d, m) -> filtered y in the work buffer (passes A, B, C).  Returns with the
+// chi^2 partials in d_chi2_part when ops includes B_CHI2.
+mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, int ops, int gain, double lam,
+                       double chi2_lam, hipStream_t s) {
+  MM_TRY_HIP(launch_pass_a(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), d, m, src, pl->d_work, pl->lds_ac, s));
+  MM_TRY_HIP(launch_pass_b(pl->dp, pl->d_itemsB, (int)pl->itemsB.size(), pl->d_work, ops, gain, lam, chi2_lam,
+                           pl->d_chi2_part, pl->lds_b, s));
+  if (ops & B_FILTER)
+    MM_TRY_HIP(launch_pass_c(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), pl->d_work, pl->lds_ac, s));
+  return MM_OK;
+}
+
+// chi^2(m, lam) of d - P m into *total (device) and optionally per chunk (device)
+mm_status chi2_device(mm_plan_s* pl, const void* d, const double* m, double lam, double* total, double* per_chunk,
+                      hipStream_t s) {
+  MM_TRY(sweep_filter(pl, d, m, SRC_D_MINUS_PM, B_CHI2, GAIN_NINV, 1.0, lam, s));
+  MM_TRY_HIP(launch_chi2_reduce(pl->d_chunk_item_begin, pl->d_chi2_part, (int)pl->nchunk, per_chunk, total, s));
+  return MM_OK;
+}
+
+// one messenger iteration m_out = m_in + W^-1 P^T G_lambda (d - P m_in); chi2(m_in) into chi2_dev if non-null
+mm_status iterate(mm_plan_s* pl, const void* d, double lam, const double* m_in, double* m_out, double* chi2_dev,
+                  hipStream_t s) {
+  if (std::isinf(lam)) {
+    if (chi2_dev) MM_TRY(chi2_device(pl, d, m_in, 1.0, chi2_dev, nullptr, s));
+    MM_TRY_HIP(launch_bin(pl->dp, BSRC_DATA_OVER_TAU, d, EPI_REPLACE, m_in, m_out, nullptr, nullptr, s));
+    return MM_OK;
+  }
+  const int ops = B_FILTER | (chi2_dev ? B_CHI2 : 0);
+  MM_TRY(sweep_filter(pl, d, m_in, SRC_D_MINUS_PM, ops, GAIN_MESSENGER, lam, 1.0, s));
+  MM_TRY_HIP(launch_bin(pl->dp, BSRC_WORK, pl->d_work, EPI_UPDATE, m_in, m_out, nullptr, nullptr, s));
+  if (chi2_dev)
+    MM_TRY_HIP(launch_chi2_reduce(pl->d_chunk_item_begin, pl->d_chi2_part, (int)pl->nchunk, nullptr, chi2_dev, s));
+  return MM_OK;
+}
+
+// out = P^T G P x (x != null) or P^T G d
+mm_status apply_op(mm_plan_s* pl, int gain, double lam, const double* x, const void* d, double* out, hipStream_t s) {
+  MM_TRY(sweep_filter(pl, x ? nullptr : d, x, x ? SRC_PM : SRC_D, B_FILTER, gain, lam, 1.0, s));
+  MM_TRY_HIP(launch_bin(pl->dp, BSRC_WORK, pl->d_work, EPI_WRITE_B, nullptr, out, nullptr, nullptr, s));
+  return MM_OK;
+}
+
+mm_status dot(mm_plan_s* pl, const double* a, const double* b, double* out, hipStream_t s) {
+  const int64_t n = mapn(pl);
+  const int nb = dot_blocks(n);
+  MM_TRY_HIP(launch_dot_partials(a, b, n, pl->d_part, nb, s));
+  MM_TRY_HIP(launch_reduce(pl->d_part, nb, out, s));
+  return MM_OK;
+}
+
+bool valid_lambda(double lam) { return std::isinf(lam) ? lam > 0 : (lam >= 1.0 && std::isfinite(lam)); }
+
+}  // namespace
+
+extern "C" {
+
+const char* mm_status_str(mm_status s) {
+  switch (s) {
+    case MM_OK: return "ok";
+    case MM_E_ARG: return "invalid argument";
+    case MM_E_LEN: return "unsupported chunk length";
+    case MM_E_NOMEM: return "out of memory";
+    case MM_E_HIP: return "HIP runtime error";
+    case MM_E_SINGULAR: return "no solvable pixel";
+    case MM_E_NONFINITE: return "non-finite chi^2";
+  }
+  return "unknown status";
+}
+
+const char* mm_last_error(void) { return g_last_error.c_str(); }
+
+mm_status mm_plan(const mm_plan_desc* desc, mm_stream_t stream, mm_plan_t* out) {
+  g_last_error.clear();
+  return build_plan(desc, S(stream), out);
+}
+
+mm_status mm_plan_destroy(mm_plan_t plan) {
+  if (!plan) return fail(MM_E_ARG, "null plan");
+  destroy_plan(plan);
+  return MM_OK;
+}
+
+mm_status mm_plan_workspace_bytes(mm_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(MM_E_ARG, "null argument");
+  *bytes = plan->bytes;
+  return MM_OK;
+}
+
+mm_status mm_plan_hits(mm_plan_t plan, int32_t* hits_dev, mm_stream_t stream) {
+  if (!plan || !hits_dev) return fail(MM_E_ARG, "null argument");
+  MM_TRY_HIP(launch_copy_bytes(hits_dev, plan->d_hits, plan->npix * (int64_t)sizeof(int32_t), S(stream)));
+  return MM_OK;
+}
+
+mm_status mm_plan_solvable(mm_plan_t plan, uint8_t* mask_dev, mm_stream_t stream) {
+  if (!plan || !mask_dev) return fail(MM_E_ARG, "null argument");
+  MM_TRY_HIP(launch_copy_bytes(mask_dev, plan->d_solvable, plan->npix, S(stream)));
+  return MM_OK;
+}
+
+mm_status mm_plan_nsolvable(mm_plan_t plan, int64_t* count) {
+  if (!plan || !count) return fail(MM_E_ARG, "null argument");
+  *count = plan->nsolvable;
+  return MM_OK;
+}
+
+mm_status mm_messenger_iter(mm_plan_t plan, const void* d, double lambda, const double* m_in, double* m_out,
+                            double* chi2_dev, mm_stream_t stream) {
+  if (!plan || !d || !m_in || !m_out) return fail(MM_E_ARG, "null argument");
+  if (!valid_lambda(lambda)) return fail(MM_E_ARG, "lambda must be >= 1 or +inf");
+  return iterate(plan, d, lambda, m_in, m_out, chi2_dev, S(stream));
+}
+
+mm_status mm_cooling_levels(mm_plan_t plan, int32_t nlevel, double lambda_max, double* out) {
+  if (!plan || !out || nlevel <= 0) return fail(MM_E_ARG, "invalid argument");
+  double lmax = lambda_max;
+  if (!(lmax > 0)) {
+    // lambda tau reaches the largest noise power: the clamped DC bin, N(f_1) (the spectrum
+    // falls with frequency for negative slopes; the largest of both ends covers the rest)
+    lmax = 1.0;
+    for (int64_t c = 0; c < plan->nchunk; ++c) {
+      const double n = (double)(plan->off[c + 1] - plan->off[c]);
+      const double s2 = plan->sigma[c] * plan->sigma[c];
+      const double f1 = plan->fsample[c] / n, fn = 0.5 * plan->fsample[c];
+      const double N1 = s2 * (1.0 + std::pow(f1 / plan->fknee[c], plan->alpha[c]));
+      const double Nn = s2 * (1.0 + std::pow(fn / plan->fknee[c], plan->alpha[c]));
+      lmax = std::max(lmax, std::max(N1, Nn) / plan->tau[c]);
+    }
+  }
+  if (lmax < 1.0) return fail(MM_E_ARG, "lambda_max must be >= 1");
+  for (int l = 0; l < nlevel; ++l)
+    out[l] = (nlevel == 1) ? 1.0 : std::pow(lmax, (double)(nlevel - 1 - l) / (double)(nlevel - 1));
+  out[nlevel - 1] = 1.0;
+  return MM_OK;
+}
+
+mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, const double* m0, double* m_out,
+                   double* chi2_hist_dev, mm_stream_t stream) {
+  if (!plan || !d || !sched || !m_out) return fail(MM_E_ARG, "null argument");
+  if (sched->nlevel < 0 || (sched->nlevel > 0 && (!sched->lambda || !sched->iters)))
+    return fail(MM_E_ARG, "invalid schedule");
+  std::vector<double> lams;
+  if (sched->first_inf) lams.push_back(INFINITY);
+  for (int l = 0; l < sched->nlevel; ++l) {
+    if (sched->iters[l] < 0 || !valid_lambda(sched->lambda[l])) return fail(MM_E_ARG, "invalid schedule level");
+    for (int i = 0; i < sched->iters[l]; ++i) lams.push_back(sched->lambda[l]);
+  }
+  hipStream_t cs = plan->cap_stream;
+  const int64_t n = mapn(plan);
+  MM_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  auto body = [&]() -> mm_status {
+    // start map into m_out (fill kernel, no memset nodes in the graph)
+    if (m0) {
+      if (m0 != m_out) MM_TRY_HIP(launch_copy(m_out, m0, n, cs));
+    } else {
+      MM_TRY_HIP(launch_fill(m_out, n, 0.0, cs));
+    }
+    // iterate in place: every pass reads the map before the binning epilogue rewrites it
+    const size_t nit = lams.size();
+    for (size_t i = 0; i < nit; ++i)
+      MM_TRY(iterate(plan, d, lams[i], m_out, m_out, chi2_hist_dev ? chi2_hist_dev + i : nullptr, cs));
+    if (chi2_hist_dev) MM_TRY(chi2_device(plan, d, m_out, 1.0, chi2_hist_dev + nit, nullptr, cs));
+    return MM_OK;
+  };
+  mm_status st = body();
+  hipGraph_t graph = nullptr;
+  hipError_t ee = hipStreamEndCapture(cs, &graph);
+  if (st != MM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph capture: ") + hipGetErrorString(ee));
+  hipGraphExec_t exec = nullptr;
+  ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ee));
+  ee = hipGraphLaunch(exec, S(stream));
+  plan->graphs.push_back(exec);
+  if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph launch: ") + hipGetErrorString(ee));
+  return MM_OK;
+}
+
+mm_status mm_chi2(mm_plan_t plan, const void* d, const double* m, double lambda, double* chi2_host,
+                  double* per_chunk_dev, mm_stream_t stream) {
+  if (!plan || !d || !m || !chi2_host) return fail(MM_E_ARG, "null argument");
+  if (!(lambda >= 1.0) || !std::isfinite(lambda)) return fail(MM_E_ARG, "lambda must be finite and >= 1");
+  hipStream_t s = S(stream);
+  MM_TRY(chi2_device(plan, d, m, lambda, plan->d_scal, per_chunk_dev, s));
+  double v = 0;
+  MM_TRY_HIP(hipMemcpyAsync(&v, plan->d_scal, sizeof(double), hipMemcpyDeviceToHost, s));
+  MM_TRY_HIP(hipStreamSynchronize(s));
+  if (!std::isfinite(v)) return fail(MM_E_NONFINITE, "chi^2 is not finite");
+  *chi2_host = v;
+  return MM_OK;
+}
+
+mm_status mm_apply(mm_plan_t plan, int32_t which, double lambda, const double* x, const void* d, double* out,
+                   mm_stream_t stream) {
+  if (!plan || !out || ((x == nullptr) == (d == nullptr))) return fail(MM_E_ARG, "exactly one of x and d");
+  if (which != 0 && which != 1) return fail(MM_E_ARG, "which must be 0 (N^-1) or 1 (messenger filter)");
+  if (which == 1 && (!(lambda >= 1.0) || !std::isfinite(lambda))) return fail(MM_E_ARG, "lambda must be >= 1");
+  return apply_op(plan, which == 0 ? GAIN_NINV : GAIN_MESSENGER, lambda, x, d, out, S(stream));
+}
+
+mm_status mm_lift_rhs(mm_plan_t plan, const double* g, void* out, mm_stream_t stream) {
+  if (!plan || !g || !out) return fail(MM_E_ARG, "null argument");
+  hipStream_t s = S(stream);
+  double* u = plan->d_map[5];
+  MM_TRY_HIP(launch_winv_apply(plan->dp, g, u, s));
+  MM_TRY(sweep_filter(plan, nullptr, u, SRC_PM, B_FILTER, GAIN_LIFT, 1.0, 1.0, s));
+  MM_TRY_HIP(launch_copy_bytes(out, plan->d_work, plan->ns * (plan->precision == MM_FP64 ? 8 : 4), s));
+  return MM_OK;
+}
+
+mm_status mm_cg_solve(mm_plan_t plan, const void* d, const double* rhs_map, int32_t maxiter, double rtol,
+                      const double* m0, double* m_out, double* chi2_hist_dev, double* rz_hist_dev,
+                      int32_t* iters_done, mm_stream_t stream) {
+  if (!plan || !m_out || maxiter < 0) return fail(MM_E_ARG, "invalid argument");
+  if ((d == nullptr) == (rhs_map == nullptr)) return fail(MM_E_ARG, "give exactly one of d and rhs_map");
+  if (chi2_hist_dev && !d) return fail(MM_E_ARG, "the chi^2 history needs the data");
+  if (!(rtol >= 0)) return fail(MM_E_ARG, "rtol must be >= 0");
+  hipStream_t s = S(stream);
+  const int64_t n = mapn(plan);
+  double* x = m_out;
+  double* b = plan->d_map[0];
+  double* r = plan->d_map[1];
+  double* z = plan->d_map[2];
+  double* p = plan->d_map[3];
+  double* q = plan->d_map[4];
+  double* zero = plan->d_map[5];
+  double* sc = plan->d_scal;  // 0: p.q  1: chi2(0)  2: x.b  3: x.r
+  double* rzh = rz_hist_dev;
+  if (!rzh) {
+    const size_t need = (size_t)maxiter + 1;
+    if (plan->hist_cap < need) {
+      void* h = nullptr;
+      MM_TRY_HIP(hipMalloc(&h, need * sizeof(double)));
+      if (plan->d_hist) {
+        MM_TRY_HIP(hipStreamSynchronize(s));
+        (void)hipFree(plan->d_hist);
+      }
+      plan->d_hist = (double*)h;
+      plan->hist_cap = need;
+      plan->extra_allocs.clear();
+      plan->extra_allocs.push_back(h);
+    }
+    rzh = plan->d_hist;
+  }
+  // b = P^T N^-1 d (or the given map)
+  if (d)
+    MM_TRY(apply_op(plan, GAIN_NINV, 1.0, nullptr, d, b, s));
+  else
+    MM_TRY_HIP(launch_copy(b, rhs_map, n, s));
+  // x0, r0 = b - A x0
+  if (m0) {
+    if (m0 != x) MM_TRY_HIP(launch_copy(x, m0, n, s));
+    MM_TRY(apply_op(plan, GAIN_NINV, 1.0, x, nullptr, q, s));
+    MM_TRY_HIP(launch_sub(r, b, q, n, s));
+  } else {
+    MM_TRY_HIP(launch_fill(x, n, 0.0, s));
+    MM_TRY_HIP(launch_copy(r, b, n, s));
+  }
+  MM_TRY_HIP(launch_winv_apply(plan->dp, r, z, s));
+  MM_TRY_HIP(launch_copy(p, z, n, s));
+  MM_TRY(dot(plan, r, z, rzh + 0, s));
+  auto record_chi2 = [&](int i) -> mm_status {
+    MM_TRY(dot(plan, x, b, sc + 2, s));
+    MM_TRY(dot(plan, x, r, sc + 3, s));
+    MM_TRY_HIP(launch_cg_chi2(sc + 1, sc + 2, sc + 3, chi2_hist_dev + i, s));
+    return MM_OK;
+  };
+  if (chi2_hist_dev) {
+    MM_TRY_HIP(launch_fill(zero, n, 0.0, s));
+    MM_TRY(chi2_device(plan, d, zero, 1.0, sc + 1, nullptr, s));
+    MM_TRY(record_chi2(0));
+  }
+  const int nb = dot_blocks(plan->npix);
+  int it = 0;
+  double rz0 = -1.0;
+  for (it = 0; it < maxiter; ++it) {
+    MM_TRY(apply_op(plan, GAIN_NINV, 1.0, p, nullptr, q, s));
+    MM_TRY(dot(plan, p, q, sc + 0, s));
+    MM_TRY_HIP(launch_cg_update_xr(plan->dp, x, r, z, p, q, rzh + it, sc + 0, plan->d_part, nb, s));
+    MM_TRY_HIP(launch_reduce(plan->d_part, nb, rzh + it + 1, s));
+    MM_TRY_HIP(launch_cg_update_p(p, z, rzh + it + 1, rzh + it, n, s));
+    if (chi2_hist_dev) MM_TRY(record_chi2(it + 1));
+    if (rtol > 0 && ((it + 1) % 10 == 0 || it + 1 == maxiter)) {
+      double h[2];
+      if (rz0 < 0) {
+        MM_TRY_HIP(hipMemcpyAsync(&h[0], rzh, sizeof(double), hipMemcpyDeviceToHost, s));
+      }
+      MM_TRY_HIP(hipMemcpyAsync(&h[1], rzh + it + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+      MM_TRY_HIP(hipStreamSynchronize(s));
+      if (rz0 < 0) rz0 = h[0];
+      if (h[1] <= rtol * rtol * rz0) {
+        ++it;
+        break;
+      }
+    }
+  }
+  if (iters_done) *iters_done = it;
+  return MM_OK;
+}
+
+}  // extern "C"

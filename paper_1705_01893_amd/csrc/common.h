@@ -1,0 +1,140 @@
+// Shared host/device definitions of libmm (messenger-field mapmaking on gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mm {
+
+constexpr int kBlock = 256;        // threads per workgroup of the transform and binning kernels
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxStages = 24;     // radix stages of one sub-transform
+constexpr int kSubBatch = 4096;    // samples staged in LDS per binning step (<= 65536: uint16 indices)
+constexpr int kMaxTilePix = 512;   // pixels per binning tile (LDS accumulators)
+
+// complex elements per thread in the LDS transforms (tile capacity = kBlock * ept)
+template <typename T> struct Ept;
+template <> struct Ept<float> { static constexpr int v = 32; };
+template <> struct Ept<double> { static constexpr int v = 16; };
+
+template <typename T> struct Cx;
+template <> struct Cx<float> { using t = float2; };
+template <> struct Cx<double> { using t = double2; };
+template <typename T> using cx = typename Cx<T>::t;
+
+// Per-chunk parameters.  A chunk of n real samples is transformed as M = n/2
+// complex points split M = M1 * M2 (M2-point column transforms, M1-point rows).
+struct DevChunk {
+  int64_t off;        // first sample of the chunk
+  int32_t n, M, M1, M2;
+  int32_t cls;        // transform class (shared by chunks of equal M)
+  int32_t cb;         // columns per column-pass item
+  double df;          // frequency step f_s / n
+  double sigma2;      // white level sigma^2
+  double fknee, alpha;
+  double tau, inv_tau;
+  double nbar0;       // sigma^2 - tau (N-bar = nbar0 + sigma^2 (f/fknee)^alpha)
+};
+
+// Per-length transform data: radix schedules and twiddle-table offsets.
+struct DevClass {
+  int32_t M, M1, M2;
+  int32_t nr1, nr2;   // number of radix stages for the M1 and M2 transforms
+  int32_t lo;         // two-level split of the omega_{2M} table: q = hi * lo + rem
+  int64_t tw1, tw2;   // offsets of omega_{M1}^q, omega_{M2}^q tables (complex entries)
+  int64_t twlo, twhi; // offsets of omega_{2M}^rem and omega_{2M}^(hi*lo)
+  int8_t rad1[kMaxStages];
+  int8_t rad2[kMaxStages];
+};
+
+struct ItemAC { int32_t chunk, j1; };            // column block starting at column j1
+struct ItemB { int32_t chunk, ra, rb, first; };  // rows ra, rb (rb == ra: one row); first item of its chunk?
+
+// Deterministic binning structures.  Samples on the map are grouped by pixel
+// tile, each tile's samples (in time order) are cut into sub-batches of at most
+// kSubBatch samples, and each sub-batch is described by its time-contiguous
+// segments (staged into LDS) plus the per-sample order sorted by local pixel.
+struct Tile {
+  int32_t sb_begin, sb_end;  // sub-batch range
+  int32_t x0, y0, tw, th;    // pixel rectangle (map row length DevPlan::nxm)
+};
+struct SubBatch {
+  int64_t sorted_begin;      // offset into perm / lp / psi_sorted
+  int32_t seg_begin, seg_end;
+  int32_t count;             // samples in the sub-batch
+  int32_t pad;
+};
+struct Segment {
+  int64_t start;             // first sample
+  int32_t len;
+  int32_t pos;               // position of the first sample in the LDS stage
+  int32_t chunk;
+  int32_t pad;
+};
+
+struct DevPlan {
+  int32_t ncomp, psi_kind, precision, pad0;
+  int64_t npix, nxm;         // pixels, map row length used by the tiles
+  int64_t nsamp;
+  int32_t nchunk, ntiles;
+  const DevChunk* chunks;
+  const DevClass* classes;
+  const double2* tw64;
+  const float2* tw32;
+  const int32_t* pix;
+  const void* psi;           // caller's angles (time order)
+  const double2* psi_cs64;   // (cos 2psi, sin 2psi) per table entry (MM_PSI_U16), float64
+  const float2* psi_cs32;    // same, float32
+  const Tile* tiles;
+  const SubBatch* sbs;
+  const Segment* segs;
+  const uint16_t* perm;      // sorted order -> stage position
+  const uint16_t* lp;        // sorted order -> local pixel
+  const void* psi_sorted;    // angles in sorted order (type psi_kind)
+  const double* winv;        // [nw][npix], nw = 1 or 6 (00 01 02 11 12 22)
+  const uint8_t* solvable;   // [npix]
+};
+
+// pass-A sources
+enum { SRC_D_MINUS_PM = 0, SRC_PM = 1, SRC_D = 2 };
+// pass-B operations (bit set)
+enum {
+  B_CHI2 = 1,         // accumulate chi^2(., chi2_lambda) partials
+  B_FILTER = 2,       // multiply by a gain, inverse-transform and write back
+};
+enum { GAIN_MESSENGER = 0, GAIN_NINV = 1, GAIN_LIFT = 2 };
+// binning sources / epilogues
+enum { BSRC_WORK = 0, BSRC_DATA_OVER_TAU = 1, BSRC_PLAN = 2 };
+enum { EPI_WRITE_B = 0, EPI_UPDATE = 1, EPI_REPLACE = 2, EPI_PLAN = 3 };
+
+// ---------------------------------------------------------------------------------------------
+// kernel launchers (kernels.hip)
+
+hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m,
+                         int src, void* work, size_t lds_bytes, hipStream_t s);
+hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void* work, int ops, int gain,
+                         double lam, double chi2_lam, double* chi2_part, size_t lds_bytes, hipStream_t s);
+hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds_bytes,
+                         hipStream_t s);
+hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
+                      double* w_out, int32_t* hits_out, hipStream_t s);
+hipError_t launch_chi2_reduce(const int32_t* chunk_item_begin, const double* part, int nchunk, double* per_chunk,
+                              double* total, hipStream_t s);
+// map-space vector kernels for CG and helpers
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+hipError_t launch_copy_bytes(void* dst, const void* src, int64_t nbytes, hipStream_t s);
+hipError_t launch_dot_partials(const double* a, const double* b, int64_t n, double* part, int nblk, hipStream_t s);
+hipError_t launch_reduce(const double* part, int n, double* out, hipStream_t s);
+hipError_t launch_winv_apply(const DevPlan& P, const double* x, double* y, hipStream_t s);
+hipError_t launch_cg_update_xr(const DevPlan& P, double* x, double* r, double* z, const double* p,
+                               const double* q, const double* rz, const double* pq, double* part, int nblk,
+                               hipStream_t s);
+hipError_t launch_cg_update_p(double* p, const double* z, const double* rz_new, const double* rz_old, int64_t n,
+                              hipStream_t s);
+hipError_t launch_cg_chi2(const double* chi2_0, const double* xb, const double* xr, double* out, hipStream_t s);
+hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
+int dot_blocks(int64_t n);
+
+}  // namespace mm

@@ -1,0 +1,227 @@
+// LDS-resident mixed-radix Stockham transforms for gfx950.
+//
+// A workgroup holds `nb` independent length-L complex sequences in LDS; element
+// i of sequence b lives at lds[i * sI + b * sB].  One radix-R stage reads every
+// element into registers (R per butterfly, a fixed number of butterflies per
+// thread), synchronises, applies twiddles and the R-point DFT in registers, and
+// writes the results to their self-sorting (Stockham) positions; after the last
+// stage the sequences are in natural frequency order in place.  Radices 2, 3, 4,
+// 5 and 8 cover every 5-smooth length.
+#pragma once
+
+#include "common.h"
+
+namespace mm {
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) {
+  C r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) {
+  C r;
+  r.x = a.x - b.x;
+  r.y = a.y - b.y;
+  return r;
+}
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename C>
+__device__ __forceinline__ C rot(C a) {
+  C r;
+  if (INV) {
+    r.x = -a.y;
+    r.y = a.x;
+  } else {
+    r.x = a.y;
+    r.y = -a.x;
+  }
+  return r;
+}
+template <typename C, typename T>
+__device__ __forceinline__ C cscale(C a, T s) {
+  C r;
+  r.x = a.x * s;
+  r.y = a.y * s;
+  return r;
+}
+
+// In-register R-point DFT, forward (exp(-2 pi i jk/R)) or inverse (exp(+...)), unnormalised.
+template <typename T, int R, bool INV>
+struct Dft;
+
+template <typename T, bool INV>
+struct Dft<T, 2, INV> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    cx<T> t = a[1];
+    a[1] = csub(a[0], t);
+    a[0] = cadd(a[0], t);
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 4, INV> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    cx<T> t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    cx<T> t2 = cadd(a[1], a[3]), t3 = rot<INV>(csub(a[1], a[3]));
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 8, INV> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    cx<T> e[4] = {a[0], a[2], a[4], a[6]};
+    cx<T> o[4] = {a[1], a[3], a[5], a[7]};
+    Dft<T, 4, INV>::run(e);
+    Dft<T, 4, INV>::run(o);
+    const T h = T(0.70710678118654752440084436210484903928);
+    // o[k] *= w8^k, w8 = exp(-+ i pi/4)
+    cx<T> o1, o3;
+    if (INV) {
+      o1.x = h * (o[1].x - o[1].y);
+      o1.y = h * (o[1].x + o[1].y);
+      o3.x = -h * (o[3].x + o[3].y);
+      o3.y = h * (o[3].x - o[3].y);
+    } else {
+      o1.x = h * (o[1].x + o[1].y);
+      o1.y = h * (o[1].y - o[1].x);
+      o3.x = h * (o[3].y - o[3].x);
+      o3.y = -h * (o[3].x + o[3].y);
+    }
+    cx<T> o2 = rot<INV>(o[2]);
+    a[0] = cadd(e[0], o[0]);
+    a[4] = csub(e[0], o[0]);
+    a[1] = cadd(e[1], o1);
+    a[5] = csub(e[1], o1);
+    a[2] = cadd(e[2], o2);
+    a[6] = csub(e[2], o2);
+    a[3] = cadd(e[3], o3);
+    a[7] = csub(e[3], o3);
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 3, INV> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    const T s3 = T(0.86602540378443864676372317075293618347);
+    cx<T> t = cadd(a[1], a[2]);
+    cx<T> u = csub(a[0], cscale(t, T(0.5)));
+    cx<T> v = rot<INV>(cscale(csub(a[1], a[2]), s3));
+    a[0] = cadd(a[0], t);
+    a[1] = cadd(u, v);
+    a[2] = csub(u, v);
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 5, INV> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    const T c1 = T(0.30901699437494742410229341718281905886);   // cos(2 pi/5)
+    const T c2 = T(-0.80901699437494742410229341718281905886);  // cos(4 pi/5)
+    const T s1 = T(0.95105651629515357211643933337938214340);   // sin(2 pi/5)
+    const T s2 = T(0.58778525229247312916870595463907276860);   // sin(4 pi/5)
+    cx<T> b1 = cadd(a[1], a[4]), b2 = cadd(a[2], a[3]);
+    cx<T> d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+    cx<T> x0 = a[0];
+    cx<T> p1 = cadd(x0, cadd(cscale(b1, c1), cscale(b2, c2)));
+    cx<T> p2 = cadd(x0, cadd(cscale(b1, c2), cscale(b2, c1)));
+    cx<T> q1 = rot<INV>(cadd(cscale(d1, s1), cscale(d2, s2)));
+    cx<T> q2 = rot<INV>(csub(cscale(d1, s2), cscale(d2, s1)));
+    a[0] = cadd(x0, cadd(b1, b2));
+    a[1] = cadd(p1, q1);
+    a[4] = csub(p1, q1);
+    a[2] = cadd(p2, q2);
+    a[3] = csub(p2, q2);
+  }
+};
+
+// One Stockham stage.  p = product of the radices already applied.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void stockham_stage(cx<T>* lds, int L, int nb, int sI, int sB, bool bfast, int p,
+                                               const cx<T>* __restrict__ tw) {
+  constexpr int K = (Ept<T>::v + R - 1) / R;  // butterflies per thread
+  const int nbf = L / R;
+  const int total = nbf * nb;
+  const int step = L / (p * R);
+  cx<T> v[K][R];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int f = threadIdx.x + u * kBlock;
+    if (f < total) {
+      int b, k;
+      if (bfast) {
+        b = f % nb;
+        k = f / nb;
+      } else {
+        k = f % nbf;
+        b = f / nbf;
+      }
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[u][m] = lds[(k + m * nbf) * sI + b * sB];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int f = threadIdx.x + u * kBlock;
+    if (f < total) {
+      int b, k;
+      if (bfast) {
+        b = f % nb;
+        k = f / nb;
+      } else {
+        k = f % nbf;
+        b = f / nbf;
+      }
+      const int j = k % p;
+      if (p > 1) {
+#pragma unroll
+        for (int m = 1; m < R; ++m) {
+          cx<T> w = tw[j * m * step];
+          if (INV) w.y = -w.y;
+          v[u][m] = cmul(v[u][m], w);
+        }
+      }
+      Dft<T, R, INV>::run(v[u]);
+      const int base = (k - j) * R + j;
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[(base + m * p) * sI + b * sB] = v[u][m];
+    }
+  }
+  __syncthreads();
+}
+
+// Full length-L transform of nb sequences (caller synchronises before the first stage).
+// tw: omega_L^q = exp(-2 pi i q / L), q < L.
+template <typename T, bool INV>
+__device__ void lds_fft(cx<T>* lds, int L, int nb, int sI, int sB, bool bfast, const int8_t* rad, int ns,
+                        const cx<T>* __restrict__ tw) {
+  int p = 1;
+  for (int s = 0; s < ns; ++s) {
+    const int R = rad[s];
+    switch (R) {
+      case 8: stockham_stage<T, 8, INV>(lds, L, nb, sI, sB, bfast, p, tw); break;
+      case 4: stockham_stage<T, 4, INV>(lds, L, nb, sI, sB, bfast, p, tw); break;
+      case 2: stockham_stage<T, 2, INV>(lds, L, nb, sI, sB, bfast, p, tw); break;
+      case 3: stockham_stage<T, 3, INV>(lds, L, nb, sI, sB, bfast, p, tw); break;
+      case 5: stockham_stage<T, 5, INV>(lds, L, nb, sI, sB, bfast, p, tw); break;
+      default: break;
+    }
+    p *= R;
+  }
+}
+
+}  // namespace mm

@@ -1,0 +1,864 @@
+// HIP kernels of the messenger-field mapmaking sweep (gfx950).
+//
+// One iteration of eqn. (mcompact), m <- m + W^-1 P^T (lambda^-1 N-bar + T)^-1 (d - P m),
+// runs as four passes over the time-ordered data of every chunk (Section 2.1 lists
+// the same cost centres: projection, forward transform, spectral filter, inverse
+// transform, back-projection):
+//
+//   pass A  gather P m, residual r = d - P m, M2-point column transforms of the
+//           complex sequence z_j = r_2j + i r_2j+1 (j = j1 + M1 j2), twiddle
+//           omega_M^(j1 k2), write in row layout X[k2 * M1 + j1];
+//   pass B  per pair of rows {k2, M2 - k2}: M1-point row transforms give Z_k
+//           (k = k2 + M2 k1); the partner bin M - k lives in the paired row, so the
+//           real spectrum R_k, R_{M-k} is untangled in registers, multiplied by the
+//           noise filter (and summed into chi^2), re-tangled, inverse-transformed
+//           along the rows and twiddled back;
+//   pass C  inverse column transforms: y = G r in time order, in place;
+//   pass D  deterministic binning P^T y per pixel tile, fused with the per-pixel
+//           3x3 solve and map update.
+//
+// All passes use one TOD-sized work buffer in place.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.h"
+#include "fft.h"
+
+namespace mm {
+
+// ---------------------------------------------------------------------------------------------
+// small helpers
+
+template <typename T>
+__device__ __forceinline__ const cx<T>* twtab(const DevPlan& P);
+template <>
+__device__ __forceinline__ const float2* twtab<float>(const DevPlan& P) { return P.tw32; }
+template <>
+__device__ __forceinline__ const double2* twtab<double>(const DevPlan& P) { return P.tw64; }
+
+// omega_{2M}^q = exp(-2 pi i q / (2M)), 0 <= q < 2M, from the two-level table
+template <typename T>
+__device__ __forceinline__ cx<T> omega2M(const DevPlan& P, const DevClass& cl, int64_t q) {
+  const cx<T>* tw = twtab<T>(P);
+  const int64_t hi = q / cl.lo;
+  const int64_t lo = q - hi * cl.lo;
+  return cmul(tw[cl.twhi + hi], tw[cl.twlo + lo]);
+}
+
+template <typename C>
+__device__ __forceinline__ C conjc(C a) {
+  a.y = -a.y;
+  return a;
+}
+
+// polarization weights (cos 2psi, sin 2psi) of one stored angle, computed in the TOD precision
+template <typename T>
+__device__ __forceinline__ void psi_weights(const DevPlan& P, const void* arr, int64_t i, T& c, T& s);
+
+template <>
+__device__ __forceinline__ void psi_weights<double>(const DevPlan& P, const void* arr, int64_t i, double& c,
+                                                    double& s) {
+  if (P.psi_kind == 1) {
+    const double a = 2.0 * ((const double*)arr)[i];
+    sincos(a, &s, &c);
+  } else if (P.psi_kind == 2) {
+    const double a = 2.0 * (double)((const float*)arr)[i];
+    sincos(a, &s, &c);
+  } else {
+    const double2 t = P.psi_cs64[((const uint16_t*)arr)[i]];
+    c = t.x;
+    s = t.y;
+  }
+}
+template <>
+__device__ __forceinline__ void psi_weights<float>(const DevPlan& P, const void* arr, int64_t i, float& c,
+                                                   float& s) {
+  if (P.psi_kind == 1) {
+    const float a = (float)(2.0 * ((const double*)arr)[i]);
+    sincosf(a, &s, &c);
+  } else if (P.psi_kind == 2) {
+    const float a = 2.0f * ((const float*)arr)[i];
+    sincosf(a, &s, &c);
+  } else {
+    const float2 t = P.psi_cs32[((const uint16_t*)arr)[i]];
+    c = t.x;
+    s = t.y;
+  }
+}
+
+// (P m)_j for one sample (float64)
+template <typename T>
+__device__ __forceinline__ double project_one(const DevPlan& P, const double* __restrict__ m, int64_t j) {
+  const int p = P.pix[j];
+  if (p < 0) return 0.0;
+  double v = m[p];
+  if (P.ncomp == 3) {
+    T c, s;
+    psi_weights<T>(P, P.psi, j, c, s);
+    v += (double)c * m[P.npix + p] + (double)s * m[2 * P.npix + p];
+  }
+  return v;
+}
+
+// noise spectrum pieces at real bin k: pl = sigma^2 (f/fknee)^alpha with the DC bin at f_1
+template <typename T>
+__device__ __forceinline__ T powerlaw(const DevChunk& ch, int64_t k);
+template <>
+__device__ __forceinline__ double powerlaw<double>(const DevChunk& ch, int64_t k) {
+  const double f = (double)(k == 0 ? 1 : k) * ch.df;
+  return ch.sigma2 * pow(f / ch.fknee, ch.alpha);
+}
+template <>
+__device__ __forceinline__ float powerlaw<float>(const DevChunk& ch, int64_t k) {
+  const float f = (float)((double)(k == 0 ? 1 : k) * ch.df);
+  return (float)ch.sigma2 * exp2f((float)ch.alpha * log2f(f / (float)ch.fknee));
+}
+
+struct BinCtx {
+  int gain;
+  double lam, chi2_lam;
+};
+
+// gain applied to R_k (includes the 1/M of the inverse transform) and chi^2 weight 1/(n N'_k)
+template <typename T>
+__device__ __forceinline__ void bin_factors(const DevChunk& ch, const BinCtx& bc, int64_t k, T& g, double& cw) {
+  const T pl = powerlaw<T>(ch, k);
+  const T N = (T)ch.sigma2 + pl;
+  const T tau = (T)ch.tau;
+  T gg;
+  if (bc.gain == GAIN_MESSENGER) {
+    const T nbar = (T)ch.nbar0 + pl;
+    gg = T(1) / (tau + nbar / (T)bc.lam);
+  } else if (bc.gain == GAIN_NINV) {
+    gg = T(1) / N;
+  } else {
+    gg = N / tau;
+  }
+  g = gg / (T)ch.M;
+  const double Np = (double)N + (bc.chi2_lam - 1.0) * ch.tau;
+  cw = 1.0 / ((double)ch.n * Np);
+}
+
+template <typename C>
+__device__ __forceinline__ double norm2(C a) {
+  return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+}
+
+// ---------------------------------------------------------------------------------------------
+// pass A: residual + column transforms
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __restrict__ items, int nitems,
+                                                   const T* __restrict__ d, const double* __restrict__ m, int src,
+                                                   cx<T>* __restrict__ X) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const ItemAC item = items[it];
+    const DevChunk ch = P.chunks[item.chunk];
+    const DevClass& cl = P.classes[ch.cls];
+    const int B = ch.cb, M1 = ch.M1, M2 = ch.M2;
+    const int j10 = item.j1;
+    const int nbv = min(B, M1 - j10);
+    const int ntot = B * M2;
+    for (int e = threadIdx.x; e < ntot; e += kBlock) {
+      const int b = e % B, j2 = e / B;
+      cx<T> z;
+      z.x = T(0);
+      z.y = T(0);
+      if (b < nbv) {
+        const int64_t s = ch.off + 2 * ((int64_t)(j10 + b) + (int64_t)M1 * j2);
+        double r0, r1;
+        if (src == SRC_D) {
+          r0 = (double)d[s];
+          r1 = (double)d[s + 1];
+        } else {
+          const double pm0 = project_one<T>(P, m, s);
+          const double pm1 = project_one<T>(P, m, s + 1);
+          if (src == SRC_PM) {
+            r0 = pm0;
+            r1 = pm1;
+          } else {
+            r0 = (double)d[s] - pm0;
+            r1 = (double)d[s + 1] - pm1;
+          }
+        }
+        z.x = (T)r0;
+        z.y = (T)r1;
+      }
+      lds[e] = z;
+    }
+    __syncthreads();
+    lds_fft<T, false>(lds, M2, B, B, 1, true, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    cx<T>* Xc = X + ch.off / 2;
+    for (int e = threadIdx.x; e < ntot; e += kBlock) {
+      const int b = e % B, k2 = e / B;
+      if (b < nbv) {
+        const int j1 = j10 + b;
+        const cx<T> w = omega2M<T>(P, cl, 2 * (int64_t)j1 * k2);
+        Xc[(int64_t)k2 * M1 + j1] = cmul(lds[e], w);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// pass B: row transforms, real-spectrum untangle, filter, chi^2, retangle, inverse rows
+
+template <typename T>
+__device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevChunk& ch, const DevClass& cl,
+                                       const BinCtx& bc, int ops, int64_t k, int ia, int ib, double& chi) {
+  const cx<T> Zk = lds[ia], Zm = lds[ib];
+  const int64_t M = ch.M;
+  cx<T> E, O;
+  E.x = T(0.5) * (Zk.x + Zm.x);
+  E.y = T(0.5) * (Zk.y - Zm.y);
+  // O = (Zk - conj(Zm)) / (2i)
+  O.x = T(0.5) * (Zk.y + Zm.y);
+  O.y = -T(0.5) * (Zk.x - Zm.x);
+  const cx<T> w = omega2M<T>(P, cl, k);
+  const cx<T> wO = cmul(w, O);
+  const cx<T> Rk = cadd(E, wO);
+  const cx<T> Rm = csub(conjc(E), conjc(wO));
+  T gk, gm;
+  double cwk, cwm;
+  bin_factors<T>(ch, bc, k, gk, cwk);
+  bin_factors<T>(ch, bc, M - k, gm, cwm);
+  if (ops & B_CHI2) chi += 2.0 * (norm2(Rk) * cwk + norm2(Rm) * cwm);
+  if (ops & B_FILTER) {
+    const cx<T> Yk = cscale(Rk, gk), Ym = cscale(Rm, gm);
+    cx<T> Ep, D;
+    Ep.x = T(0.5) * (Yk.x + Ym.x);
+    Ep.y = T(0.5) * (Yk.y - Ym.y);
+    D.x = T(0.5) * (Yk.x - Ym.x);
+    D.y = T(0.5) * (Yk.y + Ym.y);
+    const cx<T> Op = cmul(D, conjc(w));
+    // Z'_k = E' + i O',  Z'_{M-k} = conj(E') + i conj(O')
+    cx<T> zk, zm;
+    zk.x = Ep.x - Op.y;
+    zk.y = Ep.y + Op.x;
+    zm.x = Ep.x + Op.y;
+    zm.y = -Ep.y + Op.x;
+    lds[ia] = zk;
+    lds[ib] = zm;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void b_dc(cx<T>* lds, const DevChunk& ch, const BinCtx& bc, int ops, int ia,
+                                     double& chi) {
+  const cx<T> Z = lds[ia];
+  const T R0 = Z.x + Z.y, RM = Z.x - Z.y;
+  T g0, gM;
+  double c0, cM;
+  bin_factors<T>(ch, bc, 0, g0, c0);
+  bin_factors<T>(ch, bc, ch.M, gM, cM);
+  if (ops & B_CHI2) chi += (double)R0 * (double)R0 * c0 + (double)RM * (double)RM * cM;
+  if (ops & B_FILTER) {
+    const T Y0 = R0 * g0, YM = RM * gM;
+    cx<T> z;
+    z.x = T(0.5) * (Y0 + YM);
+    z.y = T(0.5) * (Y0 - YM);
+    lds[ia] = z;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void b_self(cx<T>* lds, const DevChunk& ch, const BinCtx& bc, int ops, int64_t k, int ia,
+                                       double& chi) {
+  // k = M/2: R_k = conj(Z_k); the retangled value is conj(Y_k)
+  const cx<T> Z = lds[ia];
+  T g;
+  double cw;
+  bin_factors<T>(ch, bc, k, g, cw);
+  if (ops & B_CHI2) chi += 2.0 * norm2(Z) * cw;
+  if (ops & B_FILTER) {
+    cx<T> y;
+    y.x = Z.x * g;
+    y.y = Z.y * g;  // conj(conj(Z) g)
+    lds[ia] = y;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pass_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
+                                                   cx<T>* __restrict__ X, int ops, BinCtx bc,
+                                                   double* __restrict__ chi2_part, int red_off) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  double* red = reinterpret_cast<double*>(smem_raw + red_off);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const ItemB item = items[it];
+    const DevChunk ch = P.chunks[item.chunk];
+    const DevClass& cl = P.classes[ch.cls];
+    const int M1 = ch.M1, M2 = ch.M2;
+    const int ra = item.ra, rb = item.rb;
+    const int nrow = (ra == rb) ? 1 : 2;
+    cx<T>* Xc = X + ch.off / 2;
+    for (int e = threadIdx.x; e < nrow * M1; e += kBlock) {
+      const int row = (e < M1) ? ra : rb;
+      lds[e] = Xc[(int64_t)row * M1 + (e % M1)];
+    }
+    __syncthreads();
+    const cx<T>* tw1 = twtab<T>(P) + cl.tw1;
+    lds_fft<T, false>(lds, M1, nrow, 1, M1, false, cl.rad1, cl.nr1, tw1);
+    double chi = 0.0;
+    const bool self_a = (ra == 0) || (2 * ra == M2);
+    if (!self_a) {
+      for (int k1 = threadIdx.x; k1 < M1; k1 += kBlock) {
+        const int pk1 = M1 - 1 - k1;
+        const int64_t k = ra + (int64_t)M2 * k1;
+        b_pair<T>(lds, P, ch, cl, bc, ops, k, k1, M1 + pk1, chi);
+      }
+    } else {
+      for (int sl = 0; sl < nrow; ++sl) {
+        const int row = sl == 0 ? ra : rb;
+        for (int k1 = threadIdx.x; k1 < M1; k1 += kBlock) {
+          const int pk1 = (row == 0) ? ((M1 - k1) % M1) : (M1 - 1 - k1);
+          if (k1 > pk1) continue;
+          const int64_t k = row + (int64_t)M2 * k1;
+          if (k == 0)
+            b_dc<T>(lds, ch, bc, ops, sl * M1, chi);
+          else if (k1 == pk1)
+            b_self<T>(lds, ch, bc, ops, k, sl * M1 + k1, chi);
+          else
+            b_pair<T>(lds, P, ch, cl, bc, ops, k, sl * M1 + k1, sl * M1 + pk1, chi);
+        }
+      }
+    }
+    if (ops & B_CHI2) {
+      red[threadIdx.x] = chi;
+      __syncthreads();
+      for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) chi2_part[it] = red[0];
+    }
+    if (ops & B_FILTER) {
+      __syncthreads();
+      lds_fft<T, true>(lds, M1, nrow, 1, M1, false, cl.rad1, cl.nr1, tw1);
+      for (int e = threadIdx.x; e < nrow * M1; e += kBlock) {
+        const int row = (e < M1) ? ra : rb;
+        const int j1 = e % M1;
+        const cx<T> w = conjc(omega2M<T>(P, cl, 2 * (int64_t)j1 * row));
+        Xc[(int64_t)row * M1 + j1] = cmul(lds[e], w);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// pass C: inverse column transforms -> filtered TOD in time order (in place)
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __restrict__ items, int nitems,
+                                                   cx<T>* __restrict__ X) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const ItemAC item = items[it];
+    const DevChunk ch = P.chunks[item.chunk];
+    const DevClass& cl = P.classes[ch.cls];
+    const int B = ch.cb, M1 = ch.M1, M2 = ch.M2;
+    const int j10 = item.j1;
+    const int nbv = min(B, M1 - j10);
+    const int ntot = B * M2;
+    cx<T>* Xc = X + ch.off / 2;
+    for (int e = threadIdx.x; e < ntot; e += kBlock) {
+      const int b = e % B, k2 = e / B;
+      cx<T> z;
+      z.x = T(0);
+      z.y = T(0);
+      if (b < nbv) z = Xc[(int64_t)k2 * M1 + j10 + b];
+      lds[e] = z;
+    }
+    __syncthreads();
+    lds_fft<T, true>(lds, M2, B, B, 1, true, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    for (int e = threadIdx.x; e < ntot; e += kBlock) {
+      const int b = e % B, j2 = e / B;
+      if (b < nbv) Xc[(int64_t)j10 + b + (int64_t)M1 * j2] = lds[e];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// pass D: deterministic binning per pixel tile (+ fused map update / plan precompute)
+
+template <typename T, int NV>
+__device__ __forceinline__ void contrib(const DevPlan& P, int64_t gk, double y, double* v) {
+  if (NV == 1) {
+    v[0] = y;
+  } else if (NV == 3) {
+    T c, s;
+    psi_weights<T>(P, P.psi_sorted, gk, c, s);
+    v[0] = y;
+    v[1] = (double)c * y;
+    v[2] = (double)s * y;
+  } else if (NV == 2) {  // plan, temperature: hits, sum 1/tau
+    v[0] = 1.0;
+    v[1] = y;
+  } else {  // NV == 7, plan, I/Q/U: hits and the six entries of sum a a^T / tau
+    T c, s;
+    psi_weights<T>(P, P.psi_sorted, gk, c, s);
+    const double cd = (double)c, sd = (double)s;
+    v[0] = 1.0;
+    v[1] = y;
+    v[2] = cd * y;
+    v[3] = sd * y;
+    v[4] = cd * cd * y;
+    v[5] = cd * sd * y;
+    v[6] = sd * sd * y;
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void bin_flush(double* acc, double* cv, int* clp, int wave, int lp, int first_lp,
+                                          const double* v) {
+  if (lp == first_lp) {
+    clp[wave] = lp;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) cv[wave * NV + q] = v[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[lp * NV + q] += v[q];
+  }
+}
+
+template <typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_bin(DevPlan P, int bsrc, const T* __restrict__ src, int epi,
+                                                const double* __restrict__ m_in, double* __restrict__ out,
+                                                double* __restrict__ w_out, int32_t* __restrict__ hits_out,
+                                                uint8_t* __restrict__ sol_out) {
+  extern __shared__ double smem_d[];
+  double* stage = smem_d;
+  double* acc = stage + kSubBatch;
+  double* cv = acc + kMaxTilePix * NV;
+  int* clp = reinterpret_cast<int*>(cv + kWaves * NV);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) {
+    const Tile tl = P.tiles[t];
+    const int tp = tl.tw * tl.th;
+    for (int i = threadIdx.x; i < tp * NV; i += kBlock) acc[i] = 0.0;
+    __syncthreads();
+    for (int sb = tl.sb_begin; sb < tl.sb_end; ++sb) {
+      const SubBatch S = P.sbs[sb];
+      for (int g = S.seg_begin + wave; g < S.seg_end; g += kWaves) {
+        const Segment seg = P.segs[g];
+        const double scale = (bsrc == BSRC_WORK) ? 1.0 : P.chunks[seg.chunk].inv_tau;
+        for (int i = lane; i < seg.len; i += 64) {
+          double v;
+          if (bsrc == BSRC_PLAN)
+            v = scale;
+          else
+            v = (double)src[seg.start + i] * scale;
+          stage[seg.pos + i] = v;
+        }
+      }
+      if (lane == 0) clp[wave] = -1;
+      __syncthreads();
+      const int cnt = S.count;
+      const int stripe = (((cnt + kWaves - 1) / kWaves) + 63) & ~63;
+      const int k0 = wave * stripe;
+      const int k1 = min(cnt, k0 + stripe);
+      if (k0 < k1) {
+        const int first_lp = P.lp[S.sorted_begin + k0];
+        int carry_lp = -1;
+        double carry[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) carry[q] = 0.0;
+        for (int kb = k0; kb < k1; kb += 64) {
+          const int k = kb + lane;
+          int mylp;
+          double v[NV];
+          if (k < k1) {
+            const int64_t gk = S.sorted_begin + k;
+            mylp = P.lp[gk];
+            const double y = stage[P.perm[gk]];
+            contrib<T, NV>(P, gk, y, v);
+          } else {
+            mylp = -2 - lane;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[q] = 0.0;
+          }
+          if (carry_lp >= 0) {
+            const int lp0 = __shfl(mylp, 0);
+            if (lp0 == carry_lp) {
+              if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) v[q] += carry[q];
+              }
+            } else if (lane == 0) {
+              bin_flush<NV>(acc, cv, clp, wave, carry_lp, first_lp, carry);
+            }
+          }
+          // segmented inclusive scan over equal local pixels (the order is sorted by pixel)
+#pragma unroll
+          for (int dd = 1; dd < 64; dd <<= 1) {
+            const int ulp = __shfl_up(mylp, dd);
+            double uv[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) uv[q] = __shfl_up(v[q], dd);
+            if (lane >= dd && ulp == mylp) {
+#pragma unroll
+              for (int q = 0; q < NV; ++q) v[q] += uv[q];
+            }
+          }
+          const int nlp = __shfl_down(mylp, 1);
+          if (lane < 63 && mylp >= 0 && nlp != mylp) bin_flush<NV>(acc, cv, clp, wave, mylp, first_lp, v);
+          carry_lp = __shfl(mylp, 63);
+#pragma unroll
+          for (int q = 0; q < NV; ++q) carry[q] = __shfl(v[q], 63);
+          if (carry_lp < 0) carry_lp = -1;
+        }
+        if (carry_lp >= 0 && lane == 0) bin_flush<NV>(acc, cv, clp, wave, carry_lp, first_lp, carry);
+      }
+      __syncthreads();
+      if (threadIdx.x < NV) {
+        for (int w = 0; w < kWaves; ++w) {
+          const int l = clp[w];
+          if (l >= 0) acc[l * NV + threadIdx.x] += cv[w * NV + threadIdx.x];
+        }
+      }
+      __syncthreads();
+    }
+    // epilogue: one thread per pixel of the tile
+    for (int l = threadIdx.x; l < tp; l += kBlock) {
+      const int64_t p = (int64_t)(tl.y0 + l / tl.tw) * P.nxm + tl.x0 + (l % tl.tw);
+      const double* a = acc + l * NV;
+      if (epi == EPI_PLAN) {
+        const double hits = a[0];
+        hits_out[p] = (int32_t)hits;
+        bool ok = hits > 0.5;
+        if (NV == 2) {
+          ok = ok && a[1] > 0.0;
+          w_out[p] = ok ? 1.0 / a[1] : 0.0;
+        } else {
+          const double w00 = a[1], w01 = a[2], w02 = a[3], w11 = a[4], w12 = a[5], w22 = a[6];
+          const double c00 = w11 * w22 - w12 * w12;
+          const double c01 = w02 * w12 - w01 * w22;
+          const double c02 = w01 * w12 - w02 * w11;
+          const double c11 = w00 * w22 - w02 * w02;
+          const double c12 = w01 * w02 - w00 * w12;
+          const double c22 = w00 * w11 - w01 * w01;
+          const double det = w00 * c00 + w01 * c01 + w02 * c02;
+          double i00 = 0, i01 = 0, i02 = 0, i11 = 0, i12 = 0, i22 = 0;
+          // solvable: hits and det(W) / (W00 W11 W22) >= 1e-8 (angle coverage separates Q and U)
+          const double diag = w00 * w11 * w22;
+          ok = ok && diag > 0.0 && det >= 1e-8 * diag;
+          if (ok) {
+            const double id = 1.0 / det;
+            i00 = c00 * id;
+            i01 = c01 * id;
+            i02 = c02 * id;
+            i11 = c11 * id;
+            i12 = c12 * id;
+            i22 = c22 * id;
+          }
+          if (!ok) i00 = i01 = i02 = i11 = i12 = i22 = 0.0;
+          const int64_t np = P.npix;
+          w_out[p] = i00;
+          w_out[np + p] = i01;
+          w_out[2 * np + p] = i02;
+          w_out[3 * np + p] = i11;
+          w_out[4 * np + p] = i12;
+          w_out[5 * np + p] = i22;
+        }
+        sol_out[p] = ok ? 1 : 0;
+      } else if (epi == EPI_WRITE_B) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) out[q * P.npix + p] = a[q];
+      } else {
+        const bool ok = P.solvable[p] != 0;
+        const int64_t np = P.npix;
+        double u[NV];
+        if (NV == 1) {
+          u[0] = P.winv[p] * a[0];
+        } else if (NV == 3) {
+          const double i00 = P.winv[p], i01 = P.winv[np + p], i02 = P.winv[2 * np + p];
+          const double i11 = P.winv[3 * np + p], i12 = P.winv[4 * np + p], i22 = P.winv[5 * np + p];
+          u[0] = i00 * a[0] + i01 * a[1] + i02 * a[2];
+          u[1] = i01 * a[0] + i11 * a[1] + i12 * a[2];
+          u[2] = i02 * a[0] + i12 * a[1] + i22 * a[2];
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          double r = 0.0;
+          if (ok) r = (epi == EPI_UPDATE) ? m_in[q * np + p] + u[q] : u[q];
+          out[q * np + p] = r;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// reductions and map-space vector kernels (all deterministic: fixed partition, fixed tree)
+
+__global__ __launch_bounds__(kBlock) void k_chi2_reduce(const int32_t* __restrict__ chunk_item_begin,
+                                                        const double* __restrict__ part, int nchunk,
+                                                        double* __restrict__ per_chunk, double* __restrict__ total) {
+  __shared__ double red[kBlock];
+  // one workgroup: chunk sums in chunk order, then the total
+  double acc_total = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    double s = 0.0;
+    for (int i = chunk_item_begin[c] + threadIdx.x; i < chunk_item_begin[c + 1]; i += kBlock) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (per_chunk) per_chunk[c] = red[0];
+      acc_total += red[0];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = acc_total;
+}
+
+__global__ void k_fill(double* x, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+__global__ void k_copy(double* dst, const double* src, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void k_copy_bytes(uint8_t* dst, const uint8_t* src, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void k_sub(double* out, const double* a, const double* b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = a[i] - b[i];
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot_partials(const double* __restrict__ a, const double* __restrict__ b,
+                                                         int64_t n, double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    s += a[i] * b[i];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double red[kBlock];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) *out = t;
+}
+
+__device__ __forceinline__ void winv_apply_one(const DevPlan& P, int64_t p, const double* x, double* y) {
+  const int64_t np = P.npix;
+  if (P.ncomp == 1) {
+    y[p] = P.winv[p] * x[p];
+    return;
+  }
+  const double a0 = x[p], a1 = x[np + p], a2 = x[2 * np + p];
+  const double i00 = P.winv[p], i01 = P.winv[np + p], i02 = P.winv[2 * np + p];
+  const double i11 = P.winv[3 * np + p], i12 = P.winv[4 * np + p], i22 = P.winv[5 * np + p];
+  y[p] = i00 * a0 + i01 * a1 + i02 * a2;
+  y[np + p] = i01 * a0 + i11 * a1 + i12 * a2;
+  y[2 * np + p] = i02 * a0 + i12 * a1 + i22 * a2;
+}
+
+__global__ void k_winv_apply(DevPlan P, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.npix; p += (int64_t)gridDim.x * blockDim.x)
+    winv_apply_one(P, p, x, y);
+}
+
+// x += alpha p, r -= alpha q, z = W^-1 r, partial sums of r.z ; alpha = rz / pq
+__global__ __launch_bounds__(kBlock) void k_cg_update_xr(DevPlan P, double* __restrict__ x, double* __restrict__ r,
+                                                         double* __restrict__ z, const double* __restrict__ p,
+                                                         const double* __restrict__ q, const double* __restrict__ rz,
+                                                         const double* __restrict__ pq, double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  const double alpha = (*rz) / (*pq);
+  const int64_t np = P.npix;
+  const int nc = P.ncomp;
+  double s = 0.0;
+  for (int64_t pix = blockIdx.x * (int64_t)kBlock + threadIdx.x; pix < np; pix += (int64_t)gridDim.x * kBlock) {
+    for (int c = 0; c < nc; ++c) {
+      const int64_t i = c * np + pix;
+      x[i] += alpha * p[i];
+      r[i] -= alpha * q[i];
+    }
+    winv_apply_one(P, pix, r, z);
+    for (int c = 0; c < nc; ++c) s += r[c * np + pix] * z[c * np + pix];
+  }
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// p = z + (rz_new / rz_old) p
+__global__ void k_cg_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ rz_new,
+                              const double* __restrict__ rz_old, int64_t n) {
+  const double beta = (*rz_new) / (*rz_old);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_cg_chi2(const double* chi2_0, const double* xb, const double* xr, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = *chi2_0 - *xb - *xr;
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+
+static inline int grid_for(int64_t n, int cap) { return (int)(n < cap ? (n > 0 ? n : 1) : cap); }
+constexpr int kGridCap = 1 << 16;
+
+hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m, int src,
+                         void* work, size_t lds, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (P.precision == 0)
+    hipLaunchKernelGGL(k_pass_a<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
+                       (const double*)d, m, src, (double2*)work);
+  else
+    hipLaunchKernelGGL(k_pass_a<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
+                       (const float*)d, m, src, (float2*)work);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void* work, int ops, int gain, double lam,
+                         double chi2_lam, double* chi2_part, size_t lds, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  BinCtx bc;
+  bc.gain = gain;
+  bc.lam = lam;
+  bc.chi2_lam = chi2_lam;
+  const int red_off = (int)lds;
+  const size_t tot = lds + kBlock * sizeof(double);
+  if (P.precision == 0)
+    hipLaunchKernelGGL(k_pass_b<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), tot, s, P, items, nitems,
+                       (double2*)work, ops, bc, chi2_part, red_off);
+  else
+    hipLaunchKernelGGL(k_pass_b<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), tot, s, P, items, nitems,
+                       (float2*)work, ops, bc, chi2_part, red_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (P.precision == 0)
+    hipLaunchKernelGGL(k_pass_c<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
+                       (double2*)work);
+  else
+    hipLaunchKernelGGL(k_pass_c<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
+                       (float2*)work);
+  return hipGetLastError();
+}
+
+template <typename T, int NV>
+static hipError_t launch_bin_t(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
+                               double* w_out, int32_t* hits_out, uint8_t* sol_out, hipStream_t s) {
+  const size_t lds = (kSubBatch + kMaxTilePix * NV + kWaves * NV) * sizeof(double) + kWaves * sizeof(int);
+  hipLaunchKernelGGL((k_bin<T, NV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBlock), lds, s, P, bsrc,
+                     (const T*)src, epi, m_in, out, w_out, hits_out, sol_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
+                      double* w_out, int32_t* hits_out, hipStream_t s) {
+  uint8_t* sol_out = reinterpret_cast<uint8_t*>(out);  // plan mode: the solvable mask
+  const bool f64 = P.precision == 0;
+  if (epi == EPI_PLAN) {
+    if (P.ncomp == 1)
+      return f64 ? launch_bin_t<double, 2>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s)
+                 : launch_bin_t<float, 2>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s);
+    return f64 ? launch_bin_t<double, 7>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s)
+               : launch_bin_t<float, 7>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s);
+  }
+  if (P.ncomp == 1)
+    return f64 ? launch_bin_t<double, 1>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s)
+               : launch_bin_t<float, 1>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s);
+  return f64 ? launch_bin_t<double, 3>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s)
+             : launch_bin_t<float, 3>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s);
+}
+
+hipError_t launch_chi2_reduce(const int32_t* chunk_item_begin, const double* part, int nchunk, double* per_chunk,
+                              double* total, hipStream_t s) {
+  hipLaunchKernelGGL(k_chi2_reduce, dim3(1), dim3(kBlock), 0, s, chunk_item_begin, part, nchunk, per_chunk, total);
+  return hipGetLastError();
+}
+
+static inline int vgrid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(vgrid(n)), dim3(256), 0, s, x, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(vgrid(n)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+hipError_t launch_copy_bytes(void* dst, const void* src, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_bytes, dim3(vgrid(n)), dim3(256), 0, s, (uint8_t*)dst, (const uint8_t*)src, n);
+  return hipGetLastError();
+}
+hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, out, a, b, n);
+  return hipGetLastError();
+}
+int dot_blocks(int64_t n) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+hipError_t launch_dot_partials(const double* a, const double* b, int64_t n, double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partials, dim3(nblk), dim3(kBlock), 0, s, a, b, n, part);
+  return hipGetLastError();
+}
+hipError_t launch_reduce(const double* part, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_winv_apply(const DevPlan& P, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_winv_apply, dim3(vgrid(P.npix)), dim3(256), 0, s, P, x, y);
+  return hipGetLastError();
+}
+hipError_t launch_cg_update_xr(const DevPlan& P, double* x, double* r, double* z, const double* p, const double* q,
+                               const double* rz, const double* pq, double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update_xr, dim3(nblk), dim3(kBlock), 0, s, P, x, r, z, p, q, rz, pq, part);
+  return hipGetLastError();
+}
+hipError_t launch_cg_update_p(double* p, const double* z, const double* rz_new, const double* rz_old, int64_t n,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update_p, dim3(vgrid(n)), dim3(256), 0, s, p, z, rz_new, rz_old, n);
+  return hipGetLastError();
+}
+hipError_t launch_cg_chi2(const double* chi2_0, const double* xb, const double* xr, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_chi2, dim3(1), dim3(64), 0, s, chi2_0, xb, xr, out);
+  return hipGetLastError();
+}
+
+}  // namespace mm

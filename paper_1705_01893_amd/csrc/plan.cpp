@@ -1,0 +1,538 @@
+// Plan construction for libmm: validation, transform splits, twiddle tables,
+// work lists, and the pixel-tile sort that makes binning deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "mm.h"
+#include "plan.h"
+
+namespace mm {
+
+thread_local std::string g_last_error;
+
+mm_status fail(mm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+static bool five_smooth(int64_t x) {
+  if (x < 1) return false;
+  for (int p : {2, 3, 5})
+    while (x % p == 0) x /= p;
+  return x == 1;
+}
+
+// radix schedule for a 5-smooth length: as many 8s as possible (a lone factor 2 turns
+// one 8 into 4*4), then 3s and 5s
+static std::vector<int8_t> radices(int64_t L) {
+  std::vector<int8_t> r;
+  int e2 = 0;
+  while (L % 2 == 0) {
+    L /= 2;
+    ++e2;
+  }
+  int n8 = e2 / 3, rem = e2 % 3;
+  if (rem == 1 && n8 > 0) {
+    --n8;
+    r.push_back(4);
+    r.push_back(4);
+  } else if (rem == 1) {
+    r.push_back(2);
+  } else if (rem == 2) {
+    r.push_back(4);
+  }
+  for (int i = 0; i < n8; ++i) r.push_back(8);
+  while (L % 3 == 0) {
+    L /= 3;
+    r.push_back(3);
+  }
+  while (L % 5 == 0) {
+    L /= 5;
+    r.push_back(5);
+  }
+  return r;
+}
+
+// choose M = M1 * M2 for the column (M2) and row (M1) transforms within the LDS capacity:
+// a column item holds cb * M2 complex values, a row item 2 * M1 plus the chi^2 reduction scratch
+static bool choose_split(int64_t M, int cap, int bmax, int row_cap, int64_t& M1, int64_t& M2, int& cb) {
+  int64_t best = -1, bestb = 0;
+  double bestscore = 1e300;
+  for (int64_t m2 = 1; m2 <= M; ++m2) {
+    if (M % m2) continue;
+    const int64_t m1 = M / m2;
+    const int64_t b = std::min<int64_t>(std::min<int64_t>(bmax, m1), cap / m2);
+    if (b < 1) continue;
+    if (2 * m1 > row_cap) continue;
+    // prefer full column blocks, then balanced splits
+    const double score = std::fabs(std::log((double)m2) - std::log(std::sqrt((double)M))) +
+                         (b < std::min<int64_t>(bmax, m1) ? 4.0 : 0.0);
+    if (score < bestscore) {
+      bestscore = score;
+      best = m2;
+      bestb = b;
+    }
+  }
+  if (best < 0) return false;
+  M2 = best;
+  M1 = M / best;
+  cb = (int)bestb;
+  return true;
+}
+
+static void omega_table(int64_t L, int64_t count, int64_t stride, std::vector<double2>& out) {
+  // out += exp(-2 pi i (q * stride) / L), q < count
+  for (int64_t q = 0; q < count; ++q) {
+    const int64_t e = (q * stride) % L;
+    const double a = -2.0 * M_PI * (double)e / (double)L;
+    out.push_back(make_double2(std::cos(a), std::sin(a)));
+  }
+}
+
+template <typename X>
+static mm_status upload(mm_plan_s* pl, const std::vector<X>& v, X** dptr, hipStream_t s) {
+  *dptr = nullptr;
+  if (v.empty()) return MM_OK;
+  void* p = nullptr;
+  const size_t bytes = v.size() * sizeof(X);
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(MM_E_NOMEM, "device allocation failed (plan tables)");
+  pl->allocs.push_back(p);
+  pl->bytes += bytes;
+  if (hipMemcpyAsync(p, v.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(MM_E_HIP, "host to device copy failed");
+  *dptr = (X*)p;
+  return MM_OK;
+}
+
+mm_status plan_alloc(mm_plan_s* pl, size_t bytes, void** out) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(MM_E_NOMEM, "device allocation failed");
+  pl->allocs.push_back(p);
+  pl->bytes += bytes;
+  *out = p;
+  return MM_OK;
+}
+
+static size_t psi_elem_size(int kind) {
+  switch (kind) {
+    case MM_PSI_F64: return 8;
+    case MM_PSI_F32: return 4;
+    case MM_PSI_U16: return 2;
+    default: return 0;
+  }
+}
+
+mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
+  if (!desc || !out) return fail(MM_E_ARG, "null descriptor or output");
+  const mm_plan_desc& D = *desc;
+  if (D.ncomp != 1 && D.ncomp != 3) return fail(MM_E_ARG, "ncomp must be 1 or 3");
+  if (D.precision != MM_FP64 && D.precision != MM_MIXED) return fail(MM_E_ARG, "unknown precision");
+  if (D.npix <= 0 || D.npix > (int64_t)INT32_MAX) return fail(MM_E_ARG, "npix out of range");
+  if (D.nx < 0 || (D.nx > 0 && D.npix % D.nx != 0)) return fail(MM_E_ARG, "nx must divide npix");
+  if (D.nchunk <= 0 || D.nchunk > (int64_t)INT32_MAX) return fail(MM_E_ARG, "nchunk out of range");
+  if (!D.chunk_off || !D.fsample || !D.sigma || !D.fknee || !D.alpha || !D.pix)
+    return fail(MM_E_ARG, "missing chunk table, noise parameters or pointing");
+  if (D.ncomp == 3) {
+    if (!D.psi || (D.psi_kind != MM_PSI_F64 && D.psi_kind != MM_PSI_F32 && D.psi_kind != MM_PSI_U16))
+      return fail(MM_E_ARG, "I/Q/U maps need polarization angles");
+    if (D.psi_kind == MM_PSI_U16 && (!D.psi_table || D.psi_table_len <= 0 || D.psi_table_len > 65536))
+      return fail(MM_E_ARG, "uint16 angle indices need a host angle table of 1..65536 entries");
+  }
+  if (D.chunk_off[0] != 0) return fail(MM_E_ARG, "chunk_off[0] must be 0");
+  for (int64_t c = 0; c < D.nchunk; ++c) {
+    const int64_t n = D.chunk_off[c + 1] - D.chunk_off[c];
+    if (n <= 0) return fail(MM_E_ARG, "chunk offsets must increase");
+    if (n % 2 != 0 || n < 2) return fail(MM_E_LEN, "chunk " + std::to_string(c) + ": length must be even");
+    if (!five_smooth(n / 2))
+      return fail(MM_E_LEN, "chunk " + std::to_string(c) + ": half length must factor into 2, 3 and 5");
+    if (n / 2 > (1 << 24)) return fail(MM_E_LEN, "chunk " + std::to_string(c) + ": too long");
+    const double sg = D.sigma[c], fk = D.fknee[c], al = D.alpha[c], fs = D.fsample[c];
+    if (!(sg > 0) || !(fk > 0) || !std::isfinite(al) || !(fs > 0) || !std::isfinite(sg) || !std::isfinite(fk) ||
+        !std::isfinite(fs))
+      return fail(MM_E_ARG, "chunk " + std::to_string(c) + ": invalid noise parameters");
+    if (D.tau) {
+      const double t = D.tau[c];
+      if (!(t > 0) || t > sg * sg * (1 + 1e-12))
+        return fail(MM_E_ARG, "chunk " + std::to_string(c) + ": tau must satisfy 0 < tau <= sigma^2");
+    }
+  }
+  const int64_t ns = D.chunk_off[D.nchunk];
+
+  auto* pl = new mm_plan_s();
+  std::unique_ptr<mm_plan_s, void (*)(mm_plan_s*)> guard(pl, [](mm_plan_s* p) { destroy_plan(p); });
+  pl->ncomp = D.ncomp;
+  pl->precision = D.precision;
+  pl->psi_kind = D.ncomp == 3 ? D.psi_kind : MM_PSI_NONE;
+  pl->npix = D.npix;
+  pl->nx = D.nx;
+  pl->nchunk = D.nchunk;
+  pl->ns = ns;
+  pl->off.assign(D.chunk_off, D.chunk_off + D.nchunk + 1);
+  pl->sigma.assign(D.sigma, D.sigma + D.nchunk);
+  pl->tau.resize(D.nchunk);
+  pl->fsample.assign(D.fsample, D.fsample + D.nchunk);
+  pl->fknee.assign(D.fknee, D.fknee + D.nchunk);
+  pl->alpha.assign(D.alpha, D.alpha + D.nchunk);
+  for (int64_t c = 0; c < D.nchunk; ++c) pl->tau[c] = D.tau ? D.tau[c] : D.sigma[c] * D.sigma[c];
+
+  const bool f64 = D.precision == MM_FP64;
+  const int cap = kBlock * (f64 ? Ept<double>::v : Ept<float>::v);
+  const int bmax = f64 ? 8 : 16;
+  const size_t csz = f64 ? sizeof(double2) : sizeof(float2);
+
+  // ---- transform classes, twiddles, chunk table, work lists
+  std::vector<double2> tw;
+  std::vector<DevClass> classes;
+  std::vector<DevChunk> chunks(D.nchunk);
+  std::vector<int64_t> class_M;
+  std::vector<int> class_cb;
+  size_t lds_ac = 0, lds_b = 0;
+  for (int64_t c = 0; c < D.nchunk; ++c) {
+    const int64_t n = D.chunk_off[c + 1] - D.chunk_off[c];
+    const int64_t M = n / 2;
+    int cls = -1;
+    for (size_t i = 0; i < class_M.size(); ++i)
+      if (class_M[i] == M) cls = (int)i;
+    if (cls < 0) {
+      int64_t M1, M2;
+      int cb;
+      const int row_cap = cap - (int)(kBlock * sizeof(double) / csz);
+      if (!choose_split(M, cap, bmax, row_cap, M1, M2, cb))
+        return fail(MM_E_LEN, "chunk " + std::to_string(c) + ": no transform split fits the LDS budget");
+      DevClass k;
+      std::memset(&k, 0, sizeof(k));
+      k.M = (int32_t)M;
+      k.M1 = (int32_t)M1;
+      k.M2 = (int32_t)M2;
+      auto r1 = radices(M1), r2 = radices(M2);
+      if ((int)r1.size() > kMaxStages || (int)r2.size() > kMaxStages) return fail(MM_E_LEN, "too many radix stages");
+      k.nr1 = (int32_t)r1.size();
+      k.nr2 = (int32_t)r2.size();
+      std::copy(r1.begin(), r1.end(), k.rad1);
+      std::copy(r2.begin(), r2.end(), k.rad2);
+      k.tw1 = (int64_t)tw.size();
+      omega_table(M1, M1, 1, tw);
+      k.tw2 = (int64_t)tw.size();
+      omega_table(M2, M2, 1, tw);
+      const int64_t L2 = 2 * M;
+      const int64_t lo = (int64_t)std::ceil(std::sqrt((double)L2));
+      const int64_t nhi = (L2 + lo - 1) / lo;
+      k.lo = (int32_t)lo;
+      k.twlo = (int64_t)tw.size();
+      omega_table(L2, lo, 1, tw);
+      k.twhi = (int64_t)tw.size();
+      omega_table(L2, nhi, lo, tw);
+      cls = (int)classes.size();
+      classes.push_back(k);
+      class_M.push_back(M);
+      class_cb.push_back(cb);
+      lds_ac = std::max(lds_ac, (size_t)cb * (size_t)M2 * csz);
+      lds_b = std::max(lds_b, (size_t)(2 * M1) * csz);
+    }
+    const DevClass& k = classes[cls];
+    DevChunk& ch = chunks[c];
+    std::memset(&ch, 0, sizeof(ch));
+    ch.off = D.chunk_off[c];
+    ch.n = (int32_t)n;
+    ch.M = k.M;
+    ch.M1 = k.M1;
+    ch.M2 = k.M2;
+    ch.cls = cls;
+    ch.cb = (int32_t)class_cb[cls];
+    ch.df = D.fsample[c] / (double)n;
+    ch.sigma2 = D.sigma[c] * D.sigma[c];
+    ch.fknee = D.fknee[c];
+    ch.alpha = D.alpha[c];
+    ch.tau = pl->tau[c];
+    ch.inv_tau = 1.0 / pl->tau[c];
+    ch.nbar0 = ch.sigma2 - ch.tau;
+    for (int32_t j1 = 0; j1 < ch.M1; j1 += ch.cb) pl->itemsAC.push_back({(int32_t)c, j1});
+    pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
+    const int M2 = ch.M2;
+    if (M2 % 2 == 0) {
+      pl->itemsB.push_back({(int32_t)c, 0, M2 / 2, 0});
+      for (int k2 = 1; k2 < M2 / 2; ++k2) pl->itemsB.push_back({(int32_t)c, k2, M2 - k2, 0});
+    } else {
+      pl->itemsB.push_back({(int32_t)c, 0, 0, 0});
+      for (int k2 = 1; k2 <= (M2 - 1) / 2; ++k2) pl->itemsB.push_back({(int32_t)c, k2, M2 - k2, 0});
+    }
+  }
+  pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
+  pl->lds_ac = lds_ac;
+  pl->lds_b = lds_b;
+  if (lds_ac > 65536 || lds_b + kBlock * sizeof(double) > 65536)
+    return fail(MM_E_LEN, "transform tiles exceed the LDS budget");
+  std::vector<float2> tw32(tw.size());
+  for (size_t i = 0; i < tw.size(); ++i) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
+
+  // ---- pointing: copy to host, validate, sort by pixel tile
+  std::vector<int32_t> pix(ns);
+  if (hipMemcpy(pix.data(), D.pix, ns * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(MM_E_HIP, "copying the pointing to the host failed (is pix a device pointer?)");
+  for (int64_t j = 0; j < ns; ++j)
+    if (pix[j] >= D.npix) return fail(MM_E_ARG, "pixel index " + std::to_string(pix[j]) + " beyond the map");
+  const size_t pes = psi_elem_size(pl->psi_kind);
+  std::vector<uint8_t> psi;
+  if (pes) {
+    psi.resize(ns * pes);
+    if (hipMemcpy(psi.data(), D.psi, ns * pes, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(MM_E_HIP, "copying the angles to the host failed (is psi a device pointer?)");
+    if (pl->psi_kind == MM_PSI_U16) {
+      const uint16_t* ix = (const uint16_t*)psi.data();
+      for (int64_t j = 0; j < ns; ++j)
+        if (ix[j] >= D.psi_table_len) return fail(MM_E_ARG, "angle index beyond the table");
+    }
+  }
+
+  // tiles: rectangles of tw x th pixels over a map of rows of length nxm
+  const int64_t nxm = D.nx > 0 ? D.nx : D.npix;
+  const int64_t nym = D.npix / nxm;
+  int64_t target = std::max<int64_t>(16, std::min<int64_t>(512, D.npix / 1024));
+  int64_t tw_ = 1;
+  while (tw_ * tw_ * 2 <= target) tw_ *= 2;  // tw_ ~ sqrt(target), power of two
+  int64_t th_ = std::max<int64_t>(1, target / tw_);
+  if (nym == 1) {
+    tw_ = target;
+    th_ = 1;
+  }
+  tw_ = std::min(tw_, nxm);
+  th_ = std::min(th_, nym);
+  const int64_t ntx = (nxm + tw_ - 1) / tw_, nty = (nym + th_ - 1) / th_;
+  const int64_t ntiles = ntx * nty;
+  std::vector<int64_t> tcount(ntiles + 1, 0);
+  auto tile_of = [&](int32_t p) -> int64_t {
+    const int64_t y = p / nxm, x = p % nxm;
+    return (y / th_) * ntx + (x / tw_);
+  };
+  for (int64_t j = 0; j < ns; ++j)
+    if (pix[j] >= 0) ++tcount[tile_of(pix[j]) + 1];
+  for (int64_t t = 0; t < ntiles; ++t) tcount[t + 1] += tcount[t];
+  const int64_t non = tcount[ntiles];
+  std::vector<int64_t> order(non);
+  {
+    std::vector<int64_t> fill(tcount.begin(), tcount.end() - 1);
+    for (int64_t j = 0; j < ns; ++j)
+      if (pix[j] >= 0) order[fill[tile_of(pix[j])]++] = j;
+  }
+  std::vector<uint16_t> perm(non), lpv(non);
+  std::vector<uint8_t> psi_sorted(non * pes);
+  std::vector<std::vector<Segment>> tsegs(ntiles);
+  std::vector<Tile> tiles(ntiles);
+  std::vector<int64_t> tsb(ntiles + 1, 0);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int64_t cnt = tcount[t + 1] - tcount[t];
+    tsb[t + 1] = tsb[t] + (cnt + kSubBatch - 1) / kSubBatch;
+  }
+  std::vector<SubBatch> sbs(tsb[ntiles]);
+  const std::vector<int64_t>& coff = pl->off;
+  auto chunk_of = [&](int64_t j) -> int32_t {
+    return (int32_t)(std::upper_bound(coff.begin(), coff.end(), j) - coff.begin() - 1);
+  };
+  std::atomic<int64_t> next(0);
+  auto worker = [&]() {
+    std::vector<int32_t> hist;
+    for (;;) {
+      const int64_t t = next.fetch_add(1);
+      if (t >= ntiles) break;
+      const int64_t ty = t / ntx, tx = t % ntx;
+      Tile tl;
+      tl.x0 = (int32_t)(tx * tw_);
+      tl.y0 = (int32_t)(ty * th_);
+      tl.tw = (int32_t)std::min(tw_, nxm - tx * tw_);
+      tl.th = (int32_t)std::min(th_, nym - ty * th_);
+      tl.sb_begin = (int32_t)tsb[t];
+      tl.sb_end = (int32_t)tsb[t + 1];
+      tiles[t] = tl;
+      const int64_t tp = (int64_t)tl.tw * tl.th;
+      hist.assign(tp + 1, 0);
+      for (int64_t sb = tsb[t]; sb < tsb[t + 1]; ++sb) {
+        const int64_t b0 = tcount[t] + (sb - tsb[t]) * kSubBatch;
+        const int64_t b1 = std::min(b0 + kSubBatch, tcount[t + 1]);
+        SubBatch S;
+        S.sorted_begin = b0;
+        S.count = (int32_t)(b1 - b0);
+        S.pad = 0;
+        S.seg_begin = (int32_t)tsegs[t].size();  // tile-local; rebased when concatenated
+        // segments: maximal runs of consecutive samples inside one chunk
+        int64_t cur_end = -1;
+        for (int64_t i = b0; i < b1; ++i) {
+          const int64_t j = order[i];
+          if (j == cur_end && j < coff[tsegs[t].back().chunk + 1]) {
+            tsegs[t].back().len += 1;
+          } else {
+            Segment g;
+            g.start = j;
+            g.len = 1;
+            g.pos = (int32_t)(i - b0);
+            g.chunk = chunk_of(j);
+            g.pad = 0;
+            tsegs[t].push_back(g);
+          }
+          cur_end = j + 1;
+        }
+        S.seg_end = (int32_t)tsegs[t].size();
+        // counting sort of the sub-batch by local pixel (stable: time order within a pixel)
+        std::fill(hist.begin(), hist.end(), 0);
+        auto lp_of = [&](int64_t j) -> int32_t {
+          const int64_t p = pix[j];
+          const int64_t y = p / nxm, x = p % nxm;
+          return (int32_t)((y - tl.y0) * tl.tw + (x - tl.x0));
+        };
+        for (int64_t i = b0; i < b1; ++i) ++hist[lp_of(order[i]) + 1];
+        for (int64_t l = 0; l < tp; ++l) hist[l + 1] += hist[l];
+        for (int64_t i = b0; i < b1; ++i) {
+          const int64_t j = order[i];
+          const int32_t l = lp_of(j);
+          const int64_t dst = b0 + hist[l]++;
+          perm[dst] = (uint16_t)(i - b0);
+          lpv[dst] = (uint16_t)l;
+          if (pes) std::memcpy(&psi_sorted[dst * pes], &psi[j * pes], pes);
+        }
+        sbs[sb] = S;
+      }
+    }
+  };
+  {
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned i = 0; i < nth; ++i) th.emplace_back(worker);
+    for (auto& x : th) x.join();
+  }
+  std::vector<Segment> segs;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int32_t base = (int32_t)segs.size();
+    for (int64_t sb = tsb[t]; sb < tsb[t + 1]; ++sb) {
+      sbs[sb].seg_begin += base;
+      sbs[sb].seg_end += base;
+    }
+    segs.insert(segs.end(), tsegs[t].begin(), tsegs[t].end());
+    std::vector<Segment>().swap(tsegs[t]);
+  }
+  pl->ntiles = ntiles;
+  pl->nsegs = (int64_t)segs.size();
+  pl->tile_w = (int32_t)tw_;
+  pl->tile_h = (int32_t)th_;
+
+  // ---- device uploads
+  DevPlan& P = pl->dp;
+  std::memset(&P, 0, sizeof(P));
+  P.ncomp = D.ncomp;
+  P.psi_kind = pl->psi_kind;
+  P.precision = D.precision;
+  P.npix = D.npix;
+  P.nxm = nxm;
+  P.nsamp = ns;
+  P.nchunk = (int32_t)D.nchunk;
+  P.ntiles = (int32_t)ntiles;
+  P.pix = D.pix;
+  P.psi = D.psi;
+  mm_status st;
+  DevChunk* dchunks;
+  DevClass* dclasses;
+  double2* dtw64;
+  float2* dtw32;
+  if ((st = upload(pl, chunks, &dchunks, s)) != MM_OK) return st;
+  if ((st = upload(pl, classes, &dclasses, s)) != MM_OK) return st;
+  if ((st = upload(pl, tw, &dtw64, s)) != MM_OK) return st;
+  if ((st = upload(pl, tw32, &dtw32, s)) != MM_OK) return st;
+  P.chunks = dchunks;
+  P.classes = dclasses;
+  P.tw64 = dtw64;
+  P.tw32 = dtw32;
+  if (pl->psi_kind == MM_PSI_U16) {
+    std::vector<double2> cs64(D.psi_table_len);
+    std::vector<float2> cs32(D.psi_table_len);
+    for (int64_t i = 0; i < D.psi_table_len; ++i) {
+      const double a = 2.0 * (double)D.psi_table[i];
+      cs64[i] = make_double2(std::cos(a), std::sin(a));
+      cs32[i] = make_float2((float)cs64[i].x, (float)cs64[i].y);
+    }
+    double2* d64;
+    float2* d32;
+    if ((st = upload(pl, cs64, &d64, s)) != MM_OK) return st;
+    if ((st = upload(pl, cs32, &d32, s)) != MM_OK) return st;
+    P.psi_cs64 = d64;
+    P.psi_cs32 = d32;
+  }
+  Tile* dtiles;
+  SubBatch* dsbs;
+  Segment* dsegs;
+  uint16_t *dperm, *dlp;
+  uint8_t* dpsis = nullptr;
+  if ((st = upload(pl, tiles, &dtiles, s)) != MM_OK) return st;
+  if ((st = upload(pl, sbs, &dsbs, s)) != MM_OK) return st;
+  if ((st = upload(pl, segs, &dsegs, s)) != MM_OK) return st;
+  if ((st = upload(pl, perm, &dperm, s)) != MM_OK) return st;
+  if ((st = upload(pl, lpv, &dlp, s)) != MM_OK) return st;
+  if (pes && (st = upload(pl, psi_sorted, &dpsis, s)) != MM_OK) return st;
+  P.tiles = dtiles;
+  P.sbs = dsbs;
+  P.segs = dsegs;
+  P.perm = dperm;
+  P.lp = dlp;
+  P.psi_sorted = dpsis;
+  if ((st = upload(pl, pl->itemsAC, &pl->d_itemsAC, s)) != MM_OK) return st;
+  if ((st = upload(pl, pl->itemsB, &pl->d_itemsB, s)) != MM_OK) return st;
+  if ((st = upload(pl, pl->chunk_item_begin, &pl->d_chunk_item_begin, s)) != MM_OK) return st;
+
+  const int64_t mapn = (int64_t)D.ncomp * D.npix;
+  const int nw = D.ncomp == 1 ? 1 : 6;
+  void* p;
+  if ((st = plan_alloc(pl, (size_t)nw * D.npix * sizeof(double), &p)) != MM_OK) return st;
+  pl->d_winv = (double*)p;
+  if ((st = plan_alloc(pl, (size_t)D.npix, &p)) != MM_OK) return st;
+  pl->d_solvable = (uint8_t*)p;
+  if ((st = plan_alloc(pl, (size_t)D.npix * sizeof(int32_t), &p)) != MM_OK) return st;
+  pl->d_hits = (int32_t*)p;
+  if ((st = plan_alloc(pl, (size_t)ns * (f64 ? 8 : 4), &p)) != MM_OK) return st;
+  pl->d_work = p;
+  if ((st = plan_alloc(pl, pl->itemsB.size() * sizeof(double), &p)) != MM_OK) return st;
+  pl->d_chi2_part = (double*)p;
+  if ((st = plan_alloc(pl, 64 * sizeof(double), &p)) != MM_OK) return st;
+  pl->d_scal = (double*)p;
+  if ((st = plan_alloc(pl, 1024 * sizeof(double), &p)) != MM_OK) return st;
+  pl->d_part = (double*)p;
+  for (int i = 0; i < kScratchMaps; ++i) {
+    if ((st = plan_alloc(pl, (size_t)mapn * sizeof(double), &p)) != MM_OK) return st;
+    pl->d_map[i] = (double*)p;
+  }
+  P.winv = pl->d_winv;
+  P.solvable = pl->d_solvable;
+
+  // ---- precompute: hits, weight blocks and their inverses (deterministic binning)
+  hipError_t e = launch_bin(P, BSRC_PLAN, nullptr, EPI_PLAN, nullptr, (double*)pl->d_solvable, pl->d_winv,
+                            pl->d_hits, s);
+  if (e != hipSuccess) return fail(MM_E_HIP, std::string("plan kernel launch: ") + hipGetErrorString(e));
+  std::vector<uint8_t> sol(D.npix);
+  if (hipMemcpyAsync(sol.data(), pl->d_solvable, D.npix, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(MM_E_HIP, std::string("plan precompute failed: ") + hipGetErrorString(hipGetLastError()));
+  int64_t nsol = 0;
+  for (int64_t i = 0; i < D.npix; ++i) nsol += sol[i];
+  pl->nsolvable = nsol;
+  if (nsol == 0) return fail(MM_E_SINGULAR, "no pixel has a solvable weight block");
+  if (hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(MM_E_HIP, "stream creation failed");
+  *out = guard.release();
+  return MM_OK;
+}
+
+void destroy_plan(mm_plan_s* pl) {
+  if (!pl) return;
+  if (!pl->graphs.empty() || !pl->allocs.empty()) (void)hipDeviceSynchronize();
+  for (auto g : pl->graphs) (void)hipGraphExecDestroy(g);
+  for (void* p : pl->allocs) (void)hipFree(p);
+  for (void* p : pl->extra_allocs) (void)hipFree(p);
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  delete pl;
+}
+
+}  // namespace mm

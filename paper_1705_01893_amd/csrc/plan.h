@@ -1,0 +1,61 @@
+// Internal plan object of libmm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "mm.h"
+
+namespace mm {
+
+constexpr int kScratchMaps = 6;
+
+extern thread_local std::string g_last_error;
+mm_status fail(mm_status s, const std::string& msg);
+
+}  // namespace mm
+
+struct mm_plan_s {
+  int32_t ncomp = 0, precision = 0, psi_kind = 0;
+  int64_t npix = 0, nx = 0, nchunk = 0, ns = 0;
+  std::vector<int64_t> off;
+  std::vector<double> fsample, sigma, fknee, alpha, tau;
+  // work lists
+  std::vector<mm::ItemAC> itemsAC;
+  std::vector<mm::ItemB> itemsB;
+  std::vector<int32_t> chunk_item_begin;
+  size_t lds_ac = 0, lds_b = 0;
+  int64_t ntiles = 0, nsegs = 0;
+  int32_t tile_w = 0, tile_h = 0;
+  // device
+  mm::DevPlan dp;
+  std::vector<void*> allocs;
+  std::vector<void*> extra_allocs;
+  size_t bytes = 0;
+  mm::ItemAC* d_itemsAC = nullptr;
+  mm::ItemB* d_itemsB = nullptr;
+  int32_t* d_chunk_item_begin = nullptr;
+  double* d_winv = nullptr;
+  uint8_t* d_solvable = nullptr;
+  int32_t* d_hits = nullptr;
+  void* d_work = nullptr;
+  double* d_chi2_part = nullptr;
+  double* d_scal = nullptr;
+  double* d_part = nullptr;
+  double* d_map[mm::kScratchMaps] = {};
+  double* d_hist = nullptr;  // grows on demand (CG rz history)
+  size_t hist_cap = 0;
+  int64_t nsolvable = 0;
+  hipStream_t cap_stream = nullptr;
+  std::vector<hipGraphExec_t> graphs;
+};
+
+namespace mm {
+mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out);
+void destroy_plan(mm_plan_s* pl);
+mm_status plan_alloc(mm_plan_s* pl, size_t bytes, void** out);
+}  // namespace mm

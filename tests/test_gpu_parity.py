@@ -1,0 +1,285 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU FP64 oracle.
+
+Bars: pixel hit counts and the solvable mask bit-exact; FP64 maps within 1e-10
+relative L2 and chi^2 within 1e-10 relative; FP32-mixed maps within 1e-5
+relative L2 and chi^2 within 1e-6 relative (the tolerances of the workload
+definition).
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from oracle import dense  # noqa: E402
+from oracle.cg import apply_A, pcg_solve, rhs  # noqa: E402
+from oracle.messenger import (binned_map, chi2, chi2_lambda, cooling_schedule, make_setup,  # noqa: E402
+                              messenger_solve, messenger_step)
+from paper_1705_01893_amd import mm  # noqa: E402
+from tests.tiny_inputs import random_map, tiny_problem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-10
+MIX_TOL = 1e-5
+MIX_CHI2 = 1e-6
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_plan(t, dev, precision=mm.MM_FP64, tau=None):
+    pix = torch.from_numpy(np.ascontiguousarray(t.pix)).to(dev)
+    psi = None
+    if t.ncomp == 3:
+        psi = torch.from_numpy(np.ascontiguousarray(t.psi)).to(dev)
+    plan = mm.mm_plan(ncomp=t.ncomp, npix=t.npix, nx=t.nx, chunk_off=t.chunk_off, fsample=t.fsample,
+                      sigma=t.sigma, fknee=t.fknee, alpha=t.alpha, pix=pix, psi=psi, tau=tau,
+                      precision=precision)
+    return plan
+
+
+def oracle_setup(t, tau=None):
+    return make_setup(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, t.npix, t.ncomp, tau=tau)
+
+
+def tod(t, dev, precision):
+    dt = np.float64 if precision == mm.MM_FP64 else np.float32
+    return torch.from_numpy(np.ascontiguousarray(t.d.astype(dt))).to(dev)
+
+
+# problem shapes: several chunks, ragged lengths (mixed radix, odd half-lengths), flagged samples
+SHAPES = {
+    "pow2": dict(lengths=(256, 512, 128), nx=8),
+    "mixed_radix": dict(lengths=(2 * 3 * 5 * 8, 2 * 45, 2 * 27 * 4, 2 * 125), nx=8),
+    "odd_half": dict(lengths=(30, 18, 50), nx=4),
+    "long": dict(lengths=(2 * 4096, 2 * 6000), nx=16),
+    "tiny_chunks": dict(lengths=(2, 4, 6, 10, 16), nx=4),
+}
+
+
+@pytest.mark.parametrize("shape", list(SHAPES))
+@pytest.mark.parametrize("ncomp", [1, 3])
+def test_hits_and_solvable_bit_exact(dev, shape, ncomp):
+    say(f"[hits] shape={shape} ncomp={ncomp}")
+    t = tiny_problem(101, ncomp=ncomp, **SHAPES[shape])
+    plan = gpu_plan(t, dev)
+    hits = torch.zeros(t.npix, dtype=torch.int32, device=dev)
+    mask = torch.zeros(t.npix, dtype=torch.uint8, device=dev)
+    mm.mm_plan_hits(plan, hits)
+    mm.mm_plan_solvable(plan, mask)
+    torch.cuda.synchronize()
+    S = oracle_setup(t)
+    np.testing.assert_array_equal(hits.cpu().numpy(), np.bincount(t.pix[t.pix >= 0], minlength=t.npix))
+    np.testing.assert_array_equal(mask.cpu().numpy().astype(bool), S.solvable)
+    assert mm.mm_plan_nsolvable(plan) == int(S.solvable.sum())
+
+
+@pytest.mark.parametrize("shape", list(SHAPES))
+@pytest.mark.parametrize("ncomp", [1, 3])
+@pytest.mark.parametrize("lam", [math.inf, 1.0, 37.5])
+def test_one_iteration_fp64(dev, shape, ncomp, lam):
+    say(f"[iter64] shape={shape} ncomp={ncomp} lam={lam}")
+    t = tiny_problem(202, ncomp=ncomp, **SHAPES[shape])
+    plan = gpu_plan(t, dev)
+    S = oracle_setup(t)
+    m0 = random_map(5, ncomp, t.npix)
+    m0[:, ~S.solvable] = 0.0
+    d = tod(t, dev, mm.MM_FP64)
+    mi = torch.from_numpy(m0).to(dev)
+    mo = torch.zeros_like(mi)
+    c2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    mm.mm_messenger_iter(plan, d, lam, mi, mo, c2)
+    torch.cuda.synchronize()
+    ref = messenger_step(S, t.d, m0, lam)
+    assert rel(mo.cpu().numpy(), ref) < F64_TOL
+    assert c2.item() == pytest.approx(chi2(S, t.d, m0), rel=F64_TOL)
+
+
+@pytest.mark.parametrize("shape", ["pow2", "mixed_radix", "long"])
+@pytest.mark.parametrize("lam", [1.0, 4.0, 1e3])
+def test_chi2_per_chunk_fp64(dev, shape, lam):
+    say(f"[chi2] shape={shape} lam={lam}")
+    t = tiny_problem(303, ncomp=3, **SHAPES[shape])
+    plan = gpu_plan(t, dev)
+    S = oracle_setup(t)
+    m = random_map(6, 3, t.npix)
+    per = torch.zeros(plan.nchunk, dtype=torch.float64, device=dev)
+    v = mm.mm_chi2(plan, tod(t, dev, mm.MM_FP64), torch.from_numpy(m).to(dev), lam, per)
+    r = t.d - S.pointing.project(m)
+    from oracle.messenger import chi2_of_residual
+    ref = chi2_of_residual(S, r, lam, per_chunk=True)
+    np.testing.assert_allclose(per.cpu().numpy(), ref, rtol=F64_TOL)
+    assert v == pytest.approx(ref.sum(), rel=F64_TOL)
+
+
+def test_in_place_iteration_matches(dev):
+    say("[inplace]")
+    t = tiny_problem(404, ncomp=3, **SHAPES["pow2"])
+    plan = gpu_plan(t, dev)
+    d = tod(t, dev, mm.MM_FP64)
+    m = torch.from_numpy(random_map(7, 3, t.npix)).to(dev)
+    out = torch.zeros_like(m)
+    mm.mm_messenger_iter(plan, d, 3.0, m, out)
+    m2 = m.clone()
+    mm.mm_messenger_iter(plan, d, 3.0, m2, m2)
+    torch.cuda.synchronize()
+    assert torch.equal(out, m2)
+
+
+def _t64(dev):
+    """The temperature-only 64x64 workload (one chunk of 65536 samples)."""
+    from synth import CONFIGS, make_problem
+    prob = make_problem(CONFIGS[0])
+    return prob
+
+
+def test_t64_full_schedule_fp64(dev):
+    """Temperature-only 64x64 workload, full cooled schedule (1 + 10 x 5), map and chi^2 history."""
+    say("[t64 solve]")
+    prob = _t64(dev)
+    S = make_setup(prob.chunk_off, prob.fsample, prob.sigma, prob.fknee, prob.alpha, prob.pix, None,
+                   prob.npix, 1)
+    pix = torch.from_numpy(prob.pix).to(dev)
+    plan = mm.mm_plan(ncomp=1, npix=prob.npix, nx=prob.cfg.nx, chunk_off=prob.chunk_off, fsample=prob.fsample,
+                      sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=pix)
+    levels = mm.mm_cooling_levels(plan, 10, 1e4)
+    assert levels[0] == pytest.approx(1e4) and levels[-1] == 1.0
+    d = torch.from_numpy(prob.d).to(dev)
+    m = torch.zeros((1, prob.npix), dtype=torch.float64, device=dev)
+    hist = torch.zeros(1 + 50 + 1, dtype=torch.float64, device=dev)
+    mm.mm_solve(plan, d, levels, [5] * 10, m, chi2_hist=hist)
+    torch.cuda.synchronize()
+    lams = cooling_schedule(10, 5, 1e4)
+    m_ref, h_ref = messenger_solve(S, prob.d, lams)
+    assert rel(m.cpu().numpy(), m_ref) < F64_TOL
+    np.testing.assert_allclose(hist.cpu().numpy(), h_ref, rtol=F64_TOL)
+
+
+@pytest.mark.parametrize("shape", ["pow2", "mixed_radix", "long"])
+def test_mixed_precision_iterations(dev, shape):
+    say(f"[mixed] shape={shape}")
+    t = tiny_problem(505, ncomp=3, psi_dtype=np.float32, tod_dtype=np.float32, **SHAPES[shape])
+    plan = gpu_plan(t, dev, precision=mm.MM_MIXED)
+    S = oracle_setup(t)
+    d = tod(t, dev, mm.MM_MIXED)
+    lams = cooling_schedule(3, 3, 50.0)
+    m = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+    hist = torch.zeros(len(lams) + 1, dtype=torch.float64, device=dev)
+    mm.mm_solve(plan, d, [50.0 ** 1, 50.0 ** 0.5, 1.0], [3, 3, 3], m, chi2_hist=hist)
+    torch.cuda.synchronize()
+    m_ref, h_ref = messenger_solve(S, t.d.astype(np.float64), lams)
+    assert rel(m.cpu().numpy(), m_ref) < MIX_TOL
+    np.testing.assert_allclose(hist.cpu().numpy(), h_ref, rtol=MIX_CHI2)
+
+
+@pytest.mark.parametrize("ncomp", [1, 3])
+def test_cg_matches_oracle(dev, ncomp):
+    say(f"[cg] ncomp={ncomp}")
+    t = tiny_problem(606, ncomp=ncomp, **SHAPES["pow2"])
+    plan = gpu_plan(t, dev)
+    S = oracle_setup(t)
+    d = tod(t, dev, mm.MM_FP64)
+    m = torch.zeros((ncomp, t.npix), dtype=torch.float64, device=dev)
+    maxit = 25
+    ch = torch.zeros(maxit + 1, dtype=torch.float64, device=dev)
+    rz = torch.zeros(maxit + 1, dtype=torch.float64, device=dev)
+    n = mm.mm_cg_solve(plan, m, maxit, d=d, chi2_hist=ch, rz_hist=rz)
+    torch.cuda.synchronize()
+    assert n == maxit
+    m_ref, info = pcg_solve(S, t.d, maxit, record_chi2=True)
+    assert rel(m.cpu().numpy(), m_ref) < 1e-9
+    np.testing.assert_allclose(rz.cpu().numpy(), info["rz"], rtol=1e-8, atol=1e-12 * info["rz"][0])
+    np.testing.assert_allclose(ch.cpu().numpy(), info["chi2"], rtol=1e-9)
+
+
+def test_cg_reaches_dense_gls(dev):
+    say("[cg gls]")
+    t = tiny_problem(707, ncomp=3, lengths=(64, 64, 64), nx=4)
+    plan = gpu_plan(t, dev)
+    S = oracle_setup(t)
+    m = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+    n = mm.mm_cg_solve(plan, m, 300, d=tod(t, dev, mm.MM_FP64), rtol=1e-13)
+    torch.cuda.synchronize()
+    assert n <= 300
+    assert rel(m.cpu().numpy(), dense.gls(S, t.d)) < 1e-8
+
+
+def test_apply_operators(dev):
+    say("[apply]")
+    t = tiny_problem(808, ncomp=3, **SHAPES["mixed_radix"])
+    plan = gpu_plan(t, dev)
+    S = oracle_setup(t)
+    x = random_map(8, 3, t.npix)
+    x[:, ~S.solvable] = 0
+    out = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+    mm.mm_apply(plan, 0, out, x=torch.from_numpy(x).to(dev))
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), apply_A(S, x)) < F64_TOL
+    mm.mm_apply(plan, 0, out, d=tod(t, dev, mm.MM_FP64))
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), rhs(S, t.d)) < F64_TOL
+
+
+def test_lift_rhs_inverts_the_rhs_map(dev):
+    """P^T N^-1 (N T^-1 P W^-1 g) = g on solvable pixels."""
+    say("[lift]")
+    t = tiny_problem(909, ncomp=3, **SHAPES["pow2"])
+    plan = gpu_plan(t, dev)
+    S = oracle_setup(t)
+    g = random_map(9, 3, t.npix)
+    g[:, ~S.solvable] = 0
+    dg = torch.zeros(t.nsamp, dtype=torch.float64, device=dev)
+    mm.mm_lift_rhs(plan, torch.from_numpy(g).to(dev), dg)
+    torch.cuda.synchronize()
+    back = rhs(S, dg.cpu().numpy())
+    assert rel(back[:, S.solvable], g[:, S.solvable]) < 1e-10
+
+
+def test_bitwise_determinism(dev):
+    say("[determinism]")
+    t = tiny_problem(111, ncomp=3, **SHAPES["long"])
+    plan = gpu_plan(t, dev)
+    d = tod(t, dev, mm.MM_FP64)
+    outs = []
+    for _ in range(2):
+        m = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+        h = torch.zeros(1 + 6 + 1, dtype=torch.float64, device=dev)
+        mm.mm_solve(plan, d, [20.0, 1.0], [3, 3], m, chi2_hist=h)
+        torch.cuda.synchronize()
+        outs.append((m.cpu().numpy().copy(), h.cpu().numpy().copy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_unbiased_noise_free(dev):
+    """d = P m_true: after the lambda = inf step every iterate equals m_true."""
+    say("[unbiased]")
+    t = tiny_problem(222, ncomp=3, **SHAPES["pow2"])
+    S = oracle_setup(t)
+    m_true = random_map(10, 3, t.npix, 4.0)
+    m_true[:, ~S.solvable] = 0
+    t.d = S.pointing.project(m_true)
+    plan = gpu_plan(t, dev)
+    m = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+    mm.mm_solve(plan, tod(t, dev, mm.MM_FP64), [100.0, 10.0, 1.0], [2, 2, 2], m)
+    torch.cuda.synchronize()
+    assert np.abs(m.cpu().numpy() - m_true).max() < 1e-11 * np.abs(m_true).max()
