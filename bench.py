@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the messenger-field mapmaking iteration on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload iqu256]
+
+A step is one messenger iteration (eqn. mcompact of the paper: gather P m,
+forward transforms, noise filter, inverse transforms, binning P^T and the
+per-pixel 3x3 update) over the whole time-ordered data set of the workload,
+already resident in HBM.  The value is samples per second.  One JSON line is
+printed; it carries the roofline of the dominant pass (algorithmic bytes per
+launch over the pass's average duration from HIP events on the launch stream)
+and the CPU oracle timed on a bounded sample on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
+PASS_NAMES = ["A: gather+residual+column FFT", "B: row FFT+filter+chi2+inverse rows",
+              "C: inverse column FFT", "D: binning+3x3 update"]
+KERNEL_SOURCES = ["paper_1705_01893_amd/csrc/kernels.hip", "paper_1705_01893_amd/csrc/fft.h",
+                  "paper_1705_01893_amd/csrc/common.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pass_bytes(prob, tod_bytes: int, psi_bytes: int) -> list:
+    """Algorithmic HBM bytes of one launch of each pass (compulsory streams, each once)."""
+    ns = prob.nsamp_total
+    non = int((prob.pix >= 0).sum())
+    ncomp, npix = prob.ncomp, prob.npix
+    nw = 1 if ncomp == 1 else 6
+    a = ns * tod_bytes + ns * 4 + non * psi_bytes + ns * tod_bytes          # d, pix, psi (on map), X write
+    b = 2 * ns * tod_bytes                                                  # X read + write
+    c = 2 * ns * tod_bytes                                                  # X read + y write
+    d = non * (tod_bytes + 2 + 2 + psi_bytes) + npix * 8 * (2 * ncomp + nw) + npix  # y, perm, lp, psi; maps
+    return [a, b, c, d]
+
+
+def load_traffic(workload: str, khash: str):
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_hash") != khash:
+        return None
+    return t
+
+
+def cpu_baseline(prob, seconds: float):
+    """The oracle's messenger step on the same workload, single-threaded NumPy, bounded in time."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    from oracle.messenger import messenger_step, setup_from_problem
+    import numpy as np
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        S = setup_from_problem(prob)
+        t_setup = time.perf_counter() - t0
+        m = np.zeros((prob.ncomp, prob.npix))
+        d = prob.d
+        times = []
+        t_start = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            m = messenger_step(S, d, m, 1.0)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_start > seconds or len(times) >= 50:
+                break
+    per = float(np.median(times))
+    return {"value": prob.nsamp_total / per, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{len(times)} lambda=1 iterations of the float64 NumPy oracle over the full "
+                       f"{prob.nsamp_total}-sample workload (median {per:.3f} s/iteration; plan setup "
+                       f"{t_setup:.1f} s not included), one host thread")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="iqu256")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mixed", action="store_true", help="run the FP32-mixed form (FP32 TOD and angles)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path shards over detector "
+              "chunks with one map all-reduce per iteration, which this build does not implement)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from synth import config_by_name, make_problem
+    from paper_1705_01893_amd import mm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    cfg = config_by_name(args.workload)
+    t0 = time.perf_counter()
+    prob = make_problem(cfg)
+    t_gen = time.perf_counter() - t0
+    mixed = args.mixed or cfg.tod_dtype == "f32"
+    precision = mm.MM_MIXED if mixed else mm.MM_FP64
+    tod_np = prob.d.astype(np.float32 if mixed else np.float64)
+    d = torch.from_numpy(tod_np).to(dev)
+    pix = torch.from_numpy(prob.pix).to(dev)
+    psi = None
+    psi_bytes = 0
+    if prob.ncomp == 3:
+        if prob.psi_index is not None:
+            psi = torch.from_numpy(prob.psi_index.view(np.int16)).to(dev).view(torch.uint16)
+            psi_bytes = 2
+        else:
+            ps = prob.psi.astype(np.float32) if mixed else prob.psi.astype(np.float64)
+            psi = torch.from_numpy(ps).to(dev)
+            psi_bytes = ps.dtype.itemsize
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = mm.mm_plan(ncomp=prob.ncomp, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off,
+                      fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=pix,
+                      psi=psi, psi_table=prob.psi_table, precision=precision)
+    t_plan = time.perf_counter() - t0
+    ns = prob.nsamp_total
+    m_a = torch.zeros((prob.ncomp, prob.npix), dtype=torch.float64, device=dev)
+    m_b = torch.zeros_like(m_a)
+    # start from the binned map, as the cooled solve does
+    mm.mm_messenger_iter(plan, d, math.inf, m_a, m_a)
+    for _ in range(args.warmup):
+        mm.mm_messenger_iter(plan, d, 1.0, m_a, m_b)
+        m_a, m_b = m_b, m_a
+    torch.cuda.synchronize()
+
+    # timed region: K iterations, per-pass HIP events on the launch stream
+    mm.mm_set_timing(plan, True)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        mm.mm_messenger_iter(plan, d, 1.0, m_a, m_b)
+        m_a, m_b = m_b, m_a
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    pass_ms, pass_n = mm.mm_get_timing(plan)
+    mm.mm_set_timing(plan, False)
+    ms_step = total_ms / args.steps
+    value = ns / (ms_step * 1e-3)
+
+    tod_bytes = 4 if mixed else 8
+    pb = pass_bytes(prob, tod_bytes, psi_bytes)
+    avg = [pass_ms[i] / max(pass_n[i], 1) for i in range(4)]
+    dom = int(np.argmax(avg))
+    achieved = pb[dom] / (avg[dom] * 1e-3) / 1e9
+    khash = kernel_hash()
+    traffic = load_traffic(cfg.name + ("_mixed" if args.mixed else ""), khash)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (traffic["passes"][dom]["bytes_per_launch"] if traffic else None),
+            "kernel": PASS_NAMES[dom]}
+    sweep_bytes = sum(pb)
+    extra = {
+        "passes": [{"pass": PASS_NAMES[i], "avg_ms": round(avg[i], 5), "alg_bytes": pb[i],
+                    "GBs": round(pb[i] / (avg[i] * 1e-3) / 1e9, 1) if avg[i] > 0 else None}
+                   for i in range(4)],
+        "sweep_roofline_frac": round(sweep_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "plan_s": round(t_plan, 2), "generate_s": round(t_gen, 2), "kernel_hash": khash,
+    }
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(prob, args.cpu_seconds)
+    cfg_desc = {"workload": (f"{cfg.name}: {cfg.ndet} detectors x {ns // cfg.ndet if cfg.nsamp == cfg.nsamp_min else 'uneven'} "
+                             f"samples ({ns} total), {cfg.nx}x{cfg.nx} map, ncomp={cfg.ncomp}, "
+                             f"{'FP32-mixed' if mixed else 'FP64'}"),
+                "nsamp": ns, "npix": prob.npix, "ncomp": prob.ncomp, "nchunk": prob.nchunk}
+    out = {
+        "metric": "TOD samples/s per messenger iteration", "value": round(value, 1), "unit": "samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if mixed else "f64", "data": "synthetic", "config": cfg_desc,
+        "roofline": roof, "cpu_baseline": cpu, "detail": extra,
+    }
+    print(json.dumps(out))
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -215,6 +215,18 @@ mm_status mm_apply(mm_plan_t plan, int32_t which, double lambda, const double* x
  */
 mm_status mm_lift_rhs(mm_plan_t plan, const double* g, void* out, mm_stream_t stream);
 
+/*
+ * Per-pass timing for measurement.  With timing enabled, every pass launched
+ * by mm_messenger_iter, mm_chi2, mm_apply and mm_cg_solve (not mm_solve, which
+ * replays a graph) is bracketed by HIP events recorded on the stream it runs
+ * on.  mm_get_timing waits for the recorded events, returns the summed
+ * milliseconds and launch counts per pass (index 0..3 = passes A, B, C, D:
+ * gather + column transforms, row transforms + filter, inverse column
+ * transforms, binning + map update) and clears the record.
+ */
+mm_status mm_set_timing(mm_plan_t plan, int32_t enable);
+mm_status mm_get_timing(mm_plan_t plan, double* ms, int64_t* launches);
+
 const char* mm_status_str(mm_status s);
 const char* mm_last_error(void);
 

@@ -29,15 +29,45 @@ inline hipStream_t S(mm_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
 
 int64_t mapn(const mm_plan_s* pl) { return (int64_t)pl->ncomp * pl->npix; }
 
+hipEvent_t take_event(mm_plan_s* pl) {
+  if (!pl->ev_pool.empty()) {
+    hipEvent_t e = pl->ev_pool.back();
+    pl->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// run one launch, bracketed by events when timing is on (never inside a graph capture)
+template <typename F>
+hipError_t timed(mm_plan_s* pl, int pass, hipStream_t s, F&& launch) {
+  if (!pl->timing || pl->capturing) return launch();
+  hipEvent_t a = take_event(pl), b = take_event(pl);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  pl->recs.push_back({pass, a, b});
+  return e;
+}
+
 // r = src(d, m) -> filtered y in the work buffer (passes A, B, C).  Returns with the
 // chi^2 partials in d_chi2_part when ops includes B_CHI2.
 mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, int ops, int gain, double lam,
                        double chi2_lam, hipStream_t s) {
-  MM_TRY_HIP(launch_pass_a(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), d, m, src, pl->d_work, pl->lds_ac, s));
-  MM_TRY_HIP(launch_pass_b(pl->dp, pl->d_itemsB, (int)pl->itemsB.size(), pl->d_work, ops, gain, lam, chi2_lam,
-                           pl->d_chi2_part, pl->lds_b, s));
+  MM_TRY_HIP(timed(pl, 0, s, [&] {
+    return launch_pass_a(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), d, m, src, pl->d_work, pl->lds_ac, s);
+  }));
+  MM_TRY_HIP(timed(pl, 1, s, [&] {
+    return launch_pass_b(pl->dp, pl->d_itemsB, (int)pl->itemsB.size(), pl->d_work, ops, gain, lam, chi2_lam,
+                         pl->d_chi2_part, pl->lds_b, s);
+  }));
   if (ops & B_FILTER)
-    MM_TRY_HIP(launch_pass_c(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), pl->d_work, pl->lds_ac, s));
+    MM_TRY_HIP(timed(pl, 2, s, [&] {
+      return launch_pass_c(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), pl->d_work, pl->lds_ac, s);
+    }));
   return MM_OK;
 }
 
@@ -54,12 +84,16 @@ mm_status iterate(mm_plan_s* pl, const void* d, double lam, const double* m_in, 
                   hipStream_t s) {
   if (std::isinf(lam)) {
     if (chi2_dev) MM_TRY(chi2_device(pl, d, m_in, 1.0, chi2_dev, nullptr, s));
-    MM_TRY_HIP(launch_bin(pl->dp, BSRC_DATA_OVER_TAU, d, EPI_REPLACE, m_in, m_out, nullptr, nullptr, s));
+    MM_TRY_HIP(timed(pl, 3, s, [&] {
+      return launch_bin(pl->dp, BSRC_DATA_OVER_TAU, d, EPI_REPLACE, m_in, m_out, nullptr, nullptr, s);
+    }));
     return MM_OK;
   }
   const int ops = B_FILTER | (chi2_dev ? B_CHI2 : 0);
   MM_TRY(sweep_filter(pl, d, m_in, SRC_D_MINUS_PM, ops, GAIN_MESSENGER, lam, 1.0, s));
-  MM_TRY_HIP(launch_bin(pl->dp, BSRC_WORK, pl->d_work, EPI_UPDATE, m_in, m_out, nullptr, nullptr, s));
+  MM_TRY_HIP(timed(pl, 3, s, [&] {
+    return launch_bin(pl->dp, BSRC_WORK, pl->d_work, EPI_UPDATE, m_in, m_out, nullptr, nullptr, s);
+  }));
   if (chi2_dev)
     MM_TRY_HIP(launch_chi2_reduce(pl->d_chunk_item_begin, pl->d_chi2_part, (int)pl->nchunk, nullptr, chi2_dev, s));
   return MM_OK;
@@ -68,7 +102,9 @@ mm_status iterate(mm_plan_s* pl, const void* d, double lam, const double* m_in, 
 // out = P^T G P x (x != null) or P^T G d
 mm_status apply_op(mm_plan_s* pl, int gain, double lam, const double* x, const void* d, double* out, hipStream_t s) {
   MM_TRY(sweep_filter(pl, x ? nullptr : d, x, x ? SRC_PM : SRC_D, B_FILTER, gain, lam, 1.0, s));
-  MM_TRY_HIP(launch_bin(pl->dp, BSRC_WORK, pl->d_work, EPI_WRITE_B, nullptr, out, nullptr, nullptr, s));
+  MM_TRY_HIP(timed(pl, 3, s, [&] {
+    return launch_bin(pl->dp, BSRC_WORK, pl->d_work, EPI_WRITE_B, nullptr, out, nullptr, nullptr, s);
+  }));
   return MM_OK;
 }
 
@@ -100,6 +136,37 @@ const char* mm_status_str(mm_status s) {
 }
 
 const char* mm_last_error(void) { return g_last_error.c_str(); }
+
+mm_status mm_set_timing(mm_plan_t plan, int32_t enable) {
+  if (!plan) return fail(MM_E_ARG, "null plan");
+  plan->timing = enable != 0;
+  return MM_OK;
+}
+
+mm_status mm_get_timing(mm_plan_t plan, double* ms, int64_t* launches) {
+  if (!plan || !ms || !launches) return fail(MM_E_ARG, "null argument");
+  for (int i = 0; i < 4; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  mm_status st = MM_OK;
+  for (auto& r : plan->recs) {
+    float t = 0.f;
+    if (st == MM_OK) {
+      hipError_t e = hipEventSynchronize(r.b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+      if (e != hipSuccess) st = fail(MM_E_HIP, std::string("timing events: ") + hipGetErrorString(e));
+    }
+    if (r.pass >= 0 && r.pass < 4) {
+      ms[r.pass] += t;
+      launches[r.pass] += 1;
+    }
+    plan->ev_pool.push_back(r.a);
+    plan->ev_pool.push_back(r.b);
+  }
+  plan->recs.clear();
+  return st;
+}
 
 mm_status mm_plan(const mm_plan_desc* desc, mm_stream_t stream, mm_plan_t* out) {
   g_last_error.clear();
@@ -180,6 +247,7 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, cons
   hipStream_t cs = plan->cap_stream;
   const int64_t n = mapn(plan);
   MM_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  plan->capturing = true;
   auto body = [&]() -> mm_status {
     // start map into m_out (fill kernel, no memset nodes in the graph)
     if (m0) {
@@ -195,6 +263,7 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, cons
     return MM_OK;
   };
   mm_status st = body();
+  plan->capturing = false;
   hipGraph_t graph = nullptr;
   hipError_t ee = hipStreamEndCapture(cs, &graph);
   if (st != MM_OK) {

@@ -529,6 +529,11 @@ void destroy_plan(mm_plan_s* pl) {
   if (!pl) return;
   if (!pl->graphs.empty() || !pl->allocs.empty()) (void)hipDeviceSynchronize();
   for (auto g : pl->graphs) (void)hipGraphExecDestroy(g);
+  for (auto& r : pl->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : pl->ev_pool) (void)hipEventDestroy(e);
   for (void* p : pl->allocs) (void)hipFree(p);
   for (void* p : pl->extra_allocs) (void)hipFree(p);
   if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);

@@ -52,6 +52,15 @@ struct mm_plan_s {
   int64_t nsolvable = 0;
   hipStream_t cap_stream = nullptr;
   std::vector<hipGraphExec_t> graphs;
+  // per-pass timing (measurement only)
+  bool timing = false;
+  bool capturing = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Rec {
+    int pass;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
 };
 
 namespace mm {

@@ -77,7 +77,9 @@ def lib() -> ctypes.CDLL:
     L.mm_chi2.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp]
     L.mm_apply.argtypes = [vp, i32, dbl, vp, vp, vp, vp]
     L.mm_lift_rhs.argtypes = [vp, vp, vp, vp]
-    for name in ("mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_hits", "mm_plan_solvable",
+    L.mm_set_timing.argtypes = [vp, i32]
+    L.mm_get_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    for name in ("mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_hits", "mm_plan_solvable",
                  "mm_plan_nsolvable", "mm_messenger_iter", "mm_solve", "mm_cooling_levels", "mm_cg_solve",
                  "mm_chi2", "mm_apply", "mm_lift_rhs"):
         getattr(L, name).restype = ctypes.c_int
@@ -275,6 +277,18 @@ def mm_apply(plan: Plan, which: int, out: torch.Tensor, x: Optional[torch.Tensor
 def mm_lift_rhs(plan: Plan, g: torch.Tensor, out: torch.Tensor, stream=None) -> None:
     _check(lib().mm_lift_rhs(plan.handle, _map_ptr(plan, g, "g"), _ptr(out, "out", plan.tod_dtype, plan.nsamp),
                              _stream(stream)), "mm_lift_rhs")
+
+
+def mm_set_timing(plan: Plan, enable: bool) -> None:
+    _check(lib().mm_set_timing(plan.handle, int(bool(enable))), "mm_set_timing")
+
+
+def mm_get_timing(plan: Plan):
+    """(milliseconds[4], launches[4]) per pass A, B, C, D since the last call."""
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
+    _check(lib().mm_get_timing(plan.handle, ms, n), "mm_get_timing")
+    return list(ms), list(n)
 
 
 def mm_status_str(status: int) -> str:
