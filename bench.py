@@ -48,6 +48,8 @@ def pass_bytes(prob, tod_bytes: int, psi_bytes: int) -> list:
     nw = 1 if ncomp == 1 else 6
     a = ns * tod_bytes + ns * 4 + non * psi_bytes + ns * tod_bytes          # d, pix, psi (on map), X write
     b = 2 * ns * tod_bytes                                                  # X read + write
+    if tod_bytes == 8:
+        b += (ns // 2 + prob.nchunk) * 8                                    # tabulated noise power law
     c = 2 * ns * tod_bytes                                                  # X read + y write
     d = non * (tod_bytes + 2 + 2 + psi_bytes) + npix * 8 * (2 * ncomp + nw) + npix  # y, perm, lp, psi; maps
     return [a, b, c, d]
@@ -100,6 +102,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mixed", action="store_true", help="run the FP32-mixed form (FP32 TOD and angles)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path shards over detector "
@@ -165,6 +169,13 @@ def main():
     total_ms = ev0.elapsed_time(ev1)
     pass_ms, pass_n = mm.mm_get_timing(plan)
     mm.mm_set_timing(plan, False)
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ms_step = total_ms / args.steps
     value = ns / (ms_step * 1e-3)
 

@@ -7,16 +7,17 @@
 
 namespace mm {
 
-constexpr int kBlock = 256;        // threads per workgroup of the transform and binning kernels
-constexpr int kWaves = kBlock / 64;
+constexpr int kBlock = 512;        // threads per workgroup of the transform passes
+constexpr int kBinBlock = 256;     // threads per workgroup of the binning pass
+constexpr int kWaves = kBinBlock / 64;
 constexpr int kMaxStages = 24;     // radix stages of one sub-transform
 constexpr int kSubBatch = 4096;    // samples staged in LDS per binning step (<= 65536: uint16 indices)
 constexpr int kMaxTilePix = 512;   // pixels per binning tile (LDS accumulators)
 
-// complex elements per thread in the LDS transforms (tile capacity = kBlock * ept)
+// complex elements per thread in the LDS transforms (tile capacity = kBlock * ept = 64 KB)
 template <typename T> struct Ept;
-template <> struct Ept<float> { static constexpr int v = 32; };
-template <> struct Ept<double> { static constexpr int v = 16; };
+template <> struct Ept<float> { static constexpr int v = 16; };
+template <> struct Ept<double> { static constexpr int v = 8; };
 
 template <typename T> struct Cx;
 template <> struct Cx<float> { using t = float2; };
@@ -29,21 +30,24 @@ struct DevChunk {
   int64_t off;        // first sample of the chunk
   int32_t n, M, M1, M2;
   int32_t cls;        // transform class (shared by chunks of equal M)
-  int32_t cb;         // columns per column-pass item
+  int32_t cb;         // columns per column-pass item (a power of two)
+  int32_t lgb;        // log2 cb
+  int32_t pad0;
   double df;          // frequency step f_s / n
   double sigma2;      // white level sigma^2
   double fknee, alpha;
   double tau, inv_tau;
   double nbar0;       // sigma^2 - tau (N-bar = nbar0 + sigma^2 (f/fknee)^alpha)
+  int64_t spec_off;   // offset of this chunk's M+1 power-law values in DevPlan::spec (FP64 form)
 };
 
 // Per-length transform data: radix schedules and twiddle-table offsets.
 struct DevClass {
   int32_t M, M1, M2;
   int32_t nr1, nr2;   // number of radix stages for the M1 and M2 transforms
-  int32_t lo;         // two-level split of the omega_{2M} table: q = hi * lo + rem
+  int32_t lb;         // two-level split of the omega_{2M} table: q = (hi << lb) + rem
   int64_t tw1, tw2;   // offsets of omega_{M1}^q, omega_{M2}^q tables (complex entries)
-  int64_t twlo, twhi; // offsets of omega_{2M}^rem and omega_{2M}^(hi*lo)
+  int64_t twlo, twhi; // offsets of omega_{2M}^rem and omega_{2M}^(hi << lb)
   int8_t rad1[kMaxStages];
   int8_t rad2[kMaxStages];
 };
@@ -61,10 +65,11 @@ struct Tile {
 };
 struct SubBatch {
   int64_t sorted_begin;      // offset into perm / lp / psi_sorted
-  int32_t seg_begin, seg_end;
+  int32_t seg_begin, seg_end;  // at most kMaxSegs segments
   int32_t count;             // samples in the sub-batch
   int32_t pad;
 };
+constexpr int kMaxSegs = 512;  // segments per sub-batch (LDS segment table)
 struct Segment {
   int64_t start;             // first sample
   int32_t len;
@@ -92,6 +97,7 @@ struct DevPlan {
   const uint16_t* perm;      // sorted order -> stage position
   const uint16_t* lp;        // sorted order -> local pixel
   const void* psi_sorted;    // angles in sorted order (type psi_kind)
+  const double* spec;        // FP64 form: sigma^2 (f_k / fknee)^alpha per chunk bin (f_0 -> f_1)
   const double* winv;        // [nw][npix], nw = 1 or 6 (00 01 02 11 12 22)
   const uint8_t* solvable;   // [npix]
 };
@@ -119,6 +125,7 @@ hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void
                          hipStream_t s);
 hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
                       double* w_out, int32_t* hits_out, hipStream_t s);
+hipError_t launch_spectrum(const DevPlan& P, double* spec, hipStream_t s);
 hipError_t launch_chi2_reduce(const int32_t* chunk_item_begin, const double* part, int nchunk, double* per_chunk,
                               double* total, hipStream_t s);
 // map-space vector kernels for CG and helpers

@@ -148,27 +148,59 @@ struct Dft<T, 5, INV> {
   }
 };
 
-// One Stockham stage.  p = product of the radices already applied.
-template <typename T, int R, bool INV>
-__device__ __forceinline__ void stockham_stage(cx<T>* lds, int L, int nb, int sI, int sB, bool bfast, int p,
+// Exact quotient n / d for n, d < 2^22 from a single-precision reciprocal estimate
+// (the estimate is within one of the quotient, corrected with one multiply-subtract).
+__device__ __forceinline__ uint32_t qdiv(uint32_t n, uint32_t d, float inv) {
+  uint32_t q = (uint32_t)((float)n * inv);
+  const int32_t r = (int32_t)(n - q * d);
+  if (r < 0)
+    --q;
+  else if (r >= (int32_t)d)
+    ++q;
+  return q;
+}
+
+// w^m for m = 0..R-1 from w = v[1] by balanced products (error grows like log2 m ulps)
+template <typename T, int R>
+__device__ __forceinline__ void twiddle_powers(cx<T>* v, cx<T> w1) {
+  cx<T> w[R];
+  w[1] = w1;
+#pragma unroll
+  for (int m = 2; m < R; ++m) w[m] = (m % 2 == 0) ? cmul(w[m / 2], w[m / 2]) : cmul(w[m - 1], w1);
+#pragma unroll
+  for (int m = 1; m < R; ++m) v[m] = cmul(v[m], w[m]);
+}
+
+// One Stockham stage.  p = product of the radices already applied.  Butterfly f of the
+// stage belongs to sequence b and position k: with BFAST, b = f mod nb (nb a power of
+// two, lg_nb = log2 nb), otherwise b = f / (L/R).
+// Kept out of line: inlining all five radix variants into the stage loop makes the register
+// allocator budget for their union and halves the occupancy of every pass.
+template <typename T, int R, bool INV, bool BFAST>
+__device__ __attribute__((noinline)) void stockham_stage(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, int p,
                                                const cx<T>* __restrict__ tw) {
   constexpr int K = (Ept<T>::v + R - 1) / R;  // butterflies per thread
   const int nbf = L / R;
   const int total = nbf * nb;
   const int step = L / (p * R);
+  const float inv_p = 1.0f / (float)p;
+  const float inv_nbf = 1.0f / (float)nbf;
   cx<T> v[K][R];
+  int bk[K][2];
 #pragma unroll
   for (int u = 0; u < K; ++u) {
     const int f = threadIdx.x + u * kBlock;
+    int b = 0, k = 0;
+    if (BFAST) {
+      b = f & (nb - 1);
+      k = f >> lg_nb;
+    } else {
+      b = (int)qdiv((uint32_t)f, (uint32_t)nbf, inv_nbf);
+      k = f - b * nbf;
+    }
+    bk[u][0] = b;
+    bk[u][1] = k;
     if (f < total) {
-      int b, k;
-      if (bfast) {
-        b = f % nb;
-        k = f / nb;
-      } else {
-        k = f % nbf;
-        b = f / nbf;
-      }
 #pragma unroll
       for (int m = 0; m < R; ++m) v[u][m] = lds[(k + m * nbf) * sI + b * sB];
     }
@@ -178,25 +210,16 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int L, int nb, int sI
   for (int u = 0; u < K; ++u) {
     const int f = threadIdx.x + u * kBlock;
     if (f < total) {
-      int b, k;
-      if (bfast) {
-        b = f % nb;
-        k = f / nb;
-      } else {
-        k = f % nbf;
-        b = f / nbf;
-      }
-      const int j = k % p;
-      if (p > 1) {
-#pragma unroll
-        for (int m = 1; m < R; ++m) {
-          cx<T> w = tw[j * m * step];
-          if (INV) w.y = -w.y;
-          v[u][m] = cmul(v[u][m], w);
-        }
+      const int b = bk[u][0], k = bk[u][1];
+      const int kq = (int)qdiv((uint32_t)k, (uint32_t)p, inv_p);
+      const int j = k - kq * p;
+      if (j != 0) {
+        cx<T> w = tw[j * step];
+        if (INV) w.y = -w.y;
+        twiddle_powers<T, R>(v[u], w);
       }
       Dft<T, R, INV>::run(v[u]);
-      const int base = (k - j) * R + j;
+      const int base = kq * p * R + j;
 #pragma unroll
       for (int m = 0; m < R; ++m) lds[(base + m * p) * sI + b * sB] = v[u][m];
     }
@@ -206,18 +229,18 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int L, int nb, int sI
 
 // Full length-L transform of nb sequences (caller synchronises before the first stage).
 // tw: omega_L^q = exp(-2 pi i q / L), q < L.
-template <typename T, bool INV>
-__device__ void lds_fft(cx<T>* lds, int L, int nb, int sI, int sB, bool bfast, const int8_t* rad, int ns,
+template <typename T, bool INV, bool BFAST>
+__device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, const int8_t* rad, int ns,
                         const cx<T>* __restrict__ tw) {
   int p = 1;
   for (int s = 0; s < ns; ++s) {
     const int R = rad[s];
     switch (R) {
-      case 8: stockham_stage<T, 8, INV>(lds, L, nb, sI, sB, bfast, p, tw); break;
-      case 4: stockham_stage<T, 4, INV>(lds, L, nb, sI, sB, bfast, p, tw); break;
-      case 2: stockham_stage<T, 2, INV>(lds, L, nb, sI, sB, bfast, p, tw); break;
-      case 3: stockham_stage<T, 3, INV>(lds, L, nb, sI, sB, bfast, p, tw); break;
-      case 5: stockham_stage<T, 5, INV>(lds, L, nb, sI, sB, bfast, p, tw); break;
+      case 8: stockham_stage<T, 8, INV, BFAST>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
+      case 4: stockham_stage<T, 4, INV, BFAST>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
+      case 2: stockham_stage<T, 2, INV, BFAST>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
+      case 3: stockham_stage<T, 3, INV, BFAST>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
+      case 5: stockham_stage<T, 5, INV, BFAST>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
       default: break;
     }
     p *= R;

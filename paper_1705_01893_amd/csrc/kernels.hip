@@ -39,11 +39,9 @@ __device__ __forceinline__ const double2* twtab<double>(const DevPlan& P) { retu
 
 // omega_{2M}^q = exp(-2 pi i q / (2M)), 0 <= q < 2M, from the two-level table
 template <typename T>
-__device__ __forceinline__ cx<T> omega2M(const DevPlan& P, const DevClass& cl, int64_t q) {
+__device__ __forceinline__ cx<T> omega2M(const DevPlan& P, const DevClass& cl, int q) {
   const cx<T>* tw = twtab<T>(P);
-  const int64_t hi = q / cl.lo;
-  const int64_t lo = q - hi * cl.lo;
-  return cmul(tw[cl.twhi + hi], tw[cl.twlo + lo]);
+  return cmul(tw[cl.twhi + (q >> cl.lb)], tw[cl.twlo + (q & ((1 << cl.lb) - 1))]);
 }
 
 template <typename C>
@@ -103,14 +101,14 @@ __device__ __forceinline__ double project_one(const DevPlan& P, const double* __
 
 // noise spectrum pieces at real bin k: pl = sigma^2 (f/fknee)^alpha with the DC bin at f_1
 template <typename T>
-__device__ __forceinline__ T powerlaw(const DevChunk& ch, int64_t k);
+__device__ __forceinline__ T powerlaw(const DevChunk& ch, int k);
 template <>
-__device__ __forceinline__ double powerlaw<double>(const DevChunk& ch, int64_t k) {
+__device__ __forceinline__ double powerlaw<double>(const DevChunk& ch, int k) {
   const double f = (double)(k == 0 ? 1 : k) * ch.df;
   return ch.sigma2 * pow(f / ch.fknee, ch.alpha);
 }
 template <>
-__device__ __forceinline__ float powerlaw<float>(const DevChunk& ch, int64_t k) {
+__device__ __forceinline__ float powerlaw<float>(const DevChunk& ch, int k) {
   const float f = (float)((double)(k == 0 ? 1 : k) * ch.df);
   return (float)ch.sigma2 * exp2f((float)ch.alpha * log2f(f / (float)ch.fknee));
 }
@@ -120,10 +118,24 @@ struct BinCtx {
   double lam, chi2_lam;
 };
 
+// power-law part sigma^2 (f_k/fknee)^alpha of the noise spectrum at real bin k: tabulated at plan
+// time in the FP64 form, evaluated in single precision in the FP32-mixed form
+template <typename T>
+__device__ __forceinline__ T powerlaw_bin(const DevPlan& P, const DevChunk& ch, int k);
+template <>
+__device__ __forceinline__ double powerlaw_bin<double>(const DevPlan& P, const DevChunk& ch, int k) {
+  return P.spec[ch.spec_off + k];
+}
+template <>
+__device__ __forceinline__ float powerlaw_bin<float>(const DevPlan& P, const DevChunk& ch, int k) {
+  return powerlaw<float>(ch, k);
+}
+
 // gain applied to R_k (includes the 1/M of the inverse transform) and chi^2 weight 1/(n N'_k)
 template <typename T>
-__device__ __forceinline__ void bin_factors(const DevChunk& ch, const BinCtx& bc, int64_t k, T& g, double& cw) {
-  const T pl = powerlaw<T>(ch, k);
+__device__ __forceinline__ void bin_factors(const DevPlan& P, const DevChunk& ch, const BinCtx& bc, int k, T& g,
+                                            double& cw) {
+  const T pl = powerlaw_bin<T>(P, ch, k);
   const T N = (T)ch.sigma2 + pl;
   const T tau = (T)ch.tau;
   T gg;
@@ -148,55 +160,161 @@ __device__ __forceinline__ double norm2(C a) {
 // ---------------------------------------------------------------------------------------------
 // pass A: residual + column transforms
 
+// angle pair of samples 2ci, 2ci+1 (one vector load) -> weights in the TOD precision
+template <typename T>
+struct PsiPair {
+  T c0, s0, c1, s1;
+};
+
+template <typename T>
+__device__ __forceinline__ void psi_pair_load(const DevPlan& P, int64_t ci, uint4& raw) {
+  if (P.psi_kind == 1) {
+    const double2 v = ((const double2*)P.psi)[ci];
+    raw.x = __double2loint(v.x);
+    raw.y = __double2hiint(v.x);
+    raw.z = __double2loint(v.y);
+    raw.w = __double2hiint(v.y);
+  } else if (P.psi_kind == 2) {
+    const float2 v = ((const float2*)P.psi)[ci];
+    raw.x = __float_as_uint(v.x);
+    raw.y = __float_as_uint(v.y);
+  } else {
+    raw.x = ((const uint32_t*)P.psi)[ci];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw, int which, T& c, T& s) {
+  if (P.psi_kind == 1) {
+    const double a = which == 0 ? __hiloint2double(raw.y, raw.x) : __hiloint2double(raw.w, raw.z);
+    if (sizeof(T) == 8) {
+      double sd, cd;
+      sincos(2.0 * a, &sd, &cd);
+      c = (T)cd;
+      s = (T)sd;
+    } else {
+      float sf, cf;
+      sincosf((float)(2.0 * a), &sf, &cf);
+      c = (T)cf;
+      s = (T)sf;
+    }
+  } else if (P.psi_kind == 2) {
+    const float a = __uint_as_float(which == 0 ? raw.x : raw.y);
+    if (sizeof(T) == 8) {
+      double sd, cd;
+      sincos(2.0 * (double)a, &sd, &cd);
+      c = (T)cd;
+      s = (T)sd;
+    } else {
+      float sf, cf;
+      sincosf(2.0f * a, &sf, &cf);
+      c = (T)cf;
+      s = (T)sf;
+    }
+  } else {
+    const uint32_t idx = which == 0 ? (raw.x & 0xffffu) : (raw.x >> 16);
+    if (sizeof(T) == 8) {
+      const double2 t = P.psi_cs64[idx];
+      c = (T)t.x;
+      s = (T)t.y;
+    } else {
+      const float2 t = P.psi_cs32[idx];
+      c = (T)t.x;
+      s = (T)t.y;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    const T* __restrict__ d, const double* __restrict__ m, int src,
                                                    cx<T>* __restrict__ X) {
+  constexpr int E = Ept<T>::v;
+  constexpr int G = 2;  // elements whose loads are issued together
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int np = (int)P.npix;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const ItemAC item = items[it];
     const DevChunk ch = P.chunks[item.chunk];
     const DevClass& cl = P.classes[ch.cls];
-    const int B = ch.cb, M1 = ch.M1, M2 = ch.M2;
+    const int B = ch.cb, lgB = ch.lgb, M1 = ch.M1, M2 = ch.M2;
     const int j10 = item.j1;
     const int nbv = min(B, M1 - j10);
     const int ntot = B * M2;
-    for (int e = threadIdx.x; e < ntot; e += kBlock) {
-      const int b = e % B, j2 = e / B;
-      cx<T> z;
-      z.x = T(0);
-      z.y = T(0);
-      if (b < nbv) {
-        const int64_t s = ch.off + 2 * ((int64_t)(j10 + b) + (int64_t)M1 * j2);
-        double r0, r1;
-        if (src == SRC_D) {
-          r0 = (double)d[s];
-          r1 = (double)d[s + 1];
-        } else {
-          const double pm0 = project_one<T>(P, m, s);
-          const double pm1 = project_one<T>(P, m, s + 1);
-          if (src == SRC_PM) {
-            r0 = pm0;
-            r1 = pm1;
-          } else {
-            r0 = (double)d[s] - pm0;
-            r1 = (double)d[s + 1] - pm1;
+    const int64_t cbase = ch.off / 2 + j10;
+#pragma unroll 1
+    for (int g = 0; g < E; g += G) {
+      int2 pp[G];
+      cx<T> dd[G];
+      uint4 raw[G];
+      bool ok[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int e = threadIdx.x + (g + u) * kBlock;
+        const int b = e & (B - 1), j2 = e >> lgB;
+        ok[u] = (e < ntot) && (b < nbv);
+        const int64_t ci = cbase + b + (int64_t)M1 * j2;
+        pp[u] = make_int2(-1, -1);
+        dd[u].x = T(0);
+        dd[u].y = T(0);
+        if (ok[u]) {
+          if (src != SRC_PM) dd[u] = ((const cx<T>*)d)[ci];
+          if (src != SRC_D) {
+            pp[u] = ((const int2*)P.pix)[ci];
+            if (P.ncomp == 3) psi_pair_load<T>(P, ci, raw[u]);
           }
         }
-        z.x = (T)r0;
-        z.y = (T)r1;
       }
-      lds[e] = z;
+      double pm[G][2];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int px = h == 0 ? pp[u].x : pp[u].y;
+          double v = 0.0;
+          if (px >= 0) {
+            v = m[px];
+            if (P.ncomp == 3) {
+              T c, sn;
+              psi_from_raw<T>(P, raw[u], h, c, sn);
+              v += (double)c * m[np + px] + (double)sn * m[2 * np + px];
+            }
+          }
+          pm[u][h] = v;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int e = threadIdx.x + (g + u) * kBlock;
+        if (e < ntot) {
+          cx<T> z;
+          if (!ok[u]) {
+            z.x = T(0);
+            z.y = T(0);
+          } else if (src == SRC_D) {
+            z = dd[u];
+          } else if (src == SRC_PM) {
+            z.x = (T)pm[u][0];
+            z.y = (T)pm[u][1];
+          } else {
+            z.x = (T)((double)dd[u].x - pm[u][0]);
+            z.y = (T)((double)dd[u].y - pm[u][1]);
+          }
+          lds[e] = z;
+        }
+      }
     }
     __syncthreads();
-    lds_fft<T, false>(lds, M2, B, B, 1, true, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    lds_fft<T, false, true>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
     cx<T>* Xc = X + ch.off / 2;
-    for (int e = threadIdx.x; e < ntot; e += kBlock) {
-      const int b = e % B, k2 = e / B;
-      if (b < nbv) {
+#pragma unroll 2
+    for (int u = 0; u < E; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      const int b = e & (B - 1), k2 = e >> lgB;
+      if (e < ntot && b < nbv) {
         const int j1 = j10 + b;
-        const cx<T> w = omega2M<T>(P, cl, 2 * (int64_t)j1 * k2);
+        const cx<T> w = omega2M<T>(P, cl, 2 * j1 * k2);
         Xc[(int64_t)k2 * M1 + j1] = cmul(lds[e], w);
       }
     }
@@ -209,9 +327,9 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
 
 template <typename T>
 __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevChunk& ch, const DevClass& cl,
-                                       const BinCtx& bc, int ops, int64_t k, int ia, int ib, double& chi) {
+                                       const BinCtx& bc, int ops, int k, int ia, int ib, double& chi) {
   const cx<T> Zk = lds[ia], Zm = lds[ib];
-  const int64_t M = ch.M;
+  const int M = ch.M;
   cx<T> E, O;
   E.x = T(0.5) * (Zk.x + Zm.x);
   E.y = T(0.5) * (Zk.y - Zm.y);
@@ -224,8 +342,8 @@ __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevCh
   const cx<T> Rm = csub(conjc(E), conjc(wO));
   T gk, gm;
   double cwk, cwm;
-  bin_factors<T>(ch, bc, k, gk, cwk);
-  bin_factors<T>(ch, bc, M - k, gm, cwm);
+  bin_factors<T>(P, ch, bc, k, gk, cwk);
+  bin_factors<T>(P, ch, bc, M - k, gm, cwm);
   if (ops & B_CHI2) chi += 2.0 * (norm2(Rk) * cwk + norm2(Rm) * cwm);
   if (ops & B_FILTER) {
     const cx<T> Yk = cscale(Rk, gk), Ym = cscale(Rm, gm);
@@ -247,14 +365,14 @@ __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevCh
 }
 
 template <typename T>
-__device__ __forceinline__ void b_dc(cx<T>* lds, const DevChunk& ch, const BinCtx& bc, int ops, int ia,
-                                     double& chi) {
+__device__ __forceinline__ void b_dc(cx<T>* lds, const DevPlan& P, const DevChunk& ch, const BinCtx& bc, int ops,
+                                     int ia, double& chi) {
   const cx<T> Z = lds[ia];
   const T R0 = Z.x + Z.y, RM = Z.x - Z.y;
   T g0, gM;
   double c0, cM;
-  bin_factors<T>(ch, bc, 0, g0, c0);
-  bin_factors<T>(ch, bc, ch.M, gM, cM);
+  bin_factors<T>(P, ch, bc, 0, g0, c0);
+  bin_factors<T>(P, ch, bc, ch.M, gM, cM);
   if (ops & B_CHI2) chi += (double)R0 * (double)R0 * c0 + (double)RM * (double)RM * cM;
   if (ops & B_FILTER) {
     const T Y0 = R0 * g0, YM = RM * gM;
@@ -266,13 +384,13 @@ __device__ __forceinline__ void b_dc(cx<T>* lds, const DevChunk& ch, const BinCt
 }
 
 template <typename T>
-__device__ __forceinline__ void b_self(cx<T>* lds, const DevChunk& ch, const BinCtx& bc, int ops, int64_t k, int ia,
-                                       double& chi) {
+__device__ __forceinline__ void b_self(cx<T>* lds, const DevPlan& P, const DevChunk& ch, const BinCtx& bc, int ops,
+                                       int k, int ia, double& chi) {
   // k = M/2: R_k = conj(Z_k); the retangled value is conj(Y_k)
   const cx<T> Z = lds[ia];
   T g;
   double cw;
-  bin_factors<T>(ch, bc, k, g, cw);
+  bin_factors<T>(P, ch, bc, k, g, cw);
   if (ops & B_CHI2) chi += 2.0 * norm2(Z) * cw;
   if (ops & B_FILTER) {
     cx<T> y;
@@ -286,6 +404,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pass_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
                                                    cx<T>* __restrict__ X, int ops, BinCtx bc,
                                                    double* __restrict__ chi2_part, int red_off) {
+  constexpr int E = Ept<T>::v;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   double* red = reinterpret_cast<double*>(smem_raw + red_off);
@@ -296,55 +415,68 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevPlan P, const ItemB* __res
     const int M1 = ch.M1, M2 = ch.M2;
     const int ra = item.ra, rb = item.rb;
     const int nrow = (ra == rb) ? 1 : 2;
+    const int ntot = nrow * M1;
     cx<T>* Xc = X + ch.off / 2;
-    for (int e = threadIdx.x; e < nrow * M1; e += kBlock) {
-      const int row = (e < M1) ? ra : rb;
-      lds[e] = Xc[(int64_t)row * M1 + (e % M1)];
+    cx<T>* Xa = Xc + (int64_t)ra * M1;
+    cx<T>* Xb = Xc + (int64_t)rb * M1;
+    // 2 * M1 < kBlock * E, so each row takes at most E/2 elements per thread
+#pragma unroll
+    for (int u = 0; u < E / 2; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      if (e < M1) {
+        lds[e] = Xa[e];
+        if (nrow == 2) lds[M1 + e] = Xb[e];
+      }
     }
     __syncthreads();
     const cx<T>* tw1 = twtab<T>(P) + cl.tw1;
-    lds_fft<T, false>(lds, M1, nrow, 1, M1, false, cl.rad1, cl.nr1, tw1);
+    lds_fft<T, false, false>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
     double chi = 0.0;
     const bool self_a = (ra == 0) || (2 * ra == M2);
     if (!self_a) {
       for (int k1 = threadIdx.x; k1 < M1; k1 += kBlock) {
         const int pk1 = M1 - 1 - k1;
-        const int64_t k = ra + (int64_t)M2 * k1;
+        const int k = ra + M2 * k1;
         b_pair<T>(lds, P, ch, cl, bc, ops, k, k1, M1 + pk1, chi);
       }
     } else {
       for (int sl = 0; sl < nrow; ++sl) {
         const int row = sl == 0 ? ra : rb;
         for (int k1 = threadIdx.x; k1 < M1; k1 += kBlock) {
-          const int pk1 = (row == 0) ? ((M1 - k1) % M1) : (M1 - 1 - k1);
+          const int pk1 = (row == 0) ? (k1 == 0 ? 0 : M1 - k1) : (M1 - 1 - k1);
           if (k1 > pk1) continue;
-          const int64_t k = row + (int64_t)M2 * k1;
+          const int k = row + M2 * k1;
           if (k == 0)
-            b_dc<T>(lds, ch, bc, ops, sl * M1, chi);
+            b_dc<T>(lds, P, ch, bc, ops, sl * M1, chi);
           else if (k1 == pk1)
-            b_self<T>(lds, ch, bc, ops, k, sl * M1 + k1, chi);
+            b_self<T>(lds, P, ch, bc, ops, k, sl * M1 + k1, chi);
           else
             b_pair<T>(lds, P, ch, cl, bc, ops, k, sl * M1 + k1, sl * M1 + pk1, chi);
         }
       }
     }
     if (ops & B_CHI2) {
-      red[threadIdx.x] = chi;
+      // fixed-order reduction: butterfly within each wave, then the waves in order
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) chi += __shfl_xor(chi, o);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = chi;
       __syncthreads();
-      for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+        chi2_part[it] = t;
       }
-      if (threadIdx.x == 0) chi2_part[it] = red[0];
     }
     if (ops & B_FILTER) {
       __syncthreads();
-      lds_fft<T, true>(lds, M1, nrow, 1, M1, false, cl.rad1, cl.nr1, tw1);
-      for (int e = threadIdx.x; e < nrow * M1; e += kBlock) {
-        const int row = (e < M1) ? ra : rb;
-        const int j1 = e % M1;
-        const cx<T> w = conjc(omega2M<T>(P, cl, 2 * (int64_t)j1 * row));
-        Xc[(int64_t)row * M1 + j1] = cmul(lds[e], w);
+      lds_fft<T, true, false>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
+#pragma unroll
+      for (int u = 0; u < E / 2; ++u) {
+        const int j1 = threadIdx.x + u * kBlock;
+        if (j1 < M1) {
+          Xa[j1] = cmul(lds[j1], conjc(omega2M<T>(P, cl, 2 * j1 * ra)));
+          if (nrow == 2) Xb[j1] = cmul(lds[M1 + j1], conjc(omega2M<T>(P, cl, 2 * j1 * rb)));
+        }
       }
     }
     __syncthreads();
@@ -357,30 +489,41 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevPlan P, const ItemB* __res
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    cx<T>* __restrict__ X) {
+  constexpr int E = Ept<T>::v;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const ItemAC item = items[it];
     const DevChunk ch = P.chunks[item.chunk];
     const DevClass& cl = P.classes[ch.cls];
-    const int B = ch.cb, M1 = ch.M1, M2 = ch.M2;
+    const int B = ch.cb, lgB = ch.lgb, M1 = ch.M1, M2 = ch.M2;
     const int j10 = item.j1;
     const int nbv = min(B, M1 - j10);
     const int ntot = B * M2;
-    cx<T>* Xc = X + ch.off / 2;
-    for (int e = threadIdx.x; e < ntot; e += kBlock) {
-      const int b = e % B, k2 = e / B;
-      cx<T> z;
-      z.x = T(0);
-      z.y = T(0);
-      if (b < nbv) z = Xc[(int64_t)k2 * M1 + j10 + b];
-      lds[e] = z;
+    cx<T>* Xc = X + ch.off / 2 + j10;
+    {
+      cx<T> v[E];
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const int e = threadIdx.x + u * kBlock;
+        const int b = e & (B - 1), k2 = e >> lgB;
+        v[u].x = T(0);
+        v[u].y = T(0);
+        if (e < ntot && b < nbv) v[u] = Xc[(int64_t)k2 * M1 + b];
+      }
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const int e = threadIdx.x + u * kBlock;
+        if (e < ntot) lds[e] = v[u];
+      }
     }
     __syncthreads();
-    lds_fft<T, true>(lds, M2, B, B, 1, true, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
-    for (int e = threadIdx.x; e < ntot; e += kBlock) {
-      const int b = e % B, j2 = e / B;
-      if (b < nbv) Xc[(int64_t)j10 + b + (int64_t)M1 * j2] = lds[e];
+    lds_fft<T, true, true>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      const int b = e & (B - 1), j2 = e >> lgB;
+      if (e < ntot && b < nbv) Xc[(int64_t)M1 * j2 + b] = lds[e];
     }
     __syncthreads();
   }
@@ -388,31 +531,36 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
 
 // ---------------------------------------------------------------------------------------------
 // pass D: deterministic binning per pixel tile (+ fused map update / plan precompute)
+//
+// One workgroup per tile.  For each sub-batch of the tile's samples:
+//   1. the sub-batch's segment table goes to LDS and every thread stages its share of the
+//      samples (time order) into LDS, locating each position's segment by binary search;
+//   2. each wave owns a contiguous stripe of the sub-batch in pixel-sorted order, preloaded
+//      into registers before the staging barrier; per 64-sample step it forms the
+//      contributions, runs a segmented inclusive scan over equal pixels and adds each
+//      completed run once to the LDS accumulator of its pixel.  The run that opens a stripe
+//      may continue the previous stripe, so it is parked in a per-wave slot and added after a
+//      barrier, in wave order: the summation order is fixed, hence bitwise reproducible.
 
 template <typename T, int NV>
-__device__ __forceinline__ void contrib(const DevPlan& P, int64_t gk, double y, double* v) {
+__device__ __forceinline__ void contrib(const DevPlan& P, double y, double c, double s, double* v) {
   if (NV == 1) {
     v[0] = y;
   } else if (NV == 3) {
-    T c, s;
-    psi_weights<T>(P, P.psi_sorted, gk, c, s);
     v[0] = y;
-    v[1] = (double)c * y;
-    v[2] = (double)s * y;
+    v[1] = c * y;
+    v[2] = s * y;
   } else if (NV == 2) {  // plan, temperature: hits, sum 1/tau
     v[0] = 1.0;
     v[1] = y;
   } else {  // NV == 7, plan, I/Q/U: hits and the six entries of sum a a^T / tau
-    T c, s;
-    psi_weights<T>(P, P.psi_sorted, gk, c, s);
-    const double cd = (double)c, sd = (double)s;
     v[0] = 1.0;
     v[1] = y;
-    v[2] = cd * y;
-    v[3] = sd * y;
-    v[4] = cd * cd * y;
-    v[5] = cd * sd * y;
-    v[6] = sd * sd * y;
+    v[2] = c * y;
+    v[3] = s * y;
+    v[4] = c * c * y;
+    v[5] = c * s * y;
+    v[6] = s * s * y;
   }
 }
 
@@ -429,91 +577,207 @@ __device__ __forceinline__ void bin_flush(double* acc, double* cv, int* clp, int
   }
 }
 
+// largest i in [lo, n) with pos[i] <= q (pos[0] = 0 <= q)
+__device__ __forceinline__ int seg_find(const int* pos, int lo, int n, int q) {
+  int hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pos[mid] <= q)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ uint64_t psi_sorted_raw(const DevPlan& P, int64_t gk) {
+  if (P.psi_kind == 1) return ((const unsigned long long*)P.psi_sorted)[gk];
+  if (P.psi_kind == 2) return ((const uint32_t*)P.psi_sorted)[gk];
+  return ((const uint16_t*)P.psi_sorted)[gk];
+}
+
+template <typename T>
+__device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw, double& c, double& s) {
+  T cc, ss;
+  if (P.psi_kind == 1) {
+    const double a = __longlong_as_double((long long)raw);
+    if (sizeof(T) == 8) {
+      double sd, cd;
+      sincos(2.0 * a, &sd, &cd);
+      cc = (T)cd;
+      ss = (T)sd;
+    } else {
+      float sf, cf;
+      sincosf((float)(2.0 * a), &sf, &cf);
+      cc = (T)cf;
+      ss = (T)sf;
+    }
+  } else if (P.psi_kind == 2) {
+    const float a = __uint_as_float((uint32_t)raw);
+    if (sizeof(T) == 8) {
+      double sd, cd;
+      sincos(2.0 * (double)a, &sd, &cd);
+      cc = (T)cd;
+      ss = (T)sd;
+    } else {
+      float sf, cf;
+      sincosf(2.0f * a, &sf, &cf);
+      cc = (T)cf;
+      ss = (T)sf;
+    }
+  } else {
+    if (sizeof(T) == 8) {
+      const double2 t = P.psi_cs64[(uint32_t)raw];
+      cc = (T)t.x;
+      ss = (T)t.y;
+    } else {
+      const float2 t = P.psi_cs32[(uint32_t)raw];
+      cc = (T)t.x;
+      ss = (T)t.y;
+    }
+  }
+  c = (double)cc;
+  s = (double)ss;
+}
+
+// LDS layout of k_bin (bytes): [stage | acc | carries | segment table]
+template <int NV>
+__host__ __device__ constexpr size_t bin_lds_bytes(bool plan) {
+  return (plan ? 0 : kSubBatch * sizeof(double)) + kMaxTilePix * NV * sizeof(double) +
+         kWaves * NV * sizeof(double) + kWaves * sizeof(int) + kMaxSegs * (sizeof(int64_t) + 2 * sizeof(int));
+}
+
 template <typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_bin(DevPlan P, int bsrc, const T* __restrict__ src, int epi,
+__global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T* __restrict__ src, int epi,
                                                 const double* __restrict__ m_in, double* __restrict__ out,
                                                 double* __restrict__ w_out, int32_t* __restrict__ hits_out,
                                                 uint8_t* __restrict__ sol_out) {
+  constexpr bool PLAN = (NV == 2 || NV == 7);
+  constexpr int SPW = kSubBatch / kBinBlock;  // staged samples per thread
+  constexpr int STEPS = kSubBatch / kWaves / 64;  // 64-sample steps per wave stripe
   extern __shared__ double smem_d[];
   double* stage = smem_d;
-  double* acc = stage + kSubBatch;
+  double* acc = stage + (PLAN ? 0 : kSubBatch);
   double* cv = acc + kMaxTilePix * NV;
-  int* clp = reinterpret_cast<int*>(cv + kWaves * NV);
+  int64_t* sstart = reinterpret_cast<int64_t*>(cv + kWaves * NV);
+  int* spos = reinterpret_cast<int*>(sstart + kMaxSegs);
+  int* schunk = spos + kMaxSegs;
+  int* clp = schunk + kMaxSegs;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) {
     const Tile tl = P.tiles[t];
     const int tp = tl.tw * tl.th;
-    for (int i = threadIdx.x; i < tp * NV; i += kBlock) acc[i] = 0.0;
+    for (int i = threadIdx.x; i < tp * NV; i += kBinBlock) acc[i] = 0.0;
     __syncthreads();
     for (int sb = tl.sb_begin; sb < tl.sb_end; ++sb) {
       const SubBatch S = P.sbs[sb];
-      for (int g = S.seg_begin + wave; g < S.seg_end; g += kWaves) {
-        const Segment seg = P.segs[g];
-        const double scale = (bsrc == BSRC_WORK) ? 1.0 : P.chunks[seg.chunk].inv_tau;
-        for (int i = lane; i < seg.len; i += 64) {
-          double v;
-          if (bsrc == BSRC_PLAN)
-            v = scale;
-          else
-            v = (double)src[seg.start + i] * scale;
-          stage[seg.pos + i] = v;
-        }
-      }
-      if (lane == 0) clp[wave] = -1;
-      __syncthreads();
+      const int nseg = S.seg_end - S.seg_begin;
       const int cnt = S.count;
+      // this wave's stripe of the pixel-sorted order, preloaded before the staging barrier
       const int stripe = (((cnt + kWaves - 1) / kWaves) + 63) & ~63;
       const int k0 = wave * stripe;
       const int k1 = min(cnt, k0 + stripe);
+      int lpr[STEPS], prr[STEPS];
+      uint64_t psr[STEPS];
+#pragma unroll
+      for (int s = 0; s < STEPS; ++s) {
+        const int k = k0 + 64 * s + lane;
+        lpr[s] = -2 - lane;
+        prr[s] = 0;
+        psr[s] = 0;
+        if (k < k1) {
+          const int64_t gk = S.sorted_begin + k;
+          lpr[s] = P.lp[gk];
+          prr[s] = P.perm[gk];
+          if (NV == 3 || NV == 7) psr[s] = psi_sorted_raw<T>(P, gk);
+        }
+      }
+      for (int i = threadIdx.x; i < nseg; i += kBinBlock) {
+        const Segment g = P.segs[S.seg_begin + i];
+        sstart[i] = g.start;
+        spos[i] = g.pos;
+        schunk[i] = g.chunk;
+      }
+      if (lane == 0) clp[wave] = -1;
+      __syncthreads();
+      if (!PLAN) {
+        double v[SPW];
+        int lo = 0;
+#pragma unroll
+        for (int u = 0; u < SPW; ++u) {
+          const int q = threadIdx.x + u * kBinBlock;
+          v[u] = 0.0;
+          if (q < cnt) {
+            lo = seg_find(spos, lo, nseg, q);
+            const int64_t j = sstart[lo] + (q - spos[lo]);
+            v[u] = (double)src[j];
+            if (bsrc == BSRC_DATA_OVER_TAU) v[u] *= P.chunks[schunk[lo]].inv_tau;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < SPW; ++u) {
+          const int q = threadIdx.x + u * kBinBlock;
+          if (q < cnt) stage[q] = v[u];
+        }
+        __syncthreads();
+      }
       if (k0 < k1) {
-        const int first_lp = P.lp[S.sorted_begin + k0];
+        const int first_lp = __shfl(lpr[0], 0);
         int carry_lp = -1;
         double carry[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) carry[q] = 0.0;
-        for (int kb = k0; kb < k1; kb += 64) {
-          const int k = kb + lane;
-          int mylp;
-          double v[NV];
-          if (k < k1) {
-            const int64_t gk = S.sorted_begin + k;
-            mylp = P.lp[gk];
-            const double y = stage[P.perm[gk]];
-            contrib<T, NV>(P, gk, y, v);
-          } else {
-            mylp = -2 - lane;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) v[q] = 0.0;
-          }
-          if (carry_lp >= 0) {
-            const int lp0 = __shfl(mylp, 0);
-            if (lp0 == carry_lp) {
-              if (lane == 0) {
-#pragma unroll
-                for (int q = 0; q < NV; ++q) v[q] += carry[q];
+        for (int s = 0; s < STEPS; ++s) {
+          if (k0 + 64 * s < k1) {
+            int mylp = lpr[s];
+            double v[NV];
+            if (mylp >= 0) {
+              double y;
+              if (PLAN) {
+                const int g = seg_find(spos, 0, nseg, prr[s]);
+                y = P.chunks[schunk[g]].inv_tau;
+              } else {
+                y = stage[prr[s]];
               }
-            } else if (lane == 0) {
-              bin_flush<NV>(acc, cv, clp, wave, carry_lp, first_lp, carry);
+              double c = 0.0, sn = 0.0;
+              if (NV == 3 || NV == 7) weights_from_raw<T>(P, psr[s], c, sn);
+              contrib<T, NV>(P, y, c, sn, v);
+            } else {
+#pragma unroll
+              for (int q = 0; q < NV; ++q) v[q] = 0.0;
             }
-          }
-          // segmented inclusive scan over equal local pixels (the order is sorted by pixel)
+            if (carry_lp >= 0) {
+              const int lp0 = __shfl(mylp, 0);
+              if (lp0 == carry_lp) {
+                if (lane == 0) {
 #pragma unroll
-          for (int dd = 1; dd < 64; dd <<= 1) {
-            const int ulp = __shfl_up(mylp, dd);
-            double uv[NV];
-#pragma unroll
-            for (int q = 0; q < NV; ++q) uv[q] = __shfl_up(v[q], dd);
-            if (lane >= dd && ulp == mylp) {
-#pragma unroll
-              for (int q = 0; q < NV; ++q) v[q] += uv[q];
+                  for (int q = 0; q < NV; ++q) v[q] += carry[q];
+                }
+              } else if (lane == 0) {
+                bin_flush<NV>(acc, cv, clp, wave, carry_lp, first_lp, carry);
+              }
             }
-          }
-          const int nlp = __shfl_down(mylp, 1);
-          if (lane < 63 && mylp >= 0 && nlp != mylp) bin_flush<NV>(acc, cv, clp, wave, mylp, first_lp, v);
-          carry_lp = __shfl(mylp, 63);
+            // segmented inclusive scan over equal local pixels (the order is sorted by pixel)
 #pragma unroll
-          for (int q = 0; q < NV; ++q) carry[q] = __shfl(v[q], 63);
-          if (carry_lp < 0) carry_lp = -1;
+            for (int dd = 1; dd < 64; dd <<= 1) {
+              const int ulp = __shfl_up(mylp, dd);
+              double uv[NV];
+#pragma unroll
+              for (int q = 0; q < NV; ++q) uv[q] = __shfl_up(v[q], dd);
+              if (lane >= dd && ulp == mylp) {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) v[q] += uv[q];
+              }
+            }
+            const int nlp = __shfl_down(mylp, 1);
+            if (lane < 63 && mylp >= 0 && nlp != mylp) bin_flush<NV>(acc, cv, clp, wave, mylp, first_lp, v);
+            carry_lp = __shfl(mylp, 63);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) carry[q] = __shfl(v[q], 63);
+            if (carry_lp < 0) carry_lp = -1;
+          }
         }
         if (carry_lp >= 0 && lane == 0) bin_flush<NV>(acc, cv, clp, wave, carry_lp, first_lp, carry);
       }
@@ -527,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(DevPlan P, int bsrc, const T* __
       __syncthreads();
     }
     // epilogue: one thread per pixel of the tile
-    for (int l = threadIdx.x; l < tp; l += kBlock) {
+    for (int l = threadIdx.x; l < tp; l += kBinBlock) {
       const int64_t p = (int64_t)(tl.y0 + l / tl.tw) * P.nxm + tl.x0 + (l % tl.tw);
       const double* a = acc + l * NV;
       if (epi == EPI_PLAN) {
@@ -575,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(DevPlan P, int bsrc, const T* __
       } else {
         const bool ok = P.solvable[p] != 0;
         const int64_t np = P.npix;
-        double u[NV];
+        double u[NV > 3 ? NV : 3];
         if (NV == 1) {
           u[0] = P.winv[p] * a[0];
         } else if (NV == 3) {
@@ -595,6 +859,21 @@ __global__ __launch_bounds__(kBlock) void k_bin(DevPlan P, int bsrc, const T* __
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------------------------------------
+// plan: tabulate the power-law part of every chunk's noise spectrum (FP64 form)
+
+__global__ void k_spectrum(DevPlan P, double* __restrict__ spec) {
+  const int c = blockIdx.y;
+  const DevChunk ch = P.chunks[c];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= ch.M; k += gridDim.x * blockDim.x)
+    spec[ch.spec_off + k] = powerlaw<double>(ch, k);
+}
+
+hipError_t launch_spectrum(const DevPlan& P, double* spec, hipStream_t s) {
+  hipLaunchKernelGGL(k_spectrum, dim3(64, P.nchunk), dim3(256), 0, s, P, spec);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -751,7 +1030,7 @@ hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void*
   bc.lam = lam;
   bc.chi2_lam = chi2_lam;
   const int red_off = (int)lds;
-  const size_t tot = lds + kBlock * sizeof(double);
+  const size_t tot = lds + (kBlock / 64) * sizeof(double);
   if (P.precision == 0)
     hipLaunchKernelGGL(k_pass_b<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), tot, s, P, items, nitems,
                        (double2*)work, ops, bc, chi2_part, red_off);
@@ -775,8 +1054,8 @@ hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void
 template <typename T, int NV>
 static hipError_t launch_bin_t(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
                                double* w_out, int32_t* hits_out, uint8_t* sol_out, hipStream_t s) {
-  const size_t lds = (kSubBatch + kMaxTilePix * NV + kWaves * NV) * sizeof(double) + kWaves * sizeof(int);
-  hipLaunchKernelGGL((k_bin<T, NV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBlock), lds, s, P, bsrc,
+  const size_t lds = bin_lds_bytes<NV>(NV == 2 || NV == 7);
+  hipLaunchKernelGGL((k_bin<T, NV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, bsrc,
                      (const T*)src, epi, m_in, out, w_out, hits_out, sol_out);
   return hipGetLastError();
 }

@@ -68,12 +68,16 @@ static bool choose_split(int64_t M, int cap, int bmax, int row_cap, int64_t& M1,
   for (int64_t m2 = 1; m2 <= M; ++m2) {
     if (M % m2) continue;
     const int64_t m1 = M / m2;
-    const int64_t b = std::min<int64_t>(std::min<int64_t>(bmax, m1), cap / m2);
+    auto pow2floor = [](int64_t x) {
+      while (x & (x - 1)) x &= x - 1;
+      return x;
+    };
+    const int64_t bfull = pow2floor(std::min<int64_t>(bmax, m1));
+    const int64_t b = std::min<int64_t>(bfull, cap / m2 > 0 ? pow2floor(cap / m2) : 0);
     if (b < 1) continue;
     if (2 * m1 > row_cap) continue;
     // prefer full column blocks, then balanced splits
-    const double score = std::fabs(std::log((double)m2) - std::log(std::sqrt((double)M))) +
-                         (b < std::min<int64_t>(bmax, m1) ? 4.0 : 0.0);
+    const double score = std::fabs(std::log((double)m2) - std::log(std::sqrt((double)M))) + (b < bfull ? 4.0 : 0.0);
     if (score < bestscore) {
       bestscore = score;
       best = m2;
@@ -195,6 +199,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   std::vector<int64_t> class_M;
   std::vector<int> class_cb;
   size_t lds_ac = 0, lds_b = 0;
+  int64_t spec_total = 0;
   for (int64_t c = 0; c < D.nchunk; ++c) {
     const int64_t n = D.chunk_off[c + 1] - D.chunk_off[c];
     const int64_t M = n / 2;
@@ -204,7 +209,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     if (cls < 0) {
       int64_t M1, M2;
       int cb;
-      const int row_cap = cap - (int)(kBlock * sizeof(double) / csz);
+      const int row_cap = cap - (int)((kBlock / 64) * sizeof(double) / csz + 1);
       if (!choose_split(M, cap, bmax, row_cap, M1, M2, cb))
         return fail(MM_E_LEN, "chunk " + std::to_string(c) + ": no transform split fits the LDS budget");
       DevClass k;
@@ -223,9 +228,11 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
       k.tw2 = (int64_t)tw.size();
       omega_table(M2, M2, 1, tw);
       const int64_t L2 = 2 * M;
-      const int64_t lo = (int64_t)std::ceil(std::sqrt((double)L2));
+      int lb = 0;
+      while ((int64_t(1) << (2 * lb)) < L2) ++lb;  // 2^lb >= sqrt(2M)
+      const int64_t lo = int64_t(1) << lb;
       const int64_t nhi = (L2 + lo - 1) / lo;
-      k.lo = (int32_t)lo;
+      k.lb = lb;
       k.twlo = (int64_t)tw.size();
       omega_table(L2, lo, 1, tw);
       k.twhi = (int64_t)tw.size();
@@ -247,6 +254,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     ch.M2 = k.M2;
     ch.cls = cls;
     ch.cb = (int32_t)class_cb[cls];
+    ch.lgb = 0;
+    while ((1 << (ch.lgb + 1)) <= ch.cb) ++ch.lgb;
     ch.df = D.fsample[c] / (double)n;
     ch.sigma2 = D.sigma[c] * D.sigma[c];
     ch.fknee = D.fknee[c];
@@ -254,6 +263,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     ch.tau = pl->tau[c];
     ch.inv_tau = 1.0 / pl->tau[c];
     ch.nbar0 = ch.sigma2 - ch.tau;
+    ch.spec_off = spec_total;
+    spec_total += ch.M + 1;
     for (int32_t j1 = 0; j1 < ch.M1; j1 += ch.cb) pl->itemsAC.push_back({(int32_t)c, j1});
     pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
     const int M2 = ch.M2;
@@ -268,7 +279,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
   pl->lds_ac = lds_ac;
   pl->lds_b = lds_b;
-  if (lds_ac > 65536 || lds_b + kBlock * sizeof(double) > 65536)
+  if (lds_ac > 65536 || lds_b + (kBlock / 64) * sizeof(double) > 65536)
     return fail(MM_E_LEN, "transform tiles exceed the LDS budget");
   std::vector<float2> tw32(tw.size());
   for (size_t i = 0; i < tw.size(); ++i) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
@@ -324,14 +335,11 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   }
   std::vector<uint16_t> perm(non), lpv(non);
   std::vector<uint8_t> psi_sorted(non * pes);
-  std::vector<std::vector<Segment>> tsegs(ntiles);
   std::vector<Tile> tiles(ntiles);
-  std::vector<int64_t> tsb(ntiles + 1, 0);
-  for (int64_t t = 0; t < ntiles; ++t) {
-    const int64_t cnt = tcount[t + 1] - tcount[t];
-    tsb[t + 1] = tsb[t] + (cnt + kSubBatch - 1) / kSubBatch;
-  }
-  std::vector<SubBatch> sbs(tsb[ntiles]);
+  // per-tile sub-batches: consecutive runs of the tile's time-ordered samples holding at most
+  // kSubBatch samples and kMaxSegs time-contiguous segments (segments never cross chunks)
+  std::vector<std::vector<Segment>> tsegs(ntiles);
+  std::vector<std::vector<SubBatch>> tsbs(ntiles);
   const std::vector<int64_t>& coff = pl->off;
   auto chunk_of = [&](int64_t j) -> int32_t {
     return (int32_t)(std::upper_bound(coff.begin(), coff.end(), j) - coff.begin() - 1);
@@ -348,55 +356,61 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
       tl.y0 = (int32_t)(ty * th_);
       tl.tw = (int32_t)std::min(tw_, nxm - tx * tw_);
       tl.th = (int32_t)std::min(th_, nym - ty * th_);
-      tl.sb_begin = (int32_t)tsb[t];
-      tl.sb_end = (int32_t)tsb[t + 1];
+      tl.sb_begin = tl.sb_end = 0;
       tiles[t] = tl;
       const int64_t tp = (int64_t)tl.tw * tl.th;
       hist.assign(tp + 1, 0);
-      for (int64_t sb = tsb[t]; sb < tsb[t + 1]; ++sb) {
-        const int64_t b0 = tcount[t] + (sb - tsb[t]) * kSubBatch;
-        const int64_t b1 = std::min(b0 + kSubBatch, tcount[t + 1]);
+      auto lp_of = [&](int64_t j) -> int32_t {
+        const int64_t p = pix[j];
+        const int64_t y = p / nxm, x = p % nxm;
+        return (int32_t)((y - tl.y0) * tl.tw + (x - tl.x0));
+      };
+      std::vector<Segment>& sg = tsegs[t];
+      int64_t i = tcount[t];
+      const int64_t iend = tcount[t + 1];
+      while (i < iend) {
         SubBatch S;
-        S.sorted_begin = b0;
-        S.count = (int32_t)(b1 - b0);
+        S.sorted_begin = i;
+        S.seg_begin = (int32_t)sg.size();
         S.pad = 0;
-        S.seg_begin = (int32_t)tsegs[t].size();  // tile-local; rebased when concatenated
-        // segments: maximal runs of consecutive samples inside one chunk
+        const int64_t b0 = i;
         int64_t cur_end = -1;
-        for (int64_t i = b0; i < b1; ++i) {
+        int64_t chunk_end = -1;
+        int nseg = 0;
+        for (; i < iend && i - b0 < kSubBatch; ++i) {
           const int64_t j = order[i];
-          if (j == cur_end && j < coff[tsegs[t].back().chunk + 1]) {
-            tsegs[t].back().len += 1;
+          if (j == cur_end && j < chunk_end) {
+            sg.back().len += 1;
           } else {
+            if (nseg == kMaxSegs) break;
             Segment g;
             g.start = j;
             g.len = 1;
             g.pos = (int32_t)(i - b0);
             g.chunk = chunk_of(j);
             g.pad = 0;
-            tsegs[t].push_back(g);
+            chunk_end = coff[g.chunk + 1];
+            sg.push_back(g);
+            ++nseg;
           }
           cur_end = j + 1;
         }
-        S.seg_end = (int32_t)tsegs[t].size();
+        const int64_t b1 = i;
+        S.count = (int32_t)(b1 - b0);
+        S.seg_end = (int32_t)sg.size();
         // counting sort of the sub-batch by local pixel (stable: time order within a pixel)
         std::fill(hist.begin(), hist.end(), 0);
-        auto lp_of = [&](int64_t j) -> int32_t {
-          const int64_t p = pix[j];
-          const int64_t y = p / nxm, x = p % nxm;
-          return (int32_t)((y - tl.y0) * tl.tw + (x - tl.x0));
-        };
-        for (int64_t i = b0; i < b1; ++i) ++hist[lp_of(order[i]) + 1];
+        for (int64_t q = b0; q < b1; ++q) ++hist[lp_of(order[q]) + 1];
         for (int64_t l = 0; l < tp; ++l) hist[l + 1] += hist[l];
-        for (int64_t i = b0; i < b1; ++i) {
-          const int64_t j = order[i];
+        for (int64_t q = b0; q < b1; ++q) {
+          const int64_t j = order[q];
           const int32_t l = lp_of(j);
           const int64_t dst = b0 + hist[l]++;
-          perm[dst] = (uint16_t)(i - b0);
+          perm[dst] = (uint16_t)(q - b0);
           lpv[dst] = (uint16_t)l;
           if (pes) std::memcpy(&psi_sorted[dst * pes], &psi[j * pes], pes);
         }
-        sbs[sb] = S;
+        tsbs[t].push_back(S);
       }
     }
   };
@@ -406,15 +420,20 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     for (unsigned i = 0; i < nth; ++i) th.emplace_back(worker);
     for (auto& x : th) x.join();
   }
+  std::vector<SubBatch> sbs;
   std::vector<Segment> segs;
   for (int64_t t = 0; t < ntiles; ++t) {
     const int32_t base = (int32_t)segs.size();
-    for (int64_t sb = tsb[t]; sb < tsb[t + 1]; ++sb) {
-      sbs[sb].seg_begin += base;
-      sbs[sb].seg_end += base;
+    tiles[t].sb_begin = (int32_t)sbs.size();
+    for (SubBatch S : tsbs[t]) {
+      S.seg_begin += base;
+      S.seg_end += base;
+      sbs.push_back(S);
     }
+    tiles[t].sb_end = (int32_t)sbs.size();
     segs.insert(segs.end(), tsegs[t].begin(), tsegs[t].end());
     std::vector<Segment>().swap(tsegs[t]);
+    std::vector<SubBatch>().swap(tsbs[t]);
   }
   pl->ntiles = ntiles;
   pl->nsegs = (int64_t)segs.size();
@@ -506,6 +525,12 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   }
   P.winv = pl->d_winv;
   P.solvable = pl->d_solvable;
+  if (f64) {
+    if ((st = plan_alloc(pl, (size_t)spec_total * sizeof(double), &p)) != MM_OK) return st;
+    P.spec = (double*)p;
+    hipError_t es = launch_spectrum(P, (double*)p, s);
+    if (es != hipSuccess) return fail(MM_E_HIP, std::string("spectrum kernel launch: ") + hipGetErrorString(es));
+  }
 
   // ---- precompute: hits, weight blocks and their inverses (deterministic binning)
   hipError_t e = launch_bin(P, BSRC_PLAN, nullptr, EPI_PLAN, nullptr, (double*)pl->d_solvable, pl->d_winv,
