@@ -70,6 +70,8 @@ struct SubBatch {
   int32_t pad;
 };
 constexpr int kMaxSegs = 512;  // segments per sub-batch (LDS segment table)
+constexpr int kSortAlign = 16;  // alignment (elements) of each sub-batch in the pixel-sorted arrays
+constexpr int kPerLane = 16;    // consecutive pixel-sorted samples one lane accumulates
 struct Segment {
   int64_t start;             // first sample
   int32_t len;

@@ -650,12 +650,12 @@ __host__ __device__ constexpr size_t bin_lds_bytes(bool plan) {
 
 template <typename T, int NV>
 __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T* __restrict__ src, int epi,
-                                                const double* __restrict__ m_in, double* __restrict__ out,
-                                                double* __restrict__ w_out, int32_t* __restrict__ hits_out,
-                                                uint8_t* __restrict__ sol_out) {
+                                                   const double* __restrict__ m_in, double* __restrict__ out,
+                                                   double* __restrict__ w_out, int32_t* __restrict__ hits_out,
+                                                   uint8_t* __restrict__ sol_out) {
   constexpr bool PLAN = (NV == 2 || NV == 7);
+  constexpr bool POL = (NV == 3 || NV == 7);
   constexpr int SPW = kSubBatch / kBinBlock;  // staged samples per thread
-  constexpr int STEPS = kSubBatch / kWaves / 64;  // 64-sample steps per wave stripe
   extern __shared__ double smem_d[];
   double* stage = smem_d;
   double* acc = stage + (PLAN ? 0 : kSubBatch);
@@ -674,23 +674,29 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
       const SubBatch S = P.sbs[sb];
       const int nseg = S.seg_end - S.seg_begin;
       const int cnt = S.count;
-      // this wave's stripe of the pixel-sorted order, preloaded before the staging barrier
+      // this wave's stripe of the pixel-sorted order; lane l takes kPerLane consecutive entries
       const int stripe = (((cnt + kWaves - 1) / kWaves) + 63) & ~63;
       const int k0 = wave * stripe;
       const int k1 = min(cnt, k0 + stripe);
-      int lpr[STEPS], prr[STEPS];
-      uint64_t psr[STEPS];
+      const int kl = k0 + kPerLane * lane;
+      const bool active = kl < k1;
+      uint4 lpw[2], pmw[2];
+      uint4 psw[kPerLane / 2];  // raw angles: up to 16 x 8 bytes
+      if (active) {
+        const int64_t g0 = S.sorted_begin + kl;  // a multiple of kSortAlign
+        const uint4* lpp = reinterpret_cast<const uint4*>(P.lp + g0);
+        const uint4* pmp = reinterpret_cast<const uint4*>(P.perm + g0);
+        lpw[0] = lpp[0];
+        lpw[1] = lpp[1];
+        pmw[0] = pmp[0];
+        pmw[1] = pmp[1];
+        if (POL) {
+          const int nw = P.psi_kind == 1 ? 8 : (P.psi_kind == 2 ? 4 : 2);
+          const uint4* pp = reinterpret_cast<const uint4*>((const char*)P.psi_sorted +
+                                                           g0 * (P.psi_kind == 1 ? 8 : (P.psi_kind == 2 ? 4 : 2)));
 #pragma unroll
-      for (int s = 0; s < STEPS; ++s) {
-        const int k = k0 + 64 * s + lane;
-        lpr[s] = -2 - lane;
-        prr[s] = 0;
-        psr[s] = 0;
-        if (k < k1) {
-          const int64_t gk = S.sorted_begin + k;
-          lpr[s] = P.lp[gk];
-          prr[s] = P.perm[gk];
-          if (NV == 3 || NV == 7) psr[s] = psi_sorted_raw<T>(P, gk);
+          for (int w = 0; w < kPerLane / 2; ++w)
+            if (w < nw) psw[w] = pp[w];
         }
       }
       for (int i = threadIdx.x; i < nseg; i += kBinBlock) {
@@ -723,63 +729,93 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
         __syncthreads();
       }
       if (k0 < k1) {
-        const int first_lp = __shfl(lpr[0], 0);
-        int carry_lp = -1;
-        double carry[NV];
+        const int first_lp = __shfl((int)(lpw[0].x & 0xffffu), 0);  // lane 0 is active
+        // sequential reduce-by-key over this lane's entries
+        int cur_lp = -1, h_lp = -1, nruns = 0;
+        double cur[NV], hv[NV];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) carry[q] = 0.0;
+        for (int q = 0; q < NV; ++q) cur[q] = hv[q] = 0.0;
 #pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
-          if (k0 + 64 * s < k1) {
-            int mylp = lpr[s];
+        for (int i = 0; i < kPerLane; ++i) {
+          if (kl + i < k1) {
+            const uint32_t wl = (i < 8) ? ((const uint32_t*)&lpw[0])[i / 2] : ((const uint32_t*)&lpw[1])[(i - 8) / 2];
+            const uint32_t wp = (i < 8) ? ((const uint32_t*)&pmw[0])[i / 2] : ((const uint32_t*)&pmw[1])[(i - 8) / 2];
+            const int lp = (int)((wl >> (16 * (i & 1))) & 0xffffu);
+            const int pr = (int)((wp >> (16 * (i & 1))) & 0xffffu);
+            double y;
+            if (PLAN) {
+              const int g = seg_find(spos, 0, nseg, pr);
+              y = P.chunks[schunk[g]].inv_tau;
+            } else {
+              y = stage[pr];
+            }
+            double c = 0.0, sn = 0.0;
+            if (POL) {
+              uint64_t raw;
+              const uint32_t* pw = (const uint32_t*)psw;
+              if (P.psi_kind == 1)
+                raw = ((uint64_t)pw[2 * i + 1] << 32) | pw[2 * i];
+              else if (P.psi_kind == 2)
+                raw = pw[i];
+              else
+                raw = (pw[i / 2] >> (16 * (i & 1))) & 0xffffu;
+              weights_from_raw<T>(P, raw, c, sn);
+            }
             double v[NV];
-            if (mylp >= 0) {
-              double y;
-              if (PLAN) {
-                const int g = seg_find(spos, 0, nseg, prr[s]);
-                y = P.chunks[schunk[g]].inv_tau;
-              } else {
-                y = stage[prr[s]];
+            contrib<T, NV>(P, y, c, sn, v);
+            if (lp != cur_lp) {
+              if (nruns == 1) {
+                h_lp = cur_lp;
+#pragma unroll
+                for (int q = 0; q < NV; ++q) hv[q] = cur[q];
+              } else if (nruns > 1) {
+                bin_flush<NV>(acc, cv, clp, wave, cur_lp, first_lp, cur);  // a run inside this lane
               }
-              double c = 0.0, sn = 0.0;
-              if (NV == 3 || NV == 7) weights_from_raw<T>(P, psr[s], c, sn);
-              contrib<T, NV>(P, y, c, sn, v);
+              cur_lp = lp;
+#pragma unroll
+              for (int q = 0; q < NV; ++q) cur[q] = v[q];
+              ++nruns;
             } else {
 #pragma unroll
-              for (int q = 0; q < NV; ++q) v[q] = 0.0;
+              for (int q = 0; q < NV; ++q) cur[q] += v[q];
             }
-            if (carry_lp >= 0) {
-              const int lp0 = __shfl(mylp, 0);
-              if (lp0 == carry_lp) {
-                if (lane == 0) {
-#pragma unroll
-                  for (int q = 0; q < NV; ++q) v[q] += carry[q];
-                }
-              } else if (lane == 0) {
-                bin_flush<NV>(acc, cv, clp, wave, carry_lp, first_lp, carry);
-              }
-            }
-            // segmented inclusive scan over equal local pixels (the order is sorted by pixel)
-#pragma unroll
-            for (int dd = 1; dd < 64; dd <<= 1) {
-              const int ulp = __shfl_up(mylp, dd);
-              double uv[NV];
-#pragma unroll
-              for (int q = 0; q < NV; ++q) uv[q] = __shfl_up(v[q], dd);
-              if (lane >= dd && ulp == mylp) {
-#pragma unroll
-                for (int q = 0; q < NV; ++q) v[q] += uv[q];
-              }
-            }
-            const int nlp = __shfl_down(mylp, 1);
-            if (lane < 63 && mylp >= 0 && nlp != mylp) bin_flush<NV>(acc, cv, clp, wave, mylp, first_lp, v);
-            carry_lp = __shfl(mylp, 63);
-#pragma unroll
-            for (int q = 0; q < NV; ++q) carry[q] = __shfl(v[q], 63);
-            if (carry_lp < 0) carry_lp = -1;
           }
         }
-        if (carry_lp >= 0 && lane == 0) bin_flush<NV>(acc, cv, clp, wave, carry_lp, first_lp, carry);
+        // runs that cross lane boundaries: keyed inclusive scan of the lanes' tail runs
+        const bool single = nruns <= 1;
+        int t_lp = active ? cur_lp : (-2 - lane);
+        if (single) h_lp = t_lp;
+        double Sv[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Sv[q] = active ? cur[q] : 0.0;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+          const int uk = __shfl_up(t_lp, dd);
+          double us[NV];
+#pragma unroll
+          for (int q = 0; q < NV; ++q) us[q] = __shfl_up(Sv[q], dd);
+          if (lane >= dd && uk == t_lp) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) Sv[q] += us[q];
+          }
+        }
+        int prev_key = __shfl_up(t_lp, 1);
+        double prev_S[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) prev_S[q] = __shfl_up(Sv[q], 1);
+        int next_h = __shfl_down(h_lp, 1);
+        if (lane == 0) prev_key = -1;
+        if (lane == 63) next_h = -1;
+        // a lane with several runs completes its head run (adding what earlier lanes carried in)
+        if (active && !single) {
+          if (h_lp == prev_key) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) hv[q] += prev_S[q];
+          }
+          bin_flush<NV>(acc, cv, clp, wave, h_lp, first_lp, hv);
+        }
+        // the tail run ends here unless the next lane continues it
+        if (active && next_h != t_lp) bin_flush<NV>(acc, cv, clp, wave, t_lp, first_lp, Sv);
       }
       __syncthreads();
       if (threadIdx.x < NV) {

@@ -306,7 +306,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   // tiles: rectangles of tw x th pixels over a map of rows of length nxm
   const int64_t nxm = D.nx > 0 ? D.nx : D.npix;
   const int64_t nym = D.npix / nxm;
-  int64_t target = std::max<int64_t>(16, std::min<int64_t>(512, D.npix / 1024));
+  int64_t target = std::max<int64_t>(16, std::min<int64_t>(kMaxTilePix, D.npix / 2048));
   int64_t tw_ = 1;
   while (tw_ * tw_ * 2 <= target) tw_ *= 2;  // tw_ ~ sqrt(target), power of two
   int64_t th_ = std::max<int64_t>(1, target / tw_);
@@ -333,8 +333,18 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     for (int64_t j = 0; j < ns; ++j)
       if (pix[j] >= 0) order[fill[tile_of(pix[j])]++] = j;
   }
-  std::vector<uint16_t> perm(non), lpv(non);
-  std::vector<uint8_t> psi_sorted(non * pes);
+  // pixel-sorted arrays: every sub-batch starts on a kSortAlign-element boundary so that a lane
+  // can fetch its run of consecutive entries with 16-byte loads; a tile of n samples has at most
+  // ceil(n / kMaxSegs) sub-batches (each sub-batch holds kSubBatch samples or kMaxSegs segments)
+  std::vector<int64_t> sbase(ntiles + 1, 0);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int64_t cnt = tcount[t + 1] - tcount[t];
+    const int64_t cap = cnt + kSortAlign * ((cnt + kMaxSegs - 1) / kMaxSegs + 1);
+    sbase[t + 1] = sbase[t] + (cap + kSortAlign - 1) / kSortAlign * kSortAlign;
+  }
+  const int64_t nsorted = sbase[ntiles];
+  std::vector<uint16_t> perm(nsorted, 0), lpv(nsorted, 0);
+  std::vector<uint8_t> psi_sorted(nsorted * pes, 0);
   std::vector<Tile> tiles(ntiles);
   // per-tile sub-batches: consecutive runs of the tile's time-ordered samples holding at most
   // kSubBatch samples and kMaxSegs time-contiguous segments (segments never cross chunks)
@@ -368,9 +378,10 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
       std::vector<Segment>& sg = tsegs[t];
       int64_t i = tcount[t];
       const int64_t iend = tcount[t + 1];
+      int64_t cursor = sbase[t];
       while (i < iend) {
         SubBatch S;
-        S.sorted_begin = i;
+        S.sorted_begin = cursor;
         S.seg_begin = (int32_t)sg.size();
         S.pad = 0;
         const int64_t b0 = i;
@@ -405,12 +416,13 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
         for (int64_t q = b0; q < b1; ++q) {
           const int64_t j = order[q];
           const int32_t l = lp_of(j);
-          const int64_t dst = b0 + hist[l]++;
+          const int64_t dst = cursor + hist[l]++;
           perm[dst] = (uint16_t)(q - b0);
           lpv[dst] = (uint16_t)l;
           if (pes) std::memcpy(&psi_sorted[dst * pes], &psi[j * pes], pes);
         }
         tsbs[t].push_back(S);
+        cursor += (S.count + kSortAlign - 1) / kSortAlign * kSortAlign;
       }
     }
   };
