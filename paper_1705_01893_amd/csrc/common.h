@@ -39,6 +39,7 @@ struct DevChunk {
   double tau, inv_tau;
   double nbar0;       // sigma^2 - tau (N-bar = nbar0 + sigma^2 (f/fknee)^alpha)
   int64_t spec_off;   // offset of this chunk's M+1 power-law values in DevPlan::spec (FP64 form)
+  double inv_M;       // 1 / M
 };
 
 // Per-length transform data: radix schedules and twiddle-table offsets.

@@ -115,7 +115,7 @@ __device__ __forceinline__ float powerlaw<float>(const DevChunk& ch, int k) {
 
 struct BinCtx {
   int gain;
-  double lam, chi2_lam;
+  double lam, inv_lam, chi2_lam;
 };
 
 // power-law part sigma^2 (f_k/fknee)^alpha of the noise spectrum at real bin k: tabulated at plan
@@ -124,7 +124,10 @@ template <typename T>
 __device__ __forceinline__ T powerlaw_bin(const DevPlan& P, const DevChunk& ch, int k);
 template <>
 __device__ __forceinline__ double powerlaw_bin<double>(const DevPlan& P, const DevChunk& ch, int k) {
-  return P.spec[ch.spec_off + k];
+  // row layout of the table: bin k = k2 + M2 k1 sits at k2 * M1 + k1 (bin M last), so a row
+  // of the transform reads a contiguous run of the table
+  const int idx = (k == ch.M) ? ch.M : (k % ch.M2) * ch.M1 + k / ch.M2;
+  return P.spec[ch.spec_off + idx];
 }
 template <>
 __device__ __forceinline__ float powerlaw_bin<float>(const DevPlan& P, const DevChunk& ch, int k) {
@@ -141,13 +144,13 @@ __device__ __forceinline__ void bin_factors(const DevPlan& P, const DevChunk& ch
   T gg;
   if (bc.gain == GAIN_MESSENGER) {
     const T nbar = (T)ch.nbar0 + pl;
-    gg = T(1) / (tau + nbar / (T)bc.lam);
+    gg = T(1) / (tau + nbar * (T)bc.inv_lam);
   } else if (bc.gain == GAIN_NINV) {
     gg = T(1) / N;
   } else {
-    gg = N / tau;
+    gg = N * (T)ch.inv_tau;
   }
-  g = gg / (T)ch.M;
+  g = gg * (T)ch.inv_M;
   const double Np = (double)N + (bc.chi2_lam - 1.0) * ch.tau;
   cw = 1.0 / ((double)ch.n * Np);
 }
@@ -903,8 +906,10 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
 __global__ void k_spectrum(DevPlan P, double* __restrict__ spec) {
   const int c = blockIdx.y;
   const DevChunk ch = P.chunks[c];
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= ch.M; k += gridDim.x * blockDim.x)
-    spec[ch.spec_off + k] = powerlaw<double>(ch, k);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= ch.M; i += gridDim.x * blockDim.x) {
+    const int k = (i == ch.M) ? ch.M : (i % ch.M1) * ch.M2 + i / ch.M1;  // inverse of the row layout
+    spec[ch.spec_off + i] = powerlaw<double>(ch, k);
+  }
 }
 
 hipError_t launch_spectrum(const DevPlan& P, double* spec, hipStream_t s) {
@@ -1064,6 +1069,7 @@ hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void*
   BinCtx bc;
   bc.gain = gain;
   bc.lam = lam;
+  bc.inv_lam = 1.0 / lam;
   bc.chi2_lam = chi2_lam;
   const int red_off = (int)lds;
   const size_t tot = lds + (kBlock / 64) * sizeof(double);

@@ -264,6 +264,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     ch.inv_tau = 1.0 / pl->tau[c];
     ch.nbar0 = ch.sigma2 - ch.tau;
     ch.spec_off = spec_total;
+    ch.inv_M = 1.0 / (double)ch.M;
     spec_total += ch.M + 1;
     for (int32_t j1 = 0; j1 < ch.M1; j1 += ch.cb) pl->itemsAC.push_back({(int32_t)c, j1});
     pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
