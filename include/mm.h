@@ -216,6 +216,39 @@ mm_status mm_apply(mm_plan_t plan, int32_t which, double lambda, const double* x
 mm_status mm_lift_rhs(mm_plan_t plan, const double* g, void* out, mm_stream_t stream);
 
 /*
+ * Replace the noise parameters of every chunk (host arrays of nchunk doubles;
+ * tau NULL for sigma^2) and recompute what depends on them: the noise
+ * spectrum, the weight blocks P^T T^-1 P, their inverses and the solvable
+ * mask.  The pointing sort is kept.  Waits for the stream.
+ */
+mm_status mm_plan_set_noise(mm_plan_t plan, const double* sigma, const double* fknee, const double* alpha,
+                            const double* tau, mm_stream_t stream);
+
+/*
+ * TOD-space image of a map: out = G P x with G = N^-1 (which == 0),
+ * (lambda^-1 (N - T) + T)^-1 (which == 1) or N T^-1 (which == 2).  x: device
+ * map; out: device TOD of the plan's TOD type.  With x = z = A^-1 g (A the
+ * normal matrix P^T N^-1 P of eqn. mapmaking), which == 0 gives the gradient
+ * of a loss L(m) of the solved map with respect to the data, N^-1 P z.
+ */
+mm_status mm_tod_apply(mm_plan_t plan, int32_t which, double lambda, const double* x, void* out,
+                       mm_stream_t stream);
+
+/*
+ * Gradient of a loss of the solved map m = A^-1 P^T N^-1 d (eqn. mapmaking)
+ * with respect to each chunk's noise parameters (sigma, fknee, alpha):
+ *   dL/dtheta_c = -(1/n_c) sum_k omega_k Re(conj(Zhat_k) Rhat_k) (dN_k/dtheta_c) / N_k^2
+ * with r = d - P m, Zhat = rfft of P z and z = A^-1 (dL/dm) the adjoint map
+ * (obtain it with mm_lift_rhs + mm_solve, or mm_cg_solve with rhs_map).
+ * omega_k is the multiplicity of rfft bin k.  d: device TOD; m, z: device
+ * maps; grad_dev: device [nchunk][3] doubles.  Needs a second TOD-sized work
+ * buffer (allocated on first use).  MM_E_LEN when two rows of two residuals
+ * do not fit one workgroup's LDS.
+ */
+mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const double* z, double* grad_dev,
+                        mm_stream_t stream);
+
+/*
  * Per-pass timing for measurement.  With timing enabled, every pass launched
  * by mm_messenger_iter, mm_chi2, mm_apply and mm_cg_solve (not mm_solve, which
  * replays a graph) is bracketed by HIP events recorded on the stream it runs

@@ -313,6 +313,46 @@ mm_status mm_lift_rhs(mm_plan_t plan, const double* g, void* out, mm_stream_t st
   return MM_OK;
 }
 
+mm_status mm_plan_set_noise(mm_plan_t plan, const double* sigma, const double* fknee, const double* alpha,
+                            const double* tau, mm_stream_t stream) {
+  if (!plan) return fail(MM_E_ARG, "null plan");
+  return plan_set_noise(plan, sigma, fknee, alpha, tau, S(stream));
+}
+
+mm_status mm_tod_apply(mm_plan_t plan, int32_t which, double lambda, const double* x, void* out,
+                       mm_stream_t stream) {
+  if (!plan || !x || !out) return fail(MM_E_ARG, "null argument");
+  if (which < 0 || which > 2) return fail(MM_E_ARG, "which must be 0, 1 or 2");
+  if (which == 1 && (!(lambda >= 1.0) || !std::isfinite(lambda))) return fail(MM_E_ARG, "lambda must be >= 1");
+  const int gain = which == 0 ? GAIN_NINV : (which == 1 ? GAIN_MESSENGER : GAIN_LIFT);
+  hipStream_t s = S(stream);
+  MM_TRY(sweep_filter(plan, nullptr, x, SRC_PM, B_FILTER, gain, which == 1 ? lambda : 1.0, 1.0, s));
+  MM_TRY_HIP(launch_copy_bytes(out, plan->d_work, plan->ns * (plan->precision == MM_FP64 ? 8 : 4), s));
+  return MM_OK;
+}
+
+mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const double* z, double* grad_dev,
+                        mm_stream_t stream) {
+  if (!plan || !d || !m || !z || !grad_dev) return fail(MM_E_ARG, "null argument");
+  // two rows of both residuals per workgroup: 4 M1 complex values, at most the transform capacity
+  // kBlock * Ept (= 64 KB of LDS)
+  const size_t lds = 2 * plan->lds_b;
+  if (lds > 65536) return fail(MM_E_LEN, "chunk rows too long for the two-spectrum gradient pass");
+  hipStream_t s = S(stream);
+  if (!plan->d_work2) {
+    void* p = nullptr;
+    MM_TRY(plan_alloc(plan, (size_t)plan->ns * (plan->precision == MM_FP64 ? 8 : 4), &p));
+    plan->d_work2 = p;
+  }
+  MM_TRY_HIP(launch_pass_a(plan->dp, plan->d_itemsAC, (int)plan->itemsAC.size(), d, m, SRC_D_MINUS_PM,
+                           plan->d_work, plan->lds_ac, s));
+  MM_TRY_HIP(launch_pass_a(plan->dp, plan->d_itemsAC, (int)plan->itemsAC.size(), nullptr, z, SRC_PM, plan->d_work2,
+                           plan->lds_ac, s));
+  MM_TRY_HIP(launch_grad(plan->dp, plan->d_itemsB, (int)plan->itemsB.size(), plan->d_chunk_item_begin,
+                         plan->d_work, plan->d_work2, plan->d_chi2_part, grad_dev, lds, s));
+  return MM_OK;
+}
+
 mm_status mm_cg_solve(mm_plan_t plan, const void* d, const double* rhs_map, int32_t maxiter, double rtol,
                       const double* m0, double* m_out, double* chi2_hist_dev, double* rz_hist_dev,
                       int32_t* iters_done, mm_stream_t stream) {

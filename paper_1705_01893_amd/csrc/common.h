@@ -129,6 +129,8 @@ hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void
 hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
                       double* w_out, int32_t* hits_out, hipStream_t s);
 hipError_t launch_spectrum(const DevPlan& P, double* spec, hipStream_t s);
+hipError_t launch_grad(const DevPlan& P, const ItemB* items, int nitems, const int32_t* chunk_item_begin,
+                       const void* Xr, const void* Xz, double* part, double* out, size_t lds, hipStream_t s);
 hipError_t launch_chi2_reduce(const int32_t* chunk_item_begin, const double* part, int nchunk, double* per_chunk,
                               double* total, hipStream_t s);
 // map-space vector kernels for CG and helpers

@@ -30,6 +30,9 @@ namespace mm {
 // ---------------------------------------------------------------------------------------------
 // small helpers
 
+static inline int grid_for(int64_t n, int cap) { return (int)(n < cap ? (n > 0 ? n : 1) : cap); }
+constexpr int kGridCap = 1 << 16;
+
 template <typename T>
 __device__ __forceinline__ const cx<T>* twtab(const DevPlan& P);
 template <>
@@ -901,6 +904,162 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
 }
 
 // ---------------------------------------------------------------------------------------------
+// gradient of the solved map with respect to each chunk's noise parameters
+//
+// With r = d - P m (m the GLS map) and z = A^-1 g (the adjoint map of a loss gradient g),
+// dL/dtheta_c = -(1/n_c) sum_k omega_k Re(conj(Zhat_k) Rhat_k) (dN_k/dtheta_c) / N_k^2 over the
+// real bins of chunk c, Zhat = rfft of P z.  Both residuals arrive in their column-transformed
+// row layout (pass A output); the row transforms and the real-spectrum untangle are those of
+// pass B.  theta = (sigma, fknee, alpha): dN/dsigma = 2 N / sigma, dN/dfknee = -alpha pl / fknee,
+// dN/dalpha = pl ln(f / fknee), pl = sigma^2 (f/fknee)^alpha (f_0 -> f_1).
+
+template <typename T>
+__device__ __forceinline__ void grad_bin(const DevPlan& P, const DevChunk& ch, int k, double w, cx<T> R, cx<T> Z,
+                                         double* acc) {
+  const double pl = (double)powerlaw_bin<T>(P, ch, k);
+  const double N = ch.sigma2 + pl;
+  const double f = (double)(k == 0 ? 1 : k) * ch.df;
+  const double cross = (double)Z.x * (double)R.x + (double)Z.y * (double)R.y;
+  const double c = -w * cross / ((double)ch.n * N * N);
+  acc[0] += c * 2.0 * N / sqrt(ch.sigma2);
+  acc[1] += c * (-ch.alpha * pl / ch.fknee);
+  acc[2] += c * pl * log(f / ch.fknee);
+}
+
+template <typename T>
+__device__ __forceinline__ void untangle(const DevClass& cl, const DevPlan& P, cx<T> Zk, cx<T> Zm, int k, cx<T>& Rk,
+                                         cx<T>& Rm) {
+  cx<T> E, O;
+  E.x = T(0.5) * (Zk.x + Zm.x);
+  E.y = T(0.5) * (Zk.y - Zm.y);
+  O.x = T(0.5) * (Zk.y + Zm.y);
+  O.y = -T(0.5) * (Zk.x - Zm.x);
+  const cx<T> wO = cmul(omega2M<T>(P, cl, k), O);
+  Rk = cadd(E, wO);
+  Rm = csub(conjc(E), conjc(wO));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_grad_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
+                                                   const cx<T>* __restrict__ Xr, const cx<T>* __restrict__ Xz,
+                                                   double* __restrict__ part) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const ItemB item = items[it];
+    const DevChunk ch = P.chunks[item.chunk];
+    const DevClass& cl = P.classes[ch.cls];
+    const int M1 = ch.M1, M2 = ch.M2, M = ch.M;
+    const int ra = item.ra, rb = item.rb;
+    const int nrow = (ra == rb) ? 1 : 2;
+    // sequences: rows of r at [0, nrow*M1), rows of P z at [nrow*M1, 2*nrow*M1)
+    const int off2 = nrow * M1;
+    for (int e = threadIdx.x; e < M1; e += kBlock) {
+      lds[e] = Xr[ch.off / 2 + (int64_t)ra * M1 + e];
+      lds[off2 + e] = Xz[ch.off / 2 + (int64_t)ra * M1 + e];
+      if (nrow == 2) {
+        lds[M1 + e] = Xr[ch.off / 2 + (int64_t)rb * M1 + e];
+        lds[off2 + M1 + e] = Xz[ch.off / 2 + (int64_t)rb * M1 + e];
+      }
+    }
+    __syncthreads();
+    lds_fft<T, false, false>(lds, M1, 2 * nrow, 0, 1, M1, cl.rad1, cl.nr1, twtab<T>(P) + cl.tw1);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int sl = 0; sl < nrow; ++sl) {
+      const int row = sl == 0 ? ra : rb;
+      const bool self = (row == 0) || (2 * row == M2);
+      if (!self && sl == 1) break;  // a row pair is handled from its first row
+      for (int k1 = threadIdx.x; k1 < M1; k1 += kBlock) {
+        int prow, pk1;
+        if (!self) {
+          prow = 1;
+          pk1 = M1 - 1 - k1;
+        } else {
+          prow = sl;
+          pk1 = (row == 0) ? (k1 == 0 ? 0 : M1 - k1) : (M1 - 1 - k1);
+          if (k1 > pk1) continue;
+        }
+        const int k = row + M2 * k1;
+        const int ia = sl * M1 + k1, ib = prow * M1 + pk1;
+        const cx<T> Ra = lds[ia], Rb = lds[ib], Za = lds[off2 + ia], Zb = lds[off2 + ib];
+        if (k == 0) {
+          cx<T> R0, RM, Z0, ZM;
+          R0.x = Ra.x + Ra.y;
+          R0.y = T(0);
+          RM.x = Ra.x - Ra.y;
+          RM.y = T(0);
+          Z0.x = Za.x + Za.y;
+          Z0.y = T(0);
+          ZM.x = Za.x - Za.y;
+          ZM.y = T(0);
+          grad_bin<T>(P, ch, 0, 1.0, R0, Z0, acc);
+          grad_bin<T>(P, ch, M, 1.0, RM, ZM, acc);
+        } else if (ia == ib) {
+          grad_bin<T>(P, ch, k, 2.0, conjc(Ra), conjc(Za), acc);
+        } else {
+          cx<T> Rk, Rm, Zk, Zm;
+          untangle<T>(cl, P, Ra, Rb, k, Rk, Rm);
+          untangle<T>(cl, P, Za, Zb, k, Zk, Zm);
+          grad_bin<T>(P, ch, k, 2.0, Rk, Zk, acc);
+          grad_bin<T>(P, ch, M - k, 2.0, Rm, Zm, acc);
+        }
+      }
+    }
+    __syncthreads();  // the spectra are no longer needed: reuse the LDS for the reduction
+    double* red = reinterpret_cast<double*>(smem_raw);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double v = acc[q];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if ((threadIdx.x & 63) == 0) red[q * (kBlock / 64) + (threadIdx.x >> 6)] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      double t = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) t += red[threadIdx.x * (kBlock / 64) + w];
+      part[3 * (int64_t)it + threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// per-chunk sums of the (nitems x 3) partials in item order
+__global__ __launch_bounds__(kBlock) void k_grad_reduce(const int32_t* __restrict__ chunk_item_begin,
+                                                        const double* __restrict__ part, int nchunk,
+                                                        double* __restrict__ out) {
+  __shared__ double red[kBlock];
+  const int c = blockIdx.x;
+  for (int q = 0; q < 3; ++q) {
+    double s = 0.0;
+    for (int i = chunk_item_begin[c] + threadIdx.x; i < chunk_item_begin[c + 1]; i += kBlock) s += part[3 * i + q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[3 * c + q] = red[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_grad(const DevPlan& P, const ItemB* items, int nitems, const int32_t* chunk_item_begin,
+                       const void* Xr, const void* Xz, double* part, double* out, size_t lds, hipStream_t s) {
+  const size_t tot = lds > 3 * (kBlock / 64) * sizeof(double) ? lds : 3 * (kBlock / 64) * sizeof(double);
+  if (P.precision == 0)
+    hipLaunchKernelGGL(k_grad_b<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), tot, s, P, items, nitems,
+                       (const double2*)Xr, (const double2*)Xz, part);
+  else
+    hipLaunchKernelGGL(k_grad_b<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), tot, s, P, items, nitems,
+                       (const float2*)Xr, (const float2*)Xz, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_reduce, dim3(P.nchunk), dim3(kBlock), 0, s, chunk_item_begin, part, P.nchunk, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 // plan: tabulate the power-law part of every chunk's noise spectrum (FP64 form)
 
 __global__ void k_spectrum(DevPlan P, double* __restrict__ spec) {
@@ -1048,8 +1207,6 @@ __global__ void k_cg_chi2(const double* chi2_0, const double* xb, const double* 
 // ---------------------------------------------------------------------------------------------
 // launchers
 
-static inline int grid_for(int64_t n, int cap) { return (int)(n < cap ? (n > 0 ? n : 1) : cap); }
-constexpr int kGridCap = 1 << 16;
 
 hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m, int src,
                          void* work, size_t lds, hipStream_t s) {

@@ -134,6 +134,67 @@ static size_t psi_elem_size(int kind) {
   }
 }
 
+// noise spectrum table (FP64 form), hit counts, weight blocks P^T T^-1 P, their inverses and the
+// solvable mask; waits for the stream
+static mm_status plan_precompute(mm_plan_s* pl, hipStream_t s) {
+  DevPlan& P = pl->dp;
+  if (P.spec) {
+    hipError_t es = launch_spectrum(P, (double*)P.spec, s);
+    if (es != hipSuccess) return fail(MM_E_HIP, std::string("spectrum kernel launch: ") + hipGetErrorString(es));
+  }
+  hipError_t e = launch_bin(P, BSRC_PLAN, nullptr, EPI_PLAN, nullptr, (double*)pl->d_solvable, pl->d_winv,
+                            pl->d_hits, s);
+  if (e != hipSuccess) return fail(MM_E_HIP, std::string("plan kernel launch: ") + hipGetErrorString(e));
+  std::vector<uint8_t> sol(pl->npix);
+  if (hipMemcpyAsync(sol.data(), pl->d_solvable, pl->npix, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(MM_E_HIP, std::string("plan precompute failed: ") + hipGetErrorString(hipGetLastError()));
+  int64_t nsol = 0;
+  for (int64_t i = 0; i < pl->npix; ++i) nsol += sol[i];
+  pl->nsolvable = nsol;
+  return MM_OK;
+}
+
+static bool noise_ok(double sg, double fk, double al, const double* tau, int64_t c, std::string& why) {
+  if (!(sg > 0) || !(fk > 0) || !std::isfinite(al) || !std::isfinite(sg) || !std::isfinite(fk)) {
+    why = "chunk " + std::to_string(c) + ": invalid noise parameters";
+    return false;
+  }
+  if (tau && (!(tau[c] > 0) || tau[c] > sg * sg * (1 + 1e-12))) {
+    why = "chunk " + std::to_string(c) + ": tau must satisfy 0 < tau <= sigma^2";
+    return false;
+  }
+  return true;
+}
+
+mm_status plan_set_noise(mm_plan_s* pl, const double* sigma, const double* fknee, const double* alpha,
+                         const double* tau, hipStream_t s) {
+  if (!sigma || !fknee || !alpha) return fail(MM_E_ARG, "missing noise parameters");
+  std::string why;
+  for (int64_t c = 0; c < pl->nchunk; ++c)
+    if (!noise_ok(sigma[c], fknee[c], alpha[c], tau, c, why)) return fail(MM_E_ARG, why);
+  for (int64_t c = 0; c < pl->nchunk; ++c) {
+    pl->sigma[c] = sigma[c];
+    pl->fknee[c] = fknee[c];
+    pl->alpha[c] = alpha[c];
+    pl->tau[c] = tau ? tau[c] : sigma[c] * sigma[c];
+    DevChunk& ch = pl->chunks_host[c];
+    ch.sigma2 = sigma[c] * sigma[c];
+    ch.fknee = fknee[c];
+    ch.alpha = alpha[c];
+    ch.tau = pl->tau[c];
+    ch.inv_tau = 1.0 / ch.tau;
+    ch.nbar0 = ch.sigma2 - ch.tau;
+  }
+  if (hipMemcpyAsync(pl->d_chunks, pl->chunks_host.data(), pl->chunks_host.size() * sizeof(DevChunk),
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(MM_E_HIP, "chunk table upload failed");
+  mm_status st = plan_precompute(pl, s);
+  if (st != MM_OK) return st;
+  if (pl->nsolvable == 0) return fail(MM_E_SINGULAR, "no pixel has a solvable weight block");
+  return MM_OK;
+}
+
 mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   if (!desc || !out) return fail(MM_E_ARG, "null descriptor or output");
   const mm_plan_desc& D = *desc;
@@ -472,6 +533,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   double2* dtw64;
   float2* dtw32;
   if ((st = upload(pl, chunks, &dchunks, s)) != MM_OK) return st;
+  pl->chunks_host = chunks;
+  pl->d_chunks = dchunks;
   if ((st = upload(pl, classes, &dclasses, s)) != MM_OK) return st;
   if ((st = upload(pl, tw, &dtw64, s)) != MM_OK) return st;
   if ((st = upload(pl, tw32, &dtw32, s)) != MM_OK) return st;
@@ -526,8 +589,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   pl->d_hits = (int32_t*)p;
   if ((st = plan_alloc(pl, (size_t)ns * (f64 ? 8 : 4), &p)) != MM_OK) return st;
   pl->d_work = p;
-  if ((st = plan_alloc(pl, pl->itemsB.size() * sizeof(double), &p)) != MM_OK) return st;
-  pl->d_chi2_part = (double*)p;
+  if ((st = plan_alloc(pl, 3 * pl->itemsB.size() * sizeof(double), &p)) != MM_OK) return st;
+  pl->d_chi2_part = (double*)p;  // chi^2 partials (1 per row item) or gradient partials (3 per item)
   if ((st = plan_alloc(pl, 64 * sizeof(double), &p)) != MM_OK) return st;
   pl->d_scal = (double*)p;
   if ((st = plan_alloc(pl, 1024 * sizeof(double), &p)) != MM_OK) return st;
@@ -541,22 +604,9 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   if (f64) {
     if ((st = plan_alloc(pl, (size_t)spec_total * sizeof(double), &p)) != MM_OK) return st;
     P.spec = (double*)p;
-    hipError_t es = launch_spectrum(P, (double*)p, s);
-    if (es != hipSuccess) return fail(MM_E_HIP, std::string("spectrum kernel launch: ") + hipGetErrorString(es));
   }
-
-  // ---- precompute: hits, weight blocks and their inverses (deterministic binning)
-  hipError_t e = launch_bin(P, BSRC_PLAN, nullptr, EPI_PLAN, nullptr, (double*)pl->d_solvable, pl->d_winv,
-                            pl->d_hits, s);
-  if (e != hipSuccess) return fail(MM_E_HIP, std::string("plan kernel launch: ") + hipGetErrorString(e));
-  std::vector<uint8_t> sol(D.npix);
-  if (hipMemcpyAsync(sol.data(), pl->d_solvable, D.npix, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return fail(MM_E_HIP, std::string("plan precompute failed: ") + hipGetErrorString(hipGetLastError()));
-  int64_t nsol = 0;
-  for (int64_t i = 0; i < D.npix; ++i) nsol += sol[i];
-  pl->nsolvable = nsol;
-  if (nsol == 0) return fail(MM_E_SINGULAR, "no pixel has a solvable weight block");
+  if ((st = plan_precompute(pl, s)) != MM_OK) return st;
+  if (pl->nsolvable == 0) return fail(MM_E_SINGULAR, "no pixel has a solvable weight block");
   if (hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(MM_E_HIP, "stream creation failed");
   *out = guard.release();

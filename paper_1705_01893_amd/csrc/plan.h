@@ -28,6 +28,7 @@ struct mm_plan_s {
   std::vector<mm::ItemAC> itemsAC;
   std::vector<mm::ItemB> itemsB;
   std::vector<int32_t> chunk_item_begin;
+  std::vector<mm::DevChunk> chunks_host;  // kept for noise-parameter updates
   size_t lds_ac = 0, lds_b = 0;
   int64_t ntiles = 0, nsegs = 0;
   int32_t tile_w = 0, tile_h = 0;
@@ -47,6 +48,8 @@ struct mm_plan_s {
   double* d_scal = nullptr;
   double* d_part = nullptr;
   double* d_map[mm::kScratchMaps] = {};
+  void* d_work2 = nullptr;   // second TOD-sized buffer (noise-parameter gradient), on demand
+  mm::DevChunk* d_chunks = nullptr;
   double* d_hist = nullptr;  // grows on demand (CG rz history)
   size_t hist_cap = 0;
   int64_t nsolvable = 0;
@@ -67,4 +70,6 @@ namespace mm {
 mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out);
 void destroy_plan(mm_plan_s* pl);
 mm_status plan_alloc(mm_plan_s* pl, size_t bytes, void** out);
+mm_status plan_set_noise(mm_plan_s* pl, const double* sigma, const double* fknee, const double* alpha,
+                         const double* tau, hipStream_t s);
 }  // namespace mm

@@ -77,9 +77,13 @@ def lib() -> ctypes.CDLL:
     L.mm_chi2.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp]
     L.mm_apply.argtypes = [vp, i32, dbl, vp, vp, vp, vp]
     L.mm_lift_rhs.argtypes = [vp, vp, vp, vp]
+    L.mm_plan_set_noise.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                     ctypes.POINTER(dbl), vp]
+    L.mm_tod_apply.argtypes = [vp, i32, dbl, vp, vp, vp]
+    L.mm_noise_grad.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mm_set_timing.argtypes = [vp, i32]
     L.mm_get_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
-    for name in ("mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_hits", "mm_plan_solvable",
+    for name in ("mm_plan_set_noise", "mm_tod_apply", "mm_noise_grad", "mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_hits", "mm_plan_solvable",
                  "mm_plan_nsolvable", "mm_messenger_iter", "mm_solve", "mm_cooling_levels", "mm_cg_solve",
                  "mm_chi2", "mm_apply", "mm_lift_rhs"):
         getattr(L, name).restype = ctypes.c_int
@@ -277,6 +281,28 @@ def mm_apply(plan: Plan, which: int, out: torch.Tensor, x: Optional[torch.Tensor
 def mm_lift_rhs(plan: Plan, g: torch.Tensor, out: torch.Tensor, stream=None) -> None:
     _check(lib().mm_lift_rhs(plan.handle, _map_ptr(plan, g, "g"), _ptr(out, "out", plan.tod_dtype, plan.nsamp),
                              _stream(stream)), "mm_lift_rhs")
+
+
+def mm_plan_set_noise(plan: Plan, sigma, fknee, alpha, tau=None, stream=None) -> None:
+    n = plan.nchunk
+    arrs = [_host_f64(v, n, k) for k, v in (("sigma", sigma), ("fknee", fknee), ("alpha", alpha))]
+    t = _host_f64(tau, n, "tau") if tau is not None else None
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(lib().mm_plan_set_noise(plan.handle, *[a.ctypes.data_as(P) for a in arrs],
+                                   t.ctypes.data_as(P) if t is not None else None, _stream(stream)),
+           "mm_plan_set_noise")
+
+
+def mm_tod_apply(plan: Plan, which: int, x: torch.Tensor, out: torch.Tensor, lam: float = 1.0, stream=None) -> None:
+    _check(lib().mm_tod_apply(plan.handle, int(which), float(lam), _map_ptr(plan, x, "x"),
+                              _ptr(out, "out", plan.tod_dtype, plan.nsamp), _stream(stream)), "mm_tod_apply")
+
+
+def mm_noise_grad(plan: Plan, d: torch.Tensor, m: torch.Tensor, z: torch.Tensor, grad: torch.Tensor,
+                  stream=None) -> None:
+    _check(lib().mm_noise_grad(plan.handle, _ptr(d, "d", plan.tod_dtype, plan.nsamp), _map_ptr(plan, m, "m"),
+                               _map_ptr(plan, z, "z"), _ptr(grad, "grad", torch.float64, 3 * plan.nchunk),
+                               _stream(stream)), "mm_noise_grad")
 
 
 def mm_set_timing(plan: Plan, enable: bool) -> None:
