@@ -26,8 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
-PASS_NAMES = ["A: gather+residual+column FFT", "B: row FFT+filter+chi2+inverse rows",
-              "C: inverse column FFT", "D: binning+3x3 update"]
+PASS_NAMES = ["A: residual+column FFT", "B: row FFT+filter+chi2+inverse rows",
+              "C: inverse column FFT", "D: binning+3x3 update", "P: map projection"]
 KERNEL_SOURCES = ["paper_1705_01893_amd/csrc/kernels.hip", "paper_1705_01893_amd/csrc/fft.h",
                   "paper_1705_01893_amd/csrc/common.h"]
 
@@ -40,19 +40,29 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def pass_bytes(prob, tod_bytes: int, psi_bytes: int) -> list:
-    """Algorithmic HBM bytes of one launch of each pass (compulsory streams, each once)."""
+def pass_bytes(prob, tod_bytes: int, psi_bytes: int, projected: bool) -> list:
+    """Algorithmic HBM bytes of one launch of each pass (compulsory streams, each once).
+
+    Gather access: pass A reads d, pix and the on-map angles and gathers the map (counted
+    once, with the binning pass's map traffic).  Projected access: pass A reads d and the
+    P m buffer; the binning pass also writes P m of the new map for its on-map samples."""
     ns = prob.nsamp_total
     non = int((prob.pix >= 0).sum())
     ncomp, npix = prob.ncomp, prob.npix
     nw = 1 if ncomp == 1 else 6
-    a = ns * tod_bytes + ns * 4 + non * psi_bytes + ns * tod_bytes          # d, pix, psi (on map), X write
+    if projected:
+        a = 3 * ns * tod_bytes                                              # d, P m, X write
+    else:
+        a = ns * tod_bytes + ns * 4 + non * psi_bytes + ns * tod_bytes      # d, pix, psi (on map), X write
     b = 2 * ns * tod_bytes                                                  # X read + write
     if tod_bytes == 8:
         b += (ns // 2 + prob.nchunk) * 8                                    # tabulated noise power law
     c = 2 * ns * tod_bytes                                                  # X read + y write
     d = non * (tod_bytes + 2 + 2 + psi_bytes) + npix * 8 * (2 * ncomp + nw) + npix  # y, perm, lp, psi; maps
-    return [a, b, c, d]
+    if projected:
+        d += non * tod_bytes                                                # P m of the new map
+    p = non * (2 + 2 + psi_bytes + tod_bytes) + npix * 8 * ncomp            # perm, lp, psi, P m; map
+    return [a, b, c, d, p]
 
 
 def load_traffic(workload: str, khash: str):
@@ -93,6 +103,97 @@ def cpu_baseline(prob, seconds: float):
                        f"{t_setup:.1f} s not included), one host thread")}
 
 
+def _first_at_or_below(hist, target):
+    import numpy as np
+    idx = np.nonzero(np.asarray(hist) <= target)[0]
+    return int(idx[0]) if idx.size else None
+
+
+def time_to_chi2(mm, torch, prob, cfg, dev, plans, d_by_plan, deltas=(1e-5, 1e-4, 1e-3)):
+    """Wall time (HIP events around the replayed graph / the CG loop) to reach chi2_ref (1 + delta).
+
+    chi2_ref: the lower of a long FP64 messenger run (16 x 10 then 300 iterations at lambda = 1)
+    and FP64 PCG run to 2000 iterations.  Compared: the cooled messenger in FP64 and FP32-mixed
+    with the workload's schedule (plus a lambda = 1 tail), and FP64 PCG from zero.
+    """
+    import numpy as np
+    p64 = plans["fp64"]
+    d64 = d_by_plan["fp64"]
+    shape = (prob.ncomp, prob.npix)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    # reference chi^2
+    lv = mm.mm_cooling_levels(p64, 16, 0.0)
+    m = torch.zeros(shape, dtype=torch.float64, device=dev)
+    mm.mm_solve(p64, d64, lv + [1.0], [10] * 16 + [300], m)
+    chi_m = mm.mm_chi2(p64, d64, m)
+    mc = torch.zeros_like(m)
+    mm.mm_cg_solve(p64, mc, 2000, d=d64, rtol=1e-12)
+    chi_c = mm.mm_chi2(p64, d64, mc)
+    ref = min(chi_m, chi_c)
+    out = {"chi2_ref": ref, "chi2_ref_source": "messenger 16x10+300" if chi_m <= chi_c else "pcg 2000",
+           "nsamp": prob.nsamp_total, "targets": {}}
+    levels = mm.mm_cooling_levels(p64, cfg.nlevel, cfg.lambda_max or 0.0)
+    tail = 200
+    lams = levels + [1.0]
+    its = [cfg.iters_per_level] * cfg.nlevel + [tail]
+    nit = 1 + sum(its)
+    runs = {}
+    for form in ("fp64", "mixed"):
+        if form not in plans:
+            continue
+        pl, dd = plans[form], d_by_plan[form]
+        h = torch.zeros(nit + 1, dtype=torch.float64, device=dev)
+        mm.mm_solve(pl, dd, lams, its, m, chi2_hist=h)
+        torch.cuda.synchronize()
+        runs[form] = h.cpu().numpy()
+    maxcg = 500
+    hc = torch.zeros(maxcg + 1, dtype=torch.float64, device=dev)
+    mm.mm_cg_solve(p64, mc, maxcg, d=d64, chi2_hist=hc)
+    torch.cuda.synchronize()
+    cg_hist = hc.cpu().numpy()
+
+    def timed_solve(pl, dd, niters):
+        # schedule prefix of niters iterations (first the lambda = inf step)
+        rem = niters - 1
+        lam_p, it_p = [], []
+        for lam, k in zip(lams, its):
+            if rem <= 0:
+                break
+            take = min(k, rem)
+            lam_p.append(lam)
+            it_p.append(take)
+            rem -= take
+        mm.mm_solve(pl, dd, lam_p, it_p, m)  # capture
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        mm.mm_solve(pl, dd, lam_p, it_p, m)  # replay
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    for delta in deltas:
+        target = ref * (1 + delta)
+        row = {}
+        for form, hist in runs.items():
+            i = _first_at_or_below(hist, target)  # hist[i] = chi2 of the map after i iterations
+            row[f"messenger_{form}"] = ({"iterations": i, "ms": round(timed_solve(plans[form], d_by_plan[form], i), 3)}
+                                        if i is not None and i > 0 else {"iterations": None, "ms": None})
+        i = _first_at_or_below(cg_hist, target)
+        if i is not None and i > 0:
+            e0, e1 = ev(), ev()
+            e0.record()
+            mm.mm_cg_solve(p64, mc, i, d=d64)
+            e1.record()
+            torch.cuda.synchronize()
+            row["cg_fp64"] = {"iterations": i, "ms": round(e0.elapsed_time(e1), 3)}
+        else:
+            row["cg_fp64"] = {"iterations": None, "ms": None, "chi2_after_500": float(cg_hist[-1])}
+        out["targets"][f"{delta:g}"] = row
+    out["schedule"] = f"1 + {cfg.nlevel}x{cfg.iters_per_level} + {tail} at lambda=1"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +203,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mixed", action="store_true", help="run the FP32-mixed form (FP32 TOD and angles)")
+    ap.add_argument("--no-chi2", action="store_true", help="skip the time-to-chi2-target comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -121,9 +223,12 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     cfg = config_by_name(args.workload)
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+    log(f"generating {cfg.name}")
     t0 = time.perf_counter()
-    prob = make_problem(cfg)
+    prob = make_problem(cfg, workers=16)
     t_gen = time.perf_counter() - t0
+    log(f"generated {prob.nsamp_total} samples in {t_gen:.1f} s")
     mixed = args.mixed or cfg.tod_dtype == "f32"
     precision = mm.MM_MIXED if mixed else mm.MM_FP64
     tod_np = prob.d.astype(np.float32 if mixed else np.float64)
@@ -145,30 +250,35 @@ def main():
                       fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=pix,
                       psi=psi, psi_table=prob.psi_table, precision=precision)
     t_plan = time.perf_counter() - t0
+    log(f"plan built in {t_plan:.1f} s ({mm.mm_plan_workspace_bytes(plan) / 2**30:.2f} GiB of device tables)")
     ns = prob.nsamp_total
     m_a = torch.zeros((prob.ncomp, prob.npix), dtype=torch.float64, device=dev)
     m_b = torch.zeros_like(m_a)
+    access = mm.mm_plan_map_access(plan)
+    projected = access == mm.MM_MAP_PROJECTED
+    log(f"map access: {'projected P m buffer' if projected else 'per-sample gather'}")
     # start from the binned map, as the cooled solve does
     mm.mm_messenger_iter(plan, d, math.inf, m_a, m_a)
-    for _ in range(args.warmup):
-        mm.mm_messenger_iter(plan, d, 1.0, m_a, m_b)
+    if args.warmup > 0:
+        mm.mm_solve(plan, d, [1.0], [args.warmup], m_b, first_inf=False, m0=m_a)
         m_a, m_b = m_b, m_a
     torch.cuda.synchronize()
 
-    # timed region: K iterations, per-pass HIP events on the launch stream
+    # timed region: K chained iterations at lambda = 1 (the solver's own sequence: with
+    # projected access only the first one runs the projection pass), per-pass HIP events
+    # on the launch stream
     mm.mm_set_timing(plan, True)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
-    for _ in range(args.steps):
-        mm.mm_messenger_iter(plan, d, 1.0, m_a, m_b)
-        m_a, m_b = m_b, m_a
+    mm.mm_solve(plan, d, [1.0], [args.steps], m_b, first_inf=False, m0=m_a)
     ev1.record(stream)
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
     pass_ms, pass_n = mm.mm_get_timing(plan)
     mm.mm_set_timing(plan, False)
+    log(f"timed {args.steps} iterations: {total_ms / args.steps:.4f} ms each")
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -180,9 +290,9 @@ def main():
     value = ns / (ms_step * 1e-3)
 
     tod_bytes = 4 if mixed else 8
-    pb = pass_bytes(prob, tod_bytes, psi_bytes)
-    avg = [pass_ms[i] / max(pass_n[i], 1) for i in range(4)]
-    dom = int(np.argmax(avg))
+    pb = pass_bytes(prob, tod_bytes, psi_bytes, projected)
+    avg = [pass_ms[i] / max(pass_n[i], 1) for i in range(5)]
+    dom = int(np.argmax(avg[:4]))  # the per-iteration passes
     achieved = pb[dom] / (avg[dom] * 1e-3) / 1e9
     khash = kernel_hash()
     traffic = load_traffic(cfg.name + ("_mixed" if args.mixed else ""), khash)
@@ -190,16 +300,34 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (traffic["passes"][dom]["bytes_per_launch"] if traffic else None),
             "kernel": PASS_NAMES[dom]}
-    sweep_bytes = sum(pb)
+    sweep_bytes = sum(pb[:4]) + pb[4] * pass_n[4] / args.steps
     extra = {
-        "passes": [{"pass": PASS_NAMES[i], "avg_ms": round(avg[i], 5), "alg_bytes": pb[i],
-                    "GBs": round(pb[i] / (avg[i] * 1e-3) / 1e9, 1) if avg[i] > 0 else None}
-                   for i in range(4)],
+        "map_access": "projected" if projected else "gather",
+        "passes": [{"pass": PASS_NAMES[i], "avg_ms": round(avg[i], 5), "launches": int(pass_n[i]),
+                    "alg_bytes": pb[i], "GBs": round(pb[i] / (avg[i] * 1e-3) / 1e9, 1) if avg[i] > 0 else None}
+                   for i in range(5)],
         "sweep_roofline_frac": round(sweep_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "plan_s": round(t_plan, 2), "generate_s": round(t_gen, 2), "kernel_hash": khash,
     }
+    chi2_block = None
+    if not args.no_chi2:
+        plans = {("mixed" if mixed else "fp64"): plan}
+        d_by = {("mixed" if mixed else "fp64"): d}
+        if not mixed:
+            # the FP32-mixed form of the same workload: FP32 TOD and angles
+            d32 = d.float().contiguous()
+            psi32 = psi.float().contiguous() if (psi is not None and psi.dtype == torch.float64) else psi
+            plans["mixed"] = mm.mm_plan(ncomp=prob.ncomp, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off,
+                                        fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha,
+                                        pix=pix, psi=psi32, psi_table=prob.psi_table, precision=mm.MM_MIXED)
+            d_by["mixed"] = d32
+            if "fp64" in plans:
+                log("time to chi^2 target")
+                chi2_block = time_to_chi2(mm, torch, prob, cfg, dev, plans, d_by)
+            plans["mixed"].close()
     cpu = None
     if not args.no_cpu:
+        log("oracle on the host")
         cpu = cpu_baseline(prob, args.cpu_seconds)
     cfg_desc = {"workload": (f"{cfg.name}: {cfg.ndet} detectors x {ns // cfg.ndet if cfg.nsamp == cfg.nsamp_min else 'uneven'} "
                              f"samples ({ns} total), {cfg.nx}x{cfg.nx} map, ncomp={cfg.ncomp}, "
@@ -210,7 +338,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if mixed else "f64", "data": "synthetic", "config": cfg_desc,
-        "roofline": roof, "cpu_baseline": cpu, "detail": extra,
+        "roofline": roof, "cpu_baseline": cpu, "time_to_chi2": chi2_block, "detail": extra,
     }
     print(json.dumps(out))
     plan.close()

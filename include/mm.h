@@ -73,6 +73,7 @@ typedef enum {
 
 enum { MM_FP64 = 0, MM_MIXED = 1 };                              /* precision */
 enum { MM_PSI_NONE = 0, MM_PSI_F64 = 1, MM_PSI_F32 = 2, MM_PSI_U16 = 3 }; /* psi storage */
+enum { MM_MAP_AUTO = 0, MM_MAP_GATHER = 1, MM_MAP_PROJECTED = 2 };        /* map_access */
 
 /*
  * Problem description (Section 2 data model; Section 4.2 per-chunk tau).
@@ -92,6 +93,12 @@ enum { MM_PSI_NONE = 0, MM_PSI_F64 = 1, MM_PSI_F32 = 2, MM_PSI_U16 = 3 }; /* psi
  *               (double), MM_PSI_F32 (float) or MM_PSI_U16 (uint16 index into
  *               psi_table); NULL / MM_PSI_NONE when ncomp == 1.
  *  psi_table    host, psi_table_len floats (only for MM_PSI_U16).
+ *  map_access   how the time-domain sweeps read P m: MM_MAP_GATHER gathers the
+ *               map per sample; MM_MAP_PROJECTED keeps a plan-owned N_s-sample
+ *               buffer holding P m, written in pixel-tile order by the binning
+ *               pass (or a projection pass) and read in time order; MM_MAP_AUTO
+ *               picks PROJECTED when ncomp * npix * 8 bytes exceeds 4 MiB.  The
+ *               results agree to rounding (MM_MIXED rounds P m to float32 there).
  */
 typedef struct {
   int32_t ncomp;
@@ -108,7 +115,7 @@ typedef struct {
   const int32_t* pix;
   const void* psi;
   int32_t psi_kind;
-  int32_t reserved0;
+  int32_t map_access;
   const float* psi_table;
   int64_t psi_table_len;
 } mm_plan_desc;
@@ -142,6 +149,9 @@ mm_status mm_plan_hits(mm_plan_t plan, int32_t* hits_dev, mm_stream_t stream);
 mm_status mm_plan_solvable(mm_plan_t plan, uint8_t* mask_dev, mm_stream_t stream);
 /* Number of solvable pixels (host). */
 mm_status mm_plan_nsolvable(mm_plan_t plan, int64_t* count);
+/* The map access the plan uses (host): MM_MAP_GATHER or MM_MAP_PROJECTED
+ * (MM_MAP_AUTO resolved). */
+mm_status mm_plan_map_access(mm_plan_t plan, int32_t* access);
 
 /*
  * One messenger iteration, eqn. (mcompact) of Section 2.1:
@@ -157,7 +167,8 @@ mm_status mm_messenger_iter(mm_plan_t plan, const void* d, double lambda, const 
 
 /*
  * Full cooled messenger solve (Section 3.1).  Captures the whole schedule in
- * one HIP graph and launches it on `stream`.  m0: device start map or NULL for
+ * one HIP graph and launches it on `stream`; a call with the same buffers and
+ * the same schedule as the previous one replays that graph without capture.  m0: device start map or NULL for
  * zero.  m_out: device result.  chi2_hist_dev: device array of
  * (first_inf + sum(iters) + 1) doubles or NULL; entry i is chi^2(m_i) of the
  * map entering iteration i, the last entry chi^2 of the final map.
@@ -253,9 +264,12 @@ mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const do
  * by mm_messenger_iter, mm_chi2, mm_apply and mm_cg_solve (not mm_solve, which
  * replays a graph) is bracketed by HIP events recorded on the stream it runs
  * on.  mm_get_timing waits for the recorded events, returns the summed
- * milliseconds and launch counts per pass (index 0..3 = passes A, B, C, D:
- * gather + column transforms, row transforms + filter, inverse column
- * transforms, binning + map update) and clears the record.
+ * milliseconds and launch counts per pass (ms and launches: 5 entries each;
+ * index 0..4 = passes A, B, C, D and the map projection: gather + column
+ * transforms, row transforms + filter, inverse column transforms, binning +
+ * map update, P m in pixel-tile order for large maps) and clears the record.
+ * With timing enabled mm_solve runs its iterations on the stream directly
+ * instead of capturing a graph, so that they are timed too.
  */
 mm_status mm_set_timing(mm_plan_t plan, int32_t enable);
 mm_status mm_get_timing(mm_plan_t plan, double* ms, int64_t* launches);

@@ -56,9 +56,15 @@ hipError_t timed(mm_plan_s* pl, int pass, hipStream_t s, F&& launch) {
 // r = src(d, m) -> filtered y in the work buffer (passes A, B, C).  Returns with the
 // chi^2 partials in d_chi2_part when ops includes B_CHI2.
 mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, int ops, int gain, double lam,
-                       double chi2_lam, hipStream_t s) {
+                       double chi2_lam, hipStream_t s, bool pm_current = false) {
+  // large maps: P m comes from the projection buffer (projected here unless it already holds P m)
+  if (pl->pm_mode && (src == SRC_D_MINUS_PM || src == SRC_PM)) {
+    if (!pm_current) MM_TRY_HIP(timed(pl, 4, s, [&] { return launch_project(pl->dp, m, pl->d_pm, s); }));
+    src = (src == SRC_PM) ? SRC_PMBUF : SRC_D_MINUS_PMBUF;
+  }
   MM_TRY_HIP(timed(pl, 0, s, [&] {
-    return launch_pass_a(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), d, m, src, pl->d_work, pl->lds_ac, s);
+    return launch_pass_a(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), d, m, src, pl->d_work, pl->lds_ac, s,
+                         pl->d_pm);
   }));
   MM_TRY_HIP(timed(pl, 1, s, [&] {
     return launch_pass_b(pl->dp, pl->d_itemsB, (int)pl->itemsB.size(), pl->d_work, ops, gain, lam, chi2_lam,
@@ -73,26 +79,27 @@ mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, i
 
 // chi^2(m, lam) of d - P m into *total (device) and optionally per chunk (device)
 mm_status chi2_device(mm_plan_s* pl, const void* d, const double* m, double lam, double* total, double* per_chunk,
-                      hipStream_t s) {
-  MM_TRY(sweep_filter(pl, d, m, SRC_D_MINUS_PM, B_CHI2, GAIN_NINV, 1.0, lam, s));
+                      hipStream_t s, bool pm_current = false) {
+  MM_TRY(sweep_filter(pl, d, m, SRC_D_MINUS_PM, B_CHI2, GAIN_NINV, 1.0, lam, s, pm_current));
   MM_TRY_HIP(launch_chi2_reduce(pl->d_chunk_item_begin, pl->d_chi2_part, (int)pl->nchunk, per_chunk, total, s));
   return MM_OK;
 }
 
 // one messenger iteration m_out = m_in + W^-1 P^T G_lambda (d - P m_in); chi2(m_in) into chi2_dev if non-null
+// chained: the projection buffer already holds P m_in (it was written by the previous iteration)
 mm_status iterate(mm_plan_s* pl, const void* d, double lam, const double* m_in, double* m_out, double* chi2_dev,
-                  hipStream_t s) {
+                  hipStream_t s, bool chained = false) {
   if (std::isinf(lam)) {
-    if (chi2_dev) MM_TRY(chi2_device(pl, d, m_in, 1.0, chi2_dev, nullptr, s));
+    if (chi2_dev) MM_TRY(chi2_device(pl, d, m_in, 1.0, chi2_dev, nullptr, s, chained));
     MM_TRY_HIP(timed(pl, 3, s, [&] {
-      return launch_bin(pl->dp, BSRC_DATA_OVER_TAU, d, EPI_REPLACE, m_in, m_out, nullptr, nullptr, s);
+      return launch_bin(pl->dp, BSRC_DATA_OVER_TAU, d, EPI_REPLACE, m_in, m_out, nullptr, nullptr, s, pl->d_pm);
     }));
     return MM_OK;
   }
   const int ops = B_FILTER | (chi2_dev ? B_CHI2 : 0);
-  MM_TRY(sweep_filter(pl, d, m_in, SRC_D_MINUS_PM, ops, GAIN_MESSENGER, lam, 1.0, s));
+  MM_TRY(sweep_filter(pl, d, m_in, SRC_D_MINUS_PM, ops, GAIN_MESSENGER, lam, 1.0, s, chained));
   MM_TRY_HIP(timed(pl, 3, s, [&] {
-    return launch_bin(pl->dp, BSRC_WORK, pl->d_work, EPI_UPDATE, m_in, m_out, nullptr, nullptr, s);
+    return launch_bin(pl->dp, BSRC_WORK, pl->d_work, EPI_UPDATE, m_in, m_out, nullptr, nullptr, s, pl->d_pm);
   }));
   if (chi2_dev)
     MM_TRY_HIP(launch_chi2_reduce(pl->d_chunk_item_begin, pl->d_chi2_part, (int)pl->nchunk, nullptr, chi2_dev, s));
@@ -145,7 +152,7 @@ mm_status mm_set_timing(mm_plan_t plan, int32_t enable) {
 
 mm_status mm_get_timing(mm_plan_t plan, double* ms, int64_t* launches) {
   if (!plan || !ms || !launches) return fail(MM_E_ARG, "null argument");
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 5; ++i) {
     ms[i] = 0.0;
     launches[i] = 0;
   }
@@ -157,7 +164,7 @@ mm_status mm_get_timing(mm_plan_t plan, double* ms, int64_t* launches) {
       if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
       if (e != hipSuccess) st = fail(MM_E_HIP, std::string("timing events: ") + hipGetErrorString(e));
     }
-    if (r.pass >= 0 && r.pass < 4) {
+    if (r.pass >= 0 && r.pass < 5) {
       ms[r.pass] += t;
       launches[r.pass] += 1;
     }
@@ -182,6 +189,12 @@ mm_status mm_plan_destroy(mm_plan_t plan) {
 mm_status mm_plan_workspace_bytes(mm_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MM_E_ARG, "null argument");
   *bytes = plan->bytes;
+  return MM_OK;
+}
+
+mm_status mm_plan_map_access(mm_plan_t plan, int32_t* access) {
+  if (!plan || !access) return fail(MM_E_ARG, "null argument");
+  *access = plan->pm_mode ? MM_MAP_PROJECTED : MM_MAP_GATHER;
   return MM_OK;
 }
 
@@ -244,11 +257,8 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, cons
     if (sched->iters[l] < 0 || !valid_lambda(sched->lambda[l])) return fail(MM_E_ARG, "invalid schedule level");
     for (int i = 0; i < sched->iters[l]; ++i) lams.push_back(sched->lambda[l]);
   }
-  hipStream_t cs = plan->cap_stream;
   const int64_t n = mapn(plan);
-  MM_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  plan->capturing = true;
-  auto body = [&]() -> mm_status {
+  auto body = [&](hipStream_t cs) -> mm_status {
     // start map into m_out (fill kernel, no memset nodes in the graph)
     if (m0) {
       if (m0 != m_out) MM_TRY_HIP(launch_copy(m_out, m0, n, cs));
@@ -258,11 +268,27 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, cons
     // iterate in place: every pass reads the map before the binning epilogue rewrites it
     const size_t nit = lams.size();
     for (size_t i = 0; i < nit; ++i)
-      MM_TRY(iterate(plan, d, lams[i], m_out, m_out, chi2_hist_dev ? chi2_hist_dev + i : nullptr, cs));
-    if (chi2_hist_dev) MM_TRY(chi2_device(plan, d, m_out, 1.0, chi2_hist_dev + nit, nullptr, cs));
+      MM_TRY(iterate(plan, d, lams[i], m_out, m_out, chi2_hist_dev ? chi2_hist_dev + i : nullptr, cs, i > 0));
+    if (chi2_hist_dev) MM_TRY(chi2_device(plan, d, m_out, 1.0, chi2_hist_dev + nit, nullptr, cs, nit > 0));
     return MM_OK;
   };
-  mm_status st = body();
+  // per-pass timing records events between the passes: run on the caller's stream, uncaptured
+  if (plan->timing) return body(S(stream));
+  // replay the previous graph when the call is identical (same buffers, same schedule)
+  std::vector<double> key;
+  key.push_back((double)(uintptr_t)d);
+  key.push_back((double)(uintptr_t)m0);
+  key.push_back((double)(uintptr_t)m_out);
+  key.push_back((double)(uintptr_t)chi2_hist_dev);
+  key.insert(key.end(), lams.begin(), lams.end());
+  if (plan->solve_exec && key == plan->solve_key) {
+    MM_TRY_HIP(hipGraphLaunch(plan->solve_exec, S(stream)));
+    return MM_OK;
+  }
+  hipStream_t cs = plan->cap_stream;
+  MM_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  plan->capturing = true;
+  mm_status st = body(cs);
   plan->capturing = false;
   hipGraph_t graph = nullptr;
   hipError_t ee = hipStreamEndCapture(cs, &graph);
@@ -278,6 +304,8 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, cons
   ee = hipGraphLaunch(exec, S(stream));
   plan->graphs.push_back(exec);
   if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph launch: ") + hipGetErrorString(ee));
+  plan->solve_exec = exec;
+  plan->solve_key = key;
   return MM_OK;
 }
 
@@ -344,10 +372,13 @@ mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const do
     MM_TRY(plan_alloc(plan, (size_t)plan->ns * (plan->precision == MM_FP64 ? 8 : 4), &p));
     plan->d_work2 = p;
   }
-  MM_TRY_HIP(launch_pass_a(plan->dp, plan->d_itemsAC, (int)plan->itemsAC.size(), d, m, SRC_D_MINUS_PM,
-                           plan->d_work, plan->lds_ac, s));
-  MM_TRY_HIP(launch_pass_a(plan->dp, plan->d_itemsAC, (int)plan->itemsAC.size(), nullptr, z, SRC_PM, plan->d_work2,
-                           plan->lds_ac, s));
+  const bool pm = plan->pm_mode != 0;
+  if (pm) MM_TRY_HIP(launch_project(plan->dp, m, plan->d_pm, s));
+  MM_TRY_HIP(launch_pass_a(plan->dp, plan->d_itemsAC, (int)plan->itemsAC.size(), d, m,
+                           pm ? SRC_D_MINUS_PMBUF : SRC_D_MINUS_PM, plan->d_work, plan->lds_ac, s, plan->d_pm));
+  if (pm) MM_TRY_HIP(launch_project(plan->dp, z, plan->d_pm, s));
+  MM_TRY_HIP(launch_pass_a(plan->dp, plan->d_itemsAC, (int)plan->itemsAC.size(), nullptr, z,
+                           pm ? SRC_PMBUF : SRC_PM, plan->d_work2, plan->lds_ac, s, plan->d_pm));
   MM_TRY_HIP(launch_grad(plan->dp, plan->d_itemsB, (int)plan->itemsB.size(), plan->d_chunk_item_begin,
                          plan->d_work, plan->d_work2, plan->d_chi2_part, grad_dev, lds, s));
   return MM_OK;

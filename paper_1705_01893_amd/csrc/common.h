@@ -106,7 +106,9 @@ struct DevPlan {
 };
 
 // pass-A sources
-enum { SRC_D_MINUS_PM = 0, SRC_PM = 1, SRC_D = 2 };
+// pass-A sources: gather P m directly, or read a TOD-sized buffer holding P m written in
+// pixel-tile order (by the binning epilogue or the projection kernel)
+enum { SRC_D_MINUS_PM = 0, SRC_PM = 1, SRC_D = 2, SRC_D_MINUS_PMBUF = 3, SRC_PMBUF = 4 };
 // pass-B operations (bit set)
 enum {
   B_CHI2 = 1,         // accumulate chi^2(., chi2_lambda) partials
@@ -121,13 +123,14 @@ enum { EPI_WRITE_B = 0, EPI_UPDATE = 1, EPI_REPLACE = 2, EPI_PLAN = 3 };
 // kernel launchers (kernels.hip)
 
 hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m,
-                         int src, void* work, size_t lds_bytes, hipStream_t s);
+                         int src, void* work, size_t lds_bytes, hipStream_t s, const void* pmbuf = nullptr);
 hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void* work, int ops, int gain,
                          double lam, double chi2_lam, double* chi2_part, size_t lds_bytes, hipStream_t s);
 hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds_bytes,
                          hipStream_t s);
 hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
-                      double* w_out, int32_t* hits_out, hipStream_t s);
+                      double* w_out, int32_t* hits_out, hipStream_t s, void* pm_out = nullptr);
+hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipStream_t s);
 hipError_t launch_spectrum(const DevPlan& P, double* spec, hipStream_t s);
 hipError_t launch_grad(const DevPlan& P, const ItemB* items, int nitems, const int32_t* chunk_item_begin,
                        const void* Xr, const void* Xz, double* part, double* out, size_t lds, hipStream_t s);

@@ -117,7 +117,7 @@ __device__ __forceinline__ float powerlaw<float>(const DevChunk& ch, int k) {
 }
 
 struct BinCtx {
-  int gain;
+  int gain, chi2;
   double lam, inv_lam, chi2_lam;
 };
 
@@ -154,8 +154,9 @@ __device__ __forceinline__ void bin_factors(const DevPlan& P, const DevChunk& ch
     gg = N * (T)ch.inv_tau;
   }
   g = gg * (T)ch.inv_M;
-  const double Np = (double)N + (bc.chi2_lam - 1.0) * ch.tau;
-  cw = 1.0 / ((double)ch.n * Np);
+  // chi^2 weight 1 / (n N'_k), N' = N + (lambda - 1) tau, in the TOD precision, only when asked for
+  cw = 0.0;
+  if (bc.chi2) cw = (double)(T(1) / ((T)ch.n * (N + (T)((bc.chi2_lam - 1.0) * ch.tau))));
 }
 
 template <typename C>
@@ -234,7 +235,7 @@ __device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw,
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    const T* __restrict__ d, const double* __restrict__ m, int src,
-                                                   cx<T>* __restrict__ X) {
+                                                   cx<T>* __restrict__ X, const T* __restrict__ pmbuf) {
   constexpr int E = Ept<T>::v;
   constexpr int G = 2;  // elements whose loads are issued together
   extern __shared__ unsigned char smem_raw[];
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
 #pragma unroll 1
     for (int g = 0; g < E; g += G) {
       int2 pp[G];
-      cx<T> dd[G];
+      cx<T> dd[G], pb[G];
       uint4 raw[G];
       bool ok[G];
 #pragma unroll
@@ -264,9 +265,13 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
         pp[u] = make_int2(-1, -1);
         dd[u].x = T(0);
         dd[u].y = T(0);
+        pb[u].x = T(0);
+        pb[u].y = T(0);
         if (ok[u]) {
-          if (src != SRC_PM) dd[u] = ((const cx<T>*)d)[ci];
-          if (src != SRC_D) {
+          if (src != SRC_PM && src != SRC_PMBUF) dd[u] = ((const cx<T>*)d)[ci];
+          if (src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF) {
+            pb[u] = ((const cx<T>*)pmbuf)[ci];
+          } else if (src != SRC_D) {
             pp[u] = ((const int2*)P.pix)[ci];
             if (P.ncomp == 3) psi_pair_load<T>(P, ci, raw[u]);
           }
@@ -303,6 +308,11 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
           } else if (src == SRC_PM) {
             z.x = (T)pm[u][0];
             z.y = (T)pm[u][1];
+          } else if (src == SRC_PMBUF) {
+            z = pb[u];
+          } else if (src == SRC_D_MINUS_PMBUF) {
+            z.x = (T)((double)dd[u].x - (double)pb[u].x);
+            z.y = (T)((double)dd[u].y - (double)pb[u].y);
           } else {
             z.x = (T)((double)dd[u].x - pm[u][0]);
             z.y = (T)((double)dd[u].y - pm[u][1]);
@@ -654,11 +664,75 @@ __host__ __device__ constexpr size_t bin_lds_bytes(bool plan) {
          kWaves * NV * sizeof(double) + kWaves * sizeof(int) + kMaxSegs * (sizeof(int64_t) + 2 * sizeof(int));
 }
 
+// P m for every on-map sample of one tile, written to a TOD-sized buffer in time order.
+// mt: the tile's map values in LDS, [local pixel][NC].  For each sub-batch the values are formed
+// in pixel-sorted order, scattered to their staging positions in LDS and written out along the
+// sub-batch's time-contiguous segments (coalesced within each segment).
+template <typename T, int NC>
+__device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt, double* stage, int64_t* sstart,
+                             int* spos, T* __restrict__ pm_out) {
+  constexpr int SPW = kSubBatch / kBinBlock;
+  for (int sb = tl.sb_begin; sb < tl.sb_end; ++sb) {
+    const SubBatch S = P.sbs[sb];
+    const int nseg = S.seg_end - S.seg_begin;
+    const int cnt = S.count;
+    for (int k = threadIdx.x; k < cnt; k += kBinBlock) {
+      const int64_t gk = S.sorted_begin + k;
+      const int l = P.lp[gk];
+      double v = mt[l * NC];
+      if (NC == 3) {
+        double c, sn;
+        weights_from_raw<T>(P, psi_sorted_raw<T>(P, gk), c, sn);
+        v += c * mt[l * 3 + 1] + sn * mt[l * 3 + 2];
+      }
+      stage[P.perm[gk]] = v;
+    }
+    for (int i = threadIdx.x; i < nseg; i += kBinBlock) {
+      const Segment g = P.segs[S.seg_begin + i];
+      sstart[i] = g.start;
+      spos[i] = g.pos;
+    }
+    __syncthreads();
+    int lo = 0;
+#pragma unroll
+    for (int u = 0; u < SPW; ++u) {
+      const int q = threadIdx.x + u * kBinBlock;
+      if (q < cnt) {
+        lo = seg_find(spos, lo, nseg, q);
+        pm_out[sstart[lo] + (q - spos[lo])] = (T)stage[q];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* __restrict__ m,
+                                                       T* __restrict__ pm_out) {
+  extern __shared__ double smem_d[];
+  double* stage = smem_d;
+  double* mt = stage + kSubBatch;
+  double* cv = mt + kMaxTilePix * NC;
+  int64_t* sstart = reinterpret_cast<int64_t*>(cv + kWaves * NC);
+  int* spos = reinterpret_cast<int*>(sstart + kMaxSegs);
+  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) {
+    const Tile tl = P.tiles[t];
+    const int tp = tl.tw * tl.th;
+    for (int l = threadIdx.x; l < tp; l += kBinBlock) {
+      const int64_t p = (int64_t)(tl.y0 + l / tl.tw) * P.nxm + tl.x0 + (l % tl.tw);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) mt[l * NC + q] = m[q * P.npix + p];
+    }
+    __syncthreads();
+    tile_project<T, NC>(P, tl, mt, stage, sstart, spos, pm_out);
+  }
+}
+
 template <typename T, int NV>
 __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T* __restrict__ src, int epi,
                                                    const double* __restrict__ m_in, double* __restrict__ out,
                                                    double* __restrict__ w_out, int32_t* __restrict__ hits_out,
-                                                   uint8_t* __restrict__ sol_out) {
+                                                   uint8_t* __restrict__ sol_out, T* __restrict__ pm_out) {
   constexpr bool PLAN = (NV == 2 || NV == 7);
   constexpr bool POL = (NV == 3 || NV == 7);
   constexpr int SPW = kSubBatch / kBinBlock;  // staged samples per thread
@@ -896,10 +970,13 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
           double r = 0.0;
           if (ok) r = (epi == EPI_UPDATE) ? m_in[q * np + p] + u[q] : u[q];
           out[q * np + p] = r;
+          if (!PLAN && pm_out) acc[l * NV + q] = r;  // the tile's new map values, for P m below
         }
       }
     }
     __syncthreads();
+    if (!PLAN && pm_out && (epi == EPI_UPDATE || epi == EPI_REPLACE))
+      tile_project<T, (NV == 3 ? 3 : 1)>(P, tl, acc, stage, sstart, spos, pm_out);
   }
 }
 
@@ -1209,14 +1286,14 @@ __global__ void k_cg_chi2(const double* chi2_0, const double* xb, const double* 
 
 
 hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m, int src,
-                         void* work, size_t lds, hipStream_t s) {
+                         void* work, size_t lds, hipStream_t s, const void* pmbuf) {
   if (nitems <= 0) return hipSuccess;
   if (P.precision == 0)
     hipLaunchKernelGGL(k_pass_a<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
-                       (const double*)d, m, src, (double2*)work);
+                       (const double*)d, m, src, (double2*)work, (const double*)pmbuf);
   else
     hipLaunchKernelGGL(k_pass_a<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
-                       (const float*)d, m, src, (float2*)work);
+                       (const float*)d, m, src, (float2*)work, (const float*)pmbuf);
   return hipGetLastError();
 }
 
@@ -1225,6 +1302,7 @@ hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void*
   if (nitems <= 0) return hipSuccess;
   BinCtx bc;
   bc.gain = gain;
+  bc.chi2 = (ops & B_CHI2) ? 1 : 0;
   bc.lam = lam;
   bc.inv_lam = 1.0 / lam;
   bc.chi2_lam = chi2_lam;
@@ -1252,29 +1330,51 @@ hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void
 
 template <typename T, int NV>
 static hipError_t launch_bin_t(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
-                               double* w_out, int32_t* hits_out, uint8_t* sol_out, hipStream_t s) {
+                               double* w_out, int32_t* hits_out, uint8_t* sol_out, hipStream_t s, void* pm_out) {
   const size_t lds = bin_lds_bytes<NV>(NV == 2 || NV == 7);
   hipLaunchKernelGGL((k_bin<T, NV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, bsrc,
-                     (const T*)src, epi, m_in, out, w_out, hits_out, sol_out);
+                     (const T*)src, epi, m_in, out, w_out, hits_out, sol_out, (T*)pm_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipStream_t s) {
+  const bool f64 = P.precision == 0;
+  if (P.ncomp == 1) {
+    const size_t lds = bin_lds_bytes<1>(false);
+    if (f64)
+      hipLaunchKernelGGL((k_project<double, 1>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
+                         (double*)pm_out);
+    else
+      hipLaunchKernelGGL((k_project<float, 1>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
+                         (float*)pm_out);
+  } else {
+    const size_t lds = bin_lds_bytes<3>(false);
+    if (f64)
+      hipLaunchKernelGGL((k_project<double, 3>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
+                         (double*)pm_out);
+    else
+      hipLaunchKernelGGL((k_project<float, 3>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
+                         (float*)pm_out);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
-                      double* w_out, int32_t* hits_out, hipStream_t s) {
+                      double* w_out, int32_t* hits_out, hipStream_t s, void* pm_out) {
   uint8_t* sol_out = reinterpret_cast<uint8_t*>(out);  // plan mode: the solvable mask
   const bool f64 = P.precision == 0;
   if (epi == EPI_PLAN) {
     if (P.ncomp == 1)
-      return f64 ? launch_bin_t<double, 2>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s)
-                 : launch_bin_t<float, 2>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s);
-    return f64 ? launch_bin_t<double, 7>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s)
-               : launch_bin_t<float, 7>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s);
+      return f64 ? launch_bin_t<double, 2>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s, nullptr)
+                 : launch_bin_t<float, 2>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s, nullptr);
+    return f64 ? launch_bin_t<double, 7>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s, nullptr)
+               : launch_bin_t<float, 7>(P, bsrc, src, epi, m_in, nullptr, w_out, hits_out, sol_out, s, nullptr);
   }
   if (P.ncomp == 1)
-    return f64 ? launch_bin_t<double, 1>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s)
-               : launch_bin_t<float, 1>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s);
-  return f64 ? launch_bin_t<double, 3>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s)
-             : launch_bin_t<float, 3>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s);
+    return f64 ? launch_bin_t<double, 1>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s, pm_out)
+               : launch_bin_t<float, 1>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s, pm_out);
+  return f64 ? launch_bin_t<double, 3>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s, pm_out)
+             : launch_bin_t<float, 3>(P, bsrc, src, epi, m_in, out, w_out, hits_out, nullptr, s, pm_out);
 }
 
 hipError_t launch_chi2_reduce(const int32_t* chunk_item_begin, const double* part, int nchunk, double* per_chunk,

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -211,6 +212,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     if (D.psi_kind == MM_PSI_U16 && (!D.psi_table || D.psi_table_len <= 0 || D.psi_table_len > 65536))
       return fail(MM_E_ARG, "uint16 angle indices need a host angle table of 1..65536 entries");
   }
+  if (D.map_access != MM_MAP_AUTO && D.map_access != MM_MAP_GATHER && D.map_access != MM_MAP_PROJECTED)
+    return fail(MM_E_ARG, "unknown map_access");
   if (D.chunk_off[0] != 0) return fail(MM_E_ARG, "chunk_off[0] must be 0");
   for (int64_t c = 0; c < D.nchunk; ++c) {
     const int64_t n = D.chunk_off[c + 1] - D.chunk_off[c];
@@ -604,6 +607,16 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   if (f64) {
     if ((st = plan_alloc(pl, (size_t)spec_total * sizeof(double), &p)) != MM_OK) return st;
     P.spec = (double*)p;
+  }
+  // maps larger than the L2 of one XCD (4 MB) are gathered badly by the strided column pass:
+  // then P m is produced in pixel-tile order instead
+  pl->pm_mode = D.map_access == MM_MAP_PROJECTED ||
+                (D.map_access == MM_MAP_AUTO && mapn * (int64_t)sizeof(double) > ((int64_t)4 << 20));
+  if (pl->pm_mode) {
+    if ((st = plan_alloc(pl, (size_t)ns * (f64 ? 8 : 4), &p)) != MM_OK) return st;
+    pl->d_pm = p;
+    if (hipMemsetAsync(p, 0, (size_t)ns * (f64 ? 8 : 4), s) != hipSuccess)  // off-map samples: P m = 0
+      return fail(MM_E_HIP, "clearing the projection buffer failed");
   }
   if ((st = plan_precompute(pl, s)) != MM_OK) return st;
   if (pl->nsolvable == 0) return fail(MM_E_SINGULAR, "no pixel has a solvable weight block");

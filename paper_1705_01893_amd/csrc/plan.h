@@ -49,12 +49,18 @@ struct mm_plan_s {
   double* d_part = nullptr;
   double* d_map[mm::kScratchMaps] = {};
   void* d_work2 = nullptr;   // second TOD-sized buffer (noise-parameter gradient), on demand
+  // P m in time order, written in pixel-tile order (large maps: the column pass reads it instead
+  // of gathering the map)
+  int pm_mode = 0;
+  void* d_pm = nullptr;
   mm::DevChunk* d_chunks = nullptr;
   double* d_hist = nullptr;  // grows on demand (CG rz history)
   size_t hist_cap = 0;
   int64_t nsolvable = 0;
   hipStream_t cap_stream = nullptr;
   std::vector<hipGraphExec_t> graphs;
+  std::vector<double> solve_key;        // arguments of the last captured solve (replayed when equal)
+  hipGraphExec_t solve_exec = nullptr;
   // per-pass timing (measurement only)
   bool timing = false;
   bool capturing = false;

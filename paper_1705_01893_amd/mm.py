@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libmm.so")
 
 MM_FP64, MM_MIXED = 0, 1
 MM_PSI_NONE, MM_PSI_F64, MM_PSI_F32, MM_PSI_U16 = 0, 1, 2, 3
+MM_MAP_AUTO, MM_MAP_GATHER, MM_MAP_PROJECTED = 0, 1, 2
 MM_OK, MM_E_ARG, MM_E_LEN, MM_E_NOMEM, MM_E_HIP, MM_E_SINGULAR, MM_E_NONFINITE = range(7)
 _STATUS_NAMES = {0: "MM_OK", 1: "MM_E_ARG", 2: "MM_E_LEN", 3: "MM_E_NOMEM", 4: "MM_E_HIP",
                  5: "MM_E_SINGULAR", 6: "MM_E_NONFINITE"}
@@ -42,7 +43,7 @@ class _Desc(ctypes.Structure):
         ("fknee", ctypes.POINTER(ctypes.c_double)), ("alpha", ctypes.POINTER(ctypes.c_double)),
         ("tau", ctypes.POINTER(ctypes.c_double)),
         ("pix", ctypes.c_void_p), ("psi", ctypes.c_void_p),
-        ("psi_kind", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("psi_kind", ctypes.c_int32), ("map_access", ctypes.c_int32),
         ("psi_table", ctypes.POINTER(ctypes.c_float)), ("psi_table_len", ctypes.c_int64),
     ]
 
@@ -70,6 +71,7 @@ def lib() -> ctypes.CDLL:
     L.mm_plan_hits.argtypes = [vp, vp, vp]
     L.mm_plan_solvable.argtypes = [vp, vp, vp]
     L.mm_plan_nsolvable.argtypes = [vp, ctypes.POINTER(i64)]
+    L.mm_plan_map_access.argtypes = [vp, ctypes.POINTER(i32)]
     L.mm_messenger_iter.argtypes = [vp, vp, dbl, vp, vp, vp, vp]
     L.mm_solve.argtypes = [vp, vp, ctypes.POINTER(_Sched), vp, vp, vp, vp]
     L.mm_cooling_levels.argtypes = [vp, i32, dbl, ctypes.POINTER(dbl)]
@@ -84,7 +86,7 @@ def lib() -> ctypes.CDLL:
     L.mm_set_timing.argtypes = [vp, i32]
     L.mm_get_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for name in ("mm_plan_set_noise", "mm_tod_apply", "mm_noise_grad", "mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_hits", "mm_plan_solvable",
-                 "mm_plan_nsolvable", "mm_messenger_iter", "mm_solve", "mm_cooling_levels", "mm_cg_solve",
+                 "mm_plan_nsolvable", "mm_plan_map_access", "mm_messenger_iter", "mm_solve", "mm_cooling_levels", "mm_cg_solve",
                  "mm_chi2", "mm_apply", "mm_lift_rhs"):
         getattr(L, name).restype = ctypes.c_int
     L.mm_status_str.argtypes = [ctypes.c_int]
@@ -158,7 +160,7 @@ class Plan:
 
 def mm_plan(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, pix: torch.Tensor,
             psi: Optional[torch.Tensor] = None, psi_table=None, tau=None, nx: int = 0,
-            precision: int = MM_FP64, stream=None) -> Plan:
+            precision: int = MM_FP64, map_access: int = MM_MAP_AUTO, stream=None) -> Plan:
     """Build a plan (mm_plan).  pix (int32) and psi (float64 / float32 / uint16) are device tensors."""
     off = np.ascontiguousarray(np.asarray(chunk_off, dtype=np.int64).reshape(-1))
     nchunk = off.size - 1
@@ -170,6 +172,7 @@ def mm_plan(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, p
     arrs["off"] = off
     d = _Desc()
     d.ncomp, d.precision, d.npix, d.nx, d.nchunk = ncomp, precision, npix, nx, nchunk
+    d.map_access = map_access
     d.chunk_off = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     for k in ("fsample", "sigma", "fknee", "alpha"):
         setattr(d, k, arrs[k].ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
@@ -211,6 +214,12 @@ def mm_plan_solvable(plan: Plan, mask: torch.Tensor, stream=None) -> None:
 def mm_plan_nsolvable(plan: Plan) -> int:
     v = ctypes.c_int64()
     _check(lib().mm_plan_nsolvable(plan.handle, ctypes.byref(v)), "mm_plan_nsolvable")
+    return v.value
+
+
+def mm_plan_map_access(plan: Plan) -> int:
+    v = ctypes.c_int32()
+    _check(lib().mm_plan_map_access(plan.handle, ctypes.byref(v)), "mm_plan_map_access")
     return v.value
 
 
@@ -310,9 +319,9 @@ def mm_set_timing(plan: Plan, enable: bool) -> None:
 
 
 def mm_get_timing(plan: Plan):
-    """(milliseconds[4], launches[4]) per pass A, B, C, D since the last call."""
-    ms = (ctypes.c_double * 4)()
-    n = (ctypes.c_int64 * 4)()
+    """(milliseconds[5], launches[5]) per pass A, B, C, D, projection since the last call."""
+    ms = (ctypes.c_double * 5)()
+    n = (ctypes.c_int64 * 5)()
     _check(lib().mm_get_timing(plan.handle, ms, n), "mm_get_timing")
     return list(ms), list(n)
 

@@ -62,6 +62,7 @@ def _desc(**over):
     d.pix = over.pop("pix", 0x1000)
     d.psi = over.pop("psi", None)
     d.psi_kind = over.pop("psi_kind", 0)
+    d.map_access = over.pop("map_access", 0)
     assert not over
     return d, arr
 
@@ -69,6 +70,7 @@ def _desc(**over):
 @pytest.mark.parametrize("case, status", [
     (dict(ncomp=2), mm.MM_E_ARG),
     (dict(precision=7), mm.MM_E_ARG),
+    (dict(map_access=3), mm.MM_E_ARG),
     (dict(npix=0), mm.MM_E_ARG),
     (dict(npix=15, nx=4), mm.MM_E_ARG),
     (dict(pix=None), mm.MM_E_ARG),
