@@ -7,7 +7,8 @@
 
 namespace mm {
 
-constexpr int kBlock = 512;        // threads per workgroup of the transform passes
+constexpr int kBlock = 512;        // threads per workgroup of the column passes (A, C) and reductions
+constexpr int kBlockB = 256;       // threads per workgroup of the row pass (B) and the gradient row pass
 constexpr int kBinBlock = 256;     // threads per workgroup of the binning pass
 constexpr int kWaves = kBinBlock / 64;
 constexpr int kMaxStages = 24;     // radix stages of one sub-transform

@@ -171,12 +171,12 @@ __device__ __forceinline__ void twiddle_powers(cx<T>* v, cx<T> w1) {
   for (int m = 1; m < R; ++m) v[m] = cmul(v[m], w[m]);
 }
 
-// One Stockham stage.  p = product of the radices already applied.  Butterfly f of the
-// stage belongs to sequence b and position k: with BFAST, b = f mod nb (nb a power of
-// two, lg_nb = log2 nb), otherwise b = f / (L/R).
+// One Stockham stage run by a workgroup of NT threads.  p = product of the radices already
+// applied.  Butterfly f of the stage belongs to sequence b and position k: with BFAST,
+// b = f mod nb (nb a power of two, lg_nb = log2 nb), otherwise b = f / (L/R).
 // Kept out of line: inlining all five radix variants into the stage loop makes the register
 // allocator budget for their union and halves the occupancy of every pass.
-template <typename T, int R, bool INV, bool BFAST>
+template <typename T, int R, bool INV, bool BFAST, int NT>
 __device__ __attribute__((noinline)) void stockham_stage(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, int p,
                                                const cx<T>* __restrict__ tw) {
   constexpr int K = (Ept<T>::v + R - 1) / R;  // butterflies per thread
@@ -189,7 +189,7 @@ __device__ __attribute__((noinline)) void stockham_stage(cx<T>* lds, int L, int 
   int bk[K][2];
 #pragma unroll
   for (int u = 0; u < K; ++u) {
-    const int f = threadIdx.x + u * kBlock;
+    const int f = threadIdx.x + u * NT;
     int b = 0, k = 0;
     if (BFAST) {
       b = f & (nb - 1);
@@ -208,7 +208,7 @@ __device__ __attribute__((noinline)) void stockham_stage(cx<T>* lds, int L, int 
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < K; ++u) {
-    const int f = threadIdx.x + u * kBlock;
+    const int f = threadIdx.x + u * NT;
     if (f < total) {
       const int b = bk[u][0], k = bk[u][1];
       const int kq = (int)qdiv((uint32_t)k, (uint32_t)p, inv_p);
@@ -229,18 +229,18 @@ __device__ __attribute__((noinline)) void stockham_stage(cx<T>* lds, int L, int 
 
 // Full length-L transform of nb sequences (caller synchronises before the first stage).
 // tw: omega_L^q = exp(-2 pi i q / L), q < L.
-template <typename T, bool INV, bool BFAST>
+template <typename T, bool INV, bool BFAST, int NT>
 __device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, const int8_t* rad, int ns,
                         const cx<T>* __restrict__ tw) {
   int p = 1;
   for (int s = 0; s < ns; ++s) {
     const int R = rad[s];
     switch (R) {
-      case 8: stockham_stage<T, 8, INV, BFAST>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
-      case 4: stockham_stage<T, 4, INV, BFAST>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
-      case 2: stockham_stage<T, 2, INV, BFAST>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
-      case 3: stockham_stage<T, 3, INV, BFAST>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
-      case 5: stockham_stage<T, 5, INV, BFAST>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
+      case 8: stockham_stage<T, 8, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
+      case 4: stockham_stage<T, 4, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
+      case 2: stockham_stage<T, 2, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
+      case 3: stockham_stage<T, 3, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
+      case 5: stockham_stage<T, 5, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
       default: break;
     }
     p *= R;

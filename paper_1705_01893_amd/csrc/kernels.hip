@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
       }
     }
     __syncthreads();
-    lds_fft<T, false, true>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    lds_fft<T, false, true, kBlock>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
     cx<T>* Xc = X + ch.off / 2;
 #pragma unroll 2
     for (int u = 0; u < E; ++u) {
@@ -417,7 +417,7 @@ __device__ __forceinline__ void b_self(cx<T>* lds, const DevPlan& P, const DevCh
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pass_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
+__global__ __launch_bounds__(kBlockB) void k_pass_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
                                                    cx<T>* __restrict__ X, int ops, BinCtx bc,
                                                    double* __restrict__ chi2_part, int red_off) {
   constexpr int E = Ept<T>::v;
@@ -435,10 +435,10 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevPlan P, const ItemB* __res
     cx<T>* Xc = X + ch.off / 2;
     cx<T>* Xa = Xc + (int64_t)ra * M1;
     cx<T>* Xb = Xc + (int64_t)rb * M1;
-    // 2 * M1 < kBlock * E, so each row takes at most E/2 elements per thread
+    // 2 * M1 < kBlockB * E, so each row takes at most E/2 elements per thread
 #pragma unroll
     for (int u = 0; u < E / 2; ++u) {
-      const int e = threadIdx.x + u * kBlock;
+      const int e = threadIdx.x + u * kBlockB;
       if (e < M1) {
         lds[e] = Xa[e];
         if (nrow == 2) lds[M1 + e] = Xb[e];
@@ -446,11 +446,11 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevPlan P, const ItemB* __res
     }
     __syncthreads();
     const cx<T>* tw1 = twtab<T>(P) + cl.tw1;
-    lds_fft<T, false, false>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
+    lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
     double chi = 0.0;
     const bool self_a = (ra == 0) || (2 * ra == M2);
     if (!self_a) {
-      for (int k1 = threadIdx.x; k1 < M1; k1 += kBlock) {
+      for (int k1 = threadIdx.x; k1 < M1; k1 += kBlockB) {
         const int pk1 = M1 - 1 - k1;
         const int k = ra + M2 * k1;
         b_pair<T>(lds, P, ch, cl, bc, ops, k, k1, M1 + pk1, chi);
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevPlan P, const ItemB* __res
     } else {
       for (int sl = 0; sl < nrow; ++sl) {
         const int row = sl == 0 ? ra : rb;
-        for (int k1 = threadIdx.x; k1 < M1; k1 += kBlock) {
+        for (int k1 = threadIdx.x; k1 < M1; k1 += kBlockB) {
           const int pk1 = (row == 0) ? (k1 == 0 ? 0 : M1 - k1) : (M1 - 1 - k1);
           if (k1 > pk1) continue;
           const int k = row + M2 * k1;
@@ -479,16 +479,16 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevPlan P, const ItemB* __res
       __syncthreads();
       if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+        for (int w = 0; w < kBlockB / 64; ++w) t += red[w];
         chi2_part[it] = t;
       }
     }
     if (ops & B_FILTER) {
       __syncthreads();
-      lds_fft<T, true, false>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
+      lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
 #pragma unroll
       for (int u = 0; u < E / 2; ++u) {
-        const int j1 = threadIdx.x + u * kBlock;
+        const int j1 = threadIdx.x + u * kBlockB;
         if (j1 < M1) {
           Xa[j1] = cmul(lds[j1], conjc(omega2M<T>(P, cl, 2 * j1 * ra)));
           if (nrow == 2) Xb[j1] = cmul(lds[M1 + j1], conjc(omega2M<T>(P, cl, 2 * j1 * rb)));
@@ -534,7 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
       }
     }
     __syncthreads();
-    lds_fft<T, true, true>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    lds_fft<T, true, true, kBlock>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       const int e = threadIdx.x + u * kBlock;
@@ -593,17 +593,40 @@ __device__ __forceinline__ void bin_flush(double* acc, double* cv, int* clp, int
   }
 }
 
-// largest i in [lo, n) with pos[i] <= q (pos[0] = 0 <= q)
-__device__ __forceinline__ int seg_find(const int* pos, int lo, int n, int q) {
-  int hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (pos[mid] <= q)
-      lo = mid;
-    else
-      hi = mid - 1;
+// Staging position -> segment of one sub-batch.  Positions [0, count) are split into
+// time-contiguous segments; segment i starts at position spos[i] (spos[0] = 0).  A bitmap in LDS
+// marks the starts (bit q & 63 of word q >> 6).  Lane l of each wave keeps word l and the index of
+// the segment holding position 64 l (a prefix count of the starts), so a lookup costs three lane
+// reads and a popcount instead of a search.
+struct SegIndex {
+  uint32_t lo, hi;
+  int base;
+};
+
+__device__ __forceinline__ SegIndex seg_index(const unsigned long long* smask) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long w = smask[lane];
+  const int n = __popcll(w);
+  int s = n;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(s, d);
+    if (lane >= d) s += t;
   }
-  return lo;
+  SegIndex r;
+  r.lo = (uint32_t)w;
+  r.hi = (uint32_t)(w >> 32);
+  r.base = s - n + (int)(w & 1ull) - 1;
+  return r;
+}
+
+__device__ __forceinline__ int seg_lookup(const SegIndex& si, int q) {
+  const int b = q >> 6, l = q & 63;
+  const uint32_t lo = (uint32_t)__shfl((int)si.lo, b), hi = (uint32_t)__shfl((int)si.hi, b);
+  const int base = __shfl(si.base, b);
+  const unsigned long long w = ((unsigned long long)hi << 32) | lo;
+  const unsigned long long upto = (2ull << l) - 1ull;  // bits 0..l (all 64 for l = 63)
+  return base + __popcll(w & upto & ~1ull);
 }
 
 template <typename T>
@@ -657,11 +680,51 @@ __device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw,
   s = (double)ss;
 }
 
-// LDS layout of k_bin (bytes): [stage | acc | carries | segment table]
+// LDS layout of k_bin and k_project:
+// [stage | acc | carries | start bitmaps (2 x 64 words) | sstart | schunk | spos | carry pixels]
 template <int NV>
 __host__ __device__ constexpr size_t bin_lds_bytes(bool plan) {
   return (plan ? 0 : kSubBatch * sizeof(double)) + kMaxTilePix * NV * sizeof(double) +
-         kWaves * NV * sizeof(double) + kWaves * sizeof(int) + kMaxSegs * (sizeof(int64_t) + 2 * sizeof(int));
+         kWaves * NV * sizeof(double) + 2 * (kSubBatch / 64) * sizeof(unsigned long long) +
+         kMaxSegs * (sizeof(int64_t) + sizeof(int) + sizeof(uint16_t)) + kWaves * sizeof(int);
+}
+
+struct BinLds {
+  double* stage;
+  double* acc;
+  double* cv;
+  unsigned long long* smask;  // two bitmaps, alternating between consecutive sub-batches
+  int64_t* sstart;
+  int* schunk;
+  uint16_t* spos;
+  int* clp;
+};
+
+template <int NV>
+__device__ __forceinline__ BinLds bin_lds(double* base, bool plan) {
+  BinLds L;
+  L.stage = base;
+  L.acc = base + (plan ? 0 : kSubBatch);
+  L.cv = L.acc + kMaxTilePix * NV;
+  L.smask = reinterpret_cast<unsigned long long*>(L.cv + kWaves * NV);
+  L.sstart = reinterpret_cast<int64_t*>(L.smask + 2 * (kSubBatch / 64));
+  L.schunk = reinterpret_cast<int*>(L.sstart + kMaxSegs);
+  L.spos = reinterpret_cast<uint16_t*>(L.schunk + kMaxSegs);
+  L.clp = reinterpret_cast<int*>(L.spos + kMaxSegs);
+  return L;
+}
+
+// Load the segment table of sub-batch S and mark its starts in bitmap `sm` (zeroed beforehand).
+__device__ __forceinline__ void load_segments(const DevPlan& P, const SubBatch& S, const BinLds& L,
+                                              unsigned long long* sm, bool with_chunk) {
+  const int nseg = S.seg_end - S.seg_begin;
+  for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
+    const Segment g = P.segs[S.seg_begin + i];
+    L.sstart[i] = g.start;
+    L.spos[i] = (uint16_t)g.pos;
+    if (with_chunk) L.schunk[i] = g.chunk;
+    atomicOr(&sm[g.pos >> 6], 1ull << (g.pos & 63));
+  }
 }
 
 // P m for every on-map sample of one tile, written to a TOD-sized buffer in time order.
@@ -669,13 +732,13 @@ __host__ __device__ constexpr size_t bin_lds_bytes(bool plan) {
 // in pixel-sorted order, scattered to their staging positions in LDS and written out along the
 // sub-batch's time-contiguous segments (coalesced within each segment).
 template <typename T, int NC>
-__device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt, double* stage, int64_t* sstart,
-                             int* spos, T* __restrict__ pm_out) {
+__device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt, const BinLds& L, int& sbn,
+                             T* __restrict__ pm_out) {
   constexpr int SPW = kSubBatch / kBinBlock;
-  for (int sb = tl.sb_begin; sb < tl.sb_end; ++sb) {
+  for (int sb = tl.sb_begin; sb < tl.sb_end; ++sb, ++sbn) {
     const SubBatch S = P.sbs[sb];
-    const int nseg = S.seg_end - S.seg_begin;
     const int cnt = S.count;
+#pragma unroll 2
     for (int k = threadIdx.x; k < cnt; k += kBinBlock) {
       const int64_t gk = S.sorted_begin + k;
       const int l = P.lp[gk];
@@ -685,22 +748,18 @@ __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt,
         weights_from_raw<T>(P, psi_sorted_raw<T>(P, gk), c, sn);
         v += c * mt[l * 3 + 1] + sn * mt[l * 3 + 2];
       }
-      stage[P.perm[gk]] = v;
+      L.stage[P.perm[gk]] = v;
     }
-    for (int i = threadIdx.x; i < nseg; i += kBinBlock) {
-      const Segment g = P.segs[S.seg_begin + i];
-      sstart[i] = g.start;
-      spos[i] = g.pos;
-    }
+    load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), false);
     __syncthreads();
-    int lo = 0;
-#pragma unroll
+    const SegIndex si = seg_index(L.smask + (sbn & 1) * (kSubBatch / 64));
+    // the other bitmap was last read before the previous sub-batch's final barrier
+    if (threadIdx.x < kSubBatch / 64) L.smask[((sbn + 1) & 1) * (kSubBatch / 64) + threadIdx.x] = 0ull;
+#pragma unroll 4
     for (int u = 0; u < SPW; ++u) {
       const int q = threadIdx.x + u * kBinBlock;
-      if (q < cnt) {
-        lo = seg_find(spos, lo, nseg, q);
-        pm_out[sstart[lo] + (q - spos[lo])] = (T)stage[q];
-      }
+      const int g = seg_lookup(si, q);  // lane reads with every lane active
+      if (q < cnt) pm_out[L.sstart[g] + (q - (int)L.spos[g])] = (T)L.stage[q];
     }
     __syncthreads();
   }
@@ -710,11 +769,10 @@ template <typename T, int NC>
 __global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* __restrict__ m,
                                                        T* __restrict__ pm_out) {
   extern __shared__ double smem_d[];
-  double* stage = smem_d;
-  double* mt = stage + kSubBatch;
-  double* cv = mt + kMaxTilePix * NC;
-  int64_t* sstart = reinterpret_cast<int64_t*>(cv + kWaves * NC);
-  int* spos = reinterpret_cast<int*>(sstart + kMaxSegs);
+  const BinLds L = bin_lds<NC>(smem_d, false);
+  double* mt = L.acc;
+  if (threadIdx.x < 2 * (kSubBatch / 64)) L.smask[threadIdx.x] = 0ull;
+  int sbn = 0;
   for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) {
     const Tile tl = P.tiles[t];
     const int tp = tl.tw * tl.th;
@@ -724,7 +782,7 @@ __global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* 
       for (int q = 0; q < NC; ++q) mt[l * NC + q] = m[q * P.npix + p];
     }
     __syncthreads();
-    tile_project<T, NC>(P, tl, mt, stage, sstart, spos, pm_out);
+    tile_project<T, NC>(P, tl, mt, L, sbn, pm_out);
   }
 }
 
@@ -737,22 +795,24 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
   constexpr bool POL = (NV == 3 || NV == 7);
   constexpr int SPW = kSubBatch / kBinBlock;  // staged samples per thread
   extern __shared__ double smem_d[];
-  double* stage = smem_d;
-  double* acc = stage + (PLAN ? 0 : kSubBatch);
-  double* cv = acc + kMaxTilePix * NV;
-  int64_t* sstart = reinterpret_cast<int64_t*>(cv + kWaves * NV);
-  int* spos = reinterpret_cast<int*>(sstart + kMaxSegs);
-  int* schunk = spos + kMaxSegs;
-  int* clp = schunk + kMaxSegs;
+  const BinLds L = bin_lds<NV>(smem_d, PLAN);
+  double* stage = L.stage;
+  double* acc = L.acc;
+  double* cv = L.cv;
+  const int64_t* sstart = L.sstart;
+  const uint16_t* spos = L.spos;
+  const int* schunk = L.schunk;
+  int* clp = L.clp;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < 2 * (kSubBatch / 64)) L.smask[threadIdx.x] = 0ull;
+  int sbn = 0;  // sub-batches processed: selects the start bitmap
   for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) {
     const Tile tl = P.tiles[t];
     const int tp = tl.tw * tl.th;
     for (int i = threadIdx.x; i < tp * NV; i += kBinBlock) acc[i] = 0.0;
     __syncthreads();
-    for (int sb = tl.sb_begin; sb < tl.sb_end; ++sb) {
+    for (int sb = tl.sb_begin; sb < tl.sb_end; ++sb, ++sbn) {
       const SubBatch S = P.sbs[sb];
-      const int nseg = S.seg_end - S.seg_begin;
       const int cnt = S.count;
       // this wave's stripe of the pixel-sorted order; lane l takes kPerLane consecutive entries
       const int stripe = (((cnt + kWaves - 1) / kWaves) + 63) & ~63;
@@ -760,7 +820,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
       const int k1 = min(cnt, k0 + stripe);
       const int kl = k0 + kPerLane * lane;
       const bool active = kl < k1;
-      uint4 lpw[2], pmw[2];
+      uint4 lpw[2] = {}, pmw[2] = {};
       uint4 psw[kPerLane / 2];  // raw angles: up to 16 x 8 bytes
       if (active) {
         const int64_t g0 = S.sorted_begin + kl;  // a multiple of kSortAlign
@@ -779,32 +839,33 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
             if (w < nw) psw[w] = pp[w];
         }
       }
-      for (int i = threadIdx.x; i < nseg; i += kBinBlock) {
-        const Segment g = P.segs[S.seg_begin + i];
-        sstart[i] = g.start;
-        spos[i] = g.pos;
-        schunk[i] = g.chunk;
-      }
+      load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), PLAN || bsrc == BSRC_DATA_OVER_TAU);
       if (lane == 0) clp[wave] = -1;
       __syncthreads();
+      const SegIndex si = seg_index(L.smask + (sbn & 1) * (kSubBatch / 64));
+      // the other bitmap was last read before the previous sub-batch's final barrier
+      if (threadIdx.x < kSubBatch / 64) L.smask[((sbn + 1) & 1) * (kSubBatch / 64) + threadIdx.x] = 0ull;
       if (!PLAN) {
-        double v[SPW];
-        int lo = 0;
+        // two rounds of SPW / 2 loads in flight per thread
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+          double v[SPW / 2];
 #pragma unroll
-        for (int u = 0; u < SPW; ++u) {
-          const int q = threadIdx.x + u * kBinBlock;
-          v[u] = 0.0;
-          if (q < cnt) {
-            lo = seg_find(spos, lo, nseg, q);
-            const int64_t j = sstart[lo] + (q - spos[lo]);
-            v[u] = (double)src[j];
-            if (bsrc == BSRC_DATA_OVER_TAU) v[u] *= P.chunks[schunk[lo]].inv_tau;
+          for (int u = 0; u < SPW / 2; ++u) {
+            const int q = threadIdx.x + (h * (SPW / 2) + u) * kBinBlock;
+            const int g = seg_lookup(si, q);  // lane reads with every lane active
+            v[u] = 0.0;
+            if (q < cnt) {
+              const int64_t j = sstart[g] + (q - (int)spos[g]);
+              v[u] = (double)src[j];
+              if (bsrc == BSRC_DATA_OVER_TAU) v[u] *= P.chunks[schunk[g]].inv_tau;
+            }
           }
-        }
 #pragma unroll
-        for (int u = 0; u < SPW; ++u) {
-          const int q = threadIdx.x + u * kBinBlock;
-          if (q < cnt) stage[q] = v[u];
+          for (int u = 0; u < SPW / 2; ++u) {
+            const int q = threadIdx.x + (h * (SPW / 2) + u) * kBinBlock;
+            if (q < cnt) stage[q] = v[u];
+          }
         }
         __syncthreads();
       }
@@ -817,15 +878,15 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
         for (int q = 0; q < NV; ++q) cur[q] = hv[q] = 0.0;
 #pragma unroll
         for (int i = 0; i < kPerLane; ++i) {
+          const uint32_t wp = (i < 8) ? ((const uint32_t*)&pmw[0])[i / 2] : ((const uint32_t*)&pmw[1])[(i - 8) / 2];
+          const int pr = (int)((wp >> (16 * (i & 1))) & 0xffffu);
+          const int gpr = PLAN ? seg_lookup(si, pr) : 0;  // lane reads with every lane of the wave active
           if (kl + i < k1) {
             const uint32_t wl = (i < 8) ? ((const uint32_t*)&lpw[0])[i / 2] : ((const uint32_t*)&lpw[1])[(i - 8) / 2];
-            const uint32_t wp = (i < 8) ? ((const uint32_t*)&pmw[0])[i / 2] : ((const uint32_t*)&pmw[1])[(i - 8) / 2];
             const int lp = (int)((wl >> (16 * (i & 1))) & 0xffffu);
-            const int pr = (int)((wp >> (16 * (i & 1))) & 0xffffu);
             double y;
             if (PLAN) {
-              const int g = seg_find(spos, 0, nseg, pr);
-              y = P.chunks[schunk[g]].inv_tau;
+              y = P.chunks[schunk[gpr]].inv_tau;
             } else {
               y = stage[pr];
             }
@@ -976,7 +1037,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
     }
     __syncthreads();
     if (!PLAN && pm_out && (epi == EPI_UPDATE || epi == EPI_REPLACE))
-      tile_project<T, (NV == 3 ? 3 : 1)>(P, tl, acc, stage, sstart, spos, pm_out);
+      tile_project<T, (NV == 3 ? 3 : 1)>(P, tl, acc, L, sbn, pm_out);
   }
 }
 
@@ -1017,7 +1078,7 @@ __device__ __forceinline__ void untangle(const DevClass& cl, const DevPlan& P, c
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_grad_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
+__global__ __launch_bounds__(kBlockB) void k_grad_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
                                                    const cx<T>* __restrict__ Xr, const cx<T>* __restrict__ Xz,
                                                    double* __restrict__ part) {
   extern __shared__ unsigned char smem_raw[];
@@ -1031,7 +1092,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_b(DevPlan P, const ItemB* __res
     const int nrow = (ra == rb) ? 1 : 2;
     // sequences: rows of r at [0, nrow*M1), rows of P z at [nrow*M1, 2*nrow*M1)
     const int off2 = nrow * M1;
-    for (int e = threadIdx.x; e < M1; e += kBlock) {
+    for (int e = threadIdx.x; e < M1; e += kBlockB) {
       lds[e] = Xr[ch.off / 2 + (int64_t)ra * M1 + e];
       lds[off2 + e] = Xz[ch.off / 2 + (int64_t)ra * M1 + e];
       if (nrow == 2) {
@@ -1040,13 +1101,13 @@ __global__ __launch_bounds__(kBlock) void k_grad_b(DevPlan P, const ItemB* __res
       }
     }
     __syncthreads();
-    lds_fft<T, false, false>(lds, M1, 2 * nrow, 0, 1, M1, cl.rad1, cl.nr1, twtab<T>(P) + cl.tw1);
+    lds_fft<T, false, false, kBlockB>(lds, M1, 2 * nrow, 0, 1, M1, cl.rad1, cl.nr1, twtab<T>(P) + cl.tw1);
     double acc[3] = {0.0, 0.0, 0.0};
     for (int sl = 0; sl < nrow; ++sl) {
       const int row = sl == 0 ? ra : rb;
       const bool self = (row == 0) || (2 * row == M2);
       if (!self && sl == 1) break;  // a row pair is handled from its first row
-      for (int k1 = threadIdx.x; k1 < M1; k1 += kBlock) {
+      for (int k1 = threadIdx.x; k1 < M1; k1 += kBlockB) {
         int prow, pk1;
         if (!self) {
           prow = 1;
@@ -1089,12 +1150,12 @@ __global__ __launch_bounds__(kBlock) void k_grad_b(DevPlan P, const ItemB* __res
       double v = acc[q];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      if ((threadIdx.x & 63) == 0) red[q * (kBlock / 64) + (threadIdx.x >> 6)] = v;
+      if ((threadIdx.x & 63) == 0) red[q * (kBlockB / 64) + (threadIdx.x >> 6)] = v;
     }
     __syncthreads();
     if (threadIdx.x < 3) {
       double t = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) t += red[threadIdx.x * (kBlock / 64) + w];
+      for (int w = 0; w < kBlockB / 64; ++w) t += red[threadIdx.x * (kBlockB / 64) + w];
       part[3 * (int64_t)it + threadIdx.x] = t;
     }
     __syncthreads();
@@ -1123,12 +1184,12 @@ __global__ __launch_bounds__(kBlock) void k_grad_reduce(const int32_t* __restric
 
 hipError_t launch_grad(const DevPlan& P, const ItemB* items, int nitems, const int32_t* chunk_item_begin,
                        const void* Xr, const void* Xz, double* part, double* out, size_t lds, hipStream_t s) {
-  const size_t tot = lds > 3 * (kBlock / 64) * sizeof(double) ? lds : 3 * (kBlock / 64) * sizeof(double);
+  const size_t tot = lds > 3 * (kBlockB / 64) * sizeof(double) ? lds : 3 * (kBlockB / 64) * sizeof(double);
   if (P.precision == 0)
-    hipLaunchKernelGGL(k_grad_b<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), tot, s, P, items, nitems,
+    hipLaunchKernelGGL(k_grad_b<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items, nitems,
                        (const double2*)Xr, (const double2*)Xz, part);
   else
-    hipLaunchKernelGGL(k_grad_b<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), tot, s, P, items, nitems,
+    hipLaunchKernelGGL(k_grad_b<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items, nitems,
                        (const float2*)Xr, (const float2*)Xz, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1307,12 +1368,12 @@ hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void*
   bc.inv_lam = 1.0 / lam;
   bc.chi2_lam = chi2_lam;
   const int red_off = (int)lds;
-  const size_t tot = lds + (kBlock / 64) * sizeof(double);
+  const size_t tot = lds + (kBlockB / 64) * sizeof(double);
   if (P.precision == 0)
-    hipLaunchKernelGGL(k_pass_b<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), tot, s, P, items, nitems,
+    hipLaunchKernelGGL(k_pass_b<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items, nitems,
                        (double2*)work, ops, bc, chi2_part, red_off);
   else
-    hipLaunchKernelGGL(k_pass_b<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), tot, s, P, items, nitems,
+    hipLaunchKernelGGL(k_pass_b<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items, nitems,
                        (float2*)work, ops, bc, chi2_part, red_off);
   return hipGetLastError();
 }

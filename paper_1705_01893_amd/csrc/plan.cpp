@@ -273,7 +273,10 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     if (cls < 0) {
       int64_t M1, M2;
       int cb;
-      const int row_cap = cap - (int)((kBlock / 64) * sizeof(double) / csz + 1);
+      // a row item (two rows) holds at most Ept elements per thread of the row pass, and its
+      // tile plus the chi^2 reduction slots fit 64 KB of LDS
+      const int row_cap = std::min<int>(kBlockB * (f64 ? Ept<double>::v : Ept<float>::v),
+                                        (int)((65536 - (kBlockB / 64) * sizeof(double)) / csz));
       if (!choose_split(M, cap, bmax, row_cap, M1, M2, cb))
         return fail(MM_E_LEN, "chunk " + std::to_string(c) + ": no transform split fits the LDS budget");
       DevClass k;
@@ -344,7 +347,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
   pl->lds_ac = lds_ac;
   pl->lds_b = lds_b;
-  if (lds_ac > 65536 || lds_b + (kBlock / 64) * sizeof(double) > 65536)
+  if (lds_ac > 65536 || lds_b + (kBlockB / 64) * sizeof(double) > 65536)
     return fail(MM_E_LEN, "transform tiles exceed the LDS budget");
   std::vector<float2> tw32(tw.size());
   for (size_t i = 0; i < tw.size(); ++i) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
