@@ -91,7 +91,8 @@ enum { MM_MAP_AUTO = 0, MM_MAP_GATHER = 1, MM_MAP_PROJECTED = 2 };        /* map
  *  pix          device, N_s int32 (N_s = chunk_off[nchunk]).
  *  psi          device, N_s angles (radians) of type psi_kind: MM_PSI_F64
  *               (double), MM_PSI_F32 (float) or MM_PSI_U16 (uint16 index into
- *               psi_table); NULL / MM_PSI_NONE when ncomp == 1.
+ *               psi_table); NULL / MM_PSI_NONE when ncomp == 1.  Angles must be
+ *               finite with |psi| < 1e5 (MM_E_ARG otherwise).
  *  psi_table    host, psi_table_len floats (only for MM_PSI_U16).
  *  map_access   how the time-domain sweeps read P m: MM_MAP_GATHER gathers the
  *               map per sample; MM_MAP_PROJECTED keeps a plan-owned N_s-sample

@@ -9,6 +9,7 @@ namespace mm {
 
 constexpr int kBlock = 512;        // threads per workgroup of the column passes (A, C) and reductions
 constexpr int kBlockB = 256;       // threads per workgroup of the row pass (B) and the gradient row pass
+constexpr double kMaxAngle = 1.0e5;  // |psi| bound (radians) of the stored polarization angles
 constexpr int kBinBlock = 256;     // threads per workgroup of the binning pass
 constexpr int kWaves = kBinBlock / 64;
 constexpr int kMaxStages = 24;     // radix stages of one sub-transform
@@ -95,6 +96,7 @@ struct DevPlan {
   const void* psi;           // caller's angles (time order)
   const double2* psi_cs64;   // (cos 2psi, sin 2psi) per table entry (MM_PSI_U16), float64
   const float2* psi_cs32;    // same, float32
+  const double2* sc_tab;     // (cos, sin)(k pi / 512), k < 1024, for the FP64 angle weights
   const Tile* tiles;
   const SubBatch* sbs;
   const Segment* segs;

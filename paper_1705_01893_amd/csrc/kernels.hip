@@ -53,6 +53,23 @@ __device__ __forceinline__ C conjc(C a) {
   return a;
 }
 
+// sin and cos of an angle in float64: theta = k pi/512 + r with |r| <= pi/1024 (Cody-Waite
+// reduction with a two-part constant; the fused multiply-adds keep k times the leading part
+// exact), tabulated (cos, sin)(k pi/512), Taylor series of sin r and cos r (the first omitted
+// terms are below 2e-19 relative), and the angle-sum formulas.  Exact reduction needs
+// |theta| < 2 kMaxAngle, which the plan checks for every stored angle.
+__device__ __forceinline__ void sincos_tab(const double2* __restrict__ tab, double th, double& s, double& c) {
+  const double kf = rint(th * 162.97466172610083);          // 512 / pi
+  double r = fma(-kf, 0.006135923151542565, th);            // pi/512, leading part
+  r = fma(-kf, 2.391888279584674e-19, r);                   // pi/512, trailing part
+  const double2 t = tab[(int)kf & 1023];
+  const double r2 = r * r;
+  const double sr = r * fma(r2, fma(r2, fma(r2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+  const double cr = fma(r2, fma(r2, fma(r2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+  c = fma(t.x, cr, -t.y * sr);
+  s = fma(t.y, cr, t.x * sr);
+}
+
 // polarization weights (cos 2psi, sin 2psi) of one stored angle, computed in the TOD precision
 template <typename T>
 __device__ __forceinline__ void psi_weights(const DevPlan& P, const void* arr, int64_t i, T& c, T& s);
@@ -61,11 +78,9 @@ template <>
 __device__ __forceinline__ void psi_weights<double>(const DevPlan& P, const void* arr, int64_t i, double& c,
                                                     double& s) {
   if (P.psi_kind == 1) {
-    const double a = 2.0 * ((const double*)arr)[i];
-    sincos(a, &s, &c);
+    sincos_tab(P.sc_tab, 2.0 * ((const double*)arr)[i], s, c);
   } else if (P.psi_kind == 2) {
-    const double a = 2.0 * (double)((const float*)arr)[i];
-    sincos(a, &s, &c);
+    sincos_tab(P.sc_tab, 2.0 * (double)((const float*)arr)[i], s, c);
   } else {
     const double2 t = P.psi_cs64[((const uint16_t*)arr)[i]];
     c = t.x;
@@ -196,7 +211,7 @@ __device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw,
     const double a = which == 0 ? __hiloint2double(raw.y, raw.x) : __hiloint2double(raw.w, raw.z);
     if (sizeof(T) == 8) {
       double sd, cd;
-      sincos(2.0 * a, &sd, &cd);
+      sincos_tab(P.sc_tab, 2.0 * a, sd, cd);
       c = (T)cd;
       s = (T)sd;
     } else {
@@ -209,7 +224,7 @@ __device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw,
     const float a = __uint_as_float(which == 0 ? raw.x : raw.y);
     if (sizeof(T) == 8) {
       double sd, cd;
-      sincos(2.0 * (double)a, &sd, &cd);
+      sincos_tab(P.sc_tab, 2.0 * (double)a, sd, cd);
       c = (T)cd;
       s = (T)sd;
     } else {
@@ -643,7 +658,7 @@ __device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw,
     const double a = __longlong_as_double((long long)raw);
     if (sizeof(T) == 8) {
       double sd, cd;
-      sincos(2.0 * a, &sd, &cd);
+      sincos_tab(P.sc_tab, 2.0 * a, sd, cd);
       cc = (T)cd;
       ss = (T)sd;
     } else {
@@ -656,7 +671,7 @@ __device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw,
     const float a = __uint_as_float((uint32_t)raw);
     if (sizeof(T) == 8) {
       double sd, cd;
-      sincos(2.0 * (double)a, &sd, &cd);
+      sincos_tab(P.sc_tab, 2.0 * (double)a, sd, cd);
       cc = (T)cd;
       ss = (T)sd;
     } else {

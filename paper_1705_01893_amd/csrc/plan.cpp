@@ -368,6 +368,13 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
       const uint16_t* ix = (const uint16_t*)psi.data();
       for (int64_t j = 0; j < ns; ++j)
         if (ix[j] >= D.psi_table_len) return fail(MM_E_ARG, "angle index beyond the table");
+    } else {
+      // the kernels' angle reduction is exact for |psi| < kMaxAngle
+      for (int64_t j = 0; j < ns; ++j) {
+        const double a = pl->psi_kind == MM_PSI_F64 ? ((const double*)psi.data())[j]
+                                                    : (double)((const float*)psi.data())[j];
+        if (!(std::fabs(a) < kMaxAngle)) return fail(MM_E_ARG, "angle " + std::to_string(j) + " is not finite or too large");
+      }
     }
   }
 
@@ -548,11 +555,22 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   P.classes = dclasses;
   P.tw64 = dtw64;
   P.tw32 = dtw32;
+  {
+    std::vector<double2> sc(1024);
+    for (int k = 0; k < 1024; ++k) {
+      const double a = M_PI * (double)k / 512.0;
+      sc[k] = make_double2(std::cos(a), std::sin(a));
+    }
+    double2* dsc;
+    if ((st = upload(pl, sc, &dsc, s)) != MM_OK) return st;
+    P.sc_tab = dsc;
+  }
   if (pl->psi_kind == MM_PSI_U16) {
     std::vector<double2> cs64(D.psi_table_len);
     std::vector<float2> cs32(D.psi_table_len);
     for (int64_t i = 0; i < D.psi_table_len; ++i) {
       const double a = 2.0 * (double)D.psi_table[i];
+      if (!(std::fabs(a) < 2.0 * kMaxAngle)) return fail(MM_E_ARG, "angle table entry is not finite or too large");
       cs64[i] = make_double2(std::cos(a), std::sin(a));
       cs32[i] = make_float2((float)cs64[i].x, (float)cs64[i].y);
     }
