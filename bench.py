@@ -65,6 +65,20 @@ def pass_bytes(prob, tod_bytes: int, psi_bytes: int, projected: bool) -> list:
     return [a, b, c, d, p]
 
 
+def layout_summary(mm, plan) -> list:
+    """Distinct transform layouts of the plan's chunks (split, column block, tuner's pick) with counts."""
+    seen = {}
+    for c in range(plan.nchunk):
+        lay = mm.mm_plan_chunk_layout(plan, c)
+        key = (lay["M1"], lay["M2"], lay["cb"], lay["pick"], lay["ncand"])
+        seen[key] = seen.get(key, 0) + 1
+    rows = sorted(seen.items(), key=lambda kv: -kv[1])
+    out = [{"M1": k[0], "M2": k[1], "cb": k[2], "pick": k[3], "ncand": k[4], "chunks": n} for k, n in rows[:8]]
+    if len(rows) > 8:
+        out.append({"other_layouts": len(rows) - 8, "chunks": sum(n for _, n in rows[8:])})
+    return out
+
+
 def load_traffic(workload: str, khash: str):
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
@@ -308,6 +322,7 @@ def main():
                    for i in range(5)],
         "sweep_roofline_frac": round(sweep_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "plan_s": round(t_plan, 2), "generate_s": round(t_gen, 2), "kernel_hash": khash,
+        "layouts": layout_summary(mm, plan),
     }
     chi2_block = None
     if not args.no_chi2:

@@ -74,6 +74,7 @@ typedef enum {
 enum { MM_FP64 = 0, MM_MIXED = 1 };                              /* precision */
 enum { MM_PSI_NONE = 0, MM_PSI_F64 = 1, MM_PSI_F32 = 2, MM_PSI_U16 = 3 }; /* psi storage */
 enum { MM_MAP_AUTO = 0, MM_MAP_GATHER = 1, MM_MAP_PROJECTED = 2 };        /* map_access */
+enum { MM_TUNE_MEASURE = 0, MM_TUNE_STATIC = 1, MM_TUNE_PICK0 = 16 };    /* tune */
 
 /*
  * Problem description (Section 2 data model; Section 4.2 per-chunk tau).
@@ -100,6 +101,15 @@ enum { MM_MAP_AUTO = 0, MM_MAP_GATHER = 1, MM_MAP_PROJECTED = 2 };        /* map
  *               pass (or a projection pass) and read in time order; MM_MAP_AUTO
  *               picks PROJECTED when ncomp * npix * 8 bytes exceeds 4 MiB.  The
  *               results agree to rounding (MM_MIXED rounds P m to float32 there).
+ *  tune         layout of each chunk length's transforms (split M = M1 M2 of the
+ *               n/2-point complex transform, column-block width, radix order):
+ *               MM_TUNE_MEASURE times the candidate layouts on the GPU at plan
+ *               time for chunks of n/2 >= 16384 and keeps the fastest (cached per
+ *               process and length); MM_TUNE_STATIC takes the first candidate of
+ *               a fixed rule.  Layouts differ only in rounding; MM_TUNE_STATIC
+ *               gives bitwise identical results across processes.
+ *               MM_TUNE_PICK0 + i takes candidate i of the rule's order for every
+ *               length (clamped to the last one), to exercise each layout.
  */
 typedef struct {
   int32_t ncomp;
@@ -119,6 +129,8 @@ typedef struct {
   int32_t map_access;
   const float* psi_table;
   int64_t psi_table_len;
+  int32_t tune;
+  int32_t reserved1;
 } mm_plan_desc;
 
 /* Cooling schedule (Section 3.1): optionally one lambda = inf step, then
@@ -153,6 +165,11 @@ mm_status mm_plan_nsolvable(mm_plan_t plan, int64_t* count);
 /* The map access the plan uses (host): MM_MAP_GATHER or MM_MAP_PROJECTED
  * (MM_MAP_AUTO resolved). */
 mm_status mm_plan_map_access(mm_plan_t plan, int32_t* access);
+/* Transform layout of chunk `chunk` (host outputs): M1, M2 (M = n/2 = M1 M2),
+ * cb (columns per column item), `pick` (index of the chosen candidate in the
+ * fixed rule's order) and `ncand` (number of candidates). */
+mm_status mm_plan_chunk_layout(mm_plan_t plan, int64_t chunk, int64_t* M1, int64_t* M2, int32_t* cb,
+                               int32_t* pick, int32_t* ncand);
 
 /*
  * One messenger iteration, eqn. (mcompact) of Section 2.1:

@@ -198,6 +198,19 @@ mm_status mm_plan_map_access(mm_plan_t plan, int32_t* access) {
   return MM_OK;
 }
 
+mm_status mm_plan_chunk_layout(mm_plan_t plan, int64_t chunk, int64_t* M1, int64_t* M2, int32_t* cb,
+                               int32_t* pick, int32_t* ncand) {
+  if (!plan || !M1 || !M2 || !cb || !pick || !ncand) return fail(MM_E_ARG, "null argument");
+  if (chunk < 0 || chunk >= plan->nchunk) return fail(MM_E_ARG, "chunk index out of range");
+  const DevChunk& ch = plan->chunks_host[chunk];
+  *M1 = ch.M1;
+  *M2 = ch.M2;
+  *cb = ch.cb;
+  *pick = plan->class_layout[ch.cls];
+  *ncand = plan->class_ncand[ch.cls];
+  return MM_OK;
+}
+
 mm_status mm_plan_hits(mm_plan_t plan, int32_t* hits_dev, mm_stream_t stream) {
   if (!plan || !hits_dev) return fail(MM_E_ARG, "null argument");
   MM_TRY_HIP(launch_copy_bytes(hits_dev, plan->d_hits, plan->npix * (int64_t)sizeof(int32_t), S(stream)));

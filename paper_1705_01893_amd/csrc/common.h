@@ -42,6 +42,7 @@ struct DevChunk {
   double nbar0;       // sigma^2 - tau (N-bar = nbar0 + sigma^2 (f/fknee)^alpha)
   int64_t spec_off;   // offset of this chunk's M+1 power-law values in DevPlan::spec (FP64 form)
   double inv_M;       // 1 / M
+  double lg0;         // log2(df / fknee): the power law at bin k is sigma^2 2^(alpha (log2 k + lg0))
 };
 
 // Per-length transform data: radix schedules and twiddle-table offsets.

@@ -127,8 +127,9 @@ __device__ __forceinline__ double powerlaw<double>(const DevChunk& ch, int k) {
 }
 template <>
 __device__ __forceinline__ float powerlaw<float>(const DevChunk& ch, int k) {
-  const float f = (float)((double)(k == 0 ? 1 : k) * ch.df);
-  return (float)ch.sigma2 * exp2f((float)ch.alpha * log2f(f / (float)ch.fknee));
+  // sigma^2 2^(alpha (log2 k + log2(df / fknee))) with the hardware base-2 log and exponential
+  const float lk = __builtin_amdgcn_logf((float)(k == 0 ? 1 : k));
+  return (float)ch.sigma2 * __builtin_amdgcn_exp2f((float)ch.alpha * (lk + (float)ch.lg0));
 }
 
 struct BinCtx {
@@ -152,6 +153,18 @@ __device__ __forceinline__ float powerlaw_bin<float>(const DevPlan& P, const Dev
   return powerlaw<float>(ch, k);
 }
 
+// 1/x: correctly rounded in float64; the hardware reciprocal (1 ulp) in float32
+template <typename T>
+__device__ __forceinline__ T recip(T x);
+template <>
+__device__ __forceinline__ double recip<double>(double x) {
+  return 1.0 / x;
+}
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
 // gain applied to R_k (includes the 1/M of the inverse transform) and chi^2 weight 1/(n N'_k)
 template <typename T>
 __device__ __forceinline__ void bin_factors(const DevPlan& P, const DevChunk& ch, const BinCtx& bc, int k, T& g,
@@ -162,16 +175,16 @@ __device__ __forceinline__ void bin_factors(const DevPlan& P, const DevChunk& ch
   T gg;
   if (bc.gain == GAIN_MESSENGER) {
     const T nbar = (T)ch.nbar0 + pl;
-    gg = T(1) / (tau + nbar * (T)bc.inv_lam);
+    gg = recip<T>(tau + nbar * (T)bc.inv_lam);
   } else if (bc.gain == GAIN_NINV) {
-    gg = T(1) / N;
+    gg = recip<T>(N);
   } else {
     gg = N * (T)ch.inv_tau;
   }
   g = gg * (T)ch.inv_M;
   // chi^2 weight 1 / (n N'_k), N' = N + (lambda - 1) tau, in the TOD precision, only when asked for
   cw = 0.0;
-  if (bc.chi2) cw = (double)(T(1) / ((T)ch.n * (N + (T)((bc.chi2_lam - 1.0) * ch.tau))));
+  if (bc.chi2) cw = (double)recip<T>((T)ch.n * (N + (T)((bc.chi2_lam - 1.0) * ch.tau)));
 }
 
 template <typename C>
@@ -431,8 +444,9 @@ __device__ __forceinline__ void b_self(cx<T>* lds, const DevPlan& P, const DevCh
   }
 }
 
+// at most 128 VGPRs, so that four 256-thread workgroups share a CU
 template <typename T>
-__global__ __launch_bounds__(kBlockB) void k_pass_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
+__global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
                                                    cx<T>* __restrict__ X, int ops, BinCtx bc,
                                                    double* __restrict__ chi2_part, int red_off) {
   constexpr int E = Ept<T>::v;

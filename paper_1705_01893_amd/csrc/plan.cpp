@@ -30,77 +30,6 @@ static bool five_smooth(int64_t x) {
   return x == 1;
 }
 
-// radix schedule for a 5-smooth length: as many 8s as possible (a lone factor 2 turns
-// one 8 into 4*4), then 3s and 5s
-static std::vector<int8_t> radices(int64_t L) {
-  std::vector<int8_t> r;
-  int e2 = 0;
-  while (L % 2 == 0) {
-    L /= 2;
-    ++e2;
-  }
-  int n8 = e2 / 3, rem = e2 % 3;
-  if (rem == 1 && n8 > 0) {
-    --n8;
-    r.push_back(4);
-    r.push_back(4);
-  } else if (rem == 1) {
-    r.push_back(2);
-  } else if (rem == 2) {
-    r.push_back(4);
-  }
-  for (int i = 0; i < n8; ++i) r.push_back(8);
-  while (L % 3 == 0) {
-    L /= 3;
-    r.push_back(3);
-  }
-  while (L % 5 == 0) {
-    L /= 5;
-    r.push_back(5);
-  }
-  return r;
-}
-
-// choose M = M1 * M2 for the column (M2) and row (M1) transforms within the LDS capacity:
-// a column item holds cb * M2 complex values, a row item 2 * M1 plus the chi^2 reduction scratch
-static bool choose_split(int64_t M, int cap, int bmax, int row_cap, int64_t& M1, int64_t& M2, int& cb) {
-  int64_t best = -1, bestb = 0;
-  double bestscore = 1e300;
-  for (int64_t m2 = 1; m2 <= M; ++m2) {
-    if (M % m2) continue;
-    const int64_t m1 = M / m2;
-    auto pow2floor = [](int64_t x) {
-      while (x & (x - 1)) x &= x - 1;
-      return x;
-    };
-    const int64_t bfull = pow2floor(std::min<int64_t>(bmax, m1));
-    const int64_t b = std::min<int64_t>(bfull, cap / m2 > 0 ? pow2floor(cap / m2) : 0);
-    if (b < 1) continue;
-    if (2 * m1 > row_cap) continue;
-    // prefer full column blocks, then balanced splits
-    const double score = std::fabs(std::log((double)m2) - std::log(std::sqrt((double)M))) + (b < bfull ? 4.0 : 0.0);
-    if (score < bestscore) {
-      bestscore = score;
-      best = m2;
-      bestb = b;
-    }
-  }
-  if (best < 0) return false;
-  M2 = best;
-  M1 = M / best;
-  cb = (int)bestb;
-  return true;
-}
-
-static void omega_table(int64_t L, int64_t count, int64_t stride, std::vector<double2>& out) {
-  // out += exp(-2 pi i (q * stride) / L), q < count
-  for (int64_t q = 0; q < count; ++q) {
-    const int64_t e = (q * stride) % L;
-    const double a = -2.0 * M_PI * (double)e / (double)L;
-    out.push_back(make_double2(std::cos(a), std::sin(a)));
-  }
-}
-
 template <typename X>
 static mm_status upload(mm_plan_s* pl, const std::vector<X>& v, X** dptr, hipStream_t s) {
   *dptr = nullptr;
@@ -186,6 +115,7 @@ mm_status plan_set_noise(mm_plan_s* pl, const double* sigma, const double* fknee
     ch.tau = pl->tau[c];
     ch.inv_tau = 1.0 / ch.tau;
     ch.nbar0 = ch.sigma2 - ch.tau;
+    ch.lg0 = std::log2(ch.df / ch.fknee);
   }
   if (hipMemcpyAsync(pl->d_chunks, pl->chunks_host.data(), pl->chunks_host.size() * sizeof(DevChunk),
                      hipMemcpyHostToDevice, s) != hipSuccess)
@@ -214,6 +144,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   }
   if (D.map_access != MM_MAP_AUTO && D.map_access != MM_MAP_GATHER && D.map_access != MM_MAP_PROJECTED)
     return fail(MM_E_ARG, "unknown map_access");
+  const bool pick_mode = D.tune >= MM_TUNE_PICK0 && D.tune < MM_TUNE_PICK0 + 4096;
+  if (D.tune != MM_TUNE_MEASURE && D.tune != MM_TUNE_STATIC && !pick_mode) return fail(MM_E_ARG, "unknown tune mode");
   if (D.chunk_off[0] != 0) return fail(MM_E_ARG, "chunk_off[0] must be 0");
   for (int64_t c = 0; c < D.nchunk; ++c) {
     const int64_t n = D.chunk_off[c + 1] - D.chunk_off[c];
@@ -252,11 +184,9 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   for (int64_t c = 0; c < D.nchunk; ++c) pl->tau[c] = D.tau ? D.tau[c] : D.sigma[c] * D.sigma[c];
 
   const bool f64 = D.precision == MM_FP64;
-  const int cap = kBlock * (f64 ? Ept<double>::v : Ept<float>::v);
-  const int bmax = f64 ? 8 : 16;
   const size_t csz = f64 ? sizeof(double2) : sizeof(float2);
 
-  // ---- transform classes, twiddles, chunk table, work lists
+  // ---- transform classes (one per distinct chunk length), twiddles, chunk table, work lists
   std::vector<double2> tw;
   std::vector<DevClass> classes;
   std::vector<DevChunk> chunks(D.nchunk);
@@ -271,45 +201,25 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     for (size_t i = 0; i < class_M.size(); ++i)
       if (class_M[i] == M) cls = (int)i;
     if (cls < 0) {
-      int64_t M1, M2;
-      int cb;
-      // a row item (two rows) holds at most Ept elements per thread of the row pass, and its
-      // tile plus the chi^2 reduction slots fit 64 KB of LDS
-      const int row_cap = std::min<int>(kBlockB * (f64 ? Ept<double>::v : Ept<float>::v),
-                                        (int)((65536 - (kBlockB / 64) * sizeof(double)) / csz));
-      if (!choose_split(M, cap, bmax, row_cap, M1, M2, cb))
+      const std::vector<Layout> cands = layout_candidates(M, f64);
+      if (cands.empty())
         return fail(MM_E_LEN, "chunk " + std::to_string(c) + ": no transform split fits the LDS budget");
+      int pick = 0;
+      if (D.tune == MM_TUNE_MEASURE)
+        pick = tune_layout(M, f64, cands, s);
+      else if (D.tune >= MM_TUNE_PICK0)
+        pick = std::min<int>(D.tune - MM_TUNE_PICK0, (int)cands.size() - 1);
+      const Layout& L = cands[pick];
       DevClass k;
-      std::memset(&k, 0, sizeof(k));
-      k.M = (int32_t)M;
-      k.M1 = (int32_t)M1;
-      k.M2 = (int32_t)M2;
-      auto r1 = radices(M1), r2 = radices(M2);
-      if ((int)r1.size() > kMaxStages || (int)r2.size() > kMaxStages) return fail(MM_E_LEN, "too many radix stages");
-      k.nr1 = (int32_t)r1.size();
-      k.nr2 = (int32_t)r2.size();
-      std::copy(r1.begin(), r1.end(), k.rad1);
-      std::copy(r2.begin(), r2.end(), k.rad2);
-      k.tw1 = (int64_t)tw.size();
-      omega_table(M1, M1, 1, tw);
-      k.tw2 = (int64_t)tw.size();
-      omega_table(M2, M2, 1, tw);
-      const int64_t L2 = 2 * M;
-      int lb = 0;
-      while ((int64_t(1) << (2 * lb)) < L2) ++lb;  // 2^lb >= sqrt(2M)
-      const int64_t lo = int64_t(1) << lb;
-      const int64_t nhi = (L2 + lo - 1) / lo;
-      k.lb = lb;
-      k.twlo = (int64_t)tw.size();
-      omega_table(L2, lo, 1, tw);
-      k.twhi = (int64_t)tw.size();
-      omega_table(L2, nhi, lo, tw);
+      make_class(M, L, tw, k);
       cls = (int)classes.size();
       classes.push_back(k);
       class_M.push_back(M);
-      class_cb.push_back(cb);
-      lds_ac = std::max(lds_ac, (size_t)cb * (size_t)M2 * csz);
-      lds_b = std::max(lds_b, (size_t)(2 * M1) * csz);
+      class_cb.push_back(L.cb);
+      pl->class_layout.push_back(pick);
+      pl->class_ncand.push_back((int32_t)cands.size());
+      lds_ac = std::max(lds_ac, (size_t)L.cb * (size_t)L.M2 * csz);
+      lds_b = std::max(lds_b, (size_t)(2 * L.M1) * csz);
     }
     const DevClass& k = classes[cls];
     DevChunk& ch = chunks[c];
@@ -332,17 +242,10 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     ch.nbar0 = ch.sigma2 - ch.tau;
     ch.spec_off = spec_total;
     ch.inv_M = 1.0 / (double)ch.M;
+    ch.lg0 = std::log2(ch.df / ch.fknee);
     spec_total += ch.M + 1;
-    for (int32_t j1 = 0; j1 < ch.M1; j1 += ch.cb) pl->itemsAC.push_back({(int32_t)c, j1});
     pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
-    const int M2 = ch.M2;
-    if (M2 % 2 == 0) {
-      pl->itemsB.push_back({(int32_t)c, 0, M2 / 2, 0});
-      for (int k2 = 1; k2 < M2 / 2; ++k2) pl->itemsB.push_back({(int32_t)c, k2, M2 - k2, 0});
-    } else {
-      pl->itemsB.push_back({(int32_t)c, 0, 0, 0});
-      for (int k2 = 1; k2 <= (M2 - 1) / 2; ++k2) pl->itemsB.push_back({(int32_t)c, k2, M2 - k2, 0});
-    }
+    append_chunk_items((int32_t)c, ch, pl->itemsAC, pl->itemsB);
   }
   pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
   pl->lds_ac = lds_ac;

@@ -30,6 +30,8 @@ struct mm_plan_s {
   std::vector<int32_t> chunk_item_begin;
   std::vector<mm::DevChunk> chunks_host;  // kept for noise-parameter updates
   size_t lds_ac = 0, lds_b = 0;
+  std::vector<int32_t> class_layout;      // per transform class: chosen candidate index
+  std::vector<int32_t> class_ncand;       // per transform class: number of candidates
   int64_t ntiles = 0, nsegs = 0;
   int32_t tile_w = 0, tile_h = 0;
   // device
@@ -73,6 +75,31 @@ struct mm_plan_s {
 };
 
 namespace mm {
+
+// One way to run the length-2M real transform of a chunk: split M = M1 * M2, cb columns per
+// column item, radix schedules of the row (M1) and column (M2) transforms.
+struct Layout {
+  int64_t M1 = 0, M2 = 0;
+  int cb = 0;
+  std::vector<int8_t> r1, r2;
+};
+
+constexpr int64_t kTuneMinM = int64_t(1) << 14;     // shorter chunks take the static rule
+constexpr int64_t kTuneElements = int64_t(1) << 22;  // complex values per timed launch
+constexpr size_t kTuneMaxCandidates = 6;
+
+int tile_cap_ac(bool f64);  // complex values per column item (pass A, C tile)
+int tile_cap_b(bool f64);   // complex values per row item (pass B tile)
+// layouts that fit the passes' tiles, best first by the static rule
+std::vector<Layout> layout_candidates(int64_t M, bool f64);
+// radix schedules and twiddle offsets of layout L (twiddles appended to tw)
+void make_class(int64_t M, const Layout& L, std::vector<double2>& tw, DevClass& k);
+// column items and row-pair items of chunk c
+void append_chunk_items(int32_t c, const DevChunk& ch, std::vector<ItemAC>& itemsAC, std::vector<ItemB>& itemsB);
+// index of the fastest candidate, timed on the GPU (0 for short chunks or on any failure);
+// cached per process by (M, precision)
+int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream_t s);
+
 mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out);
 void destroy_plan(mm_plan_s* pl);
 mm_status plan_alloc(mm_plan_s* pl, size_t bytes, void** out);

@@ -1,0 +1,287 @@
+// Transform layouts of the real chunk transforms and their plan-time autotuner.
+//
+// A chunk of n = 2M real samples is transformed as M complex values with the four-step
+// split M = M1 * M2: column transforms of length M2 (pass A forward, pass C inverse; a column
+// item holds cb adjacent columns) and row transforms of length M1 (pass B, two rows per item).
+// Several splits, column-block widths and radix orders fit the passes' tiles; the tuner times
+// each candidate on copies of the chunk length and keeps the fastest.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+namespace mm {
+
+namespace {
+
+int64_t pow2floor(int64_t x) {
+  while (x & (x - 1)) x &= x - 1;
+  return x;
+}
+
+// radix schedule for a 5-smooth length: as many 8s as possible (a lone factor 2 turns one 8
+// into 4*4), then 3s and 5s; eights_first puts the 8s before the 4s and 2s
+std::vector<int8_t> radices(int64_t L, bool eights_first) {
+  std::vector<int8_t> small, r;
+  int e2 = 0;
+  while (L % 2 == 0) {
+    L /= 2;
+    ++e2;
+  }
+  int n8 = e2 / 3, rem = e2 % 3;
+  if (rem == 1 && n8 > 0) {
+    --n8;
+    small = {4, 4};
+  } else if (rem == 1) {
+    small = {2};
+  } else if (rem == 2) {
+    small = {4};
+  }
+  if (!eights_first) r = small;
+  for (int i = 0; i < n8; ++i) r.push_back(8);
+  if (eights_first) r.insert(r.end(), small.begin(), small.end());
+  while (L % 3 == 0) {
+    L /= 3;
+    r.push_back(3);
+  }
+  while (L % 5 == 0) {
+    L /= 5;
+    r.push_back(5);
+  }
+  return r;
+}
+
+void omega_table(int64_t L, int64_t count, int64_t stride, std::vector<double2>& out) {
+  // out += exp(-2 pi i (q * stride) / L), q < count
+  for (int64_t q = 0; q < count; ++q) {
+    const int64_t e = (q * stride) % L;
+    const double a = -2.0 * M_PI * (double)e / (double)L;
+    out.push_back(make_double2(std::cos(a), std::sin(a)));
+  }
+}
+
+}  // namespace
+
+int tile_cap_ac(bool f64) { return kBlock * (f64 ? Ept<double>::v : Ept<float>::v); }
+
+int tile_cap_b(bool f64) {
+  // a row item (two rows) holds at most Ept elements per thread of the row pass, and its tile
+  // plus the chi^2 reduction slots fit 64 KB of LDS
+  const size_t csz = f64 ? sizeof(double2) : sizeof(float2);
+  return std::min<int>(kBlockB * (f64 ? Ept<double>::v : Ept<float>::v),
+                       (int)((65536 - (kBlockB / 64) * sizeof(double)) / csz));
+}
+
+std::vector<Layout> layout_candidates(int64_t M, bool f64) {
+  const int cap = tile_cap_ac(f64), row_cap = tile_cap_b(f64);
+  const int bmax = f64 ? 8 : 16;  // 128-byte rows of column blocks
+  struct Scored {
+    double score;
+    Layout L;
+  };
+  std::vector<Scored> v;
+  for (int64_t m2 = 1; m2 <= M && m2 <= cap; ++m2) {
+    if (M % m2) continue;
+    const int64_t m1 = M / m2;
+    if (2 * m1 > row_cap) continue;
+    const int64_t bfull = pow2floor(std::min<int64_t>(bmax, m1));
+    const int64_t b = std::min<int64_t>(bfull, pow2floor(cap / m2));
+    if (b < 1) continue;
+    // static rule: full column blocks first, then the split closest to sqrt(M)
+    const double score = std::fabs(std::log((double)m2) - 0.5 * std::log((double)M)) + (b < bfull ? 4.0 : 0.0);
+    for (int order = 0; order < 2; ++order) {
+      Layout L;
+      L.M1 = m1;
+      L.M2 = m2;
+      L.cb = (int)b;
+      L.r1 = radices(m1, order == 1);
+      L.r2 = radices(m2, order == 1);
+      if ((int)L.r1.size() > kMaxStages || (int)L.r2.size() > kMaxStages) continue;
+      // the second radix order is a distinct candidate only when it differs
+      if (order == 1 && L.r1 == radices(m1, false) && L.r2 == radices(m2, false)) continue;
+      v.push_back({score + 1e-3 * order, L});
+    }
+  }
+  std::stable_sort(v.begin(), v.end(), [](const Scored& a, const Scored& b) { return a.score < b.score; });
+  std::vector<Layout> out;
+  for (auto& s : v) out.push_back(s.L);
+  return out;
+}
+
+void make_class(int64_t M, const Layout& L, std::vector<double2>& tw, DevClass& k) {
+  std::memset(&k, 0, sizeof(k));
+  k.M = (int32_t)M;
+  k.M1 = (int32_t)L.M1;
+  k.M2 = (int32_t)L.M2;
+  k.nr1 = (int32_t)L.r1.size();
+  k.nr2 = (int32_t)L.r2.size();
+  std::copy(L.r1.begin(), L.r1.end(), k.rad1);
+  std::copy(L.r2.begin(), L.r2.end(), k.rad2);
+  k.tw1 = (int64_t)tw.size();
+  omega_table(L.M1, L.M1, 1, tw);
+  k.tw2 = (int64_t)tw.size();
+  omega_table(L.M2, L.M2, 1, tw);
+  const int64_t L2 = 2 * M;
+  int lb = 0;
+  while ((int64_t(1) << (2 * lb)) < L2) ++lb;  // 2^lb >= sqrt(2M)
+  const int64_t lo = int64_t(1) << lb;
+  const int64_t nhi = (L2 + lo - 1) / lo;
+  k.lb = lb;
+  k.twlo = (int64_t)tw.size();
+  omega_table(L2, lo, 1, tw);
+  k.twhi = (int64_t)tw.size();
+  omega_table(L2, nhi, lo, tw);
+}
+
+void append_chunk_items(int32_t c, const DevChunk& ch, std::vector<ItemAC>& itemsAC, std::vector<ItemB>& itemsB) {
+  for (int32_t j1 = 0; j1 < ch.M1; j1 += ch.cb) itemsAC.push_back({c, j1});
+  const int M2 = ch.M2;
+  // rows k2 and M2 - k2 pair up (bins k and M - k); row 0 (and row M2/2) pair with themselves
+  if (M2 % 2 == 0) {
+    itemsB.push_back({c, 0, M2 / 2, 0});
+    for (int k2 = 1; k2 < M2 / 2; ++k2) itemsB.push_back({c, k2, M2 - k2, 0});
+  } else {
+    itemsB.push_back({c, 0, 0, 0});
+    for (int k2 = 1; k2 <= (M2 - 1) / 2; ++k2) itemsB.push_back({c, k2, M2 - k2, 0});
+  }
+}
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::pair<int64_t, int>, int> g_tune_cache;  // (M, precision) -> candidate index
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  bool alloc(size_t n) { return hipMalloc(&p, n ? n : 8) == hipSuccess; }
+};
+
+template <typename X>
+bool put(DevBuf& b, const std::vector<X>& v, hipStream_t s) {
+  if (!b.alloc(v.size() * sizeof(X))) return false;
+  return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, s) == hipSuccess;
+}
+
+// passes A-C (filter on) over K copies of a length-2M chunk under layout L; best of reps, in ms
+double time_layout(int64_t M, bool f64, const Layout& L, int64_t K, void* din, void* dwork, hipStream_t s) {
+  std::vector<double2> tw;
+  std::vector<DevClass> cls(1);
+  make_class(M, L, tw, cls[0]);
+  std::vector<float2> tw32(tw.size());
+  for (size_t i = 0; i < tw.size(); ++i) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
+  std::vector<DevChunk> chunks(K);
+  std::vector<ItemAC> itemsAC;
+  std::vector<ItemB> itemsB;
+  for (int64_t c = 0; c < K; ++c) {
+    DevChunk& ch = chunks[c];
+    std::memset(&ch, 0, sizeof(ch));
+    ch.off = c * 2 * M;
+    ch.n = (int32_t)(2 * M);
+    ch.M = (int32_t)M;
+    ch.M1 = (int32_t)L.M1;
+    ch.M2 = (int32_t)L.M2;
+    ch.cb = L.cb;
+    while ((1 << (ch.lgb + 1)) <= ch.cb) ++ch.lgb;
+    ch.df = 1.0 / (double)ch.n;
+    ch.sigma2 = 1.0;
+    ch.fknee = 0.1;
+    ch.alpha = -2.0;
+    ch.tau = 1.0;
+    ch.inv_tau = 1.0;
+    ch.nbar0 = 0.0;
+    ch.spec_off = c * (M + 1);
+    ch.inv_M = 1.0 / (double)M;
+    ch.lg0 = std::log2(ch.df / ch.fknee);
+    append_chunk_items((int32_t)c, ch, itemsAC, itemsB);
+  }
+  DevBuf bch, bcl, btw, btw32, bac, bb, bspec;
+  if (!put(bch, chunks, s) || !put(bcl, cls, s) || !put(btw, tw, s) || !put(btw32, tw32, s) || !put(bac, itemsAC, s) ||
+      !put(bb, itemsB, s))
+    return -1.0;
+  DevPlan P;
+  std::memset(&P, 0, sizeof(P));
+  P.precision = f64 ? MM_FP64 : MM_MIXED;
+  P.nsamp = K * 2 * M;
+  P.nchunk = (int32_t)K;
+  P.chunks = (const DevChunk*)bch.p;
+  P.classes = (const DevClass*)bcl.p;
+  P.tw64 = (const double2*)btw.p;
+  P.tw32 = (const float2*)btw32.p;
+  if (f64) {
+    if (!bspec.alloc((size_t)K * (M + 1) * sizeof(double))) return -1.0;
+    P.spec = (const double*)bspec.p;
+    if (launch_spectrum(P, (double*)bspec.p, s) != hipSuccess) return -1.0;
+  }
+  const size_t csz = f64 ? sizeof(double2) : sizeof(float2);
+  const size_t lds_ac = (size_t)L.cb * L.M2 * csz, lds_b = (size_t)2 * L.M1 * csz;
+  auto run = [&]() -> bool {
+    return launch_pass_a(P, (const ItemAC*)bac.p, (int)itemsAC.size(), din, nullptr, SRC_D, dwork, lds_ac, s) ==
+               hipSuccess &&
+           launch_pass_b(P, (const ItemB*)bb.p, (int)itemsB.size(), dwork, B_FILTER, GAIN_MESSENGER, 1.0, 1.0,
+                         nullptr, lds_b, s) == hipSuccess &&
+           launch_pass_c(P, (const ItemAC*)bac.p, (int)itemsAC.size(), dwork, lds_ac, s) == hipSuccess;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+  double best = -1.0;
+  bool ok = run();  // warm-up
+  for (int rep = 0; ok && rep < 3; ++rep) {
+    ok = hipEventRecord(e0, s) == hipSuccess && run() && hipEventRecord(e1, s) == hipSuccess &&
+         hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && (best < 0 || ms < best)) best = ms;
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ok ? best : -1.0;
+}
+
+}  // namespace
+
+int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream_t s) {
+  if (cands.size() <= 1 || M < kTuneMinM) return 0;
+  const std::pair<int64_t, int> key(M, f64 ? 0 : 1);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) return it->second;
+  }
+  const int ncand = (int)std::min<size_t>(cands.size(), kTuneMaxCandidates);
+  // enough copies of the chunk to fill the GPU several times over
+  const int64_t K = std::max<int64_t>(1, kTuneElements / M);
+  const size_t bytes = (size_t)K * M * (f64 ? sizeof(double2) : sizeof(float2));
+  int best = 0;
+  {
+    DevBuf din, dwork;
+    if (!din.alloc(bytes) || !dwork.alloc(bytes) || hipMemsetAsync(din.p, 0, bytes, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    double tbest = -1.0;
+    for (int i = 0; i < ncand; ++i) {
+      const double t = time_layout(M, f64, cands[i], K, din.p, dwork.p, s);
+      if (t > 0 && (tbest < 0 || t < tbest * 0.98)) {  // a clear win over the better-ranked layout
+        tbest = t;
+        best = i;
+      }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipGetLastError();
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_cache[key] = best;
+  return best;
+}
+
+}  // namespace mm

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libmm.so")
 MM_FP64, MM_MIXED = 0, 1
 MM_PSI_NONE, MM_PSI_F64, MM_PSI_F32, MM_PSI_U16 = 0, 1, 2, 3
 MM_MAP_AUTO, MM_MAP_GATHER, MM_MAP_PROJECTED = 0, 1, 2
+MM_TUNE_MEASURE, MM_TUNE_STATIC, MM_TUNE_PICK0 = 0, 1, 16
 MM_OK, MM_E_ARG, MM_E_LEN, MM_E_NOMEM, MM_E_HIP, MM_E_SINGULAR, MM_E_NONFINITE = range(7)
 _STATUS_NAMES = {0: "MM_OK", 1: "MM_E_ARG", 2: "MM_E_LEN", 3: "MM_E_NOMEM", 4: "MM_E_HIP",
                  5: "MM_E_SINGULAR", 6: "MM_E_NONFINITE"}
@@ -45,6 +46,7 @@ class _Desc(ctypes.Structure):
         ("pix", ctypes.c_void_p), ("psi", ctypes.c_void_p),
         ("psi_kind", ctypes.c_int32), ("map_access", ctypes.c_int32),
         ("psi_table", ctypes.POINTER(ctypes.c_float)), ("psi_table_len", ctypes.c_int64),
+        ("tune", ctypes.c_int32), ("reserved1", ctypes.c_int32),
     ]
 
 
@@ -72,6 +74,8 @@ def lib() -> ctypes.CDLL:
     L.mm_plan_solvable.argtypes = [vp, vp, vp]
     L.mm_plan_nsolvable.argtypes = [vp, ctypes.POINTER(i64)]
     L.mm_plan_map_access.argtypes = [vp, ctypes.POINTER(i32)]
+    L.mm_plan_chunk_layout.argtypes = [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.mm_messenger_iter.argtypes = [vp, vp, dbl, vp, vp, vp, vp]
     L.mm_solve.argtypes = [vp, vp, ctypes.POINTER(_Sched), vp, vp, vp, vp]
     L.mm_cooling_levels.argtypes = [vp, i32, dbl, ctypes.POINTER(dbl)]
@@ -86,7 +90,7 @@ def lib() -> ctypes.CDLL:
     L.mm_set_timing.argtypes = [vp, i32]
     L.mm_get_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for name in ("mm_plan_set_noise", "mm_tod_apply", "mm_noise_grad", "mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_hits", "mm_plan_solvable",
-                 "mm_plan_nsolvable", "mm_plan_map_access", "mm_messenger_iter", "mm_solve", "mm_cooling_levels", "mm_cg_solve",
+                 "mm_plan_nsolvable", "mm_plan_map_access", "mm_plan_chunk_layout", "mm_messenger_iter", "mm_solve", "mm_cooling_levels", "mm_cg_solve",
                  "mm_chi2", "mm_apply", "mm_lift_rhs"):
         getattr(L, name).restype = ctypes.c_int
     L.mm_status_str.argtypes = [ctypes.c_int]
@@ -160,7 +164,8 @@ class Plan:
 
 def mm_plan(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, pix: torch.Tensor,
             psi: Optional[torch.Tensor] = None, psi_table=None, tau=None, nx: int = 0,
-            precision: int = MM_FP64, map_access: int = MM_MAP_AUTO, stream=None) -> Plan:
+            precision: int = MM_FP64, map_access: int = MM_MAP_AUTO, tune: int = MM_TUNE_MEASURE,
+            stream=None) -> Plan:
     """Build a plan (mm_plan).  pix (int32) and psi (float64 / float32 / uint16) are device tensors."""
     off = np.ascontiguousarray(np.asarray(chunk_off, dtype=np.int64).reshape(-1))
     nchunk = off.size - 1
@@ -173,6 +178,7 @@ def mm_plan(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, p
     d = _Desc()
     d.ncomp, d.precision, d.npix, d.nx, d.nchunk = ncomp, precision, npix, nx, nchunk
     d.map_access = map_access
+    d.tune = tune
     d.chunk_off = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     for k in ("fsample", "sigma", "fknee", "alpha"):
         setattr(d, k, arrs[k].ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
@@ -221,6 +227,15 @@ def mm_plan_map_access(plan: Plan) -> int:
     v = ctypes.c_int32()
     _check(lib().mm_plan_map_access(plan.handle, ctypes.byref(v)), "mm_plan_map_access")
     return v.value
+
+
+def mm_plan_chunk_layout(plan: Plan, chunk: int) -> dict:
+    """Transform layout of one chunk: M1, M2, cb, the chosen candidate and the candidate count."""
+    m1, m2 = ctypes.c_int64(), ctypes.c_int64()
+    cb, pick, ncand = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().mm_plan_chunk_layout(plan.handle, chunk, ctypes.byref(m1), ctypes.byref(m2), ctypes.byref(cb),
+                                      ctypes.byref(pick), ctypes.byref(ncand)), "mm_plan_chunk_layout")
+    return {"M1": m1.value, "M2": m2.value, "cb": cb.value, "pick": pick.value, "ncand": ncand.value}
 
 
 def _map_ptr(plan, t, name):

@@ -1,0 +1,116 @@
+"""GPU parity of the transform layouts: every candidate layout (split M = M1 M2, column-block
+width, radix order) of several chunk lengths, selected with MM_TUNE_PICK0 + i, against the CPU
+FP64 oracle; and the layout the plan-time tuner picks."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.messenger import chi2, make_setup, messenger_step  # noqa: E402
+from paper_1705_01893_amd import mm  # noqa: E402
+from tests.tiny_inputs import random_map, tiny_problem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-10
+MIX_TOL = 1e-5
+
+# chunk lengths n = 2M: a power of two, and mixed radix-2/3/5 half lengths
+LENGTHS = {
+    "pow2": (2 ** 15, 2 ** 14),
+    "mixed": (2 * 3 * 5 * 2 ** 8, 2 * 27 * 25 * 4),
+}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def plan_for(t, dev, tune, precision=mm.MM_FP64):
+    psi = torch.from_numpy(np.ascontiguousarray(t.psi)).to(dev)
+    return mm.mm_plan(ncomp=3, npix=t.npix, nx=t.nx, chunk_off=t.chunk_off, fsample=t.fsample, sigma=t.sigma,
+                      fknee=t.fknee, alpha=t.alpha, pix=torch.from_numpy(t.pix).to(dev), psi=psi,
+                      precision=precision, tune=tune)
+
+
+@pytest.mark.parametrize("shape", list(LENGTHS))
+def test_every_layout_fp64(dev, shape):
+    t = tiny_problem(77, ncomp=3, lengths=LENGTHS[shape], nx=16)
+    S = make_setup(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, t.npix, 3)
+    m0 = random_map(7, 3, t.npix)
+    m0[:, ~S.solvable] = 0
+    ref = {lam: messenger_step(S, t.d, m0, lam) for lam in (1.0, 37.5)}
+    c2ref = chi2(S, t.d, m0)
+    d = torch.from_numpy(t.d).to(dev)
+    ncand = mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_STATIC), 0)["ncand"]
+    seen = set()
+    for pick in range(max(ncand, mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_STATIC), 1)["ncand"])):
+        plan = plan_for(t, dev, mm.MM_TUNE_PICK0 + pick)
+        lay = [mm.mm_plan_chunk_layout(plan, c) for c in range(plan.nchunk)]
+        key = tuple((l["M1"], l["M2"], l["cb"], l["pick"]) for l in lay)
+        say(f"[layout] shape={shape} pick={pick} {key}")
+        assert all(l["M1"] * l["M2"] * 2 == n for l, n in zip(lay, LENGTHS[shape]))
+        seen.add(key)
+        mi = torch.from_numpy(m0).to(dev)
+        for lam, r in ref.items():
+            mo = torch.zeros_like(mi)
+            c2 = torch.zeros(1, dtype=torch.float64, device=dev)
+            mm.mm_messenger_iter(plan, d, lam, mi, mo, c2)
+            torch.cuda.synchronize()
+            assert rel(mo.cpu().numpy(), r) < F64_TOL, (pick, lam)
+            assert c2.item() == pytest.approx(c2ref, rel=F64_TOL)
+    assert len(seen) >= 3  # several distinct layouts were exercised
+
+
+def test_every_layout_mixed(dev):
+    t = tiny_problem(78, ncomp=3, lengths=LENGTHS["mixed"], nx=16, psi_dtype=np.float32, tod_dtype=np.float32)
+    S = make_setup(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, t.npix, 3)
+    m0 = random_map(8, 3, t.npix)
+    m0[:, ~S.solvable] = 0
+    ref = messenger_step(S, t.d.astype(np.float64), m0, 1.0)
+    d = torch.from_numpy(t.d).to(dev)
+    n0 = mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_STATIC, mm.MM_MIXED), 0)["ncand"]
+    for pick in range(n0):
+        say(f"[layout mixed] pick={pick}")
+        plan = plan_for(t, dev, mm.MM_TUNE_PICK0 + pick, mm.MM_MIXED)
+        mi = torch.from_numpy(m0).to(dev)
+        mo = torch.zeros_like(mi)
+        mm.mm_messenger_iter(plan, d, 1.0, mi, mo)
+        torch.cuda.synchronize()
+        assert rel(mo.cpu().numpy(), ref) < MIX_TOL, pick
+
+
+def test_tuner_picks_a_valid_layout(dev):
+    """Chunks long enough to be tuned: the measured choice is one of the candidates and the
+    iteration it runs matches the oracle."""
+    t = tiny_problem(79, ncomp=3, lengths=(2 ** 16, 2 * 3 * 5 * 2 ** 12), nx=16)
+    S = make_setup(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, t.npix, 3)
+    plan = plan_for(t, dev, mm.MM_TUNE_MEASURE)
+    for c in range(plan.nchunk):
+        lay = mm.mm_plan_chunk_layout(plan, c)
+        say(f"[tuned] chunk {c}: {lay}")
+        assert 0 <= lay["pick"] < lay["ncand"]
+        assert 2 * lay["M1"] * lay["M2"] == int(t.chunk_off[c + 1] - t.chunk_off[c])
+    assert mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_STATIC), 0)["pick"] == 0
+    m0 = random_map(9, 3, t.npix)
+    m0[:, ~S.solvable] = 0
+    mo = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+    mm.mm_messenger_iter(plan, torch.from_numpy(t.d).to(dev), 4.0, torch.from_numpy(m0).to(dev), mo)
+    torch.cuda.synchronize()
+    assert rel(mo.cpu().numpy(), messenger_step(S, t.d, m0, 4.0)) < F64_TOL
