@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mixed", action="store_true", help="run the FP32-mixed form (FP32 TOD and angles)")
     ap.add_argument("--no-chi2", action="store_true", help="skip the time-to-chi2-target comparison")
+    ap.add_argument("--map-access", choices=["auto", "gather", "projected"], default="auto",
+                    help="how the time-domain sweeps read P m (the plan's rule by default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -262,7 +264,9 @@ def main():
     t0 = time.perf_counter()
     plan = mm.mm_plan(ncomp=prob.ncomp, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off,
                       fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=pix,
-                      psi=psi, psi_table=prob.psi_table, precision=precision)
+                      psi=psi, psi_table=prob.psi_table, precision=precision,
+                      map_access={"auto": mm.MM_MAP_AUTO, "gather": mm.MM_MAP_GATHER,
+                                  "projected": mm.MM_MAP_PROJECTED}[args.map_access])
     t_plan = time.perf_counter() - t0
     log(f"plan built in {t_plan:.1f} s ({mm.mm_plan_workspace_bytes(plan) / 2**30:.2f} GiB of device tables)")
     ns = prob.nsamp_total

@@ -659,13 +659,6 @@ __device__ __forceinline__ int seg_lookup(const SegIndex& si, int q) {
 }
 
 template <typename T>
-__device__ __forceinline__ uint64_t psi_sorted_raw(const DevPlan& P, int64_t gk) {
-  if (P.psi_kind == 1) return ((const unsigned long long*)P.psi_sorted)[gk];
-  if (P.psi_kind == 2) return ((const uint32_t*)P.psi_sorted)[gk];
-  return ((const uint16_t*)P.psi_sorted)[gk];
-}
-
-template <typename T>
 __device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw, double& c, double& s) {
   T cc, ss;
   if (P.psi_kind == 1) {
@@ -756,6 +749,44 @@ __device__ __forceinline__ void load_segments(const DevPlan& P, const SubBatch& 
   }
 }
 
+// kPerLane consecutive entries of a sub-batch's pixel-sorted order, loaded with vector loads:
+// local pixels, staging positions and raw angles.  The sorted arrays are padded to kSortAlign
+// entries, so a lane whose first entry is in range may read all kPerLane.
+struct LaneEntries {
+  uint4 lpw[2], pmw[2];
+  uint4 psw[kPerLane / 2];  // raw angles: up to 16 x 8 bytes
+};
+
+template <bool POL>
+__device__ __forceinline__ void load_lane_entries(const DevPlan& P, int64_t g0, LaneEntries& e) {
+  const uint4* lpp = reinterpret_cast<const uint4*>(P.lp + g0);
+  const uint4* pmp = reinterpret_cast<const uint4*>(P.perm + g0);
+  e.lpw[0] = lpp[0];
+  e.lpw[1] = lpp[1];
+  e.pmw[0] = pmp[0];
+  e.pmw[1] = pmp[1];
+  if (POL) {
+    const int esz = P.psi_kind == 1 ? 8 : (P.psi_kind == 2 ? 4 : 2);
+    const int nw = esz;  // uint4 words holding kPerLane angles
+    const uint4* pp = reinterpret_cast<const uint4*>((const char*)P.psi_sorted + g0 * esz);
+#pragma unroll
+    for (int w = 0; w < kPerLane / 2; ++w)
+      if (w < nw) e.psw[w] = pp[w];
+  }
+}
+
+__device__ __forceinline__ int entry_u16(const uint4* w, int i) {
+  const uint32_t x = (i < 8) ? ((const uint32_t*)&w[0])[i / 2] : ((const uint32_t*)&w[1])[(i - 8) / 2];
+  return (int)((x >> (16 * (i & 1))) & 0xffffu);
+}
+
+__device__ __forceinline__ uint64_t entry_psi_raw(const DevPlan& P, const LaneEntries& e, int i) {
+  const uint32_t* pw = (const uint32_t*)e.psw;
+  if (P.psi_kind == 1) return ((uint64_t)pw[2 * i + 1] << 32) | pw[2 * i];
+  if (P.psi_kind == 2) return pw[i];
+  return (pw[i / 2] >> (16 * (i & 1))) & 0xffffu;
+}
+
 // P m for every on-map sample of one tile, written to a TOD-sized buffer in time order.
 // mt: the tile's map values in LDS, [local pixel][NC].  For each sub-batch the values are formed
 // in pixel-sorted order, scattered to their staging positions in LDS and written out along the
@@ -767,17 +798,30 @@ __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt,
   for (int sb = tl.sb_begin; sb < tl.sb_end; ++sb, ++sbn) {
     const SubBatch S = P.sbs[sb];
     const int cnt = S.count;
-#pragma unroll 2
-    for (int k = threadIdx.x; k < cnt; k += kBinBlock) {
-      const int64_t gk = S.sorted_begin + k;
-      const int l = P.lp[gk];
-      double v = mt[l * NC];
-      if (NC == 3) {
-        double c, sn;
-        weights_from_raw<T>(P, psi_sorted_raw<T>(P, gk), c, sn);
-        v += c * mt[l * 3 + 1] + sn * mt[l * 3 + 2];
+    {
+      // the binning pass's split of the pixel-sorted order: a stripe per wave, kPerLane
+      // consecutive entries per lane; P m of each entry goes to its staging position
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      const int stripe = (((cnt + kWaves - 1) / kWaves) + 63) & ~63;
+      const int k0 = wave * stripe, k1 = min(cnt, k0 + stripe);
+      const int kl = k0 + kPerLane * lane;
+      if (kl < k1) {
+        LaneEntries en;
+        load_lane_entries<NC == 3>(P, S.sorted_begin + kl, en);
+#pragma unroll
+        for (int i = 0; i < kPerLane; ++i) {
+          if (kl + i < k1) {
+            const int l = entry_u16(en.lpw, i);
+            double v = mt[l * NC];
+            if (NC == 3) {
+              double c, sn;
+              weights_from_raw<T>(P, entry_psi_raw(P, en, i), c, sn);
+              v += c * mt[l * 3 + 1] + sn * mt[l * 3 + 2];
+            }
+            L.stage[entry_u16(en.pmw, i)] = v;
+          }
+        }
       }
-      L.stage[P.perm[gk]] = v;
     }
     load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), false);
     __syncthreads();
@@ -849,25 +893,8 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
       const int k1 = min(cnt, k0 + stripe);
       const int kl = k0 + kPerLane * lane;
       const bool active = kl < k1;
-      uint4 lpw[2] = {}, pmw[2] = {};
-      uint4 psw[kPerLane / 2];  // raw angles: up to 16 x 8 bytes
-      if (active) {
-        const int64_t g0 = S.sorted_begin + kl;  // a multiple of kSortAlign
-        const uint4* lpp = reinterpret_cast<const uint4*>(P.lp + g0);
-        const uint4* pmp = reinterpret_cast<const uint4*>(P.perm + g0);
-        lpw[0] = lpp[0];
-        lpw[1] = lpp[1];
-        pmw[0] = pmp[0];
-        pmw[1] = pmp[1];
-        if (POL) {
-          const int nw = P.psi_kind == 1 ? 8 : (P.psi_kind == 2 ? 4 : 2);
-          const uint4* pp = reinterpret_cast<const uint4*>((const char*)P.psi_sorted +
-                                                           g0 * (P.psi_kind == 1 ? 8 : (P.psi_kind == 2 ? 4 : 2)));
-#pragma unroll
-          for (int w = 0; w < kPerLane / 2; ++w)
-            if (w < nw) psw[w] = pp[w];
-        }
-      }
+      LaneEntries en = {};
+      if (active) load_lane_entries<POL>(P, S.sorted_begin + kl, en);  // kl: a multiple of kSortAlign
       load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), PLAN || bsrc == BSRC_DATA_OVER_TAU);
       if (lane == 0) clp[wave] = -1;
       __syncthreads();
@@ -899,7 +926,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
         __syncthreads();
       }
       if (k0 < k1) {
-        const int first_lp = __shfl((int)(lpw[0].x & 0xffffu), 0);  // lane 0 is active
+        const int first_lp = __shfl((int)(en.lpw[0].x & 0xffffu), 0);  // lane 0 is active
         // sequential reduce-by-key over this lane's entries
         int cur_lp = -1, h_lp = -1, nruns = 0;
         double cur[NV], hv[NV];
@@ -907,12 +934,10 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
         for (int q = 0; q < NV; ++q) cur[q] = hv[q] = 0.0;
 #pragma unroll
         for (int i = 0; i < kPerLane; ++i) {
-          const uint32_t wp = (i < 8) ? ((const uint32_t*)&pmw[0])[i / 2] : ((const uint32_t*)&pmw[1])[(i - 8) / 2];
-          const int pr = (int)((wp >> (16 * (i & 1))) & 0xffffu);
+          const int pr = entry_u16(en.pmw, i);
           const int gpr = PLAN ? seg_lookup(si, pr) : 0;  // lane reads with every lane of the wave active
           if (kl + i < k1) {
-            const uint32_t wl = (i < 8) ? ((const uint32_t*)&lpw[0])[i / 2] : ((const uint32_t*)&lpw[1])[(i - 8) / 2];
-            const int lp = (int)((wl >> (16 * (i & 1))) & 0xffffu);
+            const int lp = entry_u16(en.lpw, i);
             double y;
             if (PLAN) {
               y = P.chunks[schunk[gpr]].inv_tau;
@@ -920,17 +945,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
               y = stage[pr];
             }
             double c = 0.0, sn = 0.0;
-            if (POL) {
-              uint64_t raw;
-              const uint32_t* pw = (const uint32_t*)psw;
-              if (P.psi_kind == 1)
-                raw = ((uint64_t)pw[2 * i + 1] << 32) | pw[2 * i];
-              else if (P.psi_kind == 2)
-                raw = pw[i];
-              else
-                raw = (pw[i / 2] >> (16 * (i & 1))) & 0xffffu;
-              weights_from_raw<T>(P, raw, c, sn);
-            }
+            if (POL) weights_from_raw<T>(P, entry_psi_raw(P, en, i), c, sn);
             double v[NV];
             contrib<T, NV>(P, y, c, sn, v);
             if (lp != cur_lp) {
