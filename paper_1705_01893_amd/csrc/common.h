@@ -85,7 +85,8 @@ struct Segment {
 };
 
 struct DevPlan {
-  int32_t ncomp, psi_kind, precision, pad0;
+  int32_t ncomp, psi_kind, precision;
+  int32_t all_pow2;          // every chunk length is a power of two (radix 8/4/2 transforms)
   int64_t npix, nxm;         // pixels, map row length used by the tiles
   int64_t nsamp;
   int32_t nchunk, ntiles;

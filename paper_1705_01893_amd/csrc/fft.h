@@ -177,8 +177,8 @@ __device__ __forceinline__ void twiddle_powers(cx<T>* v, cx<T> w1) {
 // Kept out of line: inlining all five radix variants into the stage loop makes the register
 // allocator budget for their union and halves the occupancy of every pass.
 template <typename T, int R, bool INV, bool BFAST, int NT>
-__device__ __attribute__((noinline)) void stockham_stage(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, int p,
-                                               const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void stage_body(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, int p,
+                                           const cx<T>* __restrict__ tw) {
   constexpr int K = (Ept<T>::v + R - 1) / R;  // butterflies per thread
   const int nbf = L / R;
   const int total = nbf * nb;
@@ -227,8 +227,15 @@ __device__ __attribute__((noinline)) void stockham_stage(cx<T>* lds, int L, int 
   __syncthreads();
 }
 
+template <typename T, int R, bool INV, bool BFAST, int NT>
+__device__ __attribute__((noinline)) void stockham_stage(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, int p,
+                                               const cx<T>* __restrict__ tw) {
+  stage_body<T, R, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw);
+}
+
 // Full length-L transform of nb sequences (caller synchronises before the first stage).
-// tw: omega_L^q = exp(-2 pi i q / L), q < L.
+// tw: omega_L^q = exp(-2 pi i q / L), q < L.  Each stage is a call: a callee waits for all
+// of the caller's outstanding memory operations on entry.
 template <typename T, bool INV, bool BFAST, int NT>
 __device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, const int8_t* rad, int ns,
                         const cx<T>* __restrict__ tw) {
@@ -245,6 +252,34 @@ __device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, co
     }
     p *= R;
   }
+}
+
+// The same transform for power-of-two lengths (radices 8, 4 and 2 only), with the stages
+// inlined: no call boundaries, so loads the caller has in flight stay in flight.
+template <typename T, bool INV, bool BFAST, int NT>
+__device__ __forceinline__ void lds_fft_pow2(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, const int8_t* rad,
+                                             int ns, const cx<T>* __restrict__ tw) {
+  int p = 1;
+#pragma unroll 1
+  for (int s = 0; s < ns; ++s) {
+    const int R = rad[s];
+    if (R == 8)
+      stage_body<T, 8, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw);
+    else if (R == 4)
+      stage_body<T, 4, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw);
+    else
+      stage_body<T, 2, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw);
+    p *= R;
+  }
+}
+
+template <typename T, bool INV, bool BFAST, int NT, bool P2>
+__device__ __forceinline__ void lds_transform(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, const int8_t* rad,
+                                              int ns, const cx<T>* __restrict__ tw) {
+  if (P2)
+    lds_fft_pow2<T, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, rad, ns, tw);
+  else
+    lds_fft<T, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, rad, ns, tw);
 }
 
 }  // namespace mm

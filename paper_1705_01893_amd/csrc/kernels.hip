@@ -260,12 +260,12 @@ __device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw,
   }
 }
 
-template <typename T>
+template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    const T* __restrict__ d, const double* __restrict__ m, int src,
                                                    cx<T>* __restrict__ X, const T* __restrict__ pmbuf) {
   constexpr int E = Ept<T>::v;
-  constexpr int G = 2;  // elements whose loads are issued together
+  constexpr int G = 4;  // elements whose loads are issued together
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int np = (int)P.npix;
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
       }
     }
     __syncthreads();
-    lds_fft<T, false, true, kBlock>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    lds_transform<T, false, true, kBlock, P2>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
     cx<T>* Xc = X + ch.off / 2;
 #pragma unroll 2
     for (int u = 0; u < E; ++u) {
@@ -445,7 +445,7 @@ __device__ __forceinline__ void b_self(cx<T>* lds, const DevPlan& P, const DevCh
 }
 
 // at most 128 VGPRs, so that four 256-thread workgroups share a CU
-template <typename T>
+template <typename T, bool P2>
 __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
                                                    cx<T>* __restrict__ X, int ops, BinCtx bc,
                                                    double* __restrict__ chi2_part, int red_off) {
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     }
     __syncthreads();
     const cx<T>* tw1 = twtab<T>(P) + cl.tw1;
-    lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
+    lds_transform<T, false, false, kBlockB, P2>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
     double chi = 0.0;
     const bool self_a = (ra == 0) || (2 * ra == M2);
     if (!self_a) {
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     }
     if (ops & B_FILTER) {
       __syncthreads();
-      lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
+      lds_transform<T, true, false, kBlockB, P2>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
 #pragma unroll
       for (int u = 0; u < E / 2; ++u) {
         const int j1 = threadIdx.x + u * kBlockB;
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
 // ---------------------------------------------------------------------------------------------
 // pass C: inverse column transforms -> filtered TOD in time order (in place)
 
-template <typename T>
+template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    cx<T>* __restrict__ X) {
   constexpr int E = Ept<T>::v;
@@ -563,7 +563,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
       }
     }
     __syncthreads();
-    lds_fft<T, true, true, kBlock>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    lds_transform<T, true, true, kBlock, P2>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       const int e = threadIdx.x + u * kBlock;
@@ -1390,16 +1390,35 @@ __global__ void k_cg_chi2(const double* chi2_0, const double* xb, const double* 
 // launchers
 
 
+template <typename T, bool P2>
+static void launch_pass_a_t(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m,
+                            int src, void* work, size_t lds, hipStream_t s, const void* pmbuf) {
+  hipLaunchKernelGGL((k_pass_a<T, P2>), dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
+                     (const T*)d, m, src, (cx<T>*)work, (const T*)pmbuf);
+}
+
 hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m, int src,
                          void* work, size_t lds, hipStream_t s, const void* pmbuf) {
   if (nitems <= 0) return hipSuccess;
-  if (P.precision == 0)
-    hipLaunchKernelGGL(k_pass_a<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
-                       (const double*)d, m, src, (double2*)work, (const double*)pmbuf);
-  else
-    hipLaunchKernelGGL(k_pass_a<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
-                       (const float*)d, m, src, (float2*)work, (const float*)pmbuf);
+  // the inlined power-of-two transforms fit the FP64 tiles; the FP32 tiles (16 values per
+  // thread) spill with them, so FP32 keeps the out-of-line stages
+  const bool p2 = P.all_pow2 != 0 && P.precision == 0;
+  if (P.precision == 0) {
+    if (p2)
+      launch_pass_a_t<double, true>(P, items, nitems, d, m, src, work, lds, s, pmbuf);
+    else
+      launch_pass_a_t<double, false>(P, items, nitems, d, m, src, work, lds, s, pmbuf);
+  } else {
+    launch_pass_a_t<float, false>(P, items, nitems, d, m, src, work, lds, s, pmbuf);
+  }
   return hipGetLastError();
+}
+
+template <typename T, bool P2>
+static void launch_pass_b_t(const DevPlan& P, const ItemB* items, int nitems, void* work, int ops, const BinCtx& bc,
+                            double* chi2_part, int red_off, size_t tot, hipStream_t s) {
+  hipLaunchKernelGGL((k_pass_b<T, P2>), dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items, nitems,
+                     (cx<T>*)work, ops, bc, chi2_part, red_off);
 }
 
 hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void* work, int ops, int gain, double lam,
@@ -1413,23 +1432,39 @@ hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void*
   bc.chi2_lam = chi2_lam;
   const int red_off = (int)lds;
   const size_t tot = lds + (kBlockB / 64) * sizeof(double);
-  if (P.precision == 0)
-    hipLaunchKernelGGL(k_pass_b<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items, nitems,
-                       (double2*)work, ops, bc, chi2_part, red_off);
-  else
-    hipLaunchKernelGGL(k_pass_b<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items, nitems,
-                       (float2*)work, ops, bc, chi2_part, red_off);
+  // the inlined power-of-two transforms fit the FP64 tiles; the FP32 tiles (16 values per
+  // thread) spill with them, so FP32 keeps the out-of-line stages
+  const bool p2 = P.all_pow2 != 0 && P.precision == 0;
+  if (P.precision == 0) {
+    if (p2)
+      launch_pass_b_t<double, true>(P, items, nitems, work, ops, bc, chi2_part, red_off, tot, s);
+    else
+      launch_pass_b_t<double, false>(P, items, nitems, work, ops, bc, chi2_part, red_off, tot, s);
+  } else {
+    launch_pass_b_t<float, false>(P, items, nitems, work, ops, bc, chi2_part, red_off, tot, s);
+  }
   return hipGetLastError();
+}
+
+template <typename T, bool P2>
+static void launch_pass_c_t(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_pass_c<T, P2>), dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
+                     (cx<T>*)work);
 }
 
 hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  if (P.precision == 0)
-    hipLaunchKernelGGL(k_pass_c<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
-                       (double2*)work);
-  else
-    hipLaunchKernelGGL(k_pass_c<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
-                       (float2*)work);
+  // the inlined power-of-two transforms fit the FP64 tiles; the FP32 tiles (16 values per
+  // thread) spill with them, so FP32 keeps the out-of-line stages
+  const bool p2 = P.all_pow2 != 0 && P.precision == 0;
+  if (P.precision == 0) {
+    if (p2)
+      launch_pass_c_t<double, true>(P, items, nitems, work, lds, s);
+    else
+      launch_pass_c_t<double, false>(P, items, nitems, work, lds, s);
+  } else {
+    launch_pass_c_t<float, false>(P, items, nitems, work, lds, s);
+  }
   return hipGetLastError();
 }
 

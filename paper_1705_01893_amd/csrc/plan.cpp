@@ -434,6 +434,12 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   DevPlan& P = pl->dp;
   std::memset(&P, 0, sizeof(P));
   P.ncomp = D.ncomp;
+  P.all_pow2 = 1;
+  for (const DevClass& k : classes)
+    for (int i = 0; i < k.nr1 + k.nr2; ++i) {
+      const int r = i < k.nr1 ? k.rad1[i] : k.rad2[i - k.nr1];
+      if (r != 2 && r != 4 && r != 8) P.all_pow2 = 0;
+    }
   P.psi_kind = pl->psi_kind;
   P.precision = D.precision;
   P.npix = D.npix;

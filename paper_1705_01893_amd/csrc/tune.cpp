@@ -211,6 +211,9 @@ double time_layout(int64_t M, bool f64, const Layout& L, int64_t K, void* din, v
   DevPlan P;
   std::memset(&P, 0, sizeof(P));
   P.precision = f64 ? MM_FP64 : MM_MIXED;
+  P.all_pow2 = 1;
+  for (int8_t r : L.r1) P.all_pow2 &= (r == 2 || r == 4 || r == 8);
+  for (int8_t r : L.r2) P.all_pow2 &= (r == 2 || r == 4 || r == 8);
   P.nsamp = K * 2 * M;
   P.nchunk = (int32_t)K;
   P.chunks = (const DevChunk*)bch.p;
