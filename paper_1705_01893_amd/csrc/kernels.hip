@@ -138,19 +138,22 @@ struct BinCtx {
 };
 
 // power-law part sigma^2 (f_k/fknee)^alpha of the noise spectrum at real bin k: tabulated at plan
-// time in the FP64 form, evaluated in single precision in the FP32-mixed form
+// time in the FP64 form, evaluated in single precision in the FP32-mixed form.  The table is in
+// row layout: bin k = k2 + M2 k1 sits at k2 * M1 + k1 (bin M last), so a row of the transform
+// reads a contiguous run; tidx is that position (the row pass knows it without dividing).
 template <typename T>
-__device__ __forceinline__ T powerlaw_bin(const DevPlan& P, const DevChunk& ch, int k);
+__device__ __forceinline__ T powerlaw_bin(const DevPlan& P, const DevChunk& ch, int k, int tidx);
 template <>
-__device__ __forceinline__ double powerlaw_bin<double>(const DevPlan& P, const DevChunk& ch, int k) {
-  // row layout of the table: bin k = k2 + M2 k1 sits at k2 * M1 + k1 (bin M last), so a row
-  // of the transform reads a contiguous run of the table
-  const int idx = (k == ch.M) ? ch.M : (k % ch.M2) * ch.M1 + k / ch.M2;
-  return P.spec[ch.spec_off + idx];
+__device__ __forceinline__ double powerlaw_bin<double>(const DevPlan& P, const DevChunk& ch, int k, int tidx) {
+  return P.spec[ch.spec_off + tidx];
 }
 template <>
-__device__ __forceinline__ float powerlaw_bin<float>(const DevPlan& P, const DevChunk& ch, int k) {
+__device__ __forceinline__ float powerlaw_bin<float>(const DevPlan& P, const DevChunk& ch, int k, int tidx) {
   return powerlaw<float>(ch, k);
+}
+
+__device__ __forceinline__ int spec_index(const DevChunk& ch, int k) {
+  return (k == ch.M) ? ch.M : (k % ch.M2) * ch.M1 + k / ch.M2;
 }
 
 // 1/x: correctly rounded in float64; the hardware reciprocal (1 ulp) in float32
@@ -167,9 +170,9 @@ __device__ __forceinline__ float recip<float>(float x) {
 
 // gain applied to R_k (includes the 1/M of the inverse transform) and chi^2 weight 1/(n N'_k)
 template <typename T>
-__device__ __forceinline__ void bin_factors(const DevPlan& P, const DevChunk& ch, const BinCtx& bc, int k, T& g,
-                                            double& cw) {
-  const T pl = powerlaw_bin<T>(P, ch, k);
+__device__ __forceinline__ void bin_factors(const DevPlan& P, const DevChunk& ch, const BinCtx& bc, int k, int tidx,
+                                            T& g, double& cw) {
+  const T pl = powerlaw_bin<T>(P, ch, k, tidx);
   const T N = (T)ch.sigma2 + pl;
   const T tau = (T)ch.tau;
   T gg;
@@ -371,7 +374,9 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
 
 template <typename T>
 __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevChunk& ch, const DevClass& cl,
-                                       const BinCtx& bc, int ops, int k, int ia, int ib, double& chi) {
+                                       const BinCtx& bc, int ops, int k, int ia, int ib, int ta, int tb,
+                                       double& chi) {
+  // bins k (LDS ia, table position ta) and M - k (LDS ib, table position tb)
   const cx<T> Zk = lds[ia], Zm = lds[ib];
   const int M = ch.M;
   cx<T> E, O;
@@ -386,8 +391,8 @@ __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevCh
   const cx<T> Rm = csub(conjc(E), conjc(wO));
   T gk, gm;
   double cwk, cwm;
-  bin_factors<T>(P, ch, bc, k, gk, cwk);
-  bin_factors<T>(P, ch, bc, M - k, gm, cwm);
+  bin_factors<T>(P, ch, bc, k, ta, gk, cwk);
+  bin_factors<T>(P, ch, bc, M - k, tb, gm, cwm);
   if (ops & B_CHI2) chi += 2.0 * (norm2(Rk) * cwk + norm2(Rm) * cwm);
   if (ops & B_FILTER) {
     const cx<T> Yk = cscale(Rk, gk), Ym = cscale(Rm, gm);
@@ -415,8 +420,8 @@ __device__ __forceinline__ void b_dc(cx<T>* lds, const DevPlan& P, const DevChun
   const T R0 = Z.x + Z.y, RM = Z.x - Z.y;
   T g0, gM;
   double c0, cM;
-  bin_factors<T>(P, ch, bc, 0, g0, c0);
-  bin_factors<T>(P, ch, bc, ch.M, gM, cM);
+  bin_factors<T>(P, ch, bc, 0, 0, g0, c0);
+  bin_factors<T>(P, ch, bc, ch.M, ch.M, gM, cM);
   if (ops & B_CHI2) chi += (double)R0 * (double)R0 * c0 + (double)RM * (double)RM * cM;
   if (ops & B_FILTER) {
     const T Y0 = R0 * g0, YM = RM * gM;
@@ -429,12 +434,12 @@ __device__ __forceinline__ void b_dc(cx<T>* lds, const DevPlan& P, const DevChun
 
 template <typename T>
 __device__ __forceinline__ void b_self(cx<T>* lds, const DevPlan& P, const DevChunk& ch, const BinCtx& bc, int ops,
-                                       int k, int ia, double& chi) {
+                                       int k, int ia, int ta, double& chi) {
   // k = M/2: R_k = conj(Z_k); the retangled value is conj(Y_k)
   const cx<T> Z = lds[ia];
   T g;
   double cw;
-  bin_factors<T>(P, ch, bc, k, g, cw);
+  bin_factors<T>(P, ch, bc, k, ta, g, cw);
   if (ops & B_CHI2) chi += 2.0 * norm2(Z) * cw;
   if (ops & B_FILTER) {
     cx<T> y;
@@ -482,7 +487,7 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
       for (int k1 = threadIdx.x; k1 < M1; k1 += kBlockB) {
         const int pk1 = M1 - 1 - k1;
         const int k = ra + M2 * k1;
-        b_pair<T>(lds, P, ch, cl, bc, ops, k, k1, M1 + pk1, chi);
+        b_pair<T>(lds, P, ch, cl, bc, ops, k, k1, M1 + pk1, ra * M1 + k1, rb * M1 + pk1, chi);
       }
     } else {
       for (int sl = 0; sl < nrow; ++sl) {
@@ -491,12 +496,13 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
           const int pk1 = (row == 0) ? (k1 == 0 ? 0 : M1 - k1) : (M1 - 1 - k1);
           if (k1 > pk1) continue;
           const int k = row + M2 * k1;
+          // bins k and M - k both lie in this row (row 0 or row M2/2)
           if (k == 0)
             b_dc<T>(lds, P, ch, bc, ops, sl * M1, chi);
           else if (k1 == pk1)
-            b_self<T>(lds, P, ch, bc, ops, k, sl * M1 + k1, chi);
+            b_self<T>(lds, P, ch, bc, ops, k, sl * M1 + k1, row * M1 + k1, chi);
           else
-            b_pair<T>(lds, P, ch, cl, bc, ops, k, sl * M1 + k1, sl * M1 + pk1, chi);
+            b_pair<T>(lds, P, ch, cl, bc, ops, k, sl * M1 + k1, sl * M1 + pk1, row * M1 + k1, row * M1 + pk1, chi);
         }
       }
     }
@@ -1098,7 +1104,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
 template <typename T>
 __device__ __forceinline__ void grad_bin(const DevPlan& P, const DevChunk& ch, int k, double w, cx<T> R, cx<T> Z,
                                          double* acc) {
-  const double pl = (double)powerlaw_bin<T>(P, ch, k);
+  const double pl = (double)powerlaw_bin<T>(P, ch, k, spec_index(ch, k));
   const double N = ch.sigma2 + pl;
   const double f = (double)(k == 0 ? 1 : k) * ch.df;
   const double cross = (double)Z.x * (double)R.x + (double)Z.y * (double)R.y;
@@ -1414,13 +1420,6 @@ hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, cons
   return hipGetLastError();
 }
 
-template <typename T, bool P2>
-static void launch_pass_b_t(const DevPlan& P, const ItemB* items, int nitems, void* work, int ops, const BinCtx& bc,
-                            double* chi2_part, int red_off, size_t tot, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass_b<T, P2>), dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items, nitems,
-                     (cx<T>*)work, ops, bc, chi2_part, red_off);
-}
-
 hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void* work, int ops, int gain, double lam,
                          double chi2_lam, double* chi2_part, size_t lds, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
@@ -1432,17 +1431,13 @@ hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void*
   bc.chi2_lam = chi2_lam;
   const int red_off = (int)lds;
   const size_t tot = lds + (kBlockB / 64) * sizeof(double);
-  // the inlined power-of-two transforms fit the FP64 tiles; the FP32 tiles (16 values per
-  // thread) spill with them, so FP32 keeps the out-of-line stages
-  const bool p2 = P.all_pow2 != 0 && P.precision == 0;
-  if (P.precision == 0) {
-    if (p2)
-      launch_pass_b_t<double, true>(P, items, nitems, work, ops, bc, chi2_part, red_off, tot, s);
-    else
-      launch_pass_b_t<double, false>(P, items, nitems, work, ops, bc, chi2_part, red_off, tot, s);
-  } else {
-    launch_pass_b_t<float, false>(P, items, nitems, work, ops, bc, chi2_part, red_off, tot, s);
-  }
+  // the row pass keeps the out-of-line stages: inlined, its 128-VGPR bound made it spill
+  if (P.precision == 0)
+    hipLaunchKernelGGL((k_pass_b<double, false>), dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items,
+                       nitems, (double2*)work, ops, bc, chi2_part, red_off);
+  else
+    hipLaunchKernelGGL((k_pass_b<float, false>), dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items,
+                       nitems, (float2*)work, ops, bc, chi2_part, red_off);
   return hipGetLastError();
 }
 
