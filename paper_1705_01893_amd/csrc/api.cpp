@@ -56,11 +56,14 @@ hipError_t timed(mm_plan_s* pl, int pass, hipStream_t s, F&& launch) {
 // r = src(d, m) -> filtered y in the work buffer (passes A, B, C).  Returns with the
 // chi^2 partials in d_chi2_part when ops includes B_CHI2.
 mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, int ops, int gain, double lam,
-                       double chi2_lam, hipStream_t s, bool pm_current = false) {
-  // large maps: P m comes from the projection buffer (projected here unless it already holds P m)
+                       double chi2_lam, hipStream_t s, bool map_current = false) {
+  // large maps: P m comes from the projection buffer (projected here unless it already holds P m);
+  // otherwise I/Q/U maps are gathered from their interleaved copy (made here unless current)
   if (pl->pm_mode && (src == SRC_D_MINUS_PM || src == SRC_PM)) {
-    if (!pm_current) MM_TRY_HIP(timed(pl, 4, s, [&] { return launch_project(pl->dp, m, pl->d_pm, s); }));
+    if (!map_current) MM_TRY_HIP(timed(pl, 4, s, [&] { return launch_project(pl->dp, m, pl->d_pm, s); }));
     src = (src == SRC_PM) ? SRC_PMBUF : SRC_D_MINUS_PMBUF;
+  } else if (pl->dp.mapi && (src == SRC_D_MINUS_PM || src == SRC_PM) && !map_current) {
+    MM_TRY_HIP(launch_interleave(pl->dp, m, s));
   }
   MM_TRY_HIP(timed(pl, 0, s, [&] {
     return launch_pass_a(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), d, m, src, pl->d_work, pl->lds_ac, s,
@@ -79,14 +82,15 @@ mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, i
 
 // chi^2(m, lam) of d - P m into *total (device) and optionally per chunk (device)
 mm_status chi2_device(mm_plan_s* pl, const void* d, const double* m, double lam, double* total, double* per_chunk,
-                      hipStream_t s, bool pm_current = false) {
-  MM_TRY(sweep_filter(pl, d, m, SRC_D_MINUS_PM, B_CHI2, GAIN_NINV, 1.0, lam, s, pm_current));
+                      hipStream_t s, bool map_current = false) {
+  MM_TRY(sweep_filter(pl, d, m, SRC_D_MINUS_PM, B_CHI2, GAIN_NINV, 1.0, lam, s, map_current));
   MM_TRY_HIP(launch_chi2_reduce(pl->d_chunk_item_begin, pl->d_chi2_part, (int)pl->nchunk, per_chunk, total, s));
   return MM_OK;
 }
 
 // one messenger iteration m_out = m_in + W^-1 P^T G_lambda (d - P m_in); chi2(m_in) into chi2_dev if non-null
-// chained: the projection buffer already holds P m_in (it was written by the previous iteration)
+// chained: the map-derived copy the sweeps read (P m, or the interleaved map) already belongs to
+// m_in: the previous iteration's binning epilogue wrote it
 mm_status iterate(mm_plan_s* pl, const void* d, double lam, const double* m_in, double* m_out, double* chi2_dev,
                   hipStream_t s, bool chained = false) {
   if (std::isinf(lam)) {
@@ -387,9 +391,11 @@ mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const do
   }
   const bool pm = plan->pm_mode != 0;
   if (pm) MM_TRY_HIP(launch_project(plan->dp, m, plan->d_pm, s));
+  MM_TRY_HIP(launch_interleave(plan->dp, m, s));  // no-op without an interleaved copy
   MM_TRY_HIP(launch_pass_a(plan->dp, plan->d_itemsAC, (int)plan->itemsAC.size(), d, m,
                            pm ? SRC_D_MINUS_PMBUF : SRC_D_MINUS_PM, plan->d_work, plan->lds_ac, s, plan->d_pm));
   if (pm) MM_TRY_HIP(launch_project(plan->dp, z, plan->d_pm, s));
+  MM_TRY_HIP(launch_interleave(plan->dp, z, s));
   MM_TRY_HIP(launch_pass_a(plan->dp, plan->d_itemsAC, (int)plan->itemsAC.size(), nullptr, z,
                            pm ? SRC_PMBUF : SRC_PM, plan->d_work2, plan->lds_ac, s, plan->d_pm));
   MM_TRY_HIP(launch_grad(plan->dp, plan->d_itemsB, (int)plan->itemsB.size(), plan->d_chunk_item_begin,

@@ -108,6 +108,8 @@ struct DevPlan {
   const double* spec;        // FP64 form: sigma^2 (f_k / fknee)^alpha per chunk bin (f_0 -> f_1)
   const double* winv;        // [nw][npix], nw = 1 or 6 (00 01 02 11 12 22)
   const uint8_t* solvable;   // [npix]
+  double2* mapi;             // I/Q/U map interleaved, [npix][2] = (I, Q), (U, 0): one line per gather
+                             // (gather access with ncomp = 3; null otherwise)
 };
 
 // pass-A sources
@@ -135,6 +137,7 @@ hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void
                          hipStream_t s);
 hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
                       double* w_out, int32_t* hits_out, hipStream_t s, void* pm_out = nullptr);
+hipError_t launch_interleave(const DevPlan& P, const double* m, hipStream_t s);
 hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipStream_t s);
 hipError_t launch_spectrum(const DevPlan& P, double* spec, hipStream_t s);
 hipError_t launch_grad(const DevPlan& P, const ItemB* items, int nitems, const int32_t* chunk_item_begin,

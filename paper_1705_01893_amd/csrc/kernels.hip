@@ -104,19 +104,6 @@ __device__ __forceinline__ void psi_weights<float>(const DevPlan& P, const void*
 }
 
 // (P m)_j for one sample (float64)
-template <typename T>
-__device__ __forceinline__ double project_one(const DevPlan& P, const double* __restrict__ m, int64_t j) {
-  const int p = P.pix[j];
-  if (p < 0) return 0.0;
-  double v = m[p];
-  if (P.ncomp == 3) {
-    T c, s;
-    psi_weights<T>(P, P.psi, j, c, s);
-    v += (double)c * m[P.npix + p] + (double)s * m[2 * P.npix + p];
-  }
-  return v;
-}
-
 // noise spectrum pieces at real bin k: pl = sigma^2 (f/fknee)^alpha with the DC bin at f_1
 template <typename T>
 __device__ __forceinline__ T powerlaw(const DevChunk& ch, int k);
@@ -316,11 +303,14 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
           const int px = h == 0 ? pp[u].x : pp[u].y;
           double v = 0.0;
           if (px >= 0) {
-            v = m[px];
             if (P.ncomp == 3) {
+              // the interleaved copy: I, Q and U of a pixel share one cache line
+              const double2 iq = P.mapi[2 * px], u0 = P.mapi[2 * px + 1];
               T c, sn;
               psi_from_raw<T>(P, raw[u], h, c, sn);
-              v += (double)c * m[np + px] + (double)sn * m[2 * np + px];
+              v = iq.x + (double)c * iq.y + (double)sn * u0.x;
+            } else {
+              v = m[px];
             }
           }
           pm[u][h] = v;
@@ -1076,12 +1066,18 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
           u[1] = i01 * a[0] + i11 * a[1] + i12 * a[2];
           u[2] = i02 * a[0] + i12 * a[1] + i22 * a[2];
         }
+        double rr[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
           double r = 0.0;
           if (ok) r = (epi == EPI_UPDATE) ? m_in[q * np + p] + u[q] : u[q];
           out[q * np + p] = r;
+          rr[q] = r;
           if (!PLAN && pm_out) acc[l * NV + q] = r;  // the tile's new map values, for P m below
+        }
+        if (NV == 3 && P.mapi && (epi == EPI_UPDATE || epi == EPI_REPLACE)) {
+          P.mapi[2 * p] = make_double2(rr[0], rr[NV > 1 ? 1 : 0]);
+          P.mapi[2 * p + 1] = make_double2(rr[NV > 2 ? 2 : 0], 0.0);
         }
       }
     }
@@ -1469,6 +1465,21 @@ static hipError_t launch_bin_t(const DevPlan& P, int bsrc, const void* src, int 
   const size_t lds = bin_lds_bytes<NV>(NV == 2 || NV == 7);
   hipLaunchKernelGGL((k_bin<T, NV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, bsrc,
                      (const T*)src, epi, m_in, out, w_out, hits_out, sol_out, (T*)pm_out);
+  return hipGetLastError();
+}
+
+__global__ void k_interleave(DevPlan P, const double* __restrict__ m) {
+  const int64_t np = P.npix;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    P.mapi[2 * p] = make_double2(m[p], m[np + p]);
+    P.mapi[2 * p + 1] = make_double2(m[2 * np + p], 0.0);
+  }
+}
+
+hipError_t launch_interleave(const DevPlan& P, const double* m, hipStream_t s) {
+  if (!P.mapi) return hipSuccess;
+  const int64_t g = (P.npix + 255) / 256;
+  hipLaunchKernelGGL(k_interleave, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, s, P, m);
   return hipGetLastError();
 }
 

@@ -542,6 +542,10 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   // then P m is produced in pixel-tile order instead
   pl->pm_mode = D.map_access == MM_MAP_PROJECTED ||
                 (D.map_access == MM_MAP_AUTO && mapn * (int64_t)sizeof(double) > ((int64_t)4 << 20));
+  if (!pl->pm_mode && D.ncomp == 3) {
+    if ((st = plan_alloc(pl, (size_t)D.npix * 2 * sizeof(double2), &p)) != MM_OK) return st;
+    P.mapi = (double2*)p;
+  }
   if (pl->pm_mode) {
     if ((st = plan_alloc(pl, (size_t)ns * (f64 ? 8 : 4), &p)) != MM_OK) return st;
     pl->d_pm = p;
