@@ -90,6 +90,94 @@ def load_traffic(workload: str, khash: str):
     return t
 
 
+PASS_KERNELS = ["k_pass_a<", "k_pass_b<", "k_pass_c<", "k_bin<", "k_project<"]
+
+
+def _counter_rows(run_dir: str):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {run_dir}")
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def write_traffic(args, fetch_dir: str, write_dir: str) -> None:
+    """HBM bytes per launch of each pass from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch).
+
+    Only the workload's dispatches count: those after the plan's precompute binning launch (the
+    transform-layout tuner's timing launches come before it) and outside the time-to-chi^2 part
+    (not run with --no-chi2).  Counters are scaled by what they read for the plain 1 GiB copy of
+    --copy-calibration (torch's copy kernel, the largest WRITE_SIZE of a non-library kernel)."""
+    per = {}
+    scale = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(d) if r["Counter_Name"] == counter]
+        start = max(int(r["Dispatch_Id"]) for r in rows
+                    if "k_bin<" in r["Kernel_Name"] and (", 7>" in r["Kernel_Name"] or ", 2>" in r["Kernel_Name"]))
+        vals = {}
+        for r in rows:
+            if int(r["Dispatch_Id"]) <= start:
+                continue
+            key = (r["Kernel_Name"], r["Dispatch_Id"])
+            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+        copies = [v for (k, _), v in vals.items() if "copy" in k.lower() and "mm::" not in k]
+        if not copies:
+            raise SystemExit("no copy kernel in the counters: profile a --copy-calibration run")
+        scale[counter] = (1 << 30) / (max(copies) * 1024.0)
+        for i, kname in enumerate(PASS_KERNELS):
+            vs = [v for (k, _), v in vals.items() if kname in k]
+            if vs:
+                per.setdefault(i, {})[counter] = sum(vs) / len(vs) * 1024.0 * scale[counter]
+                per[i]["launches_" + counter] = len(vs)
+    passes = []
+    for i, name in enumerate(PASS_NAMES):
+        f = per.get(i, {}).get("FETCH_SIZE")
+        w = per.get(i, {}).get("WRITE_SIZE")
+        passes.append({"pass": name, "fetch_bytes": f, "write_bytes": w,
+                       "bytes_per_launch": (f + w) if f is not None and w is not None else None})
+    name = args.workload + ("_mixed" if args.mixed else "")
+    out = {"workload": name, "kernel_hash": kernel_hash(),
+           "calibration": {"FETCH_SIZE": scale["FETCH_SIZE"], "WRITE_SIZE": scale["WRITE_SIZE"],
+                           "reference": "torch copy of 1 GiB (bench.py --copy-calibration)"},
+           "passes": passes,
+           "commands": [f"rocprofv3 --pmc {c} --kernel-trace -d <dir> -o run -- python3 bench.py --workload "
+                        f"{args.workload}{' --mixed' if args.mixed else ''} --steps 2 --warmup 1 --no-cpu --no-chi2 "
+                        "--copy-calibration" for c in ("FETCH_SIZE", "WRITE_SIZE")]}
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def summarize_trace(trace_dir: str) -> None:
+    """Markdown table of the workload's kernels (dispatches after the plan's precompute binning)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_trace.csv under {trace_dir}")
+    with open(files[0]) as fh:
+        rows = list(csv.DictReader(fh))
+    start = max(int(r["Dispatch_Id"]) for r in rows
+                if "k_bin<" in r["Kernel_Name"] and (", 7>" in r["Kernel_Name"] or ", 2>" in r["Kernel_Name"]))
+    acc = {}
+    for r in rows:
+        if int(r["Dispatch_Id"]) <= start or "mm::" not in r["Kernel_Name"]:
+            continue
+        k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        a = acc.setdefault(k, [0, 0.0])
+        a[0] += 1
+        a[1] += dt
+    total = sum(a[1] for a in acc.values())
+    print("| kernel | launches | mean us | share of kernel time |")
+    print("|---|---|---|---|")
+    for k, (n, t) in sorted(acc.items(), key=lambda kv: -kv[1][1]):
+        print(f"| {k} | {n} | {t / n:.1f} | {100 * t / total:.1f}% |")
+
+
 def cpu_baseline(prob, seconds: float):
     """The oracle's messenger step on the same workload, single-threaded NumPy, bounded in time."""
     from threadpoolctl import threadpool_limits
@@ -220,9 +308,23 @@ def main():
     ap.add_argument("--no-chi2", action="store_true", help="skip the time-to-chi2-target comparison")
     ap.add_argument("--map-access", choices=["auto", "gather", "projected"], default="auto",
                     help="how the time-domain sweeps read P m (the plan's rule by default)")
+    ap.add_argument("--tune", choices=["measure", "static"], default="measure",
+                    help="transform layouts: timed at plan time (default) or the fixed rule")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU run: read two rocprofv3 --pmc outputs (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--copy-calibration run of this workload and write profiles/traffic_<workload>.json")
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
+                    help="no GPU run: per-kernel launch count and mean duration of the workload's dispatches "
+                         "in a rocprofv3 --kernel-trace output (markdown table)")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args, *args.write_traffic)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path shards over detector "
               "chunks with one map all-reduce per iteration, which this build does not implement)",
@@ -266,7 +368,8 @@ def main():
                       fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=pix,
                       psi=psi, psi_table=prob.psi_table, precision=precision,
                       map_access={"auto": mm.MM_MAP_AUTO, "gather": mm.MM_MAP_GATHER,
-                                  "projected": mm.MM_MAP_PROJECTED}[args.map_access])
+                                  "projected": mm.MM_MAP_PROJECTED}[args.map_access],
+                      tune=mm.MM_TUNE_MEASURE if args.tune == "measure" else mm.MM_TUNE_STATIC)
     t_plan = time.perf_counter() - t0
     log(f"plan built in {t_plan:.1f} s ({mm.mm_plan_workspace_bytes(plan) / 2**30:.2f} GiB of device tables)")
     ns = prob.nsamp_total
