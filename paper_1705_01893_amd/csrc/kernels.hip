@@ -250,6 +250,16 @@ __device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw,
   }
 }
 
+// Item order of the column pass.  Workgroups are dispatched to the 8 XCDs round-robin by index,
+// and adjacent column blocks of a chunk share the 128-byte lines of the 8-byte pixel pairs; within
+// each group of 16 workgroups, items 2k and 2k+1 go to workgroups k and k+8, which sit on the same
+// XCD.  A bijection of every 16-aligned group, so with a grid of a multiple of 16 every item is
+// still taken exactly once (other grids keep the plain order).
+__device__ __forceinline__ int xcd_pair_order(int b, int grid) {
+  if (grid % 16) return b;
+  return (b & ~15) + 2 * (b & 7) + ((b >> 3) & 1);
+}
+
 template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    const T* __restrict__ d, const double* __restrict__ m, int src,
@@ -259,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int np = (int)P.npix;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  for (int it = xcd_pair_order(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const ItemAC item = items[it];
     const DevChunk ch = P.chunks[item.chunk];
     const DevClass& cl = P.classes[ch.cls];
