@@ -1,6 +1,10 @@
-"""Parity at the benchmark workload's full size (16 detectors x 2^20 samples, 256x256 I/Q/U,
-FP64), in the launch configuration bench.py times: the binned map (lambda = inf step), one
-lambda = 1 iteration from it and chi^2, against the oracle on every pixel."""
+"""Parity at full size, in the launch configuration bench.py times.
+
+* The benchmark workload (16 detectors x 2^20 samples, 256x256 I/Q/U, FP64): the binned map
+  (lambda = inf step), one lambda = 1 iteration from it and chi^2, against the oracle on every pixel.
+* The batched workload (512 uneven chunks, 4.4e8 samples, FP32-mixed) on outputs the oracle
+  computes piece by piece (sampled pixels and sampled chunks).
+* The large workload's structure (uint16 angle table, 2048x2048 map) at 8 detectors."""
 
 import math
 import sys
@@ -41,4 +45,127 @@ def test_iqu256_full_size_iteration():
     r2 = messenger_step(S, prob.d, r1, 1.0)
     assert np.linalg.norm(m2.cpu().numpy() - r2) / np.linalg.norm(r2) < 1e-10
     assert c2.item() == pytest.approx(chi2(S, prob.d, r1), rel=1e-10)
+    plan.close()
+
+
+def _sampled_chunks(prob, k, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(prob.nchunk, size=min(k, prob.nchunk), replace=False))
+
+
+def _chunk_subset(prob, chunks):
+    """Arrays of a subset of chunks, with their own offset table (for the oracle)."""
+    off = prob.chunk_off
+    sl = [slice(int(off[c]), int(off[c + 1])) for c in chunks]
+    lens = np.array([s.stop - s.start for s in sl], dtype=np.int64)
+    sub_off = np.concatenate([[0], np.cumsum(lens)])
+    cat = lambda a: np.concatenate([a[s] for s in sl])  # noqa: E731
+    return sl, sub_off, cat
+
+
+def _sampled_binned_map(prob, pixels):
+    """lambda = inf map W^-1 P^T T^-1 d at the given pixels, from their own samples only."""
+    from oracle.pointing import Pointing, invert_blocks
+    sel = np.isin(prob.pix, pixels)
+    idx = np.nonzero(sel)[0]
+    chunk_of = np.searchsorted(prob.chunk_off, idx, side="right") - 1
+    inv_tau = 1.0 / (prob.sigma[chunk_of] ** 2)
+    pt = Pointing(prob.pix[idx], prob.psi_values()[idx], prob.npix, prob.ncomp)
+    W = pt.weight_blocks(inv_tau)
+    W_inv, solvable = invert_blocks(W, pt.hits())
+    b = pt.back(np.asarray(prob.d[idx], dtype=np.float64) * inv_tau)
+    m = np.einsum("pqr,rp->qp", W_inv, b)
+    return m[:, pixels], solvable[pixels]
+
+
+def test_batched1024_full_size_sampled():
+    """The 512-chunk uneven FP32-mixed workload at full size (4.4e8 samples, 1024x1024 I/Q/U,
+    projected map access): hit counts bit-exact; the lambda = inf map and the solvable mask at
+    4096 sampled pixels; per-chunk chi^2 of the true sky and N^-1 P m_true sample by sample on 12
+    sampled chunks (mixed-precision bars)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle.grad import data_grad
+    from oracle.messenger import chi2_of_residual, make_setup
+    dev = torch.device("cuda:0")
+    print("[fullsize] generating batched1024", flush=True)
+    prob = make_problem(config_by_name("batched1024"), workers=16)
+    pix = torch.from_numpy(prob.pix).to(dev)
+    plan = mm.mm_plan(ncomp=3, npix=prob.npix, nx=prob.cfg.nx, chunk_off=prob.chunk_off, fsample=prob.fsample,
+                      sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=pix,
+                      psi=torch.from_numpy(prob.psi).to(dev), precision=mm.MM_MIXED)
+    assert mm.mm_plan_map_access(plan) == mm.MM_MAP_PROJECTED
+    d = torch.from_numpy(prob.d).to(dev)
+    hits = torch.zeros(prob.npix, dtype=torch.int32, device=dev)
+    mask = torch.zeros(prob.npix, dtype=torch.uint8, device=dev)
+    mm.mm_plan_hits(plan, hits)
+    mm.mm_plan_solvable(plan, mask)
+    m0 = torch.zeros((3, prob.npix), dtype=torch.float64, device=dev)
+    m1 = torch.zeros_like(m0)
+    mm.mm_messenger_iter(plan, d, math.inf, m0, m1)
+    mt = torch.from_numpy(prob.m_true).to(dev)
+    per = torch.zeros(prob.nchunk, dtype=torch.float64, device=dev)
+    mm.mm_chi2(plan, d, mt, 1.0, per)
+    per30 = torch.zeros_like(per)
+    mm.mm_chi2(plan, d, mt, 30.0, per30)
+    y = torch.zeros_like(d)
+    mm.mm_tod_apply(plan, 0, mt, y)
+    torch.cuda.synchronize()
+    print("[fullsize] oracle", flush=True)
+    np.testing.assert_array_equal(hits.cpu().numpy(), np.bincount(prob.pix[prob.pix >= 0], minlength=prob.npix))
+    rng = np.random.default_rng(11)
+    pixels = np.sort(rng.choice(prob.npix, size=4096, replace=False))
+    ref_m, ref_sol = _sampled_binned_map(prob, pixels)
+    np.testing.assert_array_equal(mask.cpu().numpy()[pixels].astype(bool), ref_sol)
+    got = m1.cpu().numpy()[:, pixels]
+    assert np.linalg.norm(got - ref_m) / np.linalg.norm(ref_m) < 1e-5
+    chunks = _sampled_chunks(prob, 12, 12)
+    sl, sub_off, cat = _chunk_subset(prob, chunks)
+    S = make_setup(sub_off, prob.fsample[chunks], prob.sigma[chunks], prob.fknee[chunks], prob.alpha[chunks],
+                   cat(prob.pix), cat(prob.psi_values()), prob.npix, 3)
+    d_sub = cat(prob.d).astype(np.float64)
+    r = d_sub - S.pointing.project(prob.m_true)
+    for lam, got_c in ((1.0, per), (30.0, per30)):
+        ref_c = chi2_of_residual(S, r, lam, per_chunk=True)
+        np.testing.assert_allclose(got_c.cpu().numpy()[chunks], ref_c, rtol=1e-6)
+    ref_y = data_grad(S, prob.m_true)
+    y_np = y.cpu().numpy()
+    for i, s in enumerate(sl):
+        a, b = int(sub_off[i]), int(sub_off[i + 1])
+        assert np.linalg.norm(y_np[s] - ref_y[a:b]) / np.linalg.norm(ref_y[a:b]) < 1e-5, int(chunks[i])
+    plan.close()
+
+
+def test_large2048_shape_reduced():
+    """The large single-GPU share's structure (2048x2048 I/Q/U, uint16 angle-table indices, 5% of
+    detectors at fknee = 5 Hz, FP32-mixed) at 8 detectors of 2^21 samples: the lambda = inf map on
+    every pixel and one lambda = 1 iteration with chi^2, against the oracle."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle.messenger import binned_map, chi2, messenger_step, setup_from_problem
+    dev = torch.device("cuda:0")
+    cfg = config_by_name("large2048").scaled("large2048_8det", ndet=8, nsamp=1 << 21, nx=2048,
+                                              frac_high_knee=0.25)
+    print("[fullsize] generating large2048 shape, 8 detectors", flush=True)
+    prob = make_problem(cfg, workers=16)
+    assert prob.psi_index is not None
+    psi = torch.from_numpy(prob.psi_index.view(np.int16)).to(dev).view(torch.uint16)
+    plan = mm.mm_plan(ncomp=3, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off, fsample=prob.fsample,
+                      sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=torch.from_numpy(prob.pix).to(dev),
+                      psi=psi, psi_table=prob.psi_table, precision=mm.MM_MIXED)
+    d = torch.from_numpy(prob.d).to(dev)
+    m0 = torch.zeros((3, prob.npix), dtype=torch.float64, device=dev)
+    m1 = torch.zeros_like(m0)
+    m2 = torch.zeros_like(m0)
+    c2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    mm.mm_messenger_iter(plan, d, math.inf, m0, m1)
+    mm.mm_messenger_iter(plan, d, 1.0, m1, m2, c2)
+    torch.cuda.synchronize()
+    print("[fullsize] oracle", flush=True)
+    S = setup_from_problem(prob)
+    r1 = binned_map(S, prob.d)
+    assert np.linalg.norm(m1.cpu().numpy() - r1) / np.linalg.norm(r1) < 1e-5
+    r2 = messenger_step(S, prob.d, r1, 1.0)
+    assert np.linalg.norm(m2.cpu().numpy() - r2) / np.linalg.norm(r2) < 1e-5
+    assert c2.item() == pytest.approx(chi2(S, prob.d, r1), rel=1e-6)
     plan.close()

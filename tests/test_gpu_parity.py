@@ -283,3 +283,33 @@ def test_unbiased_noise_free(dev):
     mm.mm_solve(plan, tod(t, dev, mm.MM_FP64), [100.0, 10.0, 1.0], [2, 2, 2], m)
     torch.cuda.synchronize()
     assert np.abs(m.cpu().numpy() - m_true).max() < 1e-11 * np.abs(m_true).max()
+
+
+@pytest.mark.parametrize("precision", [mm.MM_FP64, mm.MM_MIXED])
+def test_angle_table_indices(dev, precision):
+    """Angles stored as uint16 indices into a float32 table (MM_PSI_U16): the oracle takes the
+    identical table values promoted to float64."""
+    say(f"[psi u16] precision={precision}")
+    t = tiny_problem(919, ncomp=3, **SHAPES["mixed_radix"])
+    rng = np.random.default_rng(3)
+    table = np.linspace(0.0, np.pi, 48, endpoint=False).astype(np.float32)
+    idx = rng.integers(0, table.size, size=t.nsamp).astype(np.uint16)
+    t.psi = table[idx].astype(np.float64)
+    S = oracle_setup(t)
+    plan = mm.mm_plan(ncomp=3, npix=t.npix, nx=t.nx, chunk_off=t.chunk_off, fsample=t.fsample, sigma=t.sigma,
+                      fknee=t.fknee, alpha=t.alpha, pix=torch.from_numpy(t.pix).to(dev),
+                      psi=torch.from_numpy(idx.view(np.int16)).to(dev).view(torch.uint16), psi_table=table,
+                      precision=precision)
+    mask = torch.zeros(t.npix, dtype=torch.uint8, device=dev)
+    mm.mm_plan_solvable(plan, mask)
+    m0 = random_map(4, 3, t.npix)
+    m0[:, ~S.solvable] = 0.0
+    mo = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+    c2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    mm.mm_messenger_iter(plan, tod(t, dev, precision), 3.0, torch.from_numpy(m0).to(dev), mo, c2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(mask.cpu().numpy().astype(bool), S.solvable)
+    d64 = t.d.astype(np.float32).astype(np.float64) if precision == mm.MM_MIXED else t.d
+    tol, ctol = (F64_TOL, F64_TOL) if precision == mm.MM_FP64 else (MIX_TOL, MIX_CHI2)
+    assert rel(mo.cpu().numpy(), messenger_step(S, d64, m0, 3.0)) < tol
+    assert c2.item() == pytest.approx(chi2(S, d64, m0), rel=ctol)
