@@ -354,7 +354,7 @@ mm_status mm_lift_rhs(mm_plan_t plan, const double* g, void* out, mm_stream_t st
   double* u = plan->d_map[5];
   MM_TRY_HIP(launch_winv_apply(plan->dp, g, u, s));
   MM_TRY(sweep_filter(plan, nullptr, u, SRC_PM, B_FILTER, GAIN_LIFT, 1.0, 1.0, s));
-  MM_TRY_HIP(launch_copy_bytes(out, plan->d_work, plan->ns * (plan->precision == MM_FP64 ? 8 : 4), s));
+  MM_TRY_HIP(launch_unshift(plan->dp, plan->d_work, out, s));
   return MM_OK;
 }
 
@@ -372,7 +372,7 @@ mm_status mm_tod_apply(mm_plan_t plan, int32_t which, double lambda, const doubl
   const int gain = which == 0 ? GAIN_NINV : (which == 1 ? GAIN_MESSENGER : GAIN_LIFT);
   hipStream_t s = S(stream);
   MM_TRY(sweep_filter(plan, nullptr, x, SRC_PM, B_FILTER, gain, which == 1 ? lambda : 1.0, 1.0, s));
-  MM_TRY_HIP(launch_copy_bytes(out, plan->d_work, plan->ns * (plan->precision == MM_FP64 ? 8 : 4), s));
+  MM_TRY_HIP(launch_unshift(plan->dp, plan->d_work, out, s));
   return MM_OK;
 }
 
@@ -386,7 +386,7 @@ mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const do
   hipStream_t s = S(stream);
   if (!plan->d_work2) {
     void* p = nullptr;
-    MM_TRY(plan_alloc(plan, (size_t)plan->ns * (plan->precision == MM_FP64 ? 8 : 4), &p));
+    MM_TRY(plan_alloc(plan, (size_t)plan->nwork * (plan->precision == MM_FP64 ? 8 : 4), &p));
     plan->d_work2 = p;
   }
   const bool pm = plan->pm_mode != 0;

@@ -43,7 +43,10 @@ struct DevChunk {
   int64_t spec_off;   // offset of this chunk's M+1 power-law values in DevPlan::spec (FP64 form)
   double inv_M;       // 1 / M
   double lg0;         // log2(df / fknee): the power law at bin k is sigma^2 2^(alpha (log2 k + lg0))
+  int64_t xoff;       // complex offset of the chunk in the transform work buffers (16-aligned)
 };
+
+constexpr int kWorkAlign = 16;  // complex values: chunk bases in the work buffers sit on 128-byte lines
 
 // Per-length transform data: radix schedules and twiddle-table offsets.
 struct DevClass {
@@ -138,6 +141,8 @@ hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void
 hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
                       double* w_out, int32_t* hits_out, hipStream_t s, void* pm_out = nullptr);
 hipError_t launch_interleave(const DevPlan& P, const double* m, hipStream_t s);
+// the filtered TOD of the work buffer (chunk bases at xoff) copied to time order
+hipError_t launch_unshift(const DevPlan& P, const void* work, void* out, hipStream_t s);
 hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipStream_t s);
 hipError_t launch_spectrum(const DevPlan& P, double* spec, hipStream_t s);
 hipError_t launch_grad(const DevPlan& P, const ItemB* items, int nitems, const int32_t* chunk_item_begin,

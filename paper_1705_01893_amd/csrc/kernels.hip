@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
     }
     __syncthreads();
     lds_transform<T, false, true, kBlock, P2>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
-    cx<T>* Xc = X + ch.off / 2;
+    cx<T>* Xc = X + ch.xoff;
 #pragma unroll 2
     for (int u = 0; u < E; ++u) {
       const int e = threadIdx.x + u * kBlock;
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     const int ra = item.ra, rb = item.rb;
     const int nrow = (ra == rb) ? 1 : 2;
     const int ntot = nrow * M1;
-    cx<T>* Xc = X + ch.off / 2;
+    cx<T>* Xc = X + ch.xoff;
     cx<T>* Xa = Xc + (int64_t)ra * M1;
     cx<T>* Xb = Xc + (int64_t)rb * M1;
     // 2 * M1 < kBlockB * E, so each row takes at most E/2 elements per thread
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
     const int j10 = item.j1;
     const int nbv = min(B, M1 - j10);
     const int ntot = B * M2;
-    cx<T>* Xc = X + ch.off / 2 + j10;
+    cx<T>* Xc = X + ch.xoff + j10;
     {
       cx<T> v[E];
 #pragma unroll
@@ -743,12 +743,19 @@ __device__ __forceinline__ BinLds bin_lds(double* base, bool plan) {
 }
 
 // Load the segment table of sub-batch S and mark its starts in bitmap `sm` (zeroed beforehand).
+// Segment starts are sample indices in time order; in_work moves them to the work buffer, where
+// chunk c starts at real position 2 xoff_c instead of off_c.
 __device__ __forceinline__ void load_segments(const DevPlan& P, const SubBatch& S, const BinLds& L,
-                                              unsigned long long* sm, bool with_chunk) {
+                                              unsigned long long* sm, bool with_chunk, bool in_work) {
   const int nseg = S.seg_end - S.seg_begin;
   for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
     const Segment g = P.segs[S.seg_begin + i];
-    L.sstart[i] = g.start;
+    int64_t start = g.start;
+    if (in_work) {
+      const DevChunk& ch = P.chunks[g.chunk];
+      start += 2 * ch.xoff - ch.off;
+    }
+    L.sstart[i] = start;
     L.spos[i] = (uint16_t)g.pos;
     if (with_chunk) L.schunk[i] = g.chunk;
     atomicOr(&sm[g.pos >> 6], 1ull << (g.pos & 63));
@@ -829,7 +836,7 @@ __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt,
         }
       }
     }
-    load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), false);
+    load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), false, false);
     __syncthreads();
     const SegIndex si = seg_index(L.smask + (sbn & 1) * (kSubBatch / 64));
     // the other bitmap was last read before the previous sub-batch's final barrier
@@ -901,7 +908,8 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
       const bool active = kl < k1;
       LaneEntries en = {};
       if (active) load_lane_entries<POL>(P, S.sorted_begin + kl, en);  // kl: a multiple of kSortAlign
-      load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), PLAN || bsrc == BSRC_DATA_OVER_TAU);
+      load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), PLAN || bsrc == BSRC_DATA_OVER_TAU,
+                    bsrc == BSRC_WORK);
       if (lane == 0) clp[wave] = -1;
       __syncthreads();
       const SegIndex si = seg_index(L.smask + (sbn & 1) * (kSubBatch / 64));
@@ -1149,11 +1157,11 @@ __global__ __launch_bounds__(kBlockB) void k_grad_b(DevPlan P, const ItemB* __re
     // sequences: rows of r at [0, nrow*M1), rows of P z at [nrow*M1, 2*nrow*M1)
     const int off2 = nrow * M1;
     for (int e = threadIdx.x; e < M1; e += kBlockB) {
-      lds[e] = Xr[ch.off / 2 + (int64_t)ra * M1 + e];
-      lds[off2 + e] = Xz[ch.off / 2 + (int64_t)ra * M1 + e];
+      lds[e] = Xr[ch.xoff + (int64_t)ra * M1 + e];
+      lds[off2 + e] = Xz[ch.xoff + (int64_t)ra * M1 + e];
       if (nrow == 2) {
-        lds[M1 + e] = Xr[ch.off / 2 + (int64_t)rb * M1 + e];
-        lds[off2 + M1 + e] = Xz[ch.off / 2 + (int64_t)rb * M1 + e];
+        lds[M1 + e] = Xr[ch.xoff + (int64_t)rb * M1 + e];
+        lds[off2 + M1 + e] = Xz[ch.xoff + (int64_t)rb * M1 + e];
       }
     }
     __syncthreads();
@@ -1484,6 +1492,25 @@ __global__ void k_interleave(DevPlan P, const double* __restrict__ m) {
     P.mapi[2 * p] = make_double2(m[p], m[np + p]);
     P.mapi[2 * p + 1] = make_double2(m[2 * np + p], 0.0);
   }
+}
+
+template <typename T>
+__global__ void k_unshift(DevPlan P, const T* __restrict__ work, T* __restrict__ out) {
+  for (int c = blockIdx.x; c < P.nchunk; c += gridDim.x) {
+    const DevChunk& ch = P.chunks[c];
+    const T* src = work + 2 * ch.xoff;
+    T* dst = out + ch.off;
+    for (int t = threadIdx.x; t < ch.n; t += blockDim.x) dst[t] = src[t];
+  }
+}
+
+hipError_t launch_unshift(const DevPlan& P, const void* work, void* out, hipStream_t s) {
+  const int g = P.nchunk < 65536 ? P.nchunk : 65536;
+  if (P.precision == 0)
+    hipLaunchKernelGGL(k_unshift<double>, dim3(g), dim3(256), 0, s, P, (const double*)work, (double*)out);
+  else
+    hipLaunchKernelGGL(k_unshift<float>, dim3(g), dim3(256), 0, s, P, (const float*)work, (float*)out);
+  return hipGetLastError();
 }
 
 hipError_t launch_interleave(const DevPlan& P, const double* m, hipStream_t s) {

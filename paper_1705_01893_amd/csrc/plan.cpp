@@ -194,6 +194,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   std::vector<int> class_cb;
   size_t lds_ac = 0, lds_b = 0;
   int64_t spec_total = 0;
+  int64_t xwork = 0;  // complex values of the work buffers (chunk bases 16-aligned)
   for (int64_t c = 0; c < D.nchunk; ++c) {
     const int64_t n = D.chunk_off[c + 1] - D.chunk_off[c];
     const int64_t M = n / 2;
@@ -243,11 +244,14 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     ch.spec_off = spec_total;
     ch.inv_M = 1.0 / (double)ch.M;
     ch.lg0 = std::log2(ch.df / ch.fknee);
+    ch.xoff = xwork;
+    xwork += (ch.M + kWorkAlign - 1) / kWorkAlign * kWorkAlign;
     spec_total += ch.M + 1;
     pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
     append_chunk_items((int32_t)c, ch, pl->itemsAC, pl->itemsB);
   }
   pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
+  pl->nwork = 2 * xwork;
   pl->lds_ac = lds_ac;
   pl->lds_b = lds_b;
   if (lds_ac > 65536 || lds_b + (kBlockB / 64) * sizeof(double) > 65536)
@@ -520,7 +524,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   pl->d_solvable = (uint8_t*)p;
   if ((st = plan_alloc(pl, (size_t)D.npix * sizeof(int32_t), &p)) != MM_OK) return st;
   pl->d_hits = (int32_t*)p;
-  if ((st = plan_alloc(pl, (size_t)ns * (f64 ? 8 : 4), &p)) != MM_OK) return st;
+  if ((st = plan_alloc(pl, (size_t)pl->nwork * (f64 ? 8 : 4), &p)) != MM_OK) return st;
   pl->d_work = p;
   if ((st = plan_alloc(pl, 3 * pl->itemsB.size() * sizeof(double), &p)) != MM_OK) return st;
   pl->d_chi2_part = (double*)p;  // chi^2 partials (1 per row item) or gradient partials (3 per item)

@@ -45,7 +45,8 @@ struct mm_plan_s {
   double* d_winv = nullptr;
   uint8_t* d_solvable = nullptr;
   int32_t* d_hits = nullptr;
-  void* d_work = nullptr;
+  void* d_work = nullptr;     // transform work buffer: 2 * xoff_c + (sample - off_c) holds chunk c
+  int64_t nwork = 0;          // its length in reals (>= ns: chunk bases padded to 128-byte lines)
   double* d_chi2_part = nullptr;
   double* d_scal = nullptr;
   double* d_part = nullptr;

@@ -94,8 +94,10 @@ std::vector<Layout> layout_candidates(int64_t M, bool f64) {
     const int64_t bfull = pow2floor(std::min<int64_t>(bmax, m1));
     const int64_t b = std::min<int64_t>(bfull, pow2floor(cap / m2));
     if (b < 1) continue;
-    // static rule: full column blocks first, then the split closest to sqrt(M)
-    const double score = std::fabs(std::log((double)m2) - 0.5 * std::log((double)M)) + (b < bfull ? 4.0 : 0.0);
+    // static rule: full column blocks first, then row lengths that keep column runs on 128-byte lines
+    // (M1 a multiple of cb), then the split closest to sqrt(M)
+    const double score = std::fabs(std::log((double)m2) - 0.5 * std::log((double)M)) + (b < bfull ? 4.0 : 0.0) +
+                         (m1 % b != 0 ? 2.0 : 0.0);
     for (int order = 0; order < 2; ++order) {
       Layout L;
       L.M1 = m1;
@@ -202,6 +204,7 @@ double time_layout(int64_t M, bool f64, const Layout& L, int64_t K, void* din, v
     ch.spec_off = c * (M + 1);
     ch.inv_M = 1.0 / (double)M;
     ch.lg0 = std::log2(ch.df / ch.fknee);
+    ch.xoff = c * ((M + kWorkAlign - 1) / kWorkAlign * kWorkAlign);
     append_chunk_items((int32_t)c, ch, itemsAC, itemsB);
   }
   DevBuf bch, bcl, btw, btw32, bac, bb, bspec;
@@ -263,7 +266,8 @@ int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream
   const int ncand = (int)std::min<size_t>(cands.size(), kTuneMaxCandidates);
   // enough copies of the chunk to fill the GPU several times over
   const int64_t K = std::max<int64_t>(1, kTuneElements / M);
-  const size_t bytes = (size_t)K * M * (f64 ? sizeof(double2) : sizeof(float2));
+  const int64_t Mp = (M + kWorkAlign - 1) / kWorkAlign * kWorkAlign;
+  const size_t bytes = (size_t)K * Mp * (f64 ? sizeof(double2) : sizeof(float2));
   int best = 0;
   {
     DevBuf din, dwork;
