@@ -450,7 +450,7 @@ __device__ __forceinline__ void b_self(cx<T>* lds, const DevPlan& P, const DevCh
 }
 
 // at most 128 VGPRs, so that four 256-thread workgroups share a CU
-template <typename T, bool P2>
+template <typename T>
 __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
                                                    cx<T>* __restrict__ X, int ops, BinCtx bc,
                                                    double* __restrict__ chi2_part, int red_off) {
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     }
     __syncthreads();
     const cx<T>* tw1 = twtab<T>(P) + cl.tw1;
-    lds_transform<T, false, false, kBlockB, P2>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
+    lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
     double chi = 0.0;
     const bool self_a = (ra == 0) || (2 * ra == M2);
     if (!self_a) {
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     }
     if (ops & B_FILTER) {
       __syncthreads();
-      lds_transform<T, true, false, kBlockB, P2>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
+      lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
 #pragma unroll
       for (int u = 0; u < E / 2; ++u) {
         const int j1 = threadIdx.x + u * kBlockB;
@@ -1447,10 +1447,10 @@ hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void*
   const size_t tot = lds + (kBlockB / 64) * sizeof(double);
   // the row pass keeps the out-of-line stages: inlined, its 128-VGPR bound made it spill
   if (P.precision == 0)
-    hipLaunchKernelGGL((k_pass_b<double, false>), dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items,
+    hipLaunchKernelGGL(k_pass_b<double>, dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items,
                        nitems, (double2*)work, ops, bc, chi2_part, red_off);
   else
-    hipLaunchKernelGGL((k_pass_b<float, false>), dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items,
+    hipLaunchKernelGGL(k_pass_b<float>, dim3(grid_for(nitems, kGridCap)), dim3(kBlockB), tot, s, P, items,
                        nitems, (float2*)work, ops, bc, chi2_part, red_off);
   return hipGetLastError();
 }
