@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--no-chi2", action="store_true", help="skip the time-to-chi2-target comparison")
     ap.add_argument("--map-access", choices=["auto", "gather", "projected"], default="auto",
                     help="how the time-domain sweeps read P m (the plan's rule by default)")
+    ap.add_argument("--binning", choices=["sorted", "atomic"], default="sorted",
+                    help="deterministic sorted reduction (default) or the FP64-atomic alternative")
     ap.add_argument("--tune", choices=["measure", "static"], default="measure",
                     help="transform layouts: timed at plan time (default) or the fixed rule")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -369,7 +371,8 @@ def main():
                       psi=psi, psi_table=prob.psi_table, precision=precision,
                       map_access={"auto": mm.MM_MAP_AUTO, "gather": mm.MM_MAP_GATHER,
                                   "projected": mm.MM_MAP_PROJECTED}[args.map_access],
-                      tune=mm.MM_TUNE_MEASURE if args.tune == "measure" else mm.MM_TUNE_STATIC)
+                      tune=mm.MM_TUNE_MEASURE if args.tune == "measure" else mm.MM_TUNE_STATIC,
+                      binning=mm.MM_BIN_ATOMIC if args.binning == "atomic" else mm.MM_BIN_SORTED)
     t_plan = time.perf_counter() - t0
     log(f"plan built in {t_plan:.1f} s ({mm.mm_plan_workspace_bytes(plan) / 2**30:.2f} GiB of device tables)")
     ns = prob.nsamp_total
@@ -424,6 +427,7 @@ def main():
     sweep_bytes = sum(pb[:4]) + pb[4] * pass_n[4] / args.steps
     extra = {
         "map_access": "projected" if projected else "gather",
+        "binning": args.binning,
         "passes": [{"pass": PASS_NAMES[i], "avg_ms": round(avg[i], 5), "launches": int(pass_n[i]),
                     "alg_bytes": pb[i], "GBs": round(pb[i] / (avg[i] * 1e-3) / 1e9, 1) if avg[i] > 0 else None}
                    for i in range(5)],

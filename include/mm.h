@@ -75,6 +75,7 @@ enum { MM_FP64 = 0, MM_MIXED = 1 };                              /* precision */
 enum { MM_PSI_NONE = 0, MM_PSI_F64 = 1, MM_PSI_F32 = 2, MM_PSI_U16 = 3 }; /* psi storage */
 enum { MM_MAP_AUTO = 0, MM_MAP_GATHER = 1, MM_MAP_PROJECTED = 2 };        /* map_access */
 enum { MM_TUNE_MEASURE = 0, MM_TUNE_STATIC = 1, MM_TUNE_PICK0 = 16 };    /* tune */
+enum { MM_BIN_SORTED = 0, MM_BIN_ATOMIC = 1 };                            /* binning */
 
 /*
  * Problem description (Section 2 data model; Section 4.2 per-chunk tau).
@@ -110,6 +111,12 @@ enum { MM_TUNE_MEASURE = 0, MM_TUNE_STATIC = 1, MM_TUNE_PICK0 = 16 };    /* tune
  *               gives bitwise identical results across processes.
  *               MM_TUNE_PICK0 + i takes candidate i of the rule's order for every
  *               length (clamped to the last one), to exercise each layout.
+ *  binning      how the iterations form P^T y: MM_BIN_SORTED (default) reduces the
+ *               samples of each pixel tile in pixel-sorted order, a fixed summation
+ *               order (bitwise reproducible); MM_BIN_ATOMIC adds every sample into the
+ *               map with FP64 atomics in time order (a measured alternative: the
+ *               rounding varies from run to run).  The plan precompute (hits, W)
+ *               always uses the sorted reduction.
  */
 typedef struct {
   int32_t ncomp;
@@ -130,7 +137,7 @@ typedef struct {
   const float* psi_table;
   int64_t psi_table_len;
   int32_t tune;
-  int32_t reserved1;
+  int32_t binning;
 } mm_plan_desc;
 
 /* Cooling schedule (Section 3.1): optionally one lambda = inf step, then

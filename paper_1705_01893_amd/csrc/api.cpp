@@ -53,12 +53,24 @@ hipError_t timed(mm_plan_s* pl, int pass, hipStream_t s, F&& launch) {
   return e;
 }
 
+// binning by atomics: zero the binned vector (a fill kernel, also under graph capture), add every
+// sample, then the per-pixel update
+hipError_t bin_atomic_update(mm_plan_s* pl, int bsrc, const void* src, int epi, const double* m_in, double* m_out,
+                             hipStream_t s) {
+  hipError_t e = launch_fill(pl->d_batom, mapn(pl), 0.0, s);
+  if (e == hipSuccess) e = launch_bin_atomic(pl->dp, bsrc, src, pl->d_batom, pl->max_n, s);
+  if (e == hipSuccess) e = launch_update(pl->dp, epi, m_in, pl->d_batom, m_out, s);
+  return e;
+}
+
 // r = src(d, m) -> filtered y in the work buffer (passes A, B, C).  Returns with the
 // chi^2 partials in d_chi2_part when ops includes B_CHI2.
 mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, int ops, int gain, double lam,
                        double chi2_lam, hipStream_t s, bool map_current = false) {
   // large maps: P m comes from the projection buffer (projected here unless it already holds P m);
   // otherwise I/Q/U maps are gathered from their interleaved copy (made here unless current)
+  // atomic binning writes no P m for the next sweep
+  if (pl->bin_atomic && pl->pm_mode) map_current = false;
   if (pl->pm_mode && (src == SRC_D_MINUS_PM || src == SRC_PM)) {
     if (!map_current) MM_TRY_HIP(timed(pl, 4, s, [&] { return launch_project(pl->dp, m, pl->d_pm, s); }));
     src = (src == SRC_PM) ? SRC_PMBUF : SRC_D_MINUS_PMBUF;
@@ -96,6 +108,7 @@ mm_status iterate(mm_plan_s* pl, const void* d, double lam, const double* m_in, 
   if (std::isinf(lam)) {
     if (chi2_dev) MM_TRY(chi2_device(pl, d, m_in, 1.0, chi2_dev, nullptr, s, chained));
     MM_TRY_HIP(timed(pl, 3, s, [&] {
+      if (pl->bin_atomic) return bin_atomic_update(pl, BSRC_DATA_OVER_TAU, d, EPI_REPLACE, m_in, m_out, s);
       return launch_bin(pl->dp, BSRC_DATA_OVER_TAU, d, EPI_REPLACE, m_in, m_out, nullptr, nullptr, s, pl->d_pm);
     }));
     return MM_OK;
@@ -103,6 +116,7 @@ mm_status iterate(mm_plan_s* pl, const void* d, double lam, const double* m_in, 
   const int ops = B_FILTER | (chi2_dev ? B_CHI2 : 0);
   MM_TRY(sweep_filter(pl, d, m_in, SRC_D_MINUS_PM, ops, GAIN_MESSENGER, lam, 1.0, s, chained));
   MM_TRY_HIP(timed(pl, 3, s, [&] {
+    if (pl->bin_atomic) return bin_atomic_update(pl, BSRC_WORK, pl->d_work, EPI_UPDATE, m_in, m_out, s);
     return launch_bin(pl->dp, BSRC_WORK, pl->d_work, EPI_UPDATE, m_in, m_out, nullptr, nullptr, s, pl->d_pm);
   }));
   if (chi2_dev)
@@ -114,6 +128,10 @@ mm_status iterate(mm_plan_s* pl, const void* d, double lam, const double* m_in, 
 mm_status apply_op(mm_plan_s* pl, int gain, double lam, const double* x, const void* d, double* out, hipStream_t s) {
   MM_TRY(sweep_filter(pl, x ? nullptr : d, x, x ? SRC_PM : SRC_D, B_FILTER, gain, lam, 1.0, s));
   MM_TRY_HIP(timed(pl, 3, s, [&] {
+    if (pl->bin_atomic) {
+      hipError_t e = launch_fill(out, mapn(pl), 0.0, s);
+      return e != hipSuccess ? e : launch_bin_atomic(pl->dp, BSRC_WORK, pl->d_work, out, pl->max_n, s);
+    }
     return launch_bin(pl->dp, BSRC_WORK, pl->d_work, EPI_WRITE_B, nullptr, out, nullptr, nullptr, s);
   }));
   return MM_OK;

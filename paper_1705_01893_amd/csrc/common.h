@@ -141,6 +141,10 @@ hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void
 hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
                       double* w_out, int32_t* hits_out, hipStream_t s, void* pm_out = nullptr);
 hipError_t launch_interleave(const DevPlan& P, const double* m, hipStream_t s);
+// binning by FP64 atomics (the measured alternative): b += P^T src over all samples (b zeroed by
+// the caller), then the per-pixel update of the binning epilogue from b
+hipError_t launch_bin_atomic(const DevPlan& P, int bsrc, const void* src, double* b, int64_t max_n, hipStream_t s);
+hipError_t launch_update(const DevPlan& P, int epi, const double* m_in, const double* b, double* out, hipStream_t s);
 // the filtered TOD of the work buffer (chunk bases at xoff) copied to time order
 hipError_t launch_unshift(const DevPlan& P, const void* work, void* out, hipStream_t s);
 hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipStream_t s);

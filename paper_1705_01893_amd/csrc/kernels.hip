@@ -20,6 +20,7 @@
 // All passes use one TOD-sized work buffer in place.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -1510,6 +1511,99 @@ hipError_t launch_unshift(const DevPlan& P, const void* work, void* out, hipStre
     hipLaunchKernelGGL(k_unshift<double>, dim3(g), dim3(256), 0, s, P, (const double*)work, (double*)out);
   else
     hipLaunchKernelGGL(k_unshift<float>, dim3(g), dim3(256), 0, s, P, (const float*)work, (float*)out);
+  return hipGetLastError();
+}
+
+// Binning by global FP64 atomics, the measured alternative to the sorted segmented reduction:
+// samples in time order (coalesced reads of y, pix and the angles), one atomic add per map
+// component per on-map sample.  The order of the additions, hence the rounding, varies from run
+// to run.  Block (x, c) covers samples [x * 4096, (x + 1) * 4096) of chunk c.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_bin_atomic(DevPlan P, int bsrc, const T* __restrict__ src,
+                                                    double* __restrict__ b) {
+  const int np = (int)P.npix;
+  for (int c = blockIdx.y; c < P.nchunk; c += gridDim.y) {
+    const DevChunk& ch = P.chunks[c];
+    // y of the work buffer sits at 2 xoff + (t - off); the data are in time order
+    const T* sc = src + (bsrc == BSRC_WORK ? 2 * ch.xoff : ch.off);
+    const double scale = bsrc == BSRC_WORK ? 1.0 : ch.inv_tau;
+    for (int t0 = blockIdx.x * 4096; t0 < ch.n; t0 += gridDim.x * 4096) {
+      const int t1 = min(ch.n, t0 + 4096);
+      for (int t = t0 + (int)threadIdx.x; t < t1; t += 256) {
+        const int64_t j = ch.off + t;
+        const int p = P.pix[j];
+        if (p < 0) continue;
+        const double y = (double)sc[t] * scale;
+        unsafeAtomicAdd(&b[p], y);
+        if (NC == 3) {
+          T cc, ss;
+          psi_weights<T>(P, P.psi, j, cc, ss);
+          unsafeAtomicAdd(&b[np + p], (double)cc * y);
+          unsafeAtomicAdd(&b[2 * np + p], (double)ss * y);
+        }
+      }
+    }
+  }
+}
+
+// The binning epilogue's per-pixel step from a binned vector b: m_out = m_in + W^-1 b (EPI_UPDATE)
+// or W^-1 b (EPI_REPLACE) on solvable pixels, 0 elsewhere; refreshes the interleaved map.
+template <int NC>
+__global__ __launch_bounds__(256) void k_update(DevPlan P, int epi, const double* __restrict__ m_in,
+                                                const double* __restrict__ b, double* __restrict__ out) {
+  const int64_t np = P.npix;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    const bool ok = P.solvable[p] != 0;
+    double u[3];
+    if (NC == 1) {
+      u[0] = P.winv[p] * b[p];
+    } else {
+      const double a0 = b[p], a1 = b[np + p], a2 = b[2 * np + p];
+      const double i00 = P.winv[p], i01 = P.winv[np + p], i02 = P.winv[2 * np + p];
+      const double i11 = P.winv[3 * np + p], i12 = P.winv[4 * np + p], i22 = P.winv[5 * np + p];
+      u[0] = i00 * a0 + i01 * a1 + i02 * a2;
+      u[1] = i01 * a0 + i11 * a1 + i12 * a2;
+      u[2] = i02 * a0 + i12 * a1 + i22 * a2;
+    }
+    double r[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      if (ok) r[q] = (epi == EPI_UPDATE) ? m_in[q * np + p] + u[q] : u[q];
+      out[q * np + p] = r[q];
+    }
+    if (NC == 3 && P.mapi) {
+      P.mapi[2 * p] = make_double2(r[0], r[1]);
+      P.mapi[2 * p + 1] = make_double2(r[2], 0.0);
+    }
+  }
+}
+
+hipError_t launch_bin_atomic(const DevPlan& P, int bsrc, const void* src, double* b, int64_t max_n, hipStream_t s) {
+  // the longest chunk sets the x extent (blocks past a shorter chunk's end exit at once)
+  const int gx = (int)std::min<int64_t>((max_n + 4095) / 4096, 1024);
+  const int gy = P.nchunk < 65535 ? P.nchunk : 65535;
+  const dim3 grid(gx < 1 ? 1 : gx, gy);
+  const bool f64 = P.precision == 0;
+  if (P.ncomp == 1) {
+    if (f64)
+      hipLaunchKernelGGL((k_bin_atomic<double, 1>), grid, dim3(256), 0, s, P, bsrc, (const double*)src, b);
+    else
+      hipLaunchKernelGGL((k_bin_atomic<float, 1>), grid, dim3(256), 0, s, P, bsrc, (const float*)src, b);
+  } else {
+    if (f64)
+      hipLaunchKernelGGL((k_bin_atomic<double, 3>), grid, dim3(256), 0, s, P, bsrc, (const double*)src, b);
+    else
+      hipLaunchKernelGGL((k_bin_atomic<float, 3>), grid, dim3(256), 0, s, P, bsrc, (const float*)src, b);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const DevPlan& P, int epi, const double* m_in, const double* b, double* out, hipStream_t s) {
+  const int64_t g = std::min<int64_t>((P.npix + 255) / 256, 4096);
+  if (P.ncomp == 1)
+    hipLaunchKernelGGL(k_update<1>, dim3((unsigned)g), dim3(256), 0, s, P, epi, m_in, b, out);
+  else
+    hipLaunchKernelGGL(k_update<3>, dim3((unsigned)g), dim3(256), 0, s, P, epi, m_in, b, out);
   return hipGetLastError();
 }
 

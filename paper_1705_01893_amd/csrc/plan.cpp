@@ -146,6 +146,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     return fail(MM_E_ARG, "unknown map_access");
   const bool pick_mode = D.tune >= MM_TUNE_PICK0 && D.tune < MM_TUNE_PICK0 + 4096;
   if (D.tune != MM_TUNE_MEASURE && D.tune != MM_TUNE_STATIC && !pick_mode) return fail(MM_E_ARG, "unknown tune mode");
+  if (D.binning != MM_BIN_SORTED && D.binning != MM_BIN_ATOMIC) return fail(MM_E_ARG, "unknown binning mode");
   if (D.chunk_off[0] != 0) return fail(MM_E_ARG, "chunk_off[0] must be 0");
   for (int64_t c = 0; c < D.nchunk; ++c) {
     const int64_t n = D.chunk_off[c + 1] - D.chunk_off[c];
@@ -546,6 +547,12 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   // then P m is produced in pixel-tile order instead
   pl->pm_mode = D.map_access == MM_MAP_PROJECTED ||
                 (D.map_access == MM_MAP_AUTO && mapn * (int64_t)sizeof(double) > ((int64_t)4 << 20));
+  pl->bin_atomic = D.binning == MM_BIN_ATOMIC;
+  for (int64_t c = 0; c < D.nchunk; ++c) pl->max_n = std::max<int64_t>(pl->max_n, D.chunk_off[c + 1] - D.chunk_off[c]);
+  if (pl->bin_atomic) {
+    if ((st = plan_alloc(pl, (size_t)mapn * sizeof(double), &p)) != MM_OK) return st;
+    pl->d_batom = (double*)p;
+  }
   if (!pl->pm_mode && D.ncomp == 3) {
     if ((st = plan_alloc(pl, (size_t)D.npix * 2 * sizeof(double2), &p)) != MM_OK) return st;
     P.mapi = (double2*)p;

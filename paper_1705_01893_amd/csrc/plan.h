@@ -56,6 +56,10 @@ struct mm_plan_s {
   // of gathering the map)
   int pm_mode = 0;
   void* d_pm = nullptr;
+  // binning by FP64 atomics (measured alternative): binned vector, longest chunk
+  bool bin_atomic = false;
+  double* d_batom = nullptr;
+  int64_t max_n = 0;
   mm::DevChunk* d_chunks = nullptr;
   double* d_hist = nullptr;  // grows on demand (CG rz history)
   size_t hist_cap = 0;

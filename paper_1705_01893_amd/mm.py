@@ -24,6 +24,7 @@ MM_FP64, MM_MIXED = 0, 1
 MM_PSI_NONE, MM_PSI_F64, MM_PSI_F32, MM_PSI_U16 = 0, 1, 2, 3
 MM_MAP_AUTO, MM_MAP_GATHER, MM_MAP_PROJECTED = 0, 1, 2
 MM_TUNE_MEASURE, MM_TUNE_STATIC, MM_TUNE_PICK0 = 0, 1, 16
+MM_BIN_SORTED, MM_BIN_ATOMIC = 0, 1
 MM_OK, MM_E_ARG, MM_E_LEN, MM_E_NOMEM, MM_E_HIP, MM_E_SINGULAR, MM_E_NONFINITE = range(7)
 _STATUS_NAMES = {0: "MM_OK", 1: "MM_E_ARG", 2: "MM_E_LEN", 3: "MM_E_NOMEM", 4: "MM_E_HIP",
                  5: "MM_E_SINGULAR", 6: "MM_E_NONFINITE"}
@@ -46,7 +47,7 @@ class _Desc(ctypes.Structure):
         ("pix", ctypes.c_void_p), ("psi", ctypes.c_void_p),
         ("psi_kind", ctypes.c_int32), ("map_access", ctypes.c_int32),
         ("psi_table", ctypes.POINTER(ctypes.c_float)), ("psi_table_len", ctypes.c_int64),
-        ("tune", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+        ("tune", ctypes.c_int32), ("binning", ctypes.c_int32),
     ]
 
 
@@ -165,7 +166,7 @@ class Plan:
 def mm_plan(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, pix: torch.Tensor,
             psi: Optional[torch.Tensor] = None, psi_table=None, tau=None, nx: int = 0,
             precision: int = MM_FP64, map_access: int = MM_MAP_AUTO, tune: int = MM_TUNE_MEASURE,
-            stream=None) -> Plan:
+            binning: int = MM_BIN_SORTED, stream=None) -> Plan:
     """Build a plan (mm_plan).  pix (int32) and psi (float64 / float32 / uint16) are device tensors."""
     off = np.ascontiguousarray(np.asarray(chunk_off, dtype=np.int64).reshape(-1))
     nchunk = off.size - 1
@@ -179,6 +180,7 @@ def mm_plan(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, p
     d.ncomp, d.precision, d.npix, d.nx, d.nchunk = ncomp, precision, npix, nx, nchunk
     d.map_access = map_access
     d.tune = tune
+    d.binning = binning
     d.chunk_off = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     for k in ("fsample", "sigma", "fknee", "alpha"):
         setattr(d, k, arrs[k].ctypes.data_as(ctypes.POINTER(ctypes.c_double)))

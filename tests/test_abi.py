@@ -64,6 +64,7 @@ def _desc(**over):
     d.psi_kind = over.pop("psi_kind", 0)
     d.map_access = over.pop("map_access", 0)
     d.tune = over.pop("tune", 0)
+    d.binning = over.pop("binning", 0)
     assert not over
     return d, arr
 
@@ -73,6 +74,7 @@ def _desc(**over):
     (dict(precision=7), mm.MM_E_ARG),
     (dict(map_access=3), mm.MM_E_ARG),
     (dict(tune=2), mm.MM_E_ARG),
+    (dict(binning=2), mm.MM_E_ARG),
     (dict(npix=0), mm.MM_E_ARG),
     (dict(npix=15, nx=4), mm.MM_E_ARG),
     (dict(pix=None), mm.MM_E_ARG),
