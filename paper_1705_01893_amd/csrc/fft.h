@@ -1,9 +1,10 @@
 // LDS-resident mixed-radix Stockham transforms for gfx950.
 //
-// A workgroup holds `nb` independent length-L complex sequences in LDS; element
-// i of sequence b lives at lds[i * sI + b * sB].  One radix-R stage reads every
-// element into registers (R per butterfly, a fixed number of butterflies per
-// thread), synchronises, applies twiddles and the R-point DFT in registers, and
+// A workgroup holds `nb` independent length-L complex sequences in LDS; element i of
+// sequence b lives at lds[i * nb + b] (interleaved columns, nb a power of two) or at
+// lds[b * L + i] (consecutive rows, nb <= 4).  One radix-R stage reads every element
+// into registers (R per butterfly, a fixed number of butterflies per thread),
+// synchronises, applies twiddles and the R-point DFT in registers, and
 // writes the results to their self-sorting (Stockham) positions; after the last
 // stage the sequences are in natural frequency order in place.  Radices 2, 3, 4,
 // 5 and 8 cover every 5-smooth length.
@@ -173,18 +174,50 @@ __device__ __forceinline__ void twiddle_powers(cx<T>* v, cx<T> w1) {
 
 // One Stockham stage run by a workgroup of NT threads.  p = product of the radices already
 // applied.  Butterfly f of the stage belongs to sequence b and position k: with BFAST,
-// b = f mod nb (nb a power of two, lg_nb = log2 nb), otherwise b = f / (L/R).
+// b = f mod nb (nb a power of two, lg_nb = log2 nb), otherwise b = f / (L/R) with nb <= 4.
 // Kept out of line: inlining all five radix variants into the stage loop makes the register
 // allocator budget for their union and halves the occupancy of every pass.
+// LDS and global pointers with their address spaces spelled out (32-bit LDS address arithmetic
+// and ds_* instructions; global, not flat, loads of the twiddle tables), over a plain two-lane
+// vector type so that loads and stores stay single vector instructions.
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+using lds_v2 = __attribute__((address_space(3))) vec2<T>*;
+template <typename T>
+using glob_v2 = const __attribute__((address_space(1))) vec2<T>*;
+
+template <typename T>
+__device__ __forceinline__ cx<T> to_cx(vec2<T> a) {
+  cx<T> r;
+  r.x = a.x;
+  r.y = a.y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ vec2<T> to_v2(cx<T> a) {
+  vec2<T> r;
+  r.x = a.x;
+  r.y = a.y;
+  return r;
+}
+
 template <typename T, int R, bool INV, bool BFAST, int NT>
-__device__ __forceinline__ void stage_body(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, int p,
-                                           const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void stage_body(cx<T>* lds_generic, int L, int nb, int lg_nb, int p,
+                                           const cx<T>* __restrict__ tw_generic) {
+  const lds_v2<T> lds = (lds_v2<T>)lds_generic;
+  const glob_v2<T> tw = (glob_v2<T>)tw_generic;
   constexpr int K = (Ept<T>::v + R - 1) / R;  // butterflies per thread
   const int nbf = L / R;
   const int total = nbf * nb;
   const int step = L / (p * R);
+  // element i of sequence b sits at i * sI + b * sB: interleaved columns (BFAST: sI = nb, sB = 1)
+  // or consecutive rows (sI = 1, sB = L)
+  const int sI = BFAST ? (1 << lg_nb) : 1;
+  const int sB = BFAST ? 1 : L;
+  const int rstride = nbf * sI;  // LDS distance between the R inputs of a butterfly
+  const int wstride = p * sI;    // and between its R outputs
   const float inv_p = 1.0f / (float)p;
-  const float inv_nbf = 1.0f / (float)nbf;
   cx<T> v[K][R];
   int bk[K][2];
 #pragma unroll
@@ -195,14 +228,16 @@ __device__ __forceinline__ void stage_body(cx<T>* lds, int L, int nb, int lg_nb,
       b = f & (nb - 1);
       k = f >> lg_nb;
     } else {
-      b = (int)qdiv((uint32_t)f, (uint32_t)nbf, inv_nbf);
+      // the row transforms hold at most four sequences: b = f / nbf by comparisons
+      b = (f >= nbf) + (f >= 2 * nbf) + (f >= 3 * nbf);
       k = f - b * nbf;
     }
     bk[u][0] = b;
     bk[u][1] = k;
     if (f < total) {
+      int a = k * sI + b * sB;
 #pragma unroll
-      for (int m = 0; m < R; ++m) v[u][m] = lds[(k + m * nbf) * sI + b * sB];
+      for (int m = 0; m < R; ++m, a += rstride) v[u][m] = to_cx<T>(lds[a]);
     }
   }
   __syncthreads();
@@ -214,40 +249,40 @@ __device__ __forceinline__ void stage_body(cx<T>* lds, int L, int nb, int lg_nb,
       const int kq = (int)qdiv((uint32_t)k, (uint32_t)p, inv_p);
       const int j = k - kq * p;
       if (j != 0) {
-        cx<T> w = tw[j * step];
+        cx<T> w = to_cx<T>(tw[j * step]);
         if (INV) w.y = -w.y;
         twiddle_powers<T, R>(v[u], w);
       }
       Dft<T, R, INV>::run(v[u]);
-      const int base = kq * p * R + j;
+      int a = (kq * p * R + j) * sI + b * sB;
 #pragma unroll
-      for (int m = 0; m < R; ++m) lds[(base + m * p) * sI + b * sB] = v[u][m];
+      for (int m = 0; m < R; ++m, a += wstride) lds[a] = to_v2<T>(v[u][m]);
     }
   }
   __syncthreads();
 }
 
 template <typename T, int R, bool INV, bool BFAST, int NT>
-__device__ __attribute__((noinline)) void stockham_stage(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, int p,
+__device__ __attribute__((noinline)) void stockham_stage(cx<T>* lds, int L, int nb, int lg_nb, int p,
                                                const cx<T>* __restrict__ tw) {
-  stage_body<T, R, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw);
+  stage_body<T, R, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
 }
 
 // Full length-L transform of nb sequences (caller synchronises before the first stage).
 // tw: omega_L^q = exp(-2 pi i q / L), q < L.  Each stage is a call: a callee waits for all
 // of the caller's outstanding memory operations on entry.
 template <typename T, bool INV, bool BFAST, int NT>
-__device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, const int8_t* rad, int ns,
+__device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, const int8_t* rad, int ns,
                         const cx<T>* __restrict__ tw) {
   int p = 1;
   for (int s = 0; s < ns; ++s) {
     const int R = rad[s];
     switch (R) {
-      case 8: stockham_stage<T, 8, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
-      case 4: stockham_stage<T, 4, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
-      case 2: stockham_stage<T, 2, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
-      case 3: stockham_stage<T, 3, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
-      case 5: stockham_stage<T, 5, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw); break;
+      case 8: stockham_stage<T, 8, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
+      case 4: stockham_stage<T, 4, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
+      case 2: stockham_stage<T, 2, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
+      case 3: stockham_stage<T, 3, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
+      case 5: stockham_stage<T, 5, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
       default: break;
     }
     p *= R;
@@ -257,29 +292,29 @@ __device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, co
 // The same transform for power-of-two lengths (radices 8, 4 and 2 only), with the stages
 // inlined: no call boundaries, so loads the caller has in flight stay in flight.
 template <typename T, bool INV, bool BFAST, int NT>
-__device__ __forceinline__ void lds_fft_pow2(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, const int8_t* rad,
-                                             int ns, const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void lds_fft_pow2(cx<T>* lds, int L, int nb, int lg_nb, const int8_t* rad, int ns,
+                                             const cx<T>* __restrict__ tw) {
   int p = 1;
 #pragma unroll 1
   for (int s = 0; s < ns; ++s) {
     const int R = rad[s];
     if (R == 8)
-      stage_body<T, 8, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw);
+      stage_body<T, 8, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
     else if (R == 4)
-      stage_body<T, 4, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw);
+      stage_body<T, 4, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
     else
-      stage_body<T, 2, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, p, tw);
+      stage_body<T, 2, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
     p *= R;
   }
 }
 
 template <typename T, bool INV, bool BFAST, int NT, bool P2>
-__device__ __forceinline__ void lds_transform(cx<T>* lds, int L, int nb, int lg_nb, int sI, int sB, const int8_t* rad,
-                                              int ns, const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void lds_transform(cx<T>* lds, int L, int nb, int lg_nb, const int8_t* rad, int ns,
+                                              const cx<T>* __restrict__ tw) {
   if (P2)
-    lds_fft_pow2<T, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, rad, ns, tw);
+    lds_fft_pow2<T, INV, BFAST, NT>(lds, L, nb, lg_nb, rad, ns, tw);
   else
-    lds_fft<T, INV, BFAST, NT>(lds, L, nb, lg_nb, sI, sB, rad, ns, tw);
+    lds_fft<T, INV, BFAST, NT>(lds, L, nb, lg_nb, rad, ns, tw);
 }
 
 }  // namespace mm

@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
       }
     }
     __syncthreads();
-    lds_transform<T, false, true, kBlock, P2>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    lds_transform<T, false, true, kBlock, P2>(lds, M2, B, lgB, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
     cx<T>* Xc = X + ch.xoff;
 #pragma unroll 2
     for (int u = 0; u < E; ++u) {
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     }
     __syncthreads();
     const cx<T>* tw1 = twtab<T>(P) + cl.tw1;
-    lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
+    lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
     double chi = 0.0;
     const bool self_a = (ra == 0) || (2 * ra == M2);
     if (!self_a) {
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     }
     if (ops & B_FILTER) {
       __syncthreads();
-      lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, 1, M1, cl.rad1, cl.nr1, tw1);
+      lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
 #pragma unroll
       for (int u = 0; u < E / 2; ++u) {
         const int j1 = threadIdx.x + u * kBlockB;
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
       }
     }
     __syncthreads();
-    lds_transform<T, true, true, kBlock, P2>(lds, M2, B, lgB, B, 1, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    lds_transform<T, true, true, kBlock, P2>(lds, M2, B, lgB, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       const int e = threadIdx.x + u * kBlock;
@@ -1166,7 +1166,7 @@ __global__ __launch_bounds__(kBlockB) void k_grad_b(DevPlan P, const ItemB* __re
       }
     }
     __syncthreads();
-    lds_fft<T, false, false, kBlockB>(lds, M1, 2 * nrow, 0, 1, M1, cl.rad1, cl.nr1, twtab<T>(P) + cl.tw1);
+    lds_fft<T, false, false, kBlockB>(lds, M1, 2 * nrow, 0, cl.rad1, cl.nr1, twtab<T>(P) + cl.tw1);
     double acc[3] = {0.0, 0.0, 0.0};
     for (int sl = 0; sl < nrow; ++sl) {
       const int row = sl == 0 ? ra : rb;
