@@ -450,18 +450,29 @@ def main():
     if not args.no_chi2:
         plans = {("mixed" if mixed else "fp64"): plan}
         d_by = {("mixed" if mixed else "fp64"): d}
+        other = None
         if not mixed:
             # the FP32-mixed form of the same workload: FP32 TOD and angles
             d32 = d.float().contiguous()
             psi32 = psi.float().contiguous() if (psi is not None and psi.dtype == torch.float64) else psi
-            plans["mixed"] = mm.mm_plan(ncomp=prob.ncomp, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off,
-                                        fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha,
-                                        pix=pix, psi=psi32, psi_table=prob.psi_table, precision=mm.MM_MIXED)
-            d_by["mixed"] = d32
-            if "fp64" in plans:
-                log("time to chi^2 target")
-                chi2_block = time_to_chi2(mm, torch, prob, cfg, dev, plans, d_by)
-            plans["mixed"].close()
+            other = "mixed"
+            plans[other] = mm.mm_plan(ncomp=prob.ncomp, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off,
+                                      fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha,
+                                      pix=pix, psi=psi32, psi_table=prob.psi_table, precision=mm.MM_MIXED)
+            d_by[other] = d32
+        else:
+            # the plain FP64 form of the same workload: the stored FP32 TOD and angles promoted
+            d64 = d.double().contiguous()
+            psi64 = psi.double().contiguous() if (psi is not None and psi.dtype == torch.float32) else psi
+            other = "fp64"
+            plans[other] = mm.mm_plan(ncomp=prob.ncomp, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off,
+                                      fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha,
+                                      pix=pix, psi=psi64, psi_table=prob.psi_table, precision=mm.MM_FP64)
+            d_by[other] = d64
+        log("time to chi^2 target")
+        chi2_block = time_to_chi2(mm, torch, prob, cfg, dev, plans, d_by)
+        plans[other].close()
+        del d_by
     cpu = None
     if not args.no_cpu:
         log("oracle on the host")
