@@ -87,7 +87,7 @@ mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, i
   }));
   if (ops & B_FILTER)
     MM_TRY_HIP(timed(pl, 2, s, [&] {
-      return launch_pass_c(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), pl->d_work, pl->lds_ac, s);
+      return launch_pass_c(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), pl->d_work, pl->lds_c, s);
     }));
   return MM_OK;
 }

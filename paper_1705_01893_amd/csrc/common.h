@@ -21,6 +21,32 @@ template <typename T> struct Ept;
 template <> struct Ept<float> { static constexpr int v = 16; };
 template <> struct Ept<double> { static constexpr int v = 8; };
 
+// Column tiles of the column passes.  Element i of column b sits at i * cb + b (interleaved,
+// every stage a workgroup-wide step), or, in the wave-local layout of the inverse column pass,
+// at b * Lc + pad8(i): every wave then transforms its own cb / (kBlock / 64) columns alone.
+// pad8(i) = i + i / 8, and Lc >= pad8(M2 - 1) + 1 is an odd multiple of q = max(G / cb, 1) so
+// that the b-fastest global<->LDS copies (G = 256 / sizeof(complex) lanes per bank sweep: G / cb
+// rows of cb columns) fall in distinct banks.  Eligible: cb >= kBlock / 64 and a padded tile
+// within kMaxColTileBytes.
+constexpr int kColWaves = kBlock / 64;
+// LDS bound of a padded column tile: two workgroups per CU (160 KB)
+constexpr int kMaxColTileBytes = 81920;
+__host__ __device__ inline int pad8(int i) { return i + (i >> 3); }
+__host__ __device__ inline int wave_col_stride(int M2, int cb, int csz) {
+  const int G = 256 / csz;
+  const int q = cb < G ? G / cb : 1;
+  int L = (pad8(M2 - 1) + q) / q;  // in units of q
+  if ((L & 1) == 0) ++L;
+  return L * q;
+}
+__host__ __device__ inline bool wave_cols(int M2, int cb, int csz) {
+  return cb >= kColWaves && cb * wave_col_stride(M2, cb, csz) * csz <= kMaxColTileBytes;
+}
+// complex values of LDS a column tile takes (wave: the plan runs the wave-local layout)
+__host__ __device__ inline int col_tile_elems(int M2, int cb, int csz, bool wave) {
+  return wave ? cb * wave_col_stride(M2, cb, csz) : cb * M2;
+}
+
 template <typename T> struct Cx;
 template <> struct Cx<float> { using t = float2; };
 template <> struct Cx<double> { using t = double2; };
@@ -90,6 +116,8 @@ struct Segment {
 struct DevPlan {
   int32_t ncomp, psi_kind, precision;
   int32_t all_pow2;          // every chunk length is a power of two (radix 8/4/2 transforms)
+  int32_t col_wave;          // the column passes use the wave-local layout (every class eligible)
+  int32_t pad1;
   int64_t npix, nxm;         // pixels, map row length used by the tiles
   int64_t nsamp;
   int32_t nchunk, ntiles;

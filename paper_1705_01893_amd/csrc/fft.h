@@ -308,6 +308,95 @@ __device__ __forceinline__ void lds_fft_pow2(cx<T>* lds, int L, int nb, int lg_n
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Wave-local transforms: one wave transforms nw sequences of length L on its own, sequence c at
+// cols + c * Lc with element i at pad8(i) (one spare slot per eight keeps the stride-R outputs
+// of a stage in distinct banks).  Butterfly f of a stage belongs to sequence c = f / (L/R) and
+// position k = f mod (L/R), so consecutive lanes read consecutive elements.  A wave's LDS
+// operations are performed in order, so the stages need only a wave-scope fence (which also
+// keeps the compiler from moving LDS accesses across it), no workgroup barrier.
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void wave_stage_body(cx<T>* cols_generic, int L, int Lc, int nw, int p,
+                                                const cx<T>* __restrict__ tw_generic) {
+  const lds_v2<T> cols = (lds_v2<T>)cols_generic;
+  const glob_v2<T> tw = (glob_v2<T>)tw_generic;
+  constexpr int K = (Ept<T>::v + R - 1) / R;  // butterflies per lane
+  const int lane = (int)(threadIdx.x & 63);
+  const int nbf = L / R;
+  const int total = nbf * nw;
+  const int step = L / (p * R);
+  const float inv_p = 1.0f / (float)p, inv_n = 1.0f / (float)nbf;
+  cx<T> v[K][R];
+  int ck[K][2];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int f = lane + u * 64;
+    const int c = (int)qdiv((uint32_t)f, (uint32_t)nbf, inv_n);
+    const int k = f - c * nbf;
+    ck[u][0] = c * Lc;
+    ck[u][1] = k;
+    if (f < total) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[u][m] = to_cx<T>(cols[ck[u][0] + pad8(k + m * nbf)]);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int f = lane + u * 64;
+    if (f < total) {
+      const int k = ck[u][1];
+      const int kq = (int)qdiv((uint32_t)k, (uint32_t)p, inv_p);
+      const int j = k - kq * p;
+      if (j != 0) {
+        cx<T> w = to_cx<T>(tw[j * step]);
+        if (INV) w.y = -w.y;
+        twiddle_powers<T, R>(v[u], w);
+      }
+      Dft<T, R, INV>::run(v[u]);
+      const int o = kq * p * R + j;
+#pragma unroll
+      for (int m = 0; m < R; ++m) cols[ck[u][0] + pad8(o + m * p)] = to_v2<T>(v[u][m]);
+    }
+  }
+  wave_sync();
+}
+
+template <typename T, int R, bool INV>
+__device__ __attribute__((noinline)) void wave_stockham_stage(cx<T>* cols, int L, int Lc, int nw, int p,
+                                                              const cx<T>* __restrict__ tw) {
+  wave_stage_body<T, R, INV>(cols, L, Lc, nw, p, tw);
+}
+
+// Full transform of the calling wave's nw sequences (L * nw <= 64 * Ept<T>); the caller
+// synchronises the workgroup before (the sequences are loaded) and after (other waves read
+// them).
+template <typename T, bool INV>
+__device__ __forceinline__ void wave_fft(cx<T>* cols, int L, int Lc, int nw, const int8_t* rad, int ns,
+                                         const cx<T>* __restrict__ tw) {
+  int p = 1;
+#pragma unroll 1
+  for (int s = 0; s < ns; ++s) {
+    const int R = rad[s];
+    switch (R) {
+      case 8: wave_stockham_stage<T, 8, INV>(cols, L, Lc, nw, p, tw); break;
+      case 4: wave_stockham_stage<T, 4, INV>(cols, L, Lc, nw, p, tw); break;
+      case 2: wave_stockham_stage<T, 2, INV>(cols, L, Lc, nw, p, tw); break;
+      case 3: wave_stockham_stage<T, 3, INV>(cols, L, Lc, nw, p, tw); break;
+      case 5: wave_stockham_stage<T, 5, INV>(cols, L, Lc, nw, p, tw); break;
+      default: break;
+    }
+    p *= R;
+  }
+}
+
 template <typename T, bool INV, bool BFAST, int NT, bool P2>
 __device__ __forceinline__ void lds_transform(cx<T>* lds, int L, int nb, int lg_nb, const int8_t* rad, int ns,
                                               const cx<T>* __restrict__ tw) {

@@ -574,7 +574,7 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
 // ---------------------------------------------------------------------------------------------
 // pass C: inverse column transforms -> filtered TOD in time order (in place)
 
-template <typename T, bool P2>
+template <typename T, bool P2, bool WL>
 __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    cx<T>* __restrict__ X) {
   constexpr int E = Ept<T>::v;
@@ -588,6 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
     const int j10 = item.j1;
     const int nbv = min(B, M1 - j10);
     const int ntot = B * M2;
+    const int Lc = WL ? wave_col_stride(M2, B, (int)sizeof(cx<T>)) : 0;
     cx<T>* Xc = X + ch.xoff + j10;
     {
       cx<T> v[E];
@@ -602,16 +603,22 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
 #pragma unroll
       for (int u = 0; u < E; ++u) {
         const int e = threadIdx.x + u * kBlock;
-        if (e < ntot) lds[e] = v[u];
+        if (e < ntot) lds[WL ? (e & (B - 1)) * Lc + pad8(e >> lgB) : e] = v[u];
       }
     }
     __syncthreads();
-    lds_transform<T, true, true, kBlock, P2>(lds, M2, B, lgB, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    if constexpr (WL) {
+      const int nw = B / kColWaves;
+      wave_fft<T, true>(lds + (int)(threadIdx.x >> 6) * nw * Lc, M2, Lc, nw, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+      __syncthreads();
+    } else {
+      lds_transform<T, true, true, kBlock, P2>(lds, M2, B, lgB, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+    }
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       const int e = threadIdx.x + u * kBlock;
       const int b = e & (B - 1), j2 = e >> lgB;
-      if (e < ntot && b < nbv) Xc[(int64_t)M1 * j2 + b] = lds[e];
+      if (e < ntot && b < nbv) Xc[(int64_t)M1 * j2 + b] = lds[WL ? b * Lc + pad8(j2) : e];
     }
     __syncthreads();
   }
@@ -1492,24 +1499,29 @@ hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void*
   return hipGetLastError();
 }
 
-template <typename T, bool P2>
+template <typename T, bool P2, bool WL>
 static void launch_pass_c_t(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass_c<T, P2>), dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
+  hipLaunchKernelGGL((k_pass_c<T, P2, WL>), dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
                      (cx<T>*)work);
 }
 
 hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  // the inlined power-of-two transforms fit the FP64 tiles; the FP32 tiles (16 values per
-  // thread) spill with them, so FP32 keeps the out-of-line stages
+  // FP64 power-of-two plans: inlined workgroup-wide stages (the plan then never selects the
+  // wave-local layout); otherwise the layout the plan selected, with out-of-line stages
   const bool p2 = P.all_pow2 != 0 && P.precision == 0;
+  const bool wl = !p2 && P.col_wave != 0;
   if (P.precision == 0) {
     if (p2)
-      launch_pass_c_t<double, true>(P, items, nitems, work, lds, s);
+      launch_pass_c_t<double, true, false>(P, items, nitems, work, lds, s);
+    else if (wl)
+      launch_pass_c_t<double, false, true>(P, items, nitems, work, lds, s);
     else
-      launch_pass_c_t<double, false>(P, items, nitems, work, lds, s);
+      launch_pass_c_t<double, false, false>(P, items, nitems, work, lds, s);
+  } else if (wl) {
+    launch_pass_c_t<float, false, true>(P, items, nitems, work, lds, s);
   } else {
-    launch_pass_c_t<float, false>(P, items, nitems, work, lds, s);
+    launch_pass_c_t<float, false, false>(P, items, nitems, work, lds, s);
   }
   return hipGetLastError();
 }

@@ -220,7 +220,6 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
       class_cb.push_back(L.cb);
       pl->class_layout.push_back(pick);
       pl->class_ncand.push_back((int32_t)cands.size());
-      lds_ac = std::max(lds_ac, (size_t)L.cb * (size_t)L.M2 * csz);
       lds_b = std::max(lds_b, (size_t)(2 * L.M1) * csz);
     }
     const DevClass& k = classes[cls];
@@ -252,11 +251,36 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     append_chunk_items((int32_t)c, ch, pl->itemsAC, pl->itemsB);
   }
   pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
+  bool all_pow2 = true;
+  for (const DevClass& k : classes)
+    for (int i = 0; i < k.nr1 + k.nr2; ++i) {
+      const int r = i < k.nr1 ? k.rad1[i] : k.rad2[i - k.nr1];
+      if (r != 2 && r != 4 && r != 8) all_pow2 = false;
+    }
+  // the inverse column pass takes the wave-local layout when every class is eligible, except
+  // in FP64 power-of-two plans (their inlined workgroup-wide stages measured faster)
+  bool col_wave = !(f64 && all_pow2);
+  for (size_t i = 0; i < classes.size(); ++i) col_wave = col_wave && wave_cols(classes[i].M2, class_cb[i], (int)csz);
+  size_t lds_c = 0;
+  for (size_t i = 0; i < classes.size(); ++i) {
+    lds_ac = std::max(lds_ac, (size_t)col_tile_elems(classes[i].M2, class_cb[i], (int)csz, false) * csz);
+    lds_c = std::max(lds_c, (size_t)col_tile_elems(classes[i].M2, class_cb[i], (int)csz, col_wave) * csz);
+  }
   pl->nwork = 2 * xwork;
   pl->lds_ac = lds_ac;
+  pl->lds_c = lds_c;
   pl->lds_b = lds_b;
-  if (lds_ac > 65536 || lds_b + (kBlockB / 64) * sizeof(double) > 65536)
+  if (lds_c > (size_t)kMaxColTileBytes || lds_b + (kBlockB / 64) * sizeof(double) > 65536)
     return fail(MM_E_LEN, "transform tiles exceed the LDS budget");
+  {
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      return fail(MM_E_HIP, "device LDS query failed");
+    if (lds_c > (size_t)lds_max)
+      return fail(MM_E_LEN, "column tiles of " + std::to_string(lds_c) + " bytes exceed the device's " +
+                                std::to_string(lds_max) + " bytes of LDS per workgroup");
+  }
   std::vector<float2> tw32(tw.size());
   for (size_t i = 0; i < tw.size(); ++i) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
 
@@ -439,12 +463,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   DevPlan& P = pl->dp;
   std::memset(&P, 0, sizeof(P));
   P.ncomp = D.ncomp;
-  P.all_pow2 = 1;
-  for (const DevClass& k : classes)
-    for (int i = 0; i < k.nr1 + k.nr2; ++i) {
-      const int r = i < k.nr1 ? k.rad1[i] : k.rad2[i - k.nr1];
-      if (r != 2 && r != 4 && r != 8) P.all_pow2 = 0;
-    }
+  P.all_pow2 = all_pow2 ? 1 : 0;
+  P.col_wave = col_wave ? 1 : 0;
   P.psi_kind = pl->psi_kind;
   P.precision = D.precision;
   P.npix = D.npix;

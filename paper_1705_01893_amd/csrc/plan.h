@@ -29,7 +29,7 @@ struct mm_plan_s {
   std::vector<mm::ItemB> itemsB;
   std::vector<int32_t> chunk_item_begin;
   std::vector<mm::DevChunk> chunks_host;  // kept for noise-parameter updates
-  size_t lds_ac = 0, lds_b = 0;
+  size_t lds_ac = 0, lds_c = 0, lds_b = 0;  // dynamic LDS of the column passes A and C, the row pass
   std::vector<int32_t> class_layout;      // per transform class: chosen candidate index
   std::vector<int32_t> class_ncand;       // per transform class: number of candidates
   int64_t ntiles = 0, nsegs = 0;

@@ -229,13 +229,16 @@ double time_layout(int64_t M, bool f64, const Layout& L, int64_t K, void* din, v
     if (launch_spectrum(P, (double*)bspec.p, s) != hipSuccess) return -1.0;
   }
   const size_t csz = f64 ? sizeof(double2) : sizeof(float2);
-  const size_t lds_ac = (size_t)L.cb * L.M2 * csz, lds_b = (size_t)2 * L.M1 * csz;
+  P.col_wave = !(f64 && P.all_pow2) && wave_cols(L.M2, L.cb, (int)csz) ? 1 : 0;
+  const size_t lds_ac = (size_t)col_tile_elems(L.M2, L.cb, (int)csz, false) * csz,
+               lds_c = (size_t)col_tile_elems(L.M2, L.cb, (int)csz, P.col_wave != 0) * csz,
+               lds_b = (size_t)2 * L.M1 * csz;
   auto run = [&]() -> bool {
     return launch_pass_a(P, (const ItemAC*)bac.p, (int)itemsAC.size(), din, nullptr, SRC_D, dwork, lds_ac, s) ==
                hipSuccess &&
            launch_pass_b(P, (const ItemB*)bb.p, (int)itemsB.size(), dwork, B_FILTER, GAIN_MESSENGER, 1.0, 1.0,
                          nullptr, lds_b, s) == hipSuccess &&
-           launch_pass_c(P, (const ItemAC*)bac.p, (int)itemsAC.size(), dwork, lds_ac, s) == hipSuccess;
+           launch_pass_c(P, (const ItemAC*)bac.p, (int)itemsAC.size(), dwork, lds_c, s) == hipSuccess;
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;

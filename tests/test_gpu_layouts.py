@@ -42,6 +42,12 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
+def wave_local_inverse(lay):
+    """Whether a plan with these layouts (not FP64 power-of-two) runs the inverse column pass
+    in the wave-local LDS layout: every class holds at least one column per wave (8 waves)."""
+    return all(l["cb"] >= 8 for l in lay)
+
+
 def plan_for(t, dev, tune, precision=mm.MM_FP64):
     psi = torch.from_numpy(np.ascontiguousarray(t.psi)).to(dev)
     return mm.mm_plan(ncomp=3, npix=t.npix, nx=t.nx, chunk_off=t.chunk_off, fsample=t.fsample, sigma=t.sigma,
@@ -60,6 +66,7 @@ def test_every_layout_fp64(dev, shape):
     d = torch.from_numpy(t.d).to(dev)
     ncand = mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_STATIC), 0)["ncand"]
     seen = set()
+    kinds = set()
     for pick in range(max(ncand, mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_STATIC), 1)["ncand"])):
         plan = plan_for(t, dev, mm.MM_TUNE_PICK0 + pick)
         lay = [mm.mm_plan_chunk_layout(plan, c) for c in range(plan.nchunk)]
@@ -67,6 +74,7 @@ def test_every_layout_fp64(dev, shape):
         say(f"[layout] shape={shape} pick={pick} {key}")
         assert all(l["M1"] * l["M2"] * 2 == n for l, n in zip(lay, LENGTHS[shape]))
         seen.add(key)
+        kinds.add(wave_local_inverse(lay))
         mi = torch.from_numpy(m0).to(dev)
         for lam, r in ref.items():
             mo = torch.zeros_like(mi)
@@ -76,6 +84,8 @@ def test_every_layout_fp64(dev, shape):
             assert rel(mo.cpu().numpy(), r) < F64_TOL, (pick, lam)
             assert c2.item() == pytest.approx(c2ref, rel=F64_TOL)
     assert len(seen) >= 3  # several distinct layouts were exercised
+    if shape == "mixed":  # both LDS layouts of the inverse column pass were exercised
+        assert kinds == {True, False}
 
 
 def test_every_layout_mixed(dev):
@@ -86,14 +96,17 @@ def test_every_layout_mixed(dev):
     ref = messenger_step(S, t.d.astype(np.float64), m0, 1.0)
     d = torch.from_numpy(t.d).to(dev)
     n0 = mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_STATIC, mm.MM_MIXED), 0)["ncand"]
+    kinds = set()
     for pick in range(n0):
         say(f"[layout mixed] pick={pick}")
         plan = plan_for(t, dev, mm.MM_TUNE_PICK0 + pick, mm.MM_MIXED)
+        kinds.add(wave_local_inverse([mm.mm_plan_chunk_layout(plan, c) for c in range(plan.nchunk)]))
         mi = torch.from_numpy(m0).to(dev)
         mo = torch.zeros_like(mi)
         mm.mm_messenger_iter(plan, d, 1.0, mi, mo)
         torch.cuda.synchronize()
         assert rel(mo.cpu().numpy(), ref) < MIX_TOL, pick
+    assert kinds == {True, False}
 
 
 def test_tuner_picks_a_valid_layout(dev):
