@@ -399,8 +399,7 @@ mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const do
   if (!plan || !d || !m || !z || !grad_dev) return fail(MM_E_ARG, "null argument");
   // two rows of both residuals per workgroup: 4 M1 complex values, at most the transform capacity
   // kBlock * Ept (= 64 KB of LDS)
-  const size_t lds = 2 * plan->lds_b;
-  if (lds > 65536) return fail(MM_E_LEN, "chunk rows too long for the two-spectrum gradient pass");
+  if (plan->lds_g > 65536) return fail(MM_E_LEN, "chunk rows too long for the two-spectrum gradient pass");
   hipStream_t s = S(stream);
   if (!plan->d_work2) {
     void* p = nullptr;
@@ -416,8 +415,8 @@ mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const do
   MM_TRY_HIP(launch_interleave(plan->dp, z, s));
   MM_TRY_HIP(launch_pass_a(plan->dp, plan->d_itemsAC, (int)plan->itemsAC.size(), nullptr, z,
                            pm ? SRC_PMBUF : SRC_PM, plan->d_work2, plan->lds_ac, s, plan->d_pm));
-  MM_TRY_HIP(launch_grad(plan->dp, plan->d_itemsB, (int)plan->itemsB.size(), plan->d_chunk_item_begin,
-                         plan->d_work, plan->d_work2, plan->d_chi2_part, grad_dev, lds, s));
+  MM_TRY_HIP(launch_grad(plan->dp, plan->d_itemsG, (int)plan->itemsG.size(), plan->d_chunk_itemG_begin,
+                         plan->d_work, plan->d_work2, plan->d_chi2_part, grad_dev, plan->lds_g, s));
   return MM_OK;
 }
 

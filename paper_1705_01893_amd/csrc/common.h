@@ -86,7 +86,9 @@ struct DevClass {
 };
 
 struct ItemAC { int32_t chunk, j1; };            // column block starting at column j1
-struct ItemB { int32_t chunk, ra, rb, first; };  // rows ra, rb (rb == ra: one row); first item of its chunk?
+// rows ra, rb (rb == ra: one row); rc > 0: a second pair of rows rc, M2 - rc in the same item
+// (the row pass's items when four rows fit its tile; the gradient row pass never has one)
+struct ItemB { int32_t chunk, ra, rb, rc; };
 
 // Deterministic binning structures.  Samples on the map are grouped by pixel
 // tile, each tile's samples (in time order) are cut into sub-batches of at most

@@ -486,12 +486,43 @@ __device__ __forceinline__ void b_self(cx<T>* lds, const DevPlan& P, const DevCh
   }
 }
 
+// Rows of a row item between the work buffer and LDS (row r at r * M1).  NR: rows the item may
+// hold (2: one pair or a self-paired row, nrow <= 2; 4: two pairs); NR * M1 <= kBlockB * Ept.
+template <typename T, int NR>
+__device__ __forceinline__ void row_load(cx<T>* lds, const cx<T>* __restrict__ Xc, const int* rws, int nrow, int M1) {
+  constexpr int U = Ept<T>::v / NR;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * kBlockB;
+    if (e < M1) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nrow) lds[r * M1 + e] = Xc[(int64_t)rws[r] * M1 + e];
+    }
+  }
+}
+
+// the inverse row transforms' output, times the conjugate column twiddle, back to the work buffer
+template <typename T, int NR>
+__device__ __forceinline__ void row_store(const cx<T>* lds, cx<T>* __restrict__ Xc, const DevPlan& P,
+                                          const DevClass& cl, const int* rws, int nrow, int M1) {
+  constexpr int U = Ept<T>::v / NR;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j1 = threadIdx.x + u * kBlockB;
+    if (j1 < M1) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nrow) Xc[(int64_t)rws[r] * M1 + j1] = cmul(lds[r * M1 + j1], conjc(omega2M<T>(P, cl, 2 * j1 * rws[r])));
+    }
+  }
+}
+
 // at most 128 VGPRs, so that four 256-thread workgroups share a CU
 template <typename T>
 __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
                                                    cx<T>* __restrict__ X, int ops, BinCtx bc,
                                                    double* __restrict__ chi2_part, int red_off) {
-  constexpr int E = Ept<T>::v;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   double* red = reinterpret_cast<double*>(smem_raw + red_off);
@@ -500,27 +531,32 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     const DevChunk ch = P.chunks[item.chunk];
     const DevClass& cl = P.classes[ch.cls];
     const int M1 = ch.M1, M2 = ch.M2;
-    const int ra = item.ra, rb = item.rb;
-    const int nrow = (ra == rb) ? 1 : 2;
-    const int ntot = nrow * M1;
+    const int ra = item.ra, rb = item.rb, rc = item.rc;
+    // LDS rows: ra, rb, then (two pairs) rc, M2 - rc
+    const int nrow = rc > 0 ? 4 : ((ra == rb) ? 1 : 2);
     cx<T>* Xc = X + ch.xoff;
-    cx<T>* Xa = Xc + (int64_t)ra * M1;
-    cx<T>* Xb = Xc + (int64_t)rb * M1;
-    // 2 * M1 < kBlockB * E, so each row takes at most E/2 elements per thread
-#pragma unroll
-    for (int u = 0; u < E / 2; ++u) {
-      const int e = threadIdx.x + u * kBlockB;
-      if (e < M1) {
-        lds[e] = Xa[e];
-        if (nrow == 2) lds[M1 + e] = Xb[e];
-      }
-    }
+    const int rws[4] = {ra, rb, rc, M2 - rc};
+    if (rc > 0)
+      row_load<T, 4>(lds, Xc, rws, 4, M1);
+    else
+      row_load<T, 2>(lds, Xc, rws, nrow, M1);
     __syncthreads();
     const cx<T>* tw1 = twtab<T>(P) + cl.tw1;
     lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
     double chi = 0.0;
     const bool self_a = (ra == 0) || (2 * ra == M2);
-    if (!self_a) {
+    if (rc > 0) {
+      // two pairs of rows (r, M2 - r): bins k = r + M2 k1 and M - k = (M2 - r) + M2 (M1 - 1 - k1)
+      for (int t = threadIdx.x; t < 2 * M1; t += kBlockB) {
+        const int q = t >= M1 ? 1 : 0;
+        const int k1 = t - q * M1;
+        const int pk1 = M1 - 1 - k1;
+        const int r = q ? rc : ra, rr = M2 - r;
+        const int k = r + M2 * k1;
+        b_pair<T>(lds, P, ch, cl, bc, ops, k, 2 * q * M1 + k1, (2 * q + 1) * M1 + pk1, r * M1 + k1, rr * M1 + pk1,
+                  chi);
+      }
+    } else if (!self_a) {
       for (int k1 = threadIdx.x; k1 < M1; k1 += kBlockB) {
         const int pk1 = M1 - 1 - k1;
         const int k = ra + M2 * k1;
@@ -558,14 +594,10 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     if (ops & B_FILTER) {
       __syncthreads();
       lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
-#pragma unroll
-      for (int u = 0; u < E / 2; ++u) {
-        const int j1 = threadIdx.x + u * kBlockB;
-        if (j1 < M1) {
-          Xa[j1] = cmul(lds[j1], conjc(omega2M<T>(P, cl, 2 * j1 * ra)));
-          if (nrow == 2) Xb[j1] = cmul(lds[M1 + j1], conjc(omega2M<T>(P, cl, 2 * j1 * rb)));
-        }
-      }
+      if (rc > 0)
+        row_store<T, 4>(lds, Xc, P, cl, rws, 4, M1);
+      else
+        row_store<T, 2>(lds, Xc, P, cl, rws, nrow, M1);
     }
     __syncthreads();
   }

@@ -193,7 +193,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   std::vector<DevChunk> chunks(D.nchunk);
   std::vector<int64_t> class_M;
   std::vector<int> class_cb;
-  size_t lds_ac = 0, lds_b = 0;
+  size_t lds_ac = 0, lds_b = 0, lds_g = 0;
   int64_t spec_total = 0;
   int64_t xwork = 0;  // complex values of the work buffers (chunk bases 16-aligned)
   for (int64_t c = 0; c < D.nchunk; ++c) {
@@ -220,7 +220,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
       class_cb.push_back(L.cb);
       pl->class_layout.push_back(pick);
       pl->class_ncand.push_back((int32_t)cands.size());
-      lds_b = std::max(lds_b, (size_t)(2 * L.M1) * csz);
+      lds_b = std::max(lds_b, (size_t)((row_fuse(L.M1, f64) ? 4 : 2) * L.M1) * csz);
+      lds_g = std::max(lds_g, (size_t)(4 * L.M1) * csz);  // rows of r and of P z
     }
     const DevClass& k = classes[cls];
     DevChunk& ch = chunks[c];
@@ -248,9 +249,13 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
     xwork += (ch.M + kWorkAlign - 1) / kWorkAlign * kWorkAlign;
     spec_total += ch.M + 1;
     pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
-    append_chunk_items((int32_t)c, ch, pl->itemsAC, pl->itemsB);
+    pl->chunk_itemG_begin.push_back((int32_t)pl->itemsG.size());
+    append_col_items((int32_t)c, ch, pl->itemsAC);
+    append_row_items((int32_t)c, ch, pl->itemsB, row_fuse(ch.M1, f64));
+    append_row_items((int32_t)c, ch, pl->itemsG, false);
   }
   pl->chunk_item_begin.push_back((int32_t)pl->itemsB.size());
+  pl->chunk_itemG_begin.push_back((int32_t)pl->itemsG.size());
   bool all_pow2 = true;
   for (const DevClass& k : classes)
     for (int i = 0; i < k.nr1 + k.nr2; ++i) {
@@ -270,6 +275,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   pl->lds_ac = lds_ac;
   pl->lds_c = lds_c;
   pl->lds_b = lds_b;
+  pl->lds_g = lds_g;
   if (lds_c > (size_t)kMaxColTileBytes || lds_b + (kBlockB / 64) * sizeof(double) > 65536)
     return fail(MM_E_LEN, "transform tiles exceed the LDS budget");
   {
@@ -535,6 +541,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   if ((st = upload(pl, pl->itemsAC, &pl->d_itemsAC, s)) != MM_OK) return st;
   if ((st = upload(pl, pl->itemsB, &pl->d_itemsB, s)) != MM_OK) return st;
   if ((st = upload(pl, pl->chunk_item_begin, &pl->d_chunk_item_begin, s)) != MM_OK) return st;
+  if ((st = upload(pl, pl->itemsG, &pl->d_itemsG, s)) != MM_OK) return st;
+  if ((st = upload(pl, pl->chunk_itemG_begin, &pl->d_chunk_itemG_begin, s)) != MM_OK) return st;
 
   const int64_t mapn = (int64_t)D.ncomp * D.npix;
   const int nw = D.ncomp == 1 ? 1 : 6;
@@ -547,7 +555,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   pl->d_hits = (int32_t*)p;
   if ((st = plan_alloc(pl, (size_t)pl->nwork * (f64 ? 8 : 4), &p)) != MM_OK) return st;
   pl->d_work = p;
-  if ((st = plan_alloc(pl, 3 * pl->itemsB.size() * sizeof(double), &p)) != MM_OK) return st;
+  if ((st = plan_alloc(pl, std::max(pl->itemsB.size(), 3 * pl->itemsG.size()) * sizeof(double), &p)) != MM_OK)
+    return st;
   pl->d_chi2_part = (double*)p;  // chi^2 partials (1 per row item) or gradient partials (3 per item)
   if ((st = plan_alloc(pl, 64 * sizeof(double), &p)) != MM_OK) return st;
   pl->d_scal = (double*)p;

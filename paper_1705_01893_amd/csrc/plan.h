@@ -26,10 +26,12 @@ struct mm_plan_s {
   std::vector<double> fsample, sigma, fknee, alpha, tau;
   // work lists
   std::vector<mm::ItemAC> itemsAC;
-  std::vector<mm::ItemB> itemsB;
-  std::vector<int32_t> chunk_item_begin;
+  std::vector<mm::ItemB> itemsB;           // row pass (two row pairs per item where they fit)
+  std::vector<int32_t> chunk_item_begin;   // first row-pass item of each chunk, and the end
+  std::vector<mm::ItemB> itemsG;           // gradient row pass (one row pair per item)
+  std::vector<int32_t> chunk_itemG_begin;
   std::vector<mm::DevChunk> chunks_host;  // kept for noise-parameter updates
-  size_t lds_ac = 0, lds_c = 0, lds_b = 0;  // dynamic LDS of the column passes A and C, the row pass
+  size_t lds_ac = 0, lds_c = 0, lds_b = 0, lds_g = 0;  // dynamic LDS: column passes A, C; row passes
   std::vector<int32_t> class_layout;      // per transform class: chosen candidate index
   std::vector<int32_t> class_ncand;       // per transform class: number of candidates
   int64_t ntiles = 0, nsegs = 0;
@@ -42,6 +44,8 @@ struct mm_plan_s {
   mm::ItemAC* d_itemsAC = nullptr;
   mm::ItemB* d_itemsB = nullptr;
   int32_t* d_chunk_item_begin = nullptr;
+  mm::ItemB* d_itemsG = nullptr;
+  int32_t* d_chunk_itemG_begin = nullptr;
   double* d_winv = nullptr;
   uint8_t* d_solvable = nullptr;
   int32_t* d_hits = nullptr;
@@ -100,7 +104,10 @@ std::vector<Layout> layout_candidates(int64_t M, bool f64);
 // radix schedules and twiddle offsets of layout L (twiddles appended to tw)
 void make_class(int64_t M, const Layout& L, std::vector<double2>& tw, DevClass& k);
 // column items and row-pair items of chunk c
-void append_chunk_items(int32_t c, const DevChunk& ch, std::vector<ItemAC>& itemsAC, std::vector<ItemB>& itemsB);
+// whether the row pass holds two row pairs (four rows of length M1) per item
+bool row_fuse(int M1, bool f64);
+void append_col_items(int32_t c, const DevChunk& ch, std::vector<ItemAC>& itemsAC);
+void append_row_items(int32_t c, const DevChunk& ch, std::vector<ItemB>& itemsB, bool fuse);
 // index of the fastest candidate, timed on the GPU (0 for short chunks or on any failure);
 // cached per process by (M, precision)
 int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream_t s);

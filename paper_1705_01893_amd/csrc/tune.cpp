@@ -142,16 +142,24 @@ void make_class(int64_t M, const Layout& L, std::vector<double2>& tw, DevClass& 
   omega_table(L2, nhi, lo, tw);
 }
 
-void append_chunk_items(int32_t c, const DevChunk& ch, std::vector<ItemAC>& itemsAC, std::vector<ItemB>& itemsB) {
+bool row_fuse(int M1, bool f64) { return 4 * M1 <= tile_cap_b(f64); }
+
+void append_col_items(int32_t c, const DevChunk& ch, std::vector<ItemAC>& itemsAC) {
   for (int32_t j1 = 0; j1 < ch.M1; j1 += ch.cb) itemsAC.push_back({c, j1});
+}
+
+void append_row_items(int32_t c, const DevChunk& ch, std::vector<ItemB>& itemsB, bool fuse) {
   const int M2 = ch.M2;
   // rows k2 and M2 - k2 pair up (bins k and M - k); row 0 (and row M2/2) pair with themselves
-  if (M2 % 2 == 0) {
-    itemsB.push_back({c, 0, M2 / 2, 0});
-    for (int k2 = 1; k2 < M2 / 2; ++k2) itemsB.push_back({c, k2, M2 - k2, 0});
-  } else {
-    itemsB.push_back({c, 0, 0, 0});
-    for (int k2 = 1; k2 <= (M2 - 1) / 2; ++k2) itemsB.push_back({c, k2, M2 - k2, 0});
+  itemsB.push_back({c, 0, M2 % 2 == 0 ? M2 / 2 : 0, 0});
+  const int last = M2 % 2 == 0 ? M2 / 2 - 1 : (M2 - 1) / 2;
+  for (int k2 = 1; k2 <= last; ++k2) {
+    if (fuse && k2 + 1 <= last) {
+      itemsB.push_back({c, k2, M2 - k2, k2 + 1});
+      ++k2;
+    } else {
+      itemsB.push_back({c, k2, M2 - k2, 0});
+    }
   }
 }
 
@@ -205,7 +213,8 @@ double time_layout(int64_t M, bool f64, const Layout& L, int64_t K, void* din, v
     ch.inv_M = 1.0 / (double)M;
     ch.lg0 = std::log2(ch.df / ch.fknee);
     ch.xoff = c * ((M + kWorkAlign - 1) / kWorkAlign * kWorkAlign);
-    append_chunk_items((int32_t)c, ch, itemsAC, itemsB);
+    append_col_items((int32_t)c, ch, itemsAC);
+    append_row_items((int32_t)c, ch, itemsB, row_fuse(L.M1, f64));
   }
   DevBuf bch, bcl, btw, btw32, bac, bb, bspec;
   if (!put(bch, chunks, s) || !put(bcl, cls, s) || !put(btw, tw, s) || !put(btw32, tw32, s) || !put(bac, itemsAC, s) ||
@@ -232,7 +241,7 @@ double time_layout(int64_t M, bool f64, const Layout& L, int64_t K, void* din, v
   P.col_wave = !(f64 && P.all_pow2) && wave_cols(L.M2, L.cb, (int)csz) ? 1 : 0;
   const size_t lds_ac = (size_t)col_tile_elems(L.M2, L.cb, (int)csz, false) * csz,
                lds_c = (size_t)col_tile_elems(L.M2, L.cb, (int)csz, P.col_wave != 0) * csz,
-               lds_b = (size_t)2 * L.M1 * csz;
+               lds_b = (size_t)(row_fuse(L.M1, f64) ? 4 : 2) * L.M1 * csz;
   auto run = [&]() -> bool {
     return launch_pass_a(P, (const ItemAC*)bac.p, (int)itemsAC.size(), din, nullptr, SRC_D, dwork, lds_ac, s) ==
                hipSuccess &&
