@@ -786,15 +786,17 @@ __device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw,
 
 // LDS layout of k_bin and k_project:
 // [stage | acc | carries | start bitmaps (2 x 64 words) | sstart | schunk | spos | carry pixels]
-template <int NV>
+// The stage holds one sub-batch of TOD values (or of P m) in the TOD precision S.
+template <int NV, typename S>
 __host__ __device__ constexpr size_t bin_lds_bytes(bool plan) {
-  return (plan ? 0 : kSubBatch * sizeof(double)) + kMaxTilePix * NV * sizeof(double) +
+  return (plan ? 0 : kSubBatch * sizeof(S)) + kMaxTilePix * NV * sizeof(double) +
          kWaves * NV * sizeof(double) + 2 * (kSubBatch / 64) * sizeof(unsigned long long) +
          kMaxSegs * (sizeof(int64_t) + sizeof(int) + sizeof(uint16_t)) + kWaves * sizeof(int);
 }
 
+template <typename S>
 struct BinLds {
-  double* stage;
+  S* stage;
   double* acc;
   double* cv;
   unsigned long long* smask;  // two bitmaps, alternating between consecutive sub-batches
@@ -804,11 +806,11 @@ struct BinLds {
   int* clp;
 };
 
-template <int NV>
-__device__ __forceinline__ BinLds bin_lds(double* base, bool plan) {
-  BinLds L;
-  L.stage = base;
-  L.acc = base + (plan ? 0 : kSubBatch);
+template <int NV, typename S>
+__device__ __forceinline__ BinLds<S> bin_lds(double* base, bool plan) {
+  BinLds<S> L;
+  L.stage = reinterpret_cast<S*>(base);
+  L.acc = base + (plan ? 0 : kSubBatch * sizeof(S) / sizeof(double));
   L.cv = L.acc + kMaxTilePix * NV;
   L.smask = reinterpret_cast<unsigned long long*>(L.cv + kWaves * NV);
   L.sstart = reinterpret_cast<int64_t*>(L.smask + 2 * (kSubBatch / 64));
@@ -821,7 +823,8 @@ __device__ __forceinline__ BinLds bin_lds(double* base, bool plan) {
 // Load the segment table of sub-batch S and mark its starts in bitmap `sm` (zeroed beforehand).
 // Segment starts are sample indices in time order; in_work moves them to the work buffer, where
 // chunk c starts at real position 2 xoff_c instead of off_c.
-__device__ __forceinline__ void load_segments(const DevPlan& P, const SubBatch& S, const BinLds& L,
+template <typename SL>
+__device__ __forceinline__ void load_segments(const DevPlan& P, const SubBatch& S, const BinLds<SL>& L,
                                               unsigned long long* sm, bool with_chunk, bool in_work) {
   const int nseg = S.seg_end - S.seg_begin;
   for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
@@ -881,7 +884,7 @@ __device__ __forceinline__ uint64_t entry_psi_raw(const DevPlan& P, const LaneEn
 // in pixel-sorted order, scattered to their staging positions in LDS and written out along the
 // sub-batch's time-contiguous segments (coalesced within each segment).
 template <typename T, int NC>
-__device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt, const BinLds& L, int& sbn,
+__device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt, const BinLds<T>& L, int& sbn,
                              T* __restrict__ pm_out) {
   constexpr int SPW = kSubBatch / kBinBlock;
   for (int sb = tl.sb_begin; sb < tl.sb_end; ++sb, ++sbn) {
@@ -907,7 +910,7 @@ __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt,
               weights_from_raw<T>(P, entry_psi_raw(P, en, i), c, sn);
               v += c * mt[l * 3 + 1] + sn * mt[l * 3 + 2];
             }
-            L.stage[entry_u16(en.pmw, i)] = v;
+            L.stage[entry_u16(en.pmw, i)] = (T)v;
           }
         }
       }
@@ -921,7 +924,7 @@ __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt,
     for (int u = 0; u < SPW; ++u) {
       const int q = threadIdx.x + u * kBinBlock;
       const int g = seg_lookup(si, q);  // lane reads with every lane active
-      if (q < cnt) pm_out[L.sstart[g] + (q - (int)L.spos[g])] = (T)L.stage[q];
+      if (q < cnt) pm_out[L.sstart[g] + (q - (int)L.spos[g])] = L.stage[q];
     }
     __syncthreads();
   }
@@ -931,7 +934,7 @@ template <typename T, int NC>
 __global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* __restrict__ m,
                                                        T* __restrict__ pm_out) {
   extern __shared__ double smem_d[];
-  const BinLds L = bin_lds<NC>(smem_d, false);
+  const BinLds<T> L = bin_lds<NC, T>(smem_d, false);
   double* mt = L.acc;
   if (threadIdx.x < 2 * (kSubBatch / 64)) L.smask[threadIdx.x] = 0ull;
   int sbn = 0;
@@ -948,17 +951,20 @@ __global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* 
   }
 }
 
+// FP32 iteration binning: at most 128 VGPRs, so that four workgroups (36 KB of LDS each) share a CU
 template <typename T, int NV>
-__global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T* __restrict__ src, int epi,
+__global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) void k_bin(DevPlan P, int bsrc, const T* __restrict__ src, int epi,
                                                    const double* __restrict__ m_in, double* __restrict__ out,
                                                    double* __restrict__ w_out, int32_t* __restrict__ hits_out,
                                                    uint8_t* __restrict__ sol_out, T* __restrict__ pm_out) {
   constexpr bool PLAN = (NV == 2 || NV == 7);
   constexpr bool POL = (NV == 3 || NV == 7);
   constexpr int SPW = kSubBatch / kBinBlock;  // staged samples per thread
+  // the stage holds TOD values in the TOD precision: an FP32 stage cannot hold d / tau exactly
+  constexpr bool kScaleAtUse = sizeof(T) < sizeof(double);
   extern __shared__ double smem_d[];
-  const BinLds L = bin_lds<NV>(smem_d, PLAN);
-  double* stage = L.stage;
+  const BinLds<T> L = bin_lds<NV, T>(smem_d, PLAN);
+  T* stage = L.stage;
   double* acc = L.acc;
   double* cv = L.cv;
   const int64_t* sstart = L.sstart;
@@ -1004,13 +1010,14 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
             if (q < cnt) {
               const int64_t j = sstart[g] + (q - (int)spos[g]);
               v[u] = (double)src[j];
-              if (bsrc == BSRC_DATA_OVER_TAU) v[u] *= P.chunks[schunk[g]].inv_tau;
+              // d / tau: scaled here in FP64 staging, where it is used in FP32 staging
+              if (!kScaleAtUse && bsrc == BSRC_DATA_OVER_TAU) v[u] *= P.chunks[schunk[g]].inv_tau;
             }
           }
 #pragma unroll
           for (int u = 0; u < SPW / 2; ++u) {
             const int q = threadIdx.x + (h * (SPW / 2) + u) * kBinBlock;
-            if (q < cnt) stage[q] = v[u];
+            if (q < cnt) stage[q] = (T)v[u];
           }
         }
         __syncthreads();
@@ -1025,7 +1032,8 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
 #pragma unroll
         for (int i = 0; i < kPerLane; ++i) {
           const int pr = entry_u16(en.pmw, i);
-          const int gpr = PLAN ? seg_lookup(si, pr) : 0;  // lane reads with every lane of the wave active
+          // lane reads with every lane of the wave active
+          const int gpr = (PLAN || (kScaleAtUse && bsrc == BSRC_DATA_OVER_TAU)) ? seg_lookup(si, pr) : 0;
           if (kl + i < k1) {
             const int lp = entry_u16(en.lpw, i);
             double y;
@@ -1033,6 +1041,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(DevPlan P, int bsrc, const T*
               y = P.chunks[schunk[gpr]].inv_tau;
             } else {
               y = stage[pr];
+              if (kScaleAtUse && bsrc == BSRC_DATA_OVER_TAU) y *= P.chunks[schunk[gpr]].inv_tau;
             }
             double c = 0.0, sn = 0.0;
             if (POL) weights_from_raw<T>(P, entry_psi_raw(P, en, i), c, sn);
@@ -1561,7 +1570,7 @@ hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void
 template <typename T, int NV>
 static hipError_t launch_bin_t(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
                                double* w_out, int32_t* hits_out, uint8_t* sol_out, hipStream_t s, void* pm_out) {
-  const size_t lds = bin_lds_bytes<NV>(NV == 2 || NV == 7);
+  const size_t lds = bin_lds_bytes<NV, T>(NV == 2 || NV == 7);
   hipLaunchKernelGGL((k_bin<T, NV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, bsrc,
                      (const T*)src, epi, m_in, out, w_out, hits_out, sol_out, (T*)pm_out);
   return hipGetLastError();
@@ -1697,7 +1706,7 @@ hipError_t launch_interleave(const DevPlan& P, const double* m, hipStream_t s) {
 hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipStream_t s) {
   const bool f64 = P.precision == 0;
   if (P.ncomp == 1) {
-    const size_t lds = bin_lds_bytes<1>(false);
+    const size_t lds = f64 ? bin_lds_bytes<1, double>(false) : bin_lds_bytes<1, float>(false);
     if (f64)
       hipLaunchKernelGGL((k_project<double, 1>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
                          (double*)pm_out);
@@ -1705,7 +1714,7 @@ hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipSt
       hipLaunchKernelGGL((k_project<float, 1>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
                          (float*)pm_out);
   } else {
-    const size_t lds = bin_lds_bytes<3>(false);
+    const size_t lds = f64 ? bin_lds_bytes<3, double>(false) : bin_lds_bytes<3, float>(false);
     if (f64)
       hipLaunchKernelGGL((k_project<double, 3>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
                          (double*)pm_out);
