@@ -119,7 +119,7 @@ struct DevPlan {
   int32_t ncomp, psi_kind, precision;
   int32_t all_pow2;          // every chunk length is a power of two (radix 8/4/2 transforms)
   int32_t col_wave;          // the column passes use the wave-local layout (every class eligible)
-  int32_t pad1;
+  int32_t max_tile_pix;      // pixels of the largest binning tile (LDS accumulators)
   int64_t npix, nxm;         // pixels, map row length used by the tiles
   int64_t nsamp;
   int32_t nchunk, ntiles;

@@ -785,13 +785,15 @@ __device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw,
 }
 
 // LDS layout of k_bin and k_project:
-// [stage | acc | carries | start bitmaps (2 x 64 words) | sstart | schunk | spos | carry pixels]
-// The stage holds one sub-batch of TOD values (or of P m) in the TOD precision S.
+// [stage | acc | carries | start bitmaps (2 x 64 words) | sstart | spos | carry pixels | schunk]
+// The stage holds one sub-batch of TOD values (or of P m) in the TOD precision S; acc holds NV
+// values for each of the plan's largest tile's tpix pixels; the segment chunks (schunk) are
+// only there when the caller needs them (plan pass, d / tau binning).
 template <int NV, typename S>
-__host__ __device__ constexpr size_t bin_lds_bytes(bool plan) {
-  return (plan ? 0 : kSubBatch * sizeof(S)) + kMaxTilePix * NV * sizeof(double) +
-         kWaves * NV * sizeof(double) + 2 * (kSubBatch / 64) * sizeof(unsigned long long) +
-         kMaxSegs * (sizeof(int64_t) + sizeof(int) + sizeof(uint16_t)) + kWaves * sizeof(int);
+__host__ __device__ constexpr size_t bin_lds_bytes(bool plan, int tpix, bool with_chunk) {
+  return (plan ? 0 : kSubBatch * sizeof(S)) + (size_t)tpix * NV * sizeof(double) + kWaves * NV * sizeof(double) +
+         2 * (kSubBatch / 64) * sizeof(unsigned long long) + kMaxSegs * (sizeof(int64_t) + sizeof(uint16_t)) +
+         kWaves * sizeof(int) + (with_chunk ? kMaxSegs * sizeof(int) : 0);
 }
 
 template <typename S>
@@ -807,16 +809,16 @@ struct BinLds {
 };
 
 template <int NV, typename S>
-__device__ __forceinline__ BinLds<S> bin_lds(double* base, bool plan) {
+__device__ __forceinline__ BinLds<S> bin_lds(double* base, bool plan, int tpix) {
   BinLds<S> L;
   L.stage = reinterpret_cast<S*>(base);
   L.acc = base + (plan ? 0 : kSubBatch * sizeof(S) / sizeof(double));
-  L.cv = L.acc + kMaxTilePix * NV;
+  L.cv = L.acc + tpix * NV;
   L.smask = reinterpret_cast<unsigned long long*>(L.cv + kWaves * NV);
   L.sstart = reinterpret_cast<int64_t*>(L.smask + 2 * (kSubBatch / 64));
-  L.schunk = reinterpret_cast<int*>(L.sstart + kMaxSegs);
-  L.spos = reinterpret_cast<uint16_t*>(L.schunk + kMaxSegs);
+  L.spos = reinterpret_cast<uint16_t*>(L.sstart + kMaxSegs);
   L.clp = reinterpret_cast<int*>(L.spos + kMaxSegs);
+  L.schunk = L.clp + kWaves;
   return L;
 }
 
@@ -934,7 +936,7 @@ template <typename T, int NC>
 __global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* __restrict__ m,
                                                        T* __restrict__ pm_out) {
   extern __shared__ double smem_d[];
-  const BinLds<T> L = bin_lds<NC, T>(smem_d, false);
+  const BinLds<T> L = bin_lds<NC, T>(smem_d, false, P.max_tile_pix);
   double* mt = L.acc;
   if (threadIdx.x < 2 * (kSubBatch / 64)) L.smask[threadIdx.x] = 0ull;
   int sbn = 0;
@@ -963,7 +965,7 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
   // the stage holds TOD values in the TOD precision: an FP32 stage cannot hold d / tau exactly
   constexpr bool kScaleAtUse = sizeof(T) < sizeof(double);
   extern __shared__ double smem_d[];
-  const BinLds<T> L = bin_lds<NV, T>(smem_d, PLAN);
+  const BinLds<T> L = bin_lds<NV, T>(smem_d, PLAN, P.max_tile_pix);
   T* stage = L.stage;
   double* acc = L.acc;
   double* cv = L.cv;
@@ -1570,7 +1572,8 @@ hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void
 template <typename T, int NV>
 static hipError_t launch_bin_t(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
                                double* w_out, int32_t* hits_out, uint8_t* sol_out, hipStream_t s, void* pm_out) {
-  const size_t lds = bin_lds_bytes<NV, T>(NV == 2 || NV == 7);
+  constexpr bool plan = NV == 2 || NV == 7;
+  const size_t lds = bin_lds_bytes<NV, T>(plan, P.max_tile_pix, plan || bsrc == BSRC_DATA_OVER_TAU);
   hipLaunchKernelGGL((k_bin<T, NV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, bsrc,
                      (const T*)src, epi, m_in, out, w_out, hits_out, sol_out, (T*)pm_out);
   return hipGetLastError();
@@ -1706,7 +1709,8 @@ hipError_t launch_interleave(const DevPlan& P, const double* m, hipStream_t s) {
 hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipStream_t s) {
   const bool f64 = P.precision == 0;
   if (P.ncomp == 1) {
-    const size_t lds = f64 ? bin_lds_bytes<1, double>(false) : bin_lds_bytes<1, float>(false);
+    const size_t lds = f64 ? bin_lds_bytes<1, double>(false, P.max_tile_pix, false)
+                           : bin_lds_bytes<1, float>(false, P.max_tile_pix, false);
     if (f64)
       hipLaunchKernelGGL((k_project<double, 1>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
                          (double*)pm_out);
@@ -1714,7 +1718,8 @@ hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipSt
       hipLaunchKernelGGL((k_project<float, 1>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
                          (float*)pm_out);
   } else {
-    const size_t lds = f64 ? bin_lds_bytes<3, double>(false) : bin_lds_bytes<3, float>(false);
+    const size_t lds = f64 ? bin_lds_bytes<3, double>(false, P.max_tile_pix, false)
+                           : bin_lds_bytes<3, float>(false, P.max_tile_pix, false);
     if (f64)
       hipLaunchKernelGGL((k_project<double, 3>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
                          (double*)pm_out);

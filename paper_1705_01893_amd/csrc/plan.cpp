@@ -471,6 +471,7 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   P.ncomp = D.ncomp;
   P.all_pow2 = all_pow2 ? 1 : 0;
   P.col_wave = col_wave ? 1 : 0;
+  P.max_tile_pix = (int32_t)(tw_ * th_);
   P.psi_kind = pl->psi_kind;
   P.precision = D.precision;
   P.npix = D.npix;
