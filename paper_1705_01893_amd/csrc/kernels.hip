@@ -287,14 +287,24 @@ __device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw,
   }
 }
 
-// Item order of the column pass.  Workgroups are dispatched to the 8 XCDs round-robin by index,
-// and adjacent column blocks of a chunk share the 128-byte lines of the 8-byte pixel pairs; within
-// each group of 16 workgroups, items 2k and 2k+1 go to workgroups k and k+8, which sit on the same
-// XCD.  A bijection of every 16-aligned group, so with a grid of a multiple of 16 every item is
-// still taken exactly once (other grids keep the plain order).
-__device__ __forceinline__ int xcd_pair_order(int b, int grid) {
-  if (grid % 16) return b;
-  return (b & ~15) + 2 * (b & 7) + ((b >> 3) & 1);
+// Item order of the column passes.  Workgroups are dispatched to the 8 XCDs round-robin by
+// index, and adjacent column blocks of a chunk share 128-byte lines: a block's run in each row
+// starts wherever the row does (rows of M1 complex values), and in FP64 adjacent blocks share
+// the lines of the 8-byte pixel pairs.  Within each group of kXcd * kXcdRun workgroups, XCD x
+// takes the kXcdRun consecutive items x kXcdRun, ..., so that most shared lines are fetched by
+// one L2.  A bijection of every full group; the launch rounds the grid up to whole groups
+// (other grids keep the plain order).
+constexpr int kXcd = 8, kXcdRun = 8;
+__host__ __device__ inline int col_grid(int64_t nitems) {
+  constexpr int g = kXcd * kXcdRun;
+  const int64_t n = (nitems + g - 1) / g * g;
+  return (int)(n < kGridCap ? (n > 0 ? n : g) : kGridCap);
+}
+__device__ __forceinline__ int xcd_run_order(int b, int grid) {
+  constexpr int g = kXcd * kXcdRun;
+  if (grid % g) return b;
+  const int r = b & (g - 1);
+  return (b - r) + (r % kXcd) * kXcdRun + r / kXcd;
 }
 
 template <typename T, bool P2>
@@ -306,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int np = (int)P.npix;
-  for (int it = xcd_pair_order(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
+  for (int it = xcd_run_order(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const ItemAC item = items[it];
     const DevChunk ch = P.chunks[item.chunk];
     const DevClass& cl = P.classes[ch.cls];
@@ -612,7 +622,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
   constexpr int E = Ept<T>::v;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  for (int it = xcd_run_order(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const ItemAC item = items[it];
     const DevChunk ch = P.chunks[item.chunk];
     const DevClass& cl = P.classes[ch.cls];
@@ -1500,7 +1510,7 @@ __global__ void k_cg_chi2(const double* chi2_0, const double* xb, const double* 
 template <typename T, bool P2>
 static void launch_pass_a_t(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m,
                             int src, void* work, size_t lds, hipStream_t s, const void* pmbuf) {
-  hipLaunchKernelGGL((k_pass_a<T, P2>), dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
+  hipLaunchKernelGGL((k_pass_a<T, P2>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, nitems,
                      (const T*)d, m, src, (cx<T>*)work, (const T*)pmbuf);
 }
 
@@ -1544,7 +1554,7 @@ hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void*
 
 template <typename T, bool P2, bool WL>
 static void launch_pass_c_t(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass_c<T, P2, WL>), dim3(grid_for(nitems, kGridCap)), dim3(kBlock), lds, s, P, items, nitems,
+  hipLaunchKernelGGL((k_pass_c<T, P2, WL>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, nitems,
                      (cx<T>*)work);
 }
 
