@@ -22,8 +22,9 @@ template <> struct Ept<float> { static constexpr int v = 16; };
 template <> struct Ept<double> { static constexpr int v = 8; };
 
 // Column tiles of the column passes.  Element i of column b sits at i * cb + b (interleaved,
-// every stage a workgroup-wide step), or, in the wave-local layout of the inverse column pass,
-// at b * Lc + pad8(i): every wave then transforms its own cb / (kBlock / 64) columns alone.
+// every stage a workgroup-wide step), or, in the wave-local layout the inverse column pass takes
+// for eligible classes, at b * Lc + pad8(i): every wave then transforms its own cb / (kBlock / 64)
+// columns alone.
 // pad8(i) = i + i / 8, and Lc >= pad8(M2 - 1) + 1 is an odd multiple of q = max(G / cb, 1) so
 // that the b-fastest global<->LDS copies (G = 256 / sizeof(complex) lanes per bank sweep: G / cb
 // rows of cb columns) fall in distinct banks.  Eligible: cb >= kBlock / 64 and a padded tile
@@ -118,8 +119,8 @@ struct Segment {
 struct DevPlan {
   int32_t ncomp, psi_kind, precision;
   int32_t all_pow2;          // every chunk length is a power of two (radix 8/4/2 transforms)
-  int32_t col_wave;          // the column passes use the wave-local layout (every class eligible)
   int32_t max_tile_pix;      // pixels of the largest binning tile (LDS accumulators)
+  int32_t col_wave;          // inverse column pass: wave-local classes 0 none, 1 all, 2 some
   int64_t npix, nxm;         // pixels, map row length used by the tiles
   int64_t nsamp;
   int32_t nchunk, ntiles;

@@ -616,8 +616,11 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
 // ---------------------------------------------------------------------------------------------
 // pass C: inverse column transforms -> filtered TOD in time order (in place)
 
-template <typename T, bool P2, bool WL>
-__global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __restrict__ items, int nitems,
+// WL: the LDS layout of the plan's classes: 0 interleaved (every class), 1 wave-local (every
+// class), 2 each class's own (eligible ones wave-local).  At most 128 VGPRs: two 512-thread
+// workgroups per CU.
+template <typename T, bool P2, int WL>
+__global__ __launch_bounds__(kBlock, 4) void k_pass_c(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    cx<T>* __restrict__ X) {
   constexpr int E = Ept<T>::v;
   extern __shared__ unsigned char smem_raw[];
@@ -630,7 +633,10 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
     const int j10 = item.j1;
     const int nbv = min(B, M1 - j10);
     const int ntot = B * M2;
-    const int Lc = WL ? wave_col_stride(M2, B, (int)sizeof(cx<T>)) : 0;
+    // per transform class: the wave-local layout where it is eligible (never with the inlined
+    // power-of-two stages)
+    const bool wl = !P2 && (WL == 1 || (WL == 2 && wave_cols(M2, B, (int)sizeof(cx<T>))));
+    const int Lc = wl ? wave_col_stride(M2, B, (int)sizeof(cx<T>)) : 0;
     cx<T>* Xc = X + ch.xoff + j10;
     {
       cx<T> v[E];
@@ -645,11 +651,11 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
 #pragma unroll
       for (int u = 0; u < E; ++u) {
         const int e = threadIdx.x + u * kBlock;
-        if (e < ntot) lds[WL ? (e & (B - 1)) * Lc + pad8(e >> lgB) : e] = v[u];
+        if (e < ntot) lds[wl ? (e & (B - 1)) * Lc + pad8(e >> lgB) : e] = v[u];
       }
     }
     __syncthreads();
-    if constexpr (WL) {
+    if (wl) {
       const int nw = B / kColWaves;
       wave_fft<T, true>(lds + (int)(threadIdx.x >> 6) * nw * Lc, M2, Lc, nw, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
       __syncthreads();
@@ -660,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_c(DevPlan P, const ItemAC* __re
     for (int u = 0; u < E; ++u) {
       const int e = threadIdx.x + u * kBlock;
       const int b = e & (B - 1), j2 = e >> lgB;
-      if (e < ntot && b < nbv) Xc[(int64_t)M1 * j2 + b] = lds[WL ? b * Lc + pad8(j2) : e];
+      if (e < ntot && b < nbv) Xc[(int64_t)M1 * j2 + b] = lds[wl ? b * Lc + pad8(j2) : e];
     }
     __syncthreads();
   }
@@ -1552,29 +1558,29 @@ hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void*
   return hipGetLastError();
 }
 
-template <typename T, bool P2, bool WL>
+template <typename T, bool P2>
 static void launch_pass_c_t(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass_c<T, P2, WL>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, nitems,
-                     (cx<T>*)work);
+  const dim3 g(col_grid(nitems)), b(kBlock);
+  if (P2 || P.col_wave == 0)
+    hipLaunchKernelGGL((k_pass_c<T, P2, 0>), g, b, lds, s, P, items, nitems, (cx<T>*)work);
+  else if (P.col_wave == 1)
+    hipLaunchKernelGGL((k_pass_c<T, false, 1>), g, b, lds, s, P, items, nitems, (cx<T>*)work);
+  else
+    hipLaunchKernelGGL((k_pass_c<T, false, 2>), g, b, lds, s, P, items, nitems, (cx<T>*)work);
 }
 
 hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  // FP64 power-of-two plans: inlined workgroup-wide stages (the plan then never selects the
-  // wave-local layout); otherwise the layout the plan selected, with out-of-line stages
+  // FP64 power-of-two plans: inlined workgroup-wide stages (the plan then selects no wave-local
+  // class); otherwise the layouts the plan selected, with out-of-line stages
   const bool p2 = P.all_pow2 != 0 && P.precision == 0;
-  const bool wl = !p2 && P.col_wave != 0;
   if (P.precision == 0) {
     if (p2)
-      launch_pass_c_t<double, true, false>(P, items, nitems, work, lds, s);
-    else if (wl)
-      launch_pass_c_t<double, false, true>(P, items, nitems, work, lds, s);
+      launch_pass_c_t<double, true>(P, items, nitems, work, lds, s);
     else
-      launch_pass_c_t<double, false, false>(P, items, nitems, work, lds, s);
-  } else if (wl) {
-    launch_pass_c_t<float, false, true>(P, items, nitems, work, lds, s);
+      launch_pass_c_t<double, false>(P, items, nitems, work, lds, s);
   } else {
-    launch_pass_c_t<float, false, false>(P, items, nitems, work, lds, s);
+    launch_pass_c_t<float, false>(P, items, nitems, work, lds, s);
   }
   return hipGetLastError();
 }

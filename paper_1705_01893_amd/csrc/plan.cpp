@@ -262,14 +262,16 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
       const int r = i < k.nr1 ? k.rad1[i] : k.rad2[i - k.nr1];
       if (r != 2 && r != 4 && r != 8) all_pow2 = false;
     }
-  // the inverse column pass takes the wave-local layout when every class is eligible, except
-  // in FP64 power-of-two plans (their inlined workgroup-wide stages measured faster)
-  bool col_wave = !(f64 && all_pow2);
-  for (size_t i = 0; i < classes.size(); ++i) col_wave = col_wave && wave_cols(classes[i].M2, class_cb[i], (int)csz);
+  // the inverse column pass takes the wave-local layout for every eligible class, except in
+  // FP64 power-of-two plans (their inlined workgroup-wide stages measured faster)
+  const bool wave_ok = !(f64 && all_pow2);
   size_t lds_c = 0;
+  int nwave = 0;
   for (size_t i = 0; i < classes.size(); ++i) {
+    const bool wl = wave_ok && wave_cols(classes[i].M2, class_cb[i], (int)csz);
+    nwave += wl ? 1 : 0;
     lds_ac = std::max(lds_ac, (size_t)col_tile_elems(classes[i].M2, class_cb[i], (int)csz, false) * csz);
-    lds_c = std::max(lds_c, (size_t)col_tile_elems(classes[i].M2, class_cb[i], (int)csz, col_wave) * csz);
+    lds_c = std::max(lds_c, (size_t)col_tile_elems(classes[i].M2, class_cb[i], (int)csz, wl) * csz);
   }
   pl->nwork = 2 * xwork;
   pl->lds_ac = lds_ac;
@@ -470,8 +472,8 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   std::memset(&P, 0, sizeof(P));
   P.ncomp = D.ncomp;
   P.all_pow2 = all_pow2 ? 1 : 0;
-  P.col_wave = col_wave ? 1 : 0;
   P.max_tile_pix = (int32_t)(tw_ * th_);
+  P.col_wave = nwave == 0 ? 0 : (nwave == (int)classes.size() ? 1 : 2);
   P.psi_kind = pl->psi_kind;
   P.precision = D.precision;
   P.npix = D.npix;

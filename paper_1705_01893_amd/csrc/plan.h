@@ -96,6 +96,7 @@ struct Layout {
 constexpr int64_t kTuneMinM = int64_t(1) << 14;     // shorter chunks take the static rule
 constexpr int64_t kTuneElements = int64_t(1) << 23;  // complex values per timed launch
 constexpr size_t kTuneMaxCandidates = 6;
+constexpr int kTuneReps = 5;  // timed runs per candidate (best kept)
 
 int tile_cap_ac(bool f64);  // complex values per column item (pass A, C tile)
 int tile_cap_b(bool f64);   // complex values per row item (pass B tile)

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -182,88 +183,84 @@ bool put(DevBuf& b, const std::vector<X>& v, hipStream_t s) {
   return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, s) == hipSuccess;
 }
 
-// passes A-C (filter on) over K copies of a length-2M chunk under layout L; best of reps, in ms
-double time_layout(int64_t M, bool f64, const Layout& L, int64_t K, void* din, void* dwork, hipStream_t s) {
-  std::vector<double2> tw;
-  std::vector<DevClass> cls(1);
-  make_class(M, L, tw, cls[0]);
-  std::vector<float2> tw32(tw.size());
-  for (size_t i = 0; i < tw.size(); ++i) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
-  std::vector<DevChunk> chunks(K);
-  std::vector<ItemAC> itemsAC;
-  std::vector<ItemB> itemsB;
-  for (int64_t c = 0; c < K; ++c) {
-    DevChunk& ch = chunks[c];
-    std::memset(&ch, 0, sizeof(ch));
-    ch.off = c * 2 * M;
-    ch.n = (int32_t)(2 * M);
-    ch.M = (int32_t)M;
-    ch.M1 = (int32_t)L.M1;
-    ch.M2 = (int32_t)L.M2;
-    ch.cb = L.cb;
-    while ((1 << (ch.lgb + 1)) <= ch.cb) ++ch.lgb;
-    ch.df = 1.0 / (double)ch.n;
-    ch.sigma2 = 1.0;
-    ch.fknee = 0.1;
-    ch.alpha = -2.0;
-    ch.tau = 1.0;
-    ch.inv_tau = 1.0;
-    ch.nbar0 = 0.0;
-    ch.spec_off = c * (M + 1);
-    ch.inv_M = 1.0 / (double)M;
-    ch.lg0 = std::log2(ch.df / ch.fknee);
-    ch.xoff = c * ((M + kWorkAlign - 1) / kWorkAlign * kWorkAlign);
-    append_col_items((int32_t)c, ch, itemsAC);
-    append_row_items((int32_t)c, ch, itemsB, row_fuse(L.M1, f64));
-  }
+// Passes A-C (filter on) over K copies of a length-2M chunk under one layout: the device
+// tables and work lists, kept for repeated timing.
+struct LayoutRun {
   DevBuf bch, bcl, btw, btw32, bac, bb, bspec;
-  if (!put(bch, chunks, s) || !put(bcl, cls, s) || !put(btw, tw, s) || !put(btw32, tw32, s) || !put(bac, itemsAC, s) ||
-      !put(bb, itemsB, s))
-    return -1.0;
   DevPlan P;
-  std::memset(&P, 0, sizeof(P));
-  P.precision = f64 ? MM_FP64 : MM_MIXED;
-  P.all_pow2 = 1;
-  for (int8_t r : L.r1) P.all_pow2 &= (r == 2 || r == 4 || r == 8);
-  for (int8_t r : L.r2) P.all_pow2 &= (r == 2 || r == 4 || r == 8);
-  P.nsamp = K * 2 * M;
-  P.nchunk = (int32_t)K;
-  P.chunks = (const DevChunk*)bch.p;
-  P.classes = (const DevClass*)bcl.p;
-  P.tw64 = (const double2*)btw.p;
-  P.tw32 = (const float2*)btw32.p;
-  if (f64) {
-    if (!bspec.alloc((size_t)K * (M + 1) * sizeof(double))) return -1.0;
-    P.spec = (const double*)bspec.p;
-    if (launch_spectrum(P, (double*)bspec.p, s) != hipSuccess) return -1.0;
+  int nac = 0, nb = 0;
+  size_t lds_ac = 0, lds_c = 0, lds_b = 0;
+
+  bool prepare(int64_t M, bool f64, const Layout& L, int64_t K, hipStream_t s) {
+    std::vector<double2> tw;
+    std::vector<DevClass> cls(1);
+    make_class(M, L, tw, cls[0]);
+    std::vector<float2> tw32(tw.size());
+    for (size_t i = 0; i < tw.size(); ++i) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
+    std::vector<DevChunk> chunks(K);
+    std::vector<ItemAC> itemsAC;
+    std::vector<ItemB> itemsB;
+    for (int64_t c = 0; c < K; ++c) {
+      DevChunk& ch = chunks[c];
+      std::memset(&ch, 0, sizeof(ch));
+      ch.off = c * 2 * M;
+      ch.n = (int32_t)(2 * M);
+      ch.M = (int32_t)M;
+      ch.M1 = (int32_t)L.M1;
+      ch.M2 = (int32_t)L.M2;
+      ch.cb = L.cb;
+      while ((1 << (ch.lgb + 1)) <= ch.cb) ++ch.lgb;
+      ch.df = 1.0 / (double)ch.n;
+      ch.sigma2 = 1.0;
+      ch.fknee = 0.1;
+      ch.alpha = -2.0;
+      ch.tau = 1.0;
+      ch.inv_tau = 1.0;
+      ch.nbar0 = 0.0;
+      ch.spec_off = c * (M + 1);
+      ch.inv_M = 1.0 / (double)M;
+      ch.lg0 = std::log2(ch.df / ch.fknee);
+      ch.xoff = c * ((M + kWorkAlign - 1) / kWorkAlign * kWorkAlign);
+      append_col_items((int32_t)c, ch, itemsAC);
+      append_row_items((int32_t)c, ch, itemsB, row_fuse(L.M1, f64));
+    }
+    if (!put(bch, chunks, s) || !put(bcl, cls, s) || !put(btw, tw, s) || !put(btw32, tw32, s) ||
+        !put(bac, itemsAC, s) || !put(bb, itemsB, s))
+      return false;
+    nac = (int)itemsAC.size();
+    nb = (int)itemsB.size();
+    std::memset(&P, 0, sizeof(P));
+    P.precision = f64 ? MM_FP64 : MM_MIXED;
+    P.all_pow2 = 1;
+    for (int8_t r : L.r1) P.all_pow2 &= (r == 2 || r == 4 || r == 8);
+    for (int8_t r : L.r2) P.all_pow2 &= (r == 2 || r == 4 || r == 8);
+    P.nsamp = K * 2 * M;
+    P.nchunk = (int32_t)K;
+    P.chunks = (const DevChunk*)bch.p;
+    P.classes = (const DevClass*)bcl.p;
+    P.tw64 = (const double2*)btw.p;
+    P.tw32 = (const float2*)btw32.p;
+    if (f64) {
+      if (!bspec.alloc((size_t)K * (M + 1) * sizeof(double))) return false;
+      P.spec = (const double*)bspec.p;
+      if (launch_spectrum(P, (double*)bspec.p, s) != hipSuccess) return false;
+    }
+    const size_t csz = f64 ? sizeof(double2) : sizeof(float2);
+    const bool wl = !(f64 && P.all_pow2) && wave_cols(L.M2, L.cb, (int)csz);
+    P.col_wave = wl ? 1 : 0;
+    lds_ac = (size_t)col_tile_elems(L.M2, L.cb, (int)csz, false) * csz;
+    lds_c = (size_t)col_tile_elems(L.M2, L.cb, (int)csz, wl) * csz;
+    lds_b = (size_t)(row_fuse(L.M1, f64) ? 4 : 2) * L.M1 * csz;
+    return true;
   }
-  const size_t csz = f64 ? sizeof(double2) : sizeof(float2);
-  P.col_wave = !(f64 && P.all_pow2) && wave_cols(L.M2, L.cb, (int)csz) ? 1 : 0;
-  const size_t lds_ac = (size_t)col_tile_elems(L.M2, L.cb, (int)csz, false) * csz,
-               lds_c = (size_t)col_tile_elems(L.M2, L.cb, (int)csz, P.col_wave != 0) * csz,
-               lds_b = (size_t)(row_fuse(L.M1, f64) ? 4 : 2) * L.M1 * csz;
-  auto run = [&]() -> bool {
-    return launch_pass_a(P, (const ItemAC*)bac.p, (int)itemsAC.size(), din, nullptr, SRC_D, dwork, lds_ac, s) ==
+
+  bool run(void* din, void* dwork, hipStream_t s) const {
+    return launch_pass_a(P, (const ItemAC*)bac.p, nac, din, nullptr, SRC_D, dwork, lds_ac, s) == hipSuccess &&
+           launch_pass_b(P, (const ItemB*)bb.p, nb, dwork, B_FILTER, GAIN_MESSENGER, 1.0, 1.0, nullptr, lds_b, s) ==
                hipSuccess &&
-           launch_pass_b(P, (const ItemB*)bb.p, (int)itemsB.size(), dwork, B_FILTER, GAIN_MESSENGER, 1.0, 1.0,
-                         nullptr, lds_b, s) == hipSuccess &&
-           launch_pass_c(P, (const ItemAC*)bac.p, (int)itemsAC.size(), dwork, lds_c, s) == hipSuccess;
-  };
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
-  double best = -1.0;
-  bool ok = run();  // warm-up
-  for (int rep = 0; ok && rep < 3; ++rep) {
-    ok = hipEventRecord(e0, s) == hipSuccess && run() && hipEventRecord(e1, s) == hipSuccess &&
-         hipEventSynchronize(e1) == hipSuccess;
-    float ms = 0.f;
-    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && (best < 0 || ms < best)) best = ms;
+           launch_pass_c(P, (const ItemAC*)bac.p, nac, dwork, lds_c, s) == hipSuccess;
   }
-  (void)hipStreamSynchronize(s);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return ok ? best : -1.0;
-}
+};
 
 }  // namespace
 
@@ -287,16 +284,37 @@ int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream
       (void)hipGetLastError();
       return 0;
     }
-    double tbest = -1.0;
-    for (int i = 0; i < ncand; ++i) {
-      const double t = time_layout(M, f64, cands[i], K, din.p, dwork.p, s);
-      if (t > 0 && (tbest < 0 || t < tbest * 0.98)) {  // a clear win over the better-ranked layout
-        tbest = t;
-        best = i;
-      }
+    // every candidate prepared and warmed up, then timed round-robin (best of kTuneReps each), so
+    // that clock and cache drift during the plan affects all of them alike
+    std::vector<std::unique_ptr<LayoutRun>> runs;
+    std::vector<double> t(ncand, -1.0);
+    bool ok = true;
+    for (int i = 0; ok && i < ncand; ++i) {
+      runs.emplace_back(new LayoutRun);
+      ok = runs[i]->prepare(M, f64, cands[i], K, s) && runs[i]->run(din.p, dwork.p, s);
     }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    for (int rep = 0; ok && rep < kTuneReps; ++rep)
+      for (int i = 0; ok && i < ncand; ++i) {
+        float ms = 0.f;
+        ok = hipEventRecord(e0, s) == hipSuccess && runs[i]->run(din.p, dwork.p, s) &&
+             hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (ok && (t[i] < 0 || ms < t[i])) t[i] = ms;
+      }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(s);
     (void)hipGetLastError();
+    if (ok) {
+      double tbest = t[0];
+      for (int i = 1; i < ncand; ++i)
+        if (t[i] < tbest * 0.98) {  // a clear win over the better-ranked layouts
+          tbest = t[i];
+          best = i;
+        }
+    }
   }
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tune_cache[key] = best;

@@ -109,6 +109,25 @@ def test_every_layout_mixed(dev):
     assert kinds == {True, False}
 
 
+def test_inverse_pass_layout_per_class(dev):
+    """Two chunk lengths whose static layouts differ in the inverse column pass's LDS layout
+    (2^22 complex values: 4 columns per item, interleaved; 2^16: 16 columns, wave-local), so the
+    pass picks the layout per transform class; FP32-mixed against the FP64 oracle."""
+    t = tiny_problem(80, ncomp=3, lengths=(2 ** 23, 2 ** 17), nx=16, psi_dtype=np.float32, tod_dtype=np.float32,
+                     walk=False)
+    S = make_setup(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, t.npix, 3)
+    plan = plan_for(t, dev, mm.MM_TUNE_STATIC, mm.MM_MIXED)
+    lay = [mm.mm_plan_chunk_layout(plan, c) for c in range(plan.nchunk)]
+    say(f"[layout per class] {lay}")
+    assert lay[0]["cb"] < 8 <= lay[1]["cb"]
+    m0 = random_map(10, 3, t.npix)
+    m0[:, ~S.solvable] = 0
+    mo = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+    mm.mm_messenger_iter(plan, torch.from_numpy(t.d).to(dev), 2.0, torch.from_numpy(m0).to(dev), mo)
+    torch.cuda.synchronize()
+    assert rel(mo.cpu().numpy(), messenger_step(S, t.d.astype(np.float64), m0, 2.0)) < MIX_TOL
+
+
 def test_tuner_picks_a_valid_layout(dev):
     """Chunks long enough to be tuned: the measured choice is one of the candidates and the
     iteration it runs matches the oracle."""
