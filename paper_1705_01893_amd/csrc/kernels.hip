@@ -194,9 +194,7 @@ __device__ __forceinline__ float recip<float>(float x) {
 
 // gain applied to R_k (includes the 1/M of the inverse transform) and chi^2 weight 1/(n N'_k)
 template <typename T>
-__device__ __forceinline__ void bin_factors(const DevPlan& P, const DevChunk& ch, const BinCtx& bc, int k, int tidx,
-                                            T& g, double& cw) {
-  const T pl = powerlaw_bin<T>(P, ch, k, tidx);
+__device__ __forceinline__ void bin_factors_pl(const DevChunk& ch, const BinCtx& bc, T pl, T& g, double& cw) {
   const T N = (T)ch.sigma2 + pl;
   const T tau = (T)ch.tau;
   T gg;
@@ -212,6 +210,12 @@ __device__ __forceinline__ void bin_factors(const DevPlan& P, const DevChunk& ch
   // chi^2 weight 1 / (n N'_k), N' = N + (lambda - 1) tau, in the TOD precision, only when asked for
   cw = 0.0;
   if (bc.chi2) cw = (double)recip<T>((T)ch.n * (N + (T)((bc.chi2_lam - 1.0) * ch.tau)));
+}
+
+template <typename T>
+__device__ __forceinline__ void bin_factors(const DevPlan& P, const DevChunk& ch, const BinCtx& bc, int k, int tidx,
+                                            T& g, double& cw) {
+  bin_factors_pl<T>(ch, bc, powerlaw_bin<T>(P, ch, k, tidx), g, cw);
 }
 
 template <typename C>
@@ -421,9 +425,9 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
 
 template <typename T>
 __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevChunk& ch, const DevClass& cl,
-                                       const BinCtx& bc, int ops, int k, int ia, int ib, int ta, int tb,
+                                       const BinCtx& bc, int ops, int k, int ia, int ib, T plk, T plm,
                                        double& chi) {
-  // bins k (LDS ia, table position ta) and M - k (LDS ib, table position tb)
+  // bins k (LDS ia, power law plk) and M - k (LDS ib, power law plm)
   const cx<T> Zk = lds[ia], Zm = lds[ib];
   const int M = ch.M;
   cx<T> E, O;
@@ -438,8 +442,8 @@ __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevCh
   const cx<T> Rm = csub(conjc(E), conjc(wO));
   T gk, gm;
   double cwk, cwm;
-  bin_factors<T>(P, ch, bc, k, ta, gk, cwk);
-  bin_factors<T>(P, ch, bc, M - k, tb, gm, cwm);
+  bin_factors_pl<T>(ch, bc, plk, gk, cwk);
+  bin_factors_pl<T>(ch, bc, plm, gm, cwm);
   if (ops & B_CHI2) chi += 2.0 * (norm2(Rk) * cwk + norm2(Rm) * cwm);
   if (ops & B_FILTER) {
     const cx<T> Yk = cscale(Rk, gk), Ym = cscale(Rm, gm);
@@ -555,22 +559,44 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
     double chi = 0.0;
     const bool self_a = (ra == 0) || (2 * ra == M2);
-    if (rc > 0) {
-      // two pairs of rows (r, M2 - r): bins k = r + M2 k1 and M - k = (M2 - r) + M2 (M1 - 1 - k1)
-      for (int t = threadIdx.x; t < 2 * M1; t += kBlockB) {
-        const int q = t >= M1 ? 1 : 0;
-        const int k1 = t - q * M1;
-        const int pk1 = M1 - 1 - k1;
-        const int r = q ? rc : ra, rr = M2 - r;
-        const int k = r + M2 * k1;
-        b_pair<T>(lds, P, ch, cl, bc, ops, k, 2 * q * M1 + k1, (2 * q + 1) * M1 + pk1, r * M1 + k1, rr * M1 + pk1,
-                  chi);
-      }
-    } else if (!self_a) {
-      for (int k1 = threadIdx.x; k1 < M1; k1 += kBlockB) {
-        const int pk1 = M1 - 1 - k1;
-        const int k = ra + M2 * k1;
-        b_pair<T>(lds, P, ch, cl, bc, ops, k, k1, M1 + pk1, ra * M1 + k1, rb * M1 + pk1, chi);
+    if (!self_a) {
+      // one or two pairs of rows (r, M2 - r): bins k = r + M2 k1 and M - k = (M2 - r) + M2 (M1 - 1 - k1),
+      // at most E/2 steps per thread.  The FP64 form reads the power law from its table: all of
+      // a thread's values are fetched first, so that their latencies overlap.
+      const int nt = (rc > 0 ? 2 : 1) * M1;
+      if constexpr (sizeof(T) == 8) {
+        constexpr int U = Ept<T>::v / 2;
+        T plk[U], plm[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = threadIdx.x + u * kBlockB;
+          const int q = t >= M1 ? 1 : 0;
+          const int k1 = t - q * M1, pk1 = M1 - 1 - k1;
+          const int r = q ? rc : ra, rr = M2 - r;
+          if (t < nt) {
+            plk[u] = powerlaw_bin<T>(P, ch, r + M2 * k1, r * M1 + k1);
+            plm[u] = powerlaw_bin<T>(P, ch, ch.M - (r + M2 * k1), rr * M1 + pk1);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = threadIdx.x + u * kBlockB;
+          const int q = t >= M1 ? 1 : 0;
+          const int k1 = t - q * M1, pk1 = M1 - 1 - k1;
+          if (t < nt)
+            b_pair<T>(lds, P, ch, cl, bc, ops, (q ? rc : ra) + M2 * k1, 2 * q * M1 + k1, (2 * q + 1) * M1 + pk1,
+                      plk[u], plm[u], chi);
+        }
+      } else {
+        // the FP32-mixed form evaluates the power law in place
+        for (int t = threadIdx.x; t < nt; t += kBlockB) {
+          const int q = t >= M1 ? 1 : 0;
+          const int k1 = t - q * M1, pk1 = M1 - 1 - k1;
+          const int r = q ? rc : ra, rr = M2 - r;
+          const int k = r + M2 * k1;
+          b_pair<T>(lds, P, ch, cl, bc, ops, k, 2 * q * M1 + k1, (2 * q + 1) * M1 + pk1,
+                    powerlaw_bin<T>(P, ch, k, r * M1 + k1), powerlaw_bin<T>(P, ch, ch.M - k, rr * M1 + pk1), chi);
+        }
       }
     } else {
       for (int sl = 0; sl < nrow; ++sl) {
@@ -585,7 +611,8 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
           else if (k1 == pk1)
             b_self<T>(lds, P, ch, bc, ops, k, sl * M1 + k1, row * M1 + k1, chi);
           else
-            b_pair<T>(lds, P, ch, cl, bc, ops, k, sl * M1 + k1, sl * M1 + pk1, row * M1 + k1, row * M1 + pk1, chi);
+            b_pair<T>(lds, P, ch, cl, bc, ops, k, sl * M1 + k1, sl * M1 + pk1,
+                      powerlaw_bin<T>(P, ch, k, row * M1 + k1), powerlaw_bin<T>(P, ch, ch.M - k, row * M1 + pk1), chi);
         }
       }
     }
