@@ -299,6 +299,7 @@ __device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw,
 // one L2.  A bijection of every full group; the launch rounds the grid up to whole groups
 // (other grids keep the plain order).
 constexpr int kXcd = 8, kXcdRun = 8;
+constexpr int kGroupNoGather = 16;  // loads issued together per thread in the forward column pass, no gather
 __host__ __device__ inline int col_grid(int64_t nitems) {
   constexpr int g = kXcd * kXcdRun;
   const int64_t n = (nitems + g - 1) / g * g;
@@ -311,12 +312,15 @@ __device__ __forceinline__ int xcd_run_order(int b, int grid) {
   return (b - r) + (r % kXcd) * kXcdRun + r / kXcd;
 }
 
-template <typename T, bool P2>
+// NG: the source needs no map gather (d, P m from its buffer, or their difference)
+template <typename T, bool P2, bool NG>
 __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    const T* __restrict__ d, const double* __restrict__ m, int src,
                                                    cx<T>* __restrict__ X, const T* __restrict__ pmbuf) {
   constexpr int E = Ept<T>::v;
-  constexpr int G = 4;  // elements whose loads are issued together
+  // elements whose loads are issued together: all of them without a gather, else 4 (the
+  // gather's pixel, angle and map values take registers)
+  constexpr int G = NG ? (kGroupNoGather < E ? kGroupNoGather : E) : 4;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int np = (int)P.npix;
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
           if (src != SRC_PM && src != SRC_PMBUF) dd[u] = ((const cx<T>*)d)[ci];
           if (src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF) {
             pb[u] = ((const cx<T>*)pmbuf)[ci];
-          } else if (src != SRC_D) {
+          } else if (!NG && src != SRC_D) {
             pp[u] = ((const int2*)P.pix)[ci];
             if (P.ncomp == 3) psi_pair_load<T>(P, ci, raw[u]);
           }
@@ -387,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
             z.y = T(0);
           } else if (src == SRC_D) {
             z = dd[u];
-          } else if (src == SRC_PM) {
+          } else if (!NG && src == SRC_PM) {
             z.x = (T)pm[u][0];
             z.y = (T)pm[u][1];
           } else if (src == SRC_PMBUF) {
@@ -395,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
           } else if (src == SRC_D_MINUS_PMBUF) {
             z.x = (T)((double)dd[u].x - (double)pb[u].x);
             z.y = (T)((double)dd[u].y - (double)pb[u].y);
-          } else {
+          } else if (!NG) {
             z.x = (T)((double)dd[u].x - pm[u][0]);
             z.y = (T)((double)dd[u].y - pm[u][1]);
           }
@@ -1543,8 +1547,13 @@ __global__ void k_cg_chi2(const double* chi2_0, const double* xb, const double* 
 template <typename T, bool P2>
 static void launch_pass_a_t(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m,
                             int src, void* work, size_t lds, hipStream_t s, const void* pmbuf) {
-  hipLaunchKernelGGL((k_pass_a<T, P2>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, nitems,
-                     (const T*)d, m, src, (cx<T>*)work, (const T*)pmbuf);
+  const bool ng = src == SRC_D || src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF;
+  if (ng)
+    hipLaunchKernelGGL((k_pass_a<T, P2, true>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, nitems,
+                       (const T*)d, m, src, (cx<T>*)work, (const T*)pmbuf);
+  else
+    hipLaunchKernelGGL((k_pass_a<T, P2, false>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, nitems,
+                       (const T*)d, m, src, (cx<T>*)work, (const T*)pmbuf);
 }
 
 hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m, int src,
