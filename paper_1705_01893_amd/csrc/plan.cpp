@@ -322,9 +322,43 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
   const int64_t nxm = D.nx > 0 ? D.nx : D.npix;
   const int64_t nym = D.npix / nxm;
   int64_t target = std::max<int64_t>(16, std::min<int64_t>(kMaxTilePix, D.npix / 2048));
-  int64_t tw_ = 1;
-  while (tw_ * tw_ * 2 <= target) tw_ *= 2;  // tw_ ~ sqrt(target), power of two
-  int64_t th_ = std::max<int64_t>(1, target / tw_);
+  // Tile shape: about `target` pixels, tw a power of two, shaped by the scan.  A sample moving
+  // (mx, my) pixels per step stays about 1 / (mx / tw + my / th) steps in a tile, so the shape
+  // that maximises it gives the longest time-contiguous segments (fewer, longer HBM runs for
+  // the staging reads and the P m writes).  mx, my: mean steps between consecutive on-map
+  // samples of a chunk (every 4th pair; jumps of more than 16 pixels, such as scan-line
+  // turnarounds, left out).
+  double mx = 0.0, my = 0.0;
+  {
+    double sx = 0.0, sy = 0.0;
+    int64_t nst = 0;
+    for (int64_t c = 0; c < D.nchunk; ++c)
+      for (int64_t j = D.chunk_off[c] + 1; j < D.chunk_off[c + 1]; j += 4) {
+        const int32_t a = pix[j - 1], b = pix[j];
+        if (a < 0 || b < 0) continue;
+        const int64_t dx = std::llabs((int64_t)(b % nxm) - (a % nxm)), dy = std::llabs((int64_t)(b / nxm) - (a / nxm));
+        if (dx > 16 || dy > 16) continue;
+        sx += (double)dx;
+        sy += (double)dy;
+        ++nst;
+      }
+    mx = nst ? sx / (double)nst : 1.0;
+    my = nst ? sy / (double)nst : 1.0;
+    if (mx + my <= 0.0) mx = my = 1.0;
+  }
+  int64_t tw_ = 1, th_ = target;
+  {
+    double best = -1.0;
+    for (int64_t w = 1; w <= std::min<int64_t>(target, nxm); w *= 2) {
+      const int64_t h = std::min<int64_t>(nym, std::max<int64_t>(1, target / w));
+      const double visit = 1.0 / (mx / (double)w + my / (double)h);
+      if (visit > best * 1.000001) {
+        best = visit;
+        tw_ = w;
+        th_ = h;
+      }
+    }
+  }
   if (nym == 1) {
     tw_ = target;
     th_ = 1;
