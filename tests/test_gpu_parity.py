@@ -132,6 +132,75 @@ def test_chi2_per_chunk_fp64(dev, shape, lam):
     assert v == pytest.approx(ref.sum(), rel=F64_TOL)
 
 
+@pytest.mark.parametrize("precision", [mm.MM_FP64, mm.MM_MIXED])
+def test_chunk_entirely_off_the_map(dev, precision):
+    """A chunk whose every sample is flagged (pixel -1): its transforms still run and its chi^2
+    still counts, while it bins nothing; the iteration and the per-chunk chi^2 match the oracle."""
+    say(f"[offmap] precision={precision}")
+    dt = np.float64 if precision == mm.MM_FP64 else np.float32
+    t = tiny_problem(404, ncomp=3, psi_dtype=dt, tod_dtype=dt, **SHAPES["mixed_radix"])
+    a, b = int(t.chunk_off[1]), int(t.chunk_off[2])
+    t.pix[a:b] = -1
+    plan = gpu_plan(t, dev, precision)
+    S = oracle_setup(t)
+    m0 = random_map(11, 3, t.npix)
+    m0[:, ~S.solvable] = 0.0
+    mi = torch.from_numpy(m0).to(dev)
+    mo = torch.zeros_like(mi)
+    d = tod(t, dev, precision)
+    dref = t.d.astype(np.float64)
+    tol, ctol = (F64_TOL, F64_TOL) if precision == mm.MM_FP64 else (MIX_TOL, MIX_CHI2)
+    c2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    mm.mm_messenger_iter(plan, d, 2.0, mi, mo, c2)
+    torch.cuda.synchronize()
+    assert rel(mo.cpu().numpy(), messenger_step(S, dref, m0, 2.0)) < tol
+    assert c2.item() == pytest.approx(chi2(S, dref, m0), rel=ctol)
+    per = torch.zeros(plan.nchunk, dtype=torch.float64, device=dev)
+    mm.mm_chi2(plan, d, mi, 1.0, per)
+    from oracle.messenger import chi2_of_residual
+    ref = chi2_of_residual(S, dref - S.pointing.project(m0), 1.0, per_chunk=True)
+    np.testing.assert_allclose(per.cpu().numpy(), ref, rtol=ctol)
+
+
+@pytest.mark.parametrize("precision", [mm.MM_FP64, mm.MM_MIXED])
+def test_solve_graph_replays_match_eager(dev, precision):
+    """mm_solve captures its schedule in a HIP graph on the first call and replays it after. The
+    same schedule run eagerly (per-pass timing on runs it uncaptured) is the reference: the
+    capture and three replays, with other GPU work and synchronisations between them, must
+    each reproduce it bit for bit (and it matches the oracle)."""
+    say(f"[replay] precision={precision}")
+    dt = np.float64 if precision == mm.MM_FP64 else np.float32
+    t = tiny_problem(606, ncomp=3, psi_dtype=dt, tod_dtype=dt, **SHAPES["mixed_radix"])
+    plan = gpu_plan(t, dev, precision)
+    d = tod(t, dev, precision)
+    levels, per = [30.0, 30.0 ** 0.5, 1.0], [3, 3, 4]
+    mm.mm_set_timing(plan, True)
+    m_eager = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+    h_eager = torch.zeros(1 + sum(per) + 1, dtype=torch.float64, device=dev)  # lambda = inf step, then per
+    mm.mm_solve(plan, d, levels, per, m_eager, chi2_hist=h_eager)
+    torch.cuda.synchronize()
+    mm.mm_set_timing(plan, False)
+    S = oracle_setup(t)
+    m_ref, h_ref = messenger_solve(S, t.d.astype(np.float64), cooling_schedule(3, 3, 30.0) + [1.0])
+    tol, ctol = (F64_TOL, F64_TOL) if precision == mm.MM_FP64 else (MIX_TOL, MIX_CHI2)
+    assert rel(m_eager.cpu().numpy(), m_ref) < tol
+    np.testing.assert_allclose(h_eager.cpu().numpy(), h_ref, rtol=ctol)
+    for rep in range(4):
+        # unrelated eager work on the same stream and a host synchronisation between replays
+        scratch = torch.randn(1 << 16, device=dev)
+        scratch.mul_(2.0).add_(1.0)
+        mo = torch.zeros_like(m_eager)
+        mi = torch.from_numpy(random_map(rep, 3, t.npix)).to(dev)
+        mm.mm_messenger_iter(plan, d, 5.0, mi, mo)
+        torch.cuda.synchronize()
+        m = torch.full_like(m_eager, float("nan"))
+        h = torch.full_like(h_eager, float("nan"))
+        mm.mm_solve(plan, d, levels, per, m, chi2_hist=h)
+        torch.cuda.synchronize()
+        assert torch.equal(m, m_eager), rep
+        assert torch.equal(h, h_eager), rep
+
+
 def test_in_place_iteration_matches(dev):
     say("[inplace]")
     t = tiny_problem(404, ncomp=3, **SHAPES["pow2"])
