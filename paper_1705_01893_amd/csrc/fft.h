@@ -149,6 +149,89 @@ struct Dft<T, 5, INV> {
   }
 };
 
+// cos and sin of 2 pi e / R for the composite radices (e folded into [0, R/2] by symmetry)
+template <int R>
+__device__ __forceinline__ void root_cs(int e, double& c, double& s) {
+  e %= R;
+  const bool neg = 2 * e > R;
+  if (neg) e = R - e;
+  c = 1.0;
+  s = 0.0;
+  if (R == 9) {
+    switch (e) {
+      case 1: c = 0.766044443118978; s = 0.6427876096865393; break;
+      case 2: c = 0.17364817766693041; s = 0.984807753012208; break;
+      case 3: c = -0.4999999999999998; s = 0.8660254037844387; break;
+      case 4: c = -0.9396926207859083; s = 0.3420201433256689; break;
+      default: break;
+    }
+  } else if (R == 25) {
+    switch (e) {
+      case 1: c = 0.9685831611286311; s = 0.2486898871648548; break;
+      case 2: c = 0.8763066800438636; s = 0.4817536741017153; break;
+      case 3: c = 0.7289686274214116; s = 0.6845471059286886; break;
+      case 4: c = 0.5358267949789965; s = 0.8443279255020151; break;
+      case 5: c = 0.30901699437494745; s = 0.9510565162951535; break;
+      case 6: c = 0.06279051952931353; s = 0.9980267284282716; break;
+      case 7: c = -0.1873813145857246; s = 0.9822872507286887; break;
+      case 8: c = -0.4257792915650727; s = 0.9048270524660195; break;
+      case 9: c = -0.6374239897486897; s = 0.7705132427757893; break;
+      case 10: c = -0.8090169943749473; s = 0.5877852522924732; break;
+      case 11: c = -0.9297764858882513; s = 0.36812455268467814; break;
+      case 12: c = -0.9921147013144778; s = 0.12533323356430454; break;
+      default: break;
+    }
+  }
+  if (neg) s = -s;
+}
+
+// R = R1 R2 point DFT from R1- and R2-point ones: with n = R2 n1 + n2 and k = k1 + R1 k2,
+// X_k = sum_n2 W_R^(n2 k1) W_R2^(n2 k2) sum_n1 a_n W_R1^(n1 k1) (W_R = exp(-+ 2 pi i / R)):
+// R2 inner transforms over n1, the R1 R2 twiddles, R1 outer transforms over n2.
+template <typename T, int R1, int R2, bool INV>
+struct Dft2 {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    constexpr int R = R1 * R2;
+    cx<T> b[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) b[n2][n1] = a[R2 * n1 + n2];
+      Dft<T, R1, INV>::run(b[n2]);
+    }
+#pragma unroll
+    for (int n2 = 1; n2 < R2; ++n2)
+#pragma unroll
+      for (int k1 = 1; k1 < R1; ++k1) {
+        double c, s;
+        root_cs<R>(n2 * k1, c, s);
+        cx<T> w;
+        w.x = T(c);
+        w.y = INV ? T(s) : T(-s);
+        b[n2][k1] = cmul(b[n2][k1], w);
+      }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      cx<T> t[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) t[n2] = b[n2][k1];
+      Dft<T, R2, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) a[k1 + R1 * k2] = t[k2];
+    }
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 9, INV> {
+  __device__ __forceinline__ static void run(cx<T>* a) { Dft2<T, 3, 3, INV>::run(a); }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 25, INV> {
+  __device__ __forceinline__ static void run(cx<T>* a) { Dft2<T, 5, 5, INV>::run(a); }
+};
+
 // Exact quotient n / d for n, d < 2^22 from a single-precision reciprocal estimate
 // (the estimate is within one of the quotient, corrected with one multiply-subtract).
 __device__ __forceinline__ uint32_t qdiv(uint32_t n, uint32_t d, float inv) {
@@ -161,9 +244,26 @@ __device__ __forceinline__ uint32_t qdiv(uint32_t n, uint32_t d, float inv) {
   return q;
 }
 
-// w^m for m = 0..R-1 from w = v[1] by balanced products (error grows like log2 m ulps)
+// w^m for m = 0..R-1 from w = v[1] by balanced products (error grows like log2 m ulps); for
+// R = 25, w^m = w^(m mod 5) (w^5)^(m div 5), which keeps ten powers live instead of 24
 template <typename T, int R>
 __device__ __forceinline__ void twiddle_powers(cx<T>* v, cx<T> w1) {
+  if (R == 25) {
+    cx<T> lo[5], hi[5];
+    lo[1] = w1;
+#pragma unroll
+    for (int m = 2; m < 5; ++m) lo[m] = (m % 2 == 0) ? cmul(lo[m / 2], lo[m / 2]) : cmul(lo[m - 1], w1);
+    hi[1] = cmul(lo[4], w1);
+#pragma unroll
+    for (int m = 2; m < 5; ++m) hi[m] = (m % 2 == 0) ? cmul(hi[m / 2], hi[m / 2]) : cmul(hi[m - 1], hi[1]);
+#pragma unroll
+    for (int m = 1; m < R; ++m) {
+      const int j = m % 5, q = m / 5;
+      const cx<T> w = (q == 0) ? lo[j] : (j == 0 ? hi[q] : cmul(hi[q], lo[j]));
+      v[m] = cmul(v[m], w);
+    }
+    return;
+  }
   cx<T> w[R];
   w[1] = w1;
 #pragma unroll
@@ -283,6 +383,10 @@ __device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, const int8_t* rad,
       case 2: stockham_stage<T, 2, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
       case 3: stockham_stage<T, 3, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
       case 5: stockham_stage<T, 5, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
+      case 9: stockham_stage<T, 9, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
+      case 25:  // FP32 only: the FP64 schedules keep radix 5 (25 values of 16 bytes per lane)
+        if constexpr (sizeof(T) == 4) stockham_stage<T, 25, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
+        break;
       default: break;
     }
     p *= R;
@@ -391,6 +495,10 @@ __device__ __forceinline__ void wave_fft(cx<T>* cols, int L, int Lc, int nw, con
       case 2: wave_stockham_stage<T, 2, INV>(cols, L, Lc, nw, p, tw); break;
       case 3: wave_stockham_stage<T, 3, INV>(cols, L, Lc, nw, p, tw); break;
       case 5: wave_stockham_stage<T, 5, INV>(cols, L, Lc, nw, p, tw); break;
+      case 9: wave_stockham_stage<T, 9, INV>(cols, L, Lc, nw, p, tw); break;
+      case 25:
+        if constexpr (sizeof(T) == 4) wave_stockham_stage<T, 25, INV>(cols, L, Lc, nw, p, tw);
+        break;
       default: break;
     }
     p *= R;

@@ -28,8 +28,8 @@ int64_t pow2floor(int64_t x) {
 }
 
 // radix schedule for a 5-smooth length: as many 8s as possible (a lone factor 2 turns one 8
-// into 4*4), then 3s and 5s; eights_first puts the 8s before the 4s and 2s
-std::vector<int8_t> radices(int64_t L, bool eights_first) {
+// into 4*4), then 9s and 3s, then (FP32) 25s and 5s; eights_first puts the 8s before the 4s and 2s
+std::vector<int8_t> radices(int64_t L, bool eights_first, bool f64) {
   std::vector<int8_t> small, r;
   int e2 = 0;
   while (L % 2 == 0) {
@@ -48,9 +48,18 @@ std::vector<int8_t> radices(int64_t L, bool eights_first) {
   if (!eights_first) r = small;
   for (int i = 0; i < n8; ++i) r.push_back(8);
   if (eights_first) r.insert(r.end(), small.begin(), small.end());
+  // pairs of 3s (and, in FP32, pairs of 5s) as single radix-9 (25) stages: fewer passes over LDS
+  while (L % 9 == 0) {
+    L /= 9;
+    r.push_back(9);
+  }
   while (L % 3 == 0) {
     L /= 3;
     r.push_back(3);
+  }
+  while (!f64 && L % 25 == 0) {
+    L /= 25;
+    r.push_back(25);
   }
   while (L % 5 == 0) {
     L /= 5;
@@ -104,11 +113,11 @@ std::vector<Layout> layout_candidates(int64_t M, bool f64) {
       L.M1 = m1;
       L.M2 = m2;
       L.cb = (int)b;
-      L.r1 = radices(m1, order == 1);
-      L.r2 = radices(m2, order == 1);
+      L.r1 = radices(m1, order == 1, f64);
+      L.r2 = radices(m2, order == 1, f64);
       if ((int)L.r1.size() > kMaxStages || (int)L.r2.size() > kMaxStages) continue;
       // the second radix order is a distinct candidate only when it differs
-      if (order == 1 && L.r1 == radices(m1, false) && L.r2 == radices(m2, false)) continue;
+      if (order == 1 && L.r1 == radices(m1, false, f64) && L.r2 == radices(m2, false, f64)) continue;
       v.push_back({score + 1e-3 * order, L});
     }
   }
