@@ -48,6 +48,14 @@ __host__ __device__ inline int col_tile_elems(int M2, int cb, int csz, bool wave
   return wave ? cb * wave_col_stride(M2, cb, csz) : cb * M2;
 }
 
+// Radices of the transform stages.  A stage holds ceil(Ept / R) butterflies of R complex values
+// per lane; the composite radices (two-level DFTs) are kept where that and their twiddles fit
+// the 128-VGPR budgets of the transform passes.
+__host__ __device__ constexpr bool radix_ok(int R, bool f64) {
+  return R == 2 || R == 3 || R == 4 || R == 5 || R == 8 || R == 9 ||
+         (!f64 && (R == 16 || R == 20 || R == 25));
+}
+
 template <typename T> struct Cx;
 template <> struct Cx<float> { using t = float2; };
 template <> struct Cx<double> { using t = double2; };

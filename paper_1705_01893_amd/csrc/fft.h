@@ -149,7 +149,8 @@ struct Dft<T, 5, INV> {
   }
 };
 
-// cos and sin of 2 pi e / R for the composite radices (e folded into [0, R/2] by symmetry)
+// cos and sin of 2 pi e / R for the composite radices, correctly rounded (e folded into [0, R/2]
+// by symmetry)
 template <int R>
 __device__ __forceinline__ void root_cs(int e, double& c, double& s) {
   e %= R;
@@ -157,30 +158,103 @@ __device__ __forceinline__ void root_cs(int e, double& c, double& s) {
   if (neg) e = R - e;
   c = 1.0;
   s = 0.0;
-  if (R == 9) {
-    switch (e) {
-      case 1: c = 0.766044443118978; s = 0.6427876096865393; break;
-      case 2: c = 0.17364817766693041; s = 0.984807753012208; break;
-      case 3: c = -0.4999999999999998; s = 0.8660254037844387; break;
-      case 4: c = -0.9396926207859083; s = 0.3420201433256689; break;
-      default: break;
-    }
-  } else if (R == 25) {
-    switch (e) {
-      case 1: c = 0.9685831611286311; s = 0.2486898871648548; break;
-      case 2: c = 0.8763066800438636; s = 0.4817536741017153; break;
-      case 3: c = 0.7289686274214116; s = 0.6845471059286886; break;
-      case 4: c = 0.5358267949789965; s = 0.8443279255020151; break;
-      case 5: c = 0.30901699437494745; s = 0.9510565162951535; break;
-      case 6: c = 0.06279051952931353; s = 0.9980267284282716; break;
-      case 7: c = -0.1873813145857246; s = 0.9822872507286887; break;
-      case 8: c = -0.4257792915650727; s = 0.9048270524660195; break;
-      case 9: c = -0.6374239897486897; s = 0.7705132427757893; break;
-      case 10: c = -0.8090169943749473; s = 0.5877852522924732; break;
-      case 11: c = -0.9297764858882513; s = 0.36812455268467814; break;
-      case 12: c = -0.9921147013144778; s = 0.12533323356430454; break;
-      default: break;
-    }
+  switch (R) {
+    case 6:
+      switch (e) {
+        case 1: c = 0.5; s = 0.8660254037844386; break;
+        case 2: c = -0.5; s = 0.8660254037844386; break;
+        case 3: c = -1.0; s = 0.0; break;
+        default: break;
+      }
+      break;
+    case 9:
+      switch (e) {
+        case 1: c = 0.766044443118978; s = 0.6427876096865394; break;
+        case 2: c = 0.17364817766693036; s = 0.984807753012208; break;
+        case 3: c = -0.5; s = 0.8660254037844386; break;
+        case 4: c = -0.9396926207859084; s = 0.3420201433256687; break;
+        default: break;
+      }
+      break;
+    case 10:
+      switch (e) {
+        case 1: c = 0.8090169943749475; s = 0.5877852522924731; break;
+        case 2: c = 0.30901699437494745; s = 0.9510565162951535; break;
+        case 3: c = -0.30901699437494745; s = 0.9510565162951535; break;
+        case 4: c = -0.8090169943749475; s = 0.5877852522924731; break;
+        case 5: c = -1.0; s = 0.0; break;
+        default: break;
+      }
+      break;
+    case 12:
+      switch (e) {
+        case 1: c = 0.8660254037844386; s = 0.5; break;
+        case 2: c = 0.5; s = 0.8660254037844386; break;
+        case 3: c = 0.0; s = 1.0; break;
+        case 4: c = -0.5; s = 0.8660254037844386; break;
+        case 5: c = -0.8660254037844386; s = 0.5; break;
+        case 6: c = -1.0; s = 0.0; break;
+        default: break;
+      }
+      break;
+    case 15:
+      switch (e) {
+        case 1: c = 0.9135454576426009; s = 0.4067366430758002; break;
+        case 2: c = 0.6691306063588582; s = 0.7431448254773942; break;
+        case 3: c = 0.30901699437494745; s = 0.9510565162951535; break;
+        case 4: c = -0.10452846326765347; s = 0.9945218953682733; break;
+        case 5: c = -0.5; s = 0.8660254037844386; break;
+        case 6: c = -0.8090169943749475; s = 0.5877852522924731; break;
+        case 7: c = -0.9781476007338057; s = 0.20791169081775934; break;
+        default: break;
+      }
+      break;
+    case 16:
+      switch (e) {
+        case 1: c = 0.9238795325112867; s = 0.3826834323650898; break;
+        case 2: c = 0.7071067811865476; s = 0.7071067811865476; break;
+        case 3: c = 0.3826834323650898; s = 0.9238795325112867; break;
+        case 4: c = 0.0; s = 1.0; break;
+        case 5: c = -0.3826834323650898; s = 0.9238795325112867; break;
+        case 6: c = -0.7071067811865476; s = 0.7071067811865476; break;
+        case 7: c = -0.9238795325112867; s = 0.3826834323650898; break;
+        case 8: c = -1.0; s = 0.0; break;
+        default: break;
+      }
+      break;
+    case 20:
+      switch (e) {
+        case 1: c = 0.9510565162951535; s = 0.30901699437494745; break;
+        case 2: c = 0.8090169943749475; s = 0.5877852522924731; break;
+        case 3: c = 0.5877852522924731; s = 0.8090169943749475; break;
+        case 4: c = 0.30901699437494745; s = 0.9510565162951535; break;
+        case 5: c = 0.0; s = 1.0; break;
+        case 6: c = -0.30901699437494745; s = 0.9510565162951535; break;
+        case 7: c = -0.5877852522924731; s = 0.8090169943749475; break;
+        case 8: c = -0.8090169943749475; s = 0.5877852522924731; break;
+        case 9: c = -0.9510565162951535; s = 0.30901699437494745; break;
+        case 10: c = -1.0; s = 0.0; break;
+        default: break;
+      }
+      break;
+    case 25:
+      switch (e) {
+        case 1: c = 0.9685831611286311; s = 0.2486898871648548; break;
+        case 2: c = 0.8763066800438636; s = 0.48175367410171527; break;
+        case 3: c = 0.7289686274214116; s = 0.6845471059286887; break;
+        case 4: c = 0.5358267949789967; s = 0.8443279255020151; break;
+        case 5: c = 0.30901699437494745; s = 0.9510565162951535; break;
+        case 6: c = 0.06279051952931337; s = 0.9980267284282716; break;
+        case 7: c = -0.18738131458572463; s = 0.9822872507286887; break;
+        case 8: c = -0.42577929156507266; s = 0.9048270524660196; break;
+        case 9: c = -0.6374239897486897; s = 0.7705132427757893; break;
+        case 10: c = -0.8090169943749475; s = 0.5877852522924731; break;
+        case 11: c = -0.9297764858882515; s = 0.368124552684678; break;
+        case 12: c = -0.9921147013144779; s = 0.12533323356430426; break;
+        default: break;
+      }
+      break;
+    default: break;
   }
   if (neg) s = -s;
 }
@@ -222,15 +296,29 @@ struct Dft2 {
   }
 };
 
-template <typename T, bool INV>
-struct Dft<T, 9, INV> {
-  __device__ __forceinline__ static void run(cx<T>* a) { Dft2<T, 3, 3, INV>::run(a); }
+// composite radices R = R1 R2 (Split<R>: the factors; R2 is also the inner step of the twiddles)
+template <int R>
+struct Split {
+  static constexpr int r1 = 0, r2 = 0;
 };
-
-template <typename T, bool INV>
-struct Dft<T, 25, INV> {
-  __device__ __forceinline__ static void run(cx<T>* a) { Dft2<T, 5, 5, INV>::run(a); }
-};
+#define MM_SPLIT(R, A, B)                  \
+  template <>                              \
+  struct Split<R> {                        \
+    static constexpr int r1 = A, r2 = B;   \
+  };                                       \
+  template <typename T, bool INV>          \
+  struct Dft<T, R, INV> {                  \
+    __device__ __forceinline__ static void run(cx<T>* a) { Dft2<T, A, B, INV>::run(a); } \
+  };
+MM_SPLIT(6, 2, 3)
+MM_SPLIT(9, 3, 3)
+MM_SPLIT(10, 2, 5)
+MM_SPLIT(12, 4, 3)
+MM_SPLIT(15, 3, 5)
+MM_SPLIT(16, 4, 4)
+MM_SPLIT(20, 4, 5)
+MM_SPLIT(25, 5, 5)
+#undef MM_SPLIT
 
 // Exact quotient n / d for n, d < 2^22 from a single-precision reciprocal estimate
 // (the estimate is within one of the quotient, corrected with one multiply-subtract).
@@ -244,21 +332,26 @@ __device__ __forceinline__ uint32_t qdiv(uint32_t n, uint32_t d, float inv) {
   return q;
 }
 
-// w^m for m = 0..R-1 from w = v[1] by balanced products (error grows like log2 m ulps); for
-// R = 25, w^m = w^(m mod 5) (w^5)^(m div 5), which keeps ten powers live instead of 24
+// w^m for m = 0..R-1 from w = v[1] by balanced products (error grows like log2 m ulps); for a
+// composite radix R = R1 R2, w^m = w^(m mod R2) (w^R2)^(m div R2), which keeps R1 + R2 powers
+// live instead of R - 1
 template <typename T, int R>
 __device__ __forceinline__ void twiddle_powers(cx<T>* v, cx<T> w1) {
-  if (R == 25) {
-    cx<T> lo[5], hi[5];
+  constexpr int B = Split<R>::r2, A = Split<R>::r1;
+  if constexpr (B > 0) {
+    cx<T> lo[B], hi[A];
+    lo[0].x = T(1);
+    lo[0].y = T(0);
     lo[1] = w1;
 #pragma unroll
-    for (int m = 2; m < 5; ++m) lo[m] = (m % 2 == 0) ? cmul(lo[m / 2], lo[m / 2]) : cmul(lo[m - 1], w1);
-    hi[1] = cmul(lo[4], w1);
+    for (int m = 2; m < B; ++m) lo[m] = (m % 2 == 0) ? cmul(lo[m / 2], lo[m / 2]) : cmul(lo[m - 1], w1);
+    hi[0] = lo[0];
+    hi[1] = cmul(lo[B - 1], w1);
 #pragma unroll
-    for (int m = 2; m < 5; ++m) hi[m] = (m % 2 == 0) ? cmul(hi[m / 2], hi[m / 2]) : cmul(hi[m - 1], hi[1]);
+    for (int m = 2; m < A; ++m) hi[m] = (m % 2 == 0) ? cmul(hi[m / 2], hi[m / 2]) : cmul(hi[m - 1], hi[1]);
 #pragma unroll
     for (int m = 1; m < R; ++m) {
-      const int j = m % 5, q = m / 5;
+      const int j = m % B, q = m / B;
       const cx<T> w = (q == 0) ? lo[j] : (j == 0 ? hi[q] : cmul(hi[q], lo[j]));
       v[m] = cmul(v[m], w);
     }
@@ -383,9 +476,30 @@ __device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, const int8_t* rad,
       case 2: stockham_stage<T, 2, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
       case 3: stockham_stage<T, 3, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
       case 5: stockham_stage<T, 5, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
-      case 9: stockham_stage<T, 9, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw); break;
-      case 25:  // FP32 only: the FP64 schedules keep radix 5 (25 values of 16 bytes per lane)
-        if constexpr (sizeof(T) == 4) stockham_stage<T, 25, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
+      // composite radices, where the precision's schedules use them
+      case 6:
+        if constexpr (radix_ok(6, sizeof(T) == 8)) stockham_stage<T, 6, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
+        break;
+      case 9:
+        if constexpr (radix_ok(9, sizeof(T) == 8)) stockham_stage<T, 9, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
+        break;
+      case 10:
+        if constexpr (radix_ok(10, sizeof(T) == 8)) stockham_stage<T, 10, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
+        break;
+      case 12:
+        if constexpr (radix_ok(12, sizeof(T) == 8)) stockham_stage<T, 12, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
+        break;
+      case 15:
+        if constexpr (radix_ok(15, sizeof(T) == 8)) stockham_stage<T, 15, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
+        break;
+      case 16:
+        if constexpr (radix_ok(16, sizeof(T) == 8)) stockham_stage<T, 16, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
+        break;
+      case 20:
+        if constexpr (radix_ok(20, sizeof(T) == 8)) stockham_stage<T, 20, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
+        break;
+      case 25:
+        if constexpr (radix_ok(25, sizeof(T) == 8)) stockham_stage<T, 25, INV, BFAST, NT>(lds, L, nb, lg_nb, p, tw);
         break;
       default: break;
     }
@@ -495,9 +609,29 @@ __device__ __forceinline__ void wave_fft(cx<T>* cols, int L, int Lc, int nw, con
       case 2: wave_stockham_stage<T, 2, INV>(cols, L, Lc, nw, p, tw); break;
       case 3: wave_stockham_stage<T, 3, INV>(cols, L, Lc, nw, p, tw); break;
       case 5: wave_stockham_stage<T, 5, INV>(cols, L, Lc, nw, p, tw); break;
-      case 9: wave_stockham_stage<T, 9, INV>(cols, L, Lc, nw, p, tw); break;
+      case 6:
+        if constexpr (radix_ok(6, sizeof(T) == 8)) wave_stockham_stage<T, 6, INV>(cols, L, Lc, nw, p, tw);
+        break;
+      case 9:
+        if constexpr (radix_ok(9, sizeof(T) == 8)) wave_stockham_stage<T, 9, INV>(cols, L, Lc, nw, p, tw);
+        break;
+      case 10:
+        if constexpr (radix_ok(10, sizeof(T) == 8)) wave_stockham_stage<T, 10, INV>(cols, L, Lc, nw, p, tw);
+        break;
+      case 12:
+        if constexpr (radix_ok(12, sizeof(T) == 8)) wave_stockham_stage<T, 12, INV>(cols, L, Lc, nw, p, tw);
+        break;
+      case 15:
+        if constexpr (radix_ok(15, sizeof(T) == 8)) wave_stockham_stage<T, 15, INV>(cols, L, Lc, nw, p, tw);
+        break;
+      case 16:
+        if constexpr (radix_ok(16, sizeof(T) == 8)) wave_stockham_stage<T, 16, INV>(cols, L, Lc, nw, p, tw);
+        break;
+      case 20:
+        if constexpr (radix_ok(20, sizeof(T) == 8)) wave_stockham_stage<T, 20, INV>(cols, L, Lc, nw, p, tw);
+        break;
       case 25:
-        if constexpr (sizeof(T) == 4) wave_stockham_stage<T, 25, INV>(cols, L, Lc, nw, p, tw);
+        if constexpr (radix_ok(25, sizeof(T) == 8)) wave_stockham_stage<T, 25, INV>(cols, L, Lc, nw, p, tw);
         break;
       default: break;
     }

@@ -27,44 +27,58 @@ int64_t pow2floor(int64_t x) {
   return x;
 }
 
-// radix schedule for a 5-smooth length: as many 8s as possible (a lone factor 2 turns one 8
-// into 4*4), then 9s and 3s, then (FP32) 25s and 5s; eights_first puts the 8s before the 4s and 2s
-std::vector<int8_t> radices(int64_t L, bool eights_first, bool f64) {
-  std::vector<int8_t> small, r;
-  int e2 = 0;
-  while (L % 2 == 0) {
-    L /= 2;
-    ++e2;
+// Radix schedule for a 5-smooth length: the fewest stages over the radices the precision's
+// register budget allows (radix_ok), ties broken toward the smaller largest radix, then the
+// larger smallest one; ascending order, or descending with largest_first.
+std::vector<int8_t> radices(int64_t L, bool largest_first, bool f64) {
+  int e[3] = {0, 0, 0};
+  const int pr[3] = {2, 3, 5};
+  for (int i = 0; i < 3; ++i)
+    while (L % pr[i] == 0) {
+      L /= pr[i];
+      ++e[i];
+    }
+  std::vector<int> rs;
+  for (int R = 2; R <= 25; ++R)
+    if (radix_ok(R, f64)) rs.push_back(R);
+  const int nr = (int)rs.size();
+  // best[a][b][c] = (stages, the radices) for 2^a 3^b 5^c, by increasing exponents
+  const int A = e[0] + 1, B = e[1] + 1, C = e[2] + 1;
+  std::vector<int> cnt(A * B * C, 1 << 20), last(A * B * C, 0), peak(A * B * C, 0), low(A * B * C, 1 << 20);
+  cnt[0] = 0;
+  for (int a = 0; a < A; ++a)
+    for (int b = 0; b < B; ++b)
+      for (int c = 0; c < C; ++c) {
+        const int id = (a * B + b) * C + c;
+        if (id == 0) continue;
+        for (int k = 0; k < nr; ++k) {
+          int r = rs[k], x = 0, y = 0, z = 0;
+          while (r % 2 == 0) r /= 2, ++x;
+          while (r % 3 == 0) r /= 3, ++y;
+          while (r % 5 == 0) r /= 5, ++z;
+          if (x > a || y > b || z > c) continue;
+          const int prev = ((a - x) * B + (b - y)) * C + (c - z);
+          if (cnt[prev] >= (1 << 20)) continue;
+          const int n = cnt[prev] + 1, pk = std::max(peak[prev], rs[k]), lo = std::min(low[prev], rs[k]);
+          if (n < cnt[id] || (n == cnt[id] && (pk < peak[id] || (pk == peak[id] && lo > low[id])))) {
+            cnt[id] = n;
+            last[id] = rs[k];
+            peak[id] = pk;
+            low[id] = lo;
+          }
+        }
+      }
+  std::vector<int8_t> r;
+  for (int a = e[0], b = e[1], c = e[2]; a + b + c > 0;) {
+    const int id = (a * B + b) * C + c;
+    int q = last[id];
+    r.push_back((int8_t)q);
+    while (q % 2 == 0) q /= 2, --a;
+    while (q % 3 == 0) q /= 3, --b;
+    while (q % 5 == 0) q /= 5, --c;
   }
-  int n8 = e2 / 3, rem = e2 % 3;
-  if (rem == 1 && n8 > 0) {
-    --n8;
-    small = {4, 4};
-  } else if (rem == 1) {
-    small = {2};
-  } else if (rem == 2) {
-    small = {4};
-  }
-  if (!eights_first) r = small;
-  for (int i = 0; i < n8; ++i) r.push_back(8);
-  if (eights_first) r.insert(r.end(), small.begin(), small.end());
-  // pairs of 3s (and, in FP32, pairs of 5s) as single radix-9 (25) stages: fewer passes over LDS
-  while (L % 9 == 0) {
-    L /= 9;
-    r.push_back(9);
-  }
-  while (L % 3 == 0) {
-    L /= 3;
-    r.push_back(3);
-  }
-  while (!f64 && L % 25 == 0) {
-    L /= 25;
-    r.push_back(25);
-  }
-  while (L % 5 == 0) {
-    L /= 5;
-    r.push_back(5);
-  }
+  std::sort(r.begin(), r.end());
+  if (largest_first) std::reverse(r.begin(), r.end());
   return r;
 }
 
