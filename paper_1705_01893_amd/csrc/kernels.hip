@@ -349,7 +349,6 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
   constexpr int G = NG ? (kGroupNoGather < E ? kGroupNoGather : E) : 4;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  const int np = (int)P.npix;
   for (int it = xcd_run_order(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const ItemAC item = items[it];
     const DevChunk ch = P.chunks[item.chunk];
@@ -459,7 +458,6 @@ __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevCh
                                        double& chi) {
   // bins k (LDS ia, power law plk) and M - k (LDS ib, power law plm)
   const cx<T> Zk = lds[ia], Zm = lds[ib];
-  const int M = ch.M;
   cx<T> E, O;
   E.x = T(0.5) * (Zk.x + Zm.x);
   E.y = T(0.5) * (Zk.y - Zm.y);
