@@ -7,7 +7,9 @@
 // synchronises, applies twiddles and the R-point DFT in registers, and
 // writes the results to their self-sorting (Stockham) positions; after the last
 // stage the sequences are in natural frequency order in place.  Radices 2, 3, 4,
-// 5 and 8 cover every 5-smooth length.
+// 5 and 8 cover every 5-smooth length; the composite radices 9, 16, 20 and 25
+// (two-level DFTs in registers) cut the number of stages where the register
+// budget allows them (radix_ok).
 #pragma once
 
 #include "common.h"
