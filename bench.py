@@ -329,7 +329,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path shards over detector "
-              "chunks with one map all-reduce per iteration, which this build does not implement)",
+              "chunks with one map all-reduce per iteration, which is not implemented)",
               file=sys.stderr)
         sys.exit(2)
 
