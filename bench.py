@@ -443,6 +443,9 @@ def main():
                     "alg_bytes": pb[i], "GBs": round(pb[i] / (avg[i] * 1e-3) / 1e9, 1) if avg[i] > 0 else None}
                    for i in range(5)],
         "sweep_roofline_frac": round(sweep_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the bytes no schedule can avoid: d, pix and the on-map angles, each read once per iteration
+        "compulsory_frac": round((prob.nsamp_total * (tod_bytes + 4) + int((prob.pix >= 0).sum()) * psi_bytes)
+                                 / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "plan_s": round(t_plan, 2), "generate_s": round(t_gen, 2), "kernel_hash": khash,
         "layouts": layout_summary(mm, plan),
     }
