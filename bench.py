@@ -151,6 +151,38 @@ def write_traffic(args, fetch_dir: str, write_dir: str) -> None:
     print(json.dumps(out))
 
 
+def summarize_counters(run_dirs: list) -> None:
+    """Markdown table of per-kernel shader counters (rocprofv3 --pmc runs of SQ_ counters), mean per
+    dispatch over the workload's dispatches (those after the plan's precompute binning launch)."""
+    per = {}
+    for d in run_dirs:
+        rows = _counter_rows(d)
+        start = max(int(r["Dispatch_Id"]) for r in rows
+                    if "k_bin<" in r["Kernel_Name"] and (", 7>" in r["Kernel_Name"] or ", 2>" in r["Kernel_Name"]))
+        acc, disp = {}, {}
+        for r in rows:
+            if int(r["Dispatch_Id"]) <= start or "mm::" not in r["Kernel_Name"]:
+                continue
+            k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            acc.setdefault(k, {}).setdefault(r["Counter_Name"], 0.0)
+            acc[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp.setdefault(k, set()).add(r["Dispatch_Id"])
+        for k, cs in acc.items():
+            for c, v in cs.items():
+                per.setdefault(k, {})[c] = v / len(disp[k])
+    print("| kernel | waves | VALU instr / wave | LDS instr / wave | LDS bank-conflict cycles / wave | "
+          "waiting (share of wave cycles) | issuing VALU (share) |")
+    print("|---|---|---|---|---|---|---|")
+    for k, c in sorted(per.items(), key=lambda kv: -kv[1].get("SQ_WAVE_CYCLES", 0.0)):
+        w = c.get("SQ_WAVES", 0.0) or 1.0
+        cyc = c.get("SQ_WAVE_CYCLES", 0.0) or 1.0
+        def f(name, scale=1.0, fmt="{:.0f}"):
+            return fmt.format(c[name] * scale) if name in c else "-"
+        print(f"| {k} | {w:.0f} | {f('SQ_INSTS_VALU', 1 / w)} | {f('SQ_INSTS_LDS', 1 / w)} | "
+              f"{f('SQ_LDS_BANK_CONFLICT', 1 / w)} | {f('SQ_WAIT_ANY', 1 / cyc, '{:.2f}')} | "
+              f"{f('SQ_ACTIVE_INST_VALU', 1 / cyc, '{:.2f}')} |")
+
+
 def summarize_trace(trace_dir: str) -> None:
     """Markdown table of the workload's kernels (dispatches after the plan's precompute binning)."""
     import csv
@@ -317,12 +349,17 @@ def main():
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no GPU run: read two rocprofv3 --pmc outputs (FETCH_SIZE, WRITE_SIZE) of a "
                          "--copy-calibration run of this workload and write profiles/traffic_<workload>.json")
+    ap.add_argument("--summarize-counters", metavar="PMC_DIR", nargs="+",
+                    help="print per-kernel shader-counter ratios from rocprofv3 --pmc runs of SQ_ counters")
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
                     help="no GPU run: per-kernel launch count and mean duration of the workload's dispatches "
                          "in a rocprofv3 --kernel-trace output (markdown table)")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(args, *args.write_traffic)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
