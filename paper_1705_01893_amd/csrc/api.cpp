@@ -45,7 +45,11 @@ template <typename F>
 hipError_t timed(mm_plan_s* pl, int pass, hipStream_t s, F&& launch) {
   if (!pl->timing || pl->capturing) return launch();
   hipEvent_t a = take_event(pl), b = take_event(pl);
-  if (!a || !b) return hipErrorOutOfMemory;
+  if (!a || !b) {
+    if (a) pl->ev_pool.push_back(a);
+    if (b) pl->ev_pool.push_back(b);
+    return hipErrorOutOfMemory;
+  }
   hipError_t e = hipEventRecord(a, s);
   if (e == hipSuccess) e = launch();
   if (e == hipSuccess) e = hipEventRecord(b, s);
@@ -442,9 +446,14 @@ mm_status mm_cg_solve(mm_plan_t plan, const void* d, const double* rhs_map, int3
     const size_t need = (size_t)maxiter + 1;
     if (plan->hist_cap < need) {
       void* h = nullptr;
-      MM_TRY_HIP(hipMalloc(&h, need * sizeof(double)));
+      if (hipMalloc(&h, need * sizeof(double)) != hipSuccess) return fail(MM_E_NOMEM, "device allocation failed (CG history)");
       if (plan->d_hist) {
-        MM_TRY_HIP(hipStreamSynchronize(s));
+        // the old history may still be read by queued work
+        const hipError_t es = hipStreamSynchronize(s);
+        if (es != hipSuccess) {
+          (void)hipFree(h);
+          return fail(MM_E_HIP, std::string("stream synchronize: ") + hipGetErrorString(es));
+        }
         (void)hipFree(plan->d_hist);
       }
       plan->d_hist = (double*)h;
