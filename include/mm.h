@@ -193,8 +193,10 @@ mm_status mm_messenger_iter(mm_plan_t plan, const void* d, double lambda, const 
 /*
  * Full cooled messenger solve (Section 3.1).  Captures the whole schedule in
  * one HIP graph and launches it on `stream`; a call with the same buffers and
- * the same schedule as the previous one replays that graph without capture.  m0: device start map or NULL for
- * zero.  m_out: device result.  chi2_hist_dev: device array of
+ * the same schedule as the previous one replays that graph without capture.
+ * The plan keeps only the latest graph: a call that captures a new one first
+ * waits on the host until the previous graph's last launch has completed, then
+ * destroys it.  m0: device start map or NULL for zero.  m_out: device result.  chi2_hist_dev: device array of
  * (first_inf + sum(iters) + 1) doubles or NULL; entry i is chi^2(m_i) of the
  * map entering iteration i, the last entry chi^2 of the final map.
  */

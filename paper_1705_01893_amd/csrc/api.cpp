@@ -322,6 +322,7 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, cons
   key.insert(key.end(), lams.begin(), lams.end());
   if (plan->solve_exec && key == plan->solve_key) {
     MM_TRY_HIP(hipGraphLaunch(plan->solve_exec, S(stream)));
+    MM_TRY_HIP(hipEventRecord(plan->solve_done, S(stream)));
     return MM_OK;
   }
   hipStream_t cs = plan->cap_stream;
@@ -340,10 +341,22 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, cons
   ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ee));
+  // one cached solve graph: the previous one is destroyed once its last launch has completed
+  if (plan->solve_exec) {
+    (void)hipEventSynchronize(plan->solve_done);
+    (void)hipGraphExecDestroy(plan->solve_exec);
+    plan->solve_exec = nullptr;
+    plan->solve_key.clear();
+  }
+  if (!plan->solve_done && (ee = hipEventCreateWithFlags(&plan->solve_done, hipEventDisableTiming)) != hipSuccess) {
+    plan->solve_done = nullptr;
+    (void)hipGraphExecDestroy(exec);
+    return fail(MM_E_HIP, std::string("event create: ") + hipGetErrorString(ee));
+  }
+  plan->solve_exec = exec;  // owned by the plan from here on; replayed only once the key is set
   ee = hipGraphLaunch(exec, S(stream));
-  plan->graphs.push_back(exec);
+  if (ee == hipSuccess) ee = hipEventRecord(plan->solve_done, S(stream));
   if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph launch: ") + hipGetErrorString(ee));
-  plan->solve_exec = exec;
   plan->solve_key = key;
   return MM_OK;
 }

@@ -639,8 +639,9 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
 
 void destroy_plan(mm_plan_s* pl) {
   if (!pl) return;
-  if (!pl->graphs.empty() || !pl->allocs.empty()) (void)hipDeviceSynchronize();
-  for (auto g : pl->graphs) (void)hipGraphExecDestroy(g);
+  if (pl->solve_exec || !pl->allocs.empty()) (void)hipDeviceSynchronize();
+  if (pl->solve_exec) (void)hipGraphExecDestroy(pl->solve_exec);
+  if (pl->solve_done) (void)hipEventDestroy(pl->solve_done);
   for (auto& r : pl->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

@@ -69,9 +69,9 @@ struct mm_plan_s {
   size_t hist_cap = 0;
   int64_t nsolvable = 0;
   hipStream_t cap_stream = nullptr;
-  std::vector<hipGraphExec_t> graphs;
   std::vector<double> solve_key;        // arguments of the last captured solve (replayed when equal)
-  hipGraphExec_t solve_exec = nullptr;
+  hipGraphExec_t solve_exec = nullptr;  // the one cached solve graph
+  hipEvent_t solve_done = nullptr;      // recorded after each launch of solve_exec
   // per-pass timing (measurement only)
   bool timing = false;
   bool capturing = false;

@@ -201,6 +201,35 @@ def test_solve_graph_replays_match_eager(dev, precision):
         assert torch.equal(h, h_eager), rep
 
 
+def test_solve_recapture_alternating_buffers(dev):
+    """The plan caches one solve graph: a call with other buffers captures a new one and retires
+    the previous graph once its last launch has completed. Solves alternating between two sets of
+    buffers, queued with no host synchronisation between them, must all give the same map and
+    history."""
+    say("[recapture]")
+    t = tiny_problem(607, ncomp=3, **SHAPES["mixed_radix"])
+    plan = gpu_plan(t, dev)
+    d = tod(t, dev, mm.MM_FP64)
+    levels, per = [30.0, 1.0], [2, 3]
+    nh = 1 + sum(per) + 1
+    bufs = [(torch.zeros((3, t.npix), dtype=torch.float64, device=dev),
+             torch.zeros(nh, dtype=torch.float64, device=dev)) for _ in range(2)]
+    outs = []
+    for rep in range(6):
+        m, h = bufs[rep % 2]
+        mm.mm_solve(plan, d, levels, per, m, chi2_hist=h)
+        outs.append((m.clone(), h.clone()))  # stream-ordered after the solve
+    torch.cuda.synchronize()
+    S = oracle_setup(t)
+    m_ref, h_ref = messenger_solve(S, t.d.astype(np.float64), [math.inf] + [30.0] * 2 + [1.0] * 3)
+    assert rel(outs[0][0].cpu().numpy(), m_ref) < F64_TOL
+    np.testing.assert_allclose(outs[0][1].cpu().numpy(), h_ref, rtol=F64_TOL)
+    for rep, (m, h) in enumerate(outs[1:], 1):
+        assert torch.equal(m, outs[0][0]), rep
+        assert torch.equal(h, outs[0][1]), rep
+    plan.close()
+
+
 def test_in_place_iteration_matches(dev):
     say("[inplace]")
     t = tiny_problem(404, ncomp=3, **SHAPES["pow2"])
