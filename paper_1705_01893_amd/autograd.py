@@ -52,6 +52,7 @@ class MessengerSolve(torch.autograd.Function):
         dd = d.detach().to(plan.tod_dtype).contiguous()
         mm.mm_solve(plan, dd, lambdas, iters, m)
         ctx.plan = plan
+        ctx.noise = (s, f, a)
         ctx.sched = (list(lambdas), list(iters))
         ctx.adjoint = (adjoint, adjoint_iters, adjoint_rtol)
         ctx.d_dtype = d.dtype
@@ -63,6 +64,9 @@ class MessengerSolve(torch.autograd.Function):
     def backward(ctx, gm: torch.Tensor):
         dd, m = ctx.saved_tensors
         plan = ctx.plan
+        # another forward may have set other noise parameters on the plan since this one ran
+        if _noise_changed(plan, *ctx.noise):
+            mm.mm_plan_set_noise(plan, *ctx.noise)
         g = gm.detach().double().contiguous()
         z = torch.zeros_like(m)
         kind, maxit, rtol = ctx.adjoint

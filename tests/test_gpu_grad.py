@@ -130,6 +130,34 @@ def test_autograd_matches_dense_gradient(dev, adjoint):
     assert np.linalg.norm(d.grad.cpu().numpy() - ref_d) / np.linalg.norm(ref_d) < 1e-6
 
 
+def test_backward_after_another_forward(dev):
+    """The plan holds one set of noise parameters: a forward with other parameters between a
+    forward and its backward must not change that backward's gradient."""
+    say("[autograd interleaved]")
+    t = _mild(47)
+    plan = _plan(t, dev)
+    m_ref = torch.from_numpy(random_map(7, 3, t.npix)).to(dev)
+    lams = mm.mm_cooling_levels(plan, 4, 0.0) + [1.0]
+    iters = [8] * 4 + [200]
+    d = torch.from_numpy(t.d).to(dev)
+
+    def grads(interleave):
+        sig = torch.tensor(t.sigma, dtype=torch.float64, requires_grad=True)
+        fk = torch.tensor(t.fknee, dtype=torch.float64, requires_grad=True)
+        al = torch.tensor(t.alpha, dtype=torch.float64, requires_grad=True)
+        loss = ((messenger_solve(d, sig, fk, al, plan, lams, iters) - m_ref) ** 2).sum()
+        if interleave:
+            with torch.no_grad():
+                messenger_solve(d, torch.tensor(t.sigma * 1.3), torch.tensor(t.fknee * 0.7),
+                                torch.tensor(t.alpha * 1.1), plan, lams, iters)
+        loss.backward()
+        return np.stack([sig.grad.numpy(), fk.grad.numpy(), al.grad.numpy()], axis=1)
+
+    ref = grads(False)
+    got = grads(True)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+
+
 def test_autograd_central_differences(dev):
     """Central differences (h = 1e-4 relative) of the GPU forward solve against the adjoint gradient."""
     say("[autograd fd]")
