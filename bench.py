@@ -450,6 +450,19 @@ def main():
     pass_ms, pass_n = mm.mm_get_timing(plan)
     mm.mm_set_timing(plan, False)
     log(f"per-pass run: {timed_passes_ms / args.steps:.4f} ms per iteration with events between passes")
+    # what a plain device-to-device copy reaches on this GPU (read + write bytes per second):
+    # the practical ceiling of a streaming pass, beside the published HBM peak
+    csrc = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    ev4, ev5 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev4.record()
+    for _ in range(5):
+        cdst.copy_(csrc)
+    ev5.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * csrc.numel() * 8 * 5 / (ev4.elapsed_time(ev5) * 1e-3) / 1e9
+    del csrc, cdst
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -483,6 +496,7 @@ def main():
         # the bytes no schedule can avoid: d, pix and the on-map angles, each read once per iteration
         "compulsory_frac": round((prob.nsamp_total * (tod_bytes + 4) + int((prob.pix >= 0).sum()) * psi_bytes)
                                  / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "copy_GBs": round(copy_gbs, 1), "copy_frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
         "plan_s": round(t_plan, 2), "generate_s": round(t_gen, 2), "kernel_hash": khash,
         "layouts": layout_summary(mm, plan),
     }
