@@ -5,7 +5,7 @@ benchmark's CPU-baseline leg.
 
 The comparison solver of Sections 1, 2 and 3.1: textbook preconditioned CG on
 (P^T N^-1 P) m = P^T N^-1 d, started from zero (Section 3.1).  The paper
-names a "diagonal preconditioner" without defining it; the reading used here
+calls its CG diagonal-preconditioned without defining the preconditioner; the reading used here
 is the per-pixel block P^T diag(1/tau) P, i.e. the same W^-1 blocks the
 messenger iteration uses, which with the default tau_c = sigma_c^2 is the
 white-noise weight map (diagonal for temperature-only maps, 3x3 blocks for
