@@ -455,8 +455,9 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
 template <typename T>
 __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevChunk& ch, const DevClass& cl,
                                        const BinCtx& bc, int ops, int k, int ia, int ib, T plk, T plm,
-                                       double& chi) {
-  // bins k (LDS ia, power law plk) and M - k (LDS ib, power law plm)
+                                       double& chi, const cx<T>* wpre = nullptr) {
+  // bins k (LDS ia, power law plk) and M - k (LDS ib, power law plm); wpre: omega_2M^k when the
+  // caller has fetched it already
   const cx<T> Zk = lds[ia], Zm = lds[ib];
   cx<T> E, O;
   E.x = T(0.5) * (Zk.x + Zm.x);
@@ -464,7 +465,7 @@ __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevCh
   // O = (Zk - conj(Zm)) / (2i)
   O.x = T(0.5) * (Zk.y + Zm.y);
   O.y = -T(0.5) * (Zk.x - Zm.x);
-  const cx<T> w = omega2M<T>(P, cl, k);
+  const cx<T> w = wpre ? *wpre : omega2M<T>(P, cl, k);
   const cx<T> wO = cmul(w, O);
   const cx<T> Rk = cadd(E, wO);
   const cx<T> Rm = csub(conjc(E), conjc(wO));
@@ -530,33 +531,73 @@ __device__ __forceinline__ void b_self(cx<T>* lds, const DevPlan& P, const DevCh
 
 // Rows of a row item between the work buffer and LDS (row r at r * M1).  NR: rows the item may
 // hold (2: one pair or a self-paired row, nrow <= 2; 4: two pairs); NR * M1 <= kBlockB * Ept.
+// FP32: every load of a thread is issued before the first LDS write (one memory round trip per
+// item, not one per element); slots past the row end or the item's rows read element 0 of the
+// chunk, a valid address, and are not stored.  FP64 keeps the per-element form, which measured
+// faster there.
 template <typename T, int NR>
 __device__ __forceinline__ void row_load(cx<T>* lds, const cx<T>* __restrict__ Xc, const int* rws, int nrow, int M1) {
   constexpr int U = Ept<T>::v / NR;
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = threadIdx.x + u * kBlockB;
+      if (e < M1) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (r < nrow) lds[r * M1 + e] = Xc[(int64_t)rws[r] * M1 + e];
+      }
+    }
+    return;
+  }
+  cx<T> v[U][NR];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int e = threadIdx.x + u * kBlockB;
-    if (e < M1) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (r < nrow) lds[r * M1 + e] = Xc[(int64_t)rws[r] * M1 + e];
-    }
+    for (int r = 0; r < NR; ++r) v[u][r] = Xc[(e < M1 && r < nrow) ? (int64_t)rws[r] * M1 + e : 0];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * kBlockB;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (e < M1 && r < nrow) lds[r * M1 + e] = v[u][r];
   }
 }
 
-// the inverse row transforms' output, times the conjugate column twiddle, back to the work buffer
+// the inverse row transforms' output, times the conjugate column twiddle, back to the work buffer;
+// FP32: the twiddle-table reads of every element are issued together (slots past the row end or
+// the item's rows read the q = 0 entries and store nothing)
 template <typename T, int NR>
 __device__ __forceinline__ void row_store(const cx<T>* lds, cx<T>* __restrict__ Xc, const DevPlan& P,
                                           const DevClass& cl, const int* rws, int nrow, int M1) {
   constexpr int U = Ept<T>::v / NR;
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j1 = threadIdx.x + u * kBlockB;
+      if (j1 < M1) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (r < nrow) Xc[(int64_t)rws[r] * M1 + j1] = cmul(lds[r * M1 + j1], conjc(omega2M<T>(P, cl, 2 * j1 * rws[r])));
+      }
+    }
+    return;
+  }
+  cx<T> w[U][NR];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int j1 = threadIdx.x + u * kBlockB;
-    if (j1 < M1) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (r < nrow) Xc[(int64_t)rws[r] * M1 + j1] = cmul(lds[r * M1 + j1], conjc(omega2M<T>(P, cl, 2 * j1 * rws[r])));
-    }
+    for (int r = 0; r < NR; ++r) w[u][r] = omega2M<T>(P, cl, (j1 < M1 && r < nrow) ? 2 * j1 * rws[r] : 0);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j1 = threadIdx.x + u * kBlockB;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (j1 < M1 && r < nrow) Xc[(int64_t)rws[r] * M1 + j1] = cmul(lds[r * M1 + j1], conjc(w[u][r]));
   }
 }
 
@@ -616,14 +657,29 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
                       plk[u], plm[u], chi);
         }
       } else {
-        // the FP32-mixed form evaluates the power law in place
-        for (int t = threadIdx.x; t < nt; t += kBlockB) {
+        // the FP32-mixed form evaluates the power law in place; the twiddle reads of all of a
+        // thread's bins go out first
+        constexpr int U = Ept<T>::v / 2;
+        cx<T> wk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = threadIdx.x + u * kBlockB;
           const int q = t >= M1 ? 1 : 0;
-          const int k1 = t - q * M1, pk1 = M1 - 1 - k1;
-          const int r = q ? rc : ra, rr = M2 - r;
-          const int k = r + M2 * k1;
-          b_pair<T>(lds, P, ch, cl, bc, ops, k, 2 * q * M1 + k1, (2 * q + 1) * M1 + pk1,
-                    powerlaw_bin<T>(P, ch, k, r * M1 + k1), powerlaw_bin<T>(P, ch, ch.M - k, rr * M1 + pk1), chi);
+          const int k1 = t - q * M1;
+          wk[u] = omega2M<T>(P, cl, t < nt ? (q ? rc : ra) + M2 * k1 : 0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = threadIdx.x + u * kBlockB;
+          if (t < nt) {
+            const int q = t >= M1 ? 1 : 0;
+            const int k1 = t - q * M1, pk1 = M1 - 1 - k1;
+            const int r = q ? rc : ra, rr = M2 - r;
+            const int k = r + M2 * k1;
+            b_pair<T>(lds, P, ch, cl, bc, ops, k, 2 * q * M1 + k1, (2 * q + 1) * M1 + pk1,
+                      powerlaw_bin<T>(P, ch, k, r * M1 + k1), powerlaw_bin<T>(P, ch, ch.M - k, rr * M1 + pk1), chi,
+                      &wk[u]);
+          }
         }
       }
     } else {
