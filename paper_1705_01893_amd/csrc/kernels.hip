@@ -331,6 +331,14 @@ __host__ __device__ inline int col_grid(int64_t nitems) {
   const int64_t n = (nitems + g - 1) / g * g;
   return (int)(n < kGridCap ? (n > 0 ? n : g) : kGridCap);
 }
+// wave-uniform values in scalar registers: a work item's sizes and offsets, read once, so that
+// per-element address arithmetic does not wait on the vector loads that fetched them
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+  const uint32_t lo = (uint32_t)uni((int)(uint32_t)x), hi = (uint32_t)uni((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int xcd_run_order(int b, int grid) {
   constexpr int g = kXcd * kXcdRun;
   if (grid % g) return b;
@@ -340,7 +348,7 @@ __device__ __forceinline__ int xcd_run_order(int b, int grid) {
 
 // NG: the source needs no map gather (d, P m from its buffer, or their difference)
 template <typename T, bool P2, bool NG>
-__global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __restrict__ items, int nitems,
+__global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    const T* __restrict__ d, const double* __restrict__ m, int src,
                                                    cx<T>* __restrict__ X, const T* __restrict__ pmbuf) {
   constexpr int E = Ept<T>::v;
@@ -353,36 +361,38 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
     const ItemAC item = items[it];
     const DevChunk ch = P.chunks[item.chunk];
     const DevClass& cl = P.classes[ch.cls];
-    const int B = ch.cb, lgB = ch.lgb, M1 = ch.M1, M2 = ch.M2;
-    const int j10 = item.j1;
+    const int B = uni(ch.cb), lgB = uni(ch.lgb), M1 = uni(ch.M1), M2 = uni(ch.M2);
+    const int j10 = uni(item.j1);
     const int nbv = min(B, M1 - j10);
     const int ntot = B * M2;
-    const int64_t cbase = ch.off / 2 + j10;
+    const int64_t cbase = uni64(ch.off) / 2 + j10;
 #pragma unroll 1
     for (int g = 0; g < E; g += G) {
       int2 pp[G];
       cx<T> dd[G], pb[G];
       uint4 raw[G];
       bool ok[G];
+      // every load of the group goes out before any is used: elements outside the item read the
+      // item's first pair (a valid address) and are discarded, so no per-element branch separates
+      // the loads
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const int e = threadIdx.x + (g + u) * kBlock;
         const int b = e & (B - 1), j2 = e >> lgB;
         ok[u] = (e < ntot) && (b < nbv);
-        const int64_t ci = cbase + b + (int64_t)M1 * j2;
+        const int64_t ci = ok[u] ? cbase + b + (int64_t)M1 * j2 : cbase;
         pp[u] = make_int2(-1, -1);
         dd[u].x = T(0);
         dd[u].y = T(0);
         pb[u].x = T(0);
         pb[u].y = T(0);
-        if (ok[u]) {
-          if (src != SRC_PM && src != SRC_PMBUF) dd[u] = ((const cx<T>*)d)[ci];
-          if (src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF) {
-            pb[u] = ((const cx<T>*)pmbuf)[ci];
-          } else if (!NG && src != SRC_D) {
-            pp[u] = ((const int2*)P.pix)[ci];
-            if (P.ncomp == 3) psi_pair_load<T>(P, ci, raw[u]);
-          }
+        if (src != SRC_PM && src != SRC_PMBUF) dd[u] = ((const cx<T>*)d)[ci];
+        if (src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF) {
+          pb[u] = ((const cx<T>*)pmbuf)[ci];
+        } else if (!NG && src != SRC_D) {
+          const int2 q = ((const int2*)P.pix)[ci];
+          pp[u] = ok[u] ? q : make_int2(-1, -1);
+          if (P.ncomp == 3) psi_pair_load<T>(P, ci, raw[u]);
         }
       }
       double pm[G][2];
@@ -390,20 +400,20 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
       for (int u = 0; u < G; ++u) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
+          // flagged samples (px < 0) read pixel 0 and are discarded: no branch between the gathers
           const int px = h == 0 ? pp[u].x : pp[u].y;
-          double v = 0.0;
-          if (px >= 0) {
-            if (P.ncomp == 3) {
-              // the interleaved copy: I, Q and U of a pixel share one cache line
-              const double2 iq = P.mapi[2 * px], u0 = P.mapi[2 * px + 1];
-              T c, sn;
-              psi_from_raw<T>(P, raw[u], h, c, sn);
-              v = iq.x + (double)c * iq.y + (double)sn * u0.x;
-            } else {
-              v = m[px];
-            }
+          const int pc = px >= 0 ? px : 0;
+          double v;
+          if (P.ncomp == 3) {
+            // the interleaved copy: I, Q and U of a pixel share one cache line
+            const double2 iq = P.mapi[2 * pc], u0 = P.mapi[2 * pc + 1];
+            T c, sn;
+            psi_from_raw<T>(P, raw[u], h, c, sn);
+            v = iq.x + (double)c * iq.y + (double)sn * u0.x;
+          } else {
+            v = m[pc];
           }
-          pm[u][h] = v;
+          pm[u][h] = px >= 0 ? v : 0.0;
         }
       }
 #pragma unroll
@@ -434,15 +444,28 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevPlan P, const ItemAC* __re
     }
     __syncthreads();
     lds_transform<T, false, true, kBlock, P2>(lds, M2, B, lgB, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
-    cx<T>* Xc = X + ch.xoff;
-#pragma unroll 2
-    for (int u = 0; u < E; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      const int b = e & (B - 1), k2 = e >> lgB;
-      if (e < ntot && b < nbv) {
-        const int j1 = j10 + b;
-        const cx<T> w = omega2M<T>(P, cl, 2 * j1 * k2);
-        Xc[(int64_t)k2 * M1 + j1] = cmul(lds[e], w);
+    cx<T>* Xc = X + uni64(ch.xoff);
+    // the four-step twiddles omega_2M^(2 j1 k2): the table offsets read once, then the two
+    // table reads of half of a thread's elements issued together, twice (elements outside the
+    // item read the q = 0 entries and store nothing)
+    const cx<T>* tw = twtab<T>(P);
+    const int64_t twhi = uni64(cl.twhi), twlo = uni64(cl.twlo);
+    const int lb = uni(cl.lb);
+#pragma unroll 1
+    for (int h = 0; h < E; h += E / 2) {
+      cx<T> w[E / 2];
+#pragma unroll
+      for (int u = 0; u < E / 2; ++u) {
+        const int e = threadIdx.x + (h + u) * kBlock;
+        const int b = e & (B - 1), k2 = e >> lgB;
+        const int q = (e < ntot && b < nbv) ? 2 * (j10 + b) * k2 : 0;
+        w[u] = cmul(tw[twhi + (q >> lb)], tw[twlo + (q & ((1 << lb) - 1))]);
+      }
+#pragma unroll
+      for (int u = 0; u < E / 2; ++u) {
+        const int e = threadIdx.x + (h + u) * kBlock;
+        const int b = e & (B - 1), k2 = e >> lgB;
+        if (e < ntot && b < nbv) Xc[(int64_t)k2 * M1 + j10 + b] = cmul(lds[e], w[u]);
       }
     }
     __syncthreads();
