@@ -1157,13 +1157,20 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
 #pragma unroll
           for (int u = 0; u < SPW / 2; ++u) {
             const int q = threadIdx.x + (h * (SPW / 2) + u) * kBinBlock;
-            const int g = seg_lookup(si, q);  // lane reads with every lane active
-            v[u] = 0.0;
-            if (q < cnt) {
-              const int64_t j = sstart[g] + (q - (int)spos[g]);
-              v[u] = (double)src[j];
-              // d / tau: scaled here in FP64 staging, where it is used in FP32 staging
-              if (!kScaleAtUse && bsrc == BSRC_DATA_OVER_TAU) v[u] *= P.chunks[schunk[g]].inv_tau;
+            const int gq = seg_lookup(si, q);  // lane reads with every lane active
+            if constexpr (sizeof(T) == 4) {
+              // FP32: positions past the sub-batch read its first sample (a valid address) and
+              // are not stored, so no per-element branch separates the loads (FP64 measured
+              // faster with the branch)
+              const int g = q < cnt ? gq : 0;
+              v[u] = (double)src[sstart[g] + (q < cnt ? q - (int)spos[g] : 0)];
+            } else {
+              v[u] = 0.0;
+              if (q < cnt) {
+                v[u] = (double)src[sstart[gq] + (q - (int)spos[gq])];
+                // d / tau: scaled here in FP64 staging, where it is used in FP32 staging
+                if (bsrc == BSRC_DATA_OVER_TAU) v[u] *= P.chunks[schunk[gq]].inv_tau;
+              }
             }
           }
 #pragma unroll
