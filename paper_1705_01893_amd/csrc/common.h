@@ -116,12 +116,10 @@ struct SubBatch {
 constexpr int kMaxSegs = 512;  // segments per sub-batch (LDS segment table)
 constexpr int kSortAlign = 16;  // alignment (elements) of each sub-batch in the pixel-sorted arrays
 constexpr int kPerLane = 16;    // consecutive pixel-sorted samples one lane accumulates
-struct Segment {
+struct Segment {             // 16 bytes: read by both walks of the binning pass every iteration
   int64_t start;             // first sample
-  int32_t len;
   int32_t pos;               // position of the first sample in the LDS stage
   int32_t chunk;
-  int32_t pad;
 };
 
 struct DevPlan {

@@ -439,16 +439,12 @@ mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out) {
         int nseg = 0;
         for (; i < iend && i - b0 < kSubBatch; ++i) {
           const int64_t j = order[i];
-          if (j == cur_end && j < chunk_end) {
-            sg.back().len += 1;
-          } else {
+          if (!(j == cur_end && j < chunk_end)) {
             if (nseg == kMaxSegs) break;
             Segment g;
             g.start = j;
-            g.len = 1;
             g.pos = (int32_t)(i - b0);
             g.chunk = chunk_of(j);
-            g.pad = 0;
             chunk_end = coff[g.chunk + 1];
             sg.push_back(g);
             ++nseg;
