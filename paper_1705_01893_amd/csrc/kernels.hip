@@ -259,14 +259,14 @@ struct PsiPair {
 };
 
 template <typename T>
-__device__ __forceinline__ void psi_pair_load(const DevPlan& P, int64_t ci, uint4& raw) {
-  if (P.psi_kind == 1) {
+__device__ __forceinline__ void psi_pair_load(const DevPlan& P, int pk, int64_t ci, uint4& raw) {
+  if (pk == 1) {
     const double2 v = ((const double2*)P.psi)[ci];
     raw.x = __double2loint(v.x);
     raw.y = __double2hiint(v.x);
     raw.z = __double2loint(v.y);
     raw.w = __double2hiint(v.y);
-  } else if (P.psi_kind == 2) {
+  } else if (pk == 2) {
     const float2 v = ((const float2*)P.psi)[ci];
     raw.x = __float_as_uint(v.x);
     raw.y = __float_as_uint(v.y);
@@ -276,8 +276,8 @@ __device__ __forceinline__ void psi_pair_load(const DevPlan& P, int64_t ci, uint
 }
 
 template <typename T>
-__device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw, int which, T& c, T& s) {
-  if (P.psi_kind == 1) {
+__device__ __forceinline__ void psi_from_raw(const DevPlan& P, int pk, const uint4& raw, int which, T& c, T& s) {
+  if (pk == 1) {
     const double a = which == 0 ? __hiloint2double(raw.y, raw.x) : __hiloint2double(raw.w, raw.z);
     if (sizeof(T) == 8) {
       double sd, cd;
@@ -290,7 +290,7 @@ __device__ __forceinline__ void psi_from_raw(const DevPlan& P, const uint4& raw,
       c = (T)cf;
       s = (T)sf;
     }
-  } else if (P.psi_kind == 2) {
+  } else if (pk == 2) {
     const float a = __uint_as_float(which == 0 ? raw.x : raw.y);
     if (sizeof(T) == 8) {
       double sd, cd;
@@ -346,15 +346,19 @@ __device__ __forceinline__ int xcd_run_order(int b, int grid) {
   return (b - r) + (r % kXcd) * kXcdRun + r / kXcd;
 }
 
-// NG: the source needs no map gather (d, P m from its buffer, or their difference)
-template <typename T, bool P2, bool NG>
+// NG: the source needs no map gather (d, P m from its buffer, or their difference).  PK: the
+// angles of the gather form, fixed at compile time so that no run-time branch on them separates
+// the loads (0 none: temperature only; 1 float64, 2 float32, 3 uint16 table index; -1: not used)
+template <typename T, bool P2, bool NG, int PK>
 __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    const T* __restrict__ d, const double* __restrict__ m, int src,
                                                    cx<T>* __restrict__ X, const T* __restrict__ pmbuf) {
   constexpr int E = Ept<T>::v;
   // elements whose loads are issued together: all of them without a gather, else 4 (the
   // gather's pixel, angle and map values take registers)
-  constexpr int G = NG ? (kGroupNoGather < E ? kGroupNoGather : E) : 4;
+  constexpr int G = NG ? (kGroupNoGather < E ? kGroupNoGather : E) : (sizeof(T) == 8 && PK > 0 ? 2 : 4);
+  constexpr int pk = PK;
+  constexpr int nc = PK == 0 ? 1 : 3;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   for (int it = xcd_run_order(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
@@ -392,7 +396,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* _
         } else if (!NG && src != SRC_D) {
           const int2 q = ((const int2*)P.pix)[ci];
           pp[u] = ok[u] ? q : make_int2(-1, -1);
-          if (P.ncomp == 3) psi_pair_load<T>(P, ci, raw[u]);
+          if (nc == 3) psi_pair_load<T>(P, pk, ci, raw[u]);
         }
       }
       double pm[G][2];
@@ -404,11 +408,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* _
           const int px = h == 0 ? pp[u].x : pp[u].y;
           const int pc = px >= 0 ? px : 0;
           double v;
-          if (P.ncomp == 3) {
+          if (nc == 3) {
             // the interleaved copy: I, Q and U of a pixel share one cache line
             const double2 iq = P.mapi[2 * pc], u0 = P.mapi[2 * pc + 1];
             T c, sn;
-            psi_from_raw<T>(P, raw[u], h, c, sn);
+            psi_from_raw<T>(P, pk, raw[u], h, c, sn);
             v = iq.x + (double)c * iq.y + (double)sn * u0.x;
           } else {
             v = m[pc];
@@ -1658,12 +1662,20 @@ template <typename T, bool P2>
 static void launch_pass_a_t(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m,
                             int src, void* work, size_t lds, hipStream_t s, const void* pmbuf) {
   const bool ng = src == SRC_D || src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF;
-  if (ng)
-    hipLaunchKernelGGL((k_pass_a<T, P2, true>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, nitems,
-                       (const T*)d, m, src, (cx<T>*)work, (const T*)pmbuf);
-  else
-    hipLaunchKernelGGL((k_pass_a<T, P2, false>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, nitems,
-                       (const T*)d, m, src, (cx<T>*)work, (const T*)pmbuf);
+#define MM_PASS_A(NGV, PKV)                                                                          \
+  hipLaunchKernelGGL((k_pass_a<T, P2, NGV, PKV>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, \
+                     nitems, (const T*)d, m, src, (cx<T>*)work, (const T*)pmbuf)
+  if (ng) {
+    MM_PASS_A(true, -1);
+  } else {
+    switch (P.ncomp == 1 ? 0 : P.psi_kind) {
+      case 0: MM_PASS_A(false, 0); break;
+      case 1: MM_PASS_A(false, 1); break;
+      case 2: MM_PASS_A(false, 2); break;
+      default: MM_PASS_A(false, 3); break;
+    }
+  }
+#undef MM_PASS_A
 }
 
 hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m, int src,
