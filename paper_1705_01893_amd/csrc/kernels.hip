@@ -895,9 +895,9 @@ __device__ __forceinline__ int seg_lookup(const SegIndex& si, int q) {
 }
 
 template <typename T>
-__device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw, double& c, double& s) {
+__device__ __forceinline__ void weights_from_raw(const DevPlan& P, int pk, uint64_t raw, double& c, double& s) {
   T cc, ss;
-  if (P.psi_kind == 1) {
+  if (pk == 1) {
     const double a = __longlong_as_double((long long)raw);
     if (sizeof(T) == 8) {
       double sd, cd;
@@ -910,7 +910,7 @@ __device__ __forceinline__ void weights_from_raw(const DevPlan& P, uint64_t raw,
       cc = (T)cf;
       ss = (T)sf;
     }
-  } else if (P.psi_kind == 2) {
+  } else if (pk == 2) {
     const float a = __uint_as_float((uint32_t)raw);
     if (sizeof(T) == 8) {
       double sd, cd;
@@ -1006,7 +1006,7 @@ struct LaneEntries {
 };
 
 template <bool POL>
-__device__ __forceinline__ void load_lane_entries(const DevPlan& P, int64_t g0, LaneEntries& e) {
+__device__ __forceinline__ void load_lane_entries(const DevPlan& P, int pk, int64_t g0, LaneEntries& e) {
   const uint4* lpp = reinterpret_cast<const uint4*>(P.lp + g0);
   const uint4* pmp = reinterpret_cast<const uint4*>(P.perm + g0);
   e.lpw[0] = lpp[0];
@@ -1014,7 +1014,7 @@ __device__ __forceinline__ void load_lane_entries(const DevPlan& P, int64_t g0, 
   e.pmw[0] = pmp[0];
   e.pmw[1] = pmp[1];
   if (POL) {
-    const int esz = P.psi_kind == 1 ? 8 : (P.psi_kind == 2 ? 4 : 2);
+    const int esz = pk == 1 ? 8 : (pk == 2 ? 4 : 2);
     const int nw = esz;  // uint4 words holding kPerLane angles
     const uint4* pp = reinterpret_cast<const uint4*>((const char*)P.psi_sorted + g0 * esz);
 #pragma unroll
@@ -1028,10 +1028,10 @@ __device__ __forceinline__ int entry_u16(const uint4* w, int i) {
   return (int)((x >> (16 * (i & 1))) & 0xffffu);
 }
 
-__device__ __forceinline__ uint64_t entry_psi_raw(const DevPlan& P, const LaneEntries& e, int i) {
+__device__ __forceinline__ uint64_t entry_psi_raw(int pk, const LaneEntries& e, int i) {
   const uint32_t* pw = (const uint32_t*)e.psw;
-  if (P.psi_kind == 1) return ((uint64_t)pw[2 * i + 1] << 32) | pw[2 * i];
-  if (P.psi_kind == 2) return pw[i];
+  if (pk == 1) return ((uint64_t)pw[2 * i + 1] << 32) | pw[2 * i];
+  if (pk == 2) return pw[i];
   return (pw[i / 2] >> (16 * (i & 1))) & 0xffffu;
 }
 
@@ -1039,7 +1039,7 @@ __device__ __forceinline__ uint64_t entry_psi_raw(const DevPlan& P, const LaneEn
 // mt: the tile's map values in LDS, [local pixel][NC].  For each sub-batch the values are formed
 // in pixel-sorted order, scattered to their staging positions in LDS and written out along the
 // sub-batch's time-contiguous segments (coalesced within each segment).
-template <typename T, int NC>
+template <typename T, int NC, int PK>
 __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt, const BinLds<T>& L, int& sbn,
                              T* __restrict__ pm_out) {
   constexpr int SPW = kSubBatch / kBinBlock;
@@ -1055,7 +1055,7 @@ __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt,
       const int kl = k0 + kPerLane * lane;
       if (kl < k1) {
         LaneEntries en;
-        load_lane_entries<NC == 3>(P, S.sorted_begin + kl, en);
+        load_lane_entries<NC == 3>(P, PK >= 0 ? PK : P.psi_kind, S.sorted_begin + kl, en);
 #pragma unroll
         for (int i = 0; i < kPerLane; ++i) {
           if (kl + i < k1) {
@@ -1063,7 +1063,8 @@ __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt,
             double v = mt[l * NC];
             if (NC == 3) {
               double c, sn;
-              weights_from_raw<T>(P, entry_psi_raw(P, en, i), c, sn);
+              const int pk = PK >= 0 ? PK : P.psi_kind;
+              weights_from_raw<T>(P, pk, entry_psi_raw(pk, en, i), c, sn);
               v += c * mt[l * 3 + 1] + sn * mt[l * 3 + 2];
             }
             L.stage[entry_u16(en.pmw, i)] = (T)v;
@@ -1103,12 +1104,14 @@ __global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* 
       for (int q = 0; q < NC; ++q) mt[l * NC + q] = m[q * P.npix + p];
     }
     __syncthreads();
-    tile_project<T, NC>(P, tl, mt, L, sbn, pm_out);
+    tile_project<T, NC, -1>(P, tl, mt, L, sbn, pm_out);
   }
 }
 
 // FP32 iteration binning: at most 128 VGPRs, so that four workgroups (36 KB of LDS each) share a CU
-template <typename T, int NV>
+// PK: the angle kind fixed at compile time (1 float64, 2 float32, 3 uint16 table index), or -1
+// (read from the plan)
+template <typename T, int NV, int PK>
 __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) void k_bin(DevPlan P, int bsrc, const T* __restrict__ src, int epi,
                                                    const double* __restrict__ m_in, double* __restrict__ out,
                                                    double* __restrict__ w_out, int32_t* __restrict__ hits_out,
@@ -1118,6 +1121,7 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
   constexpr int SPW = kSubBatch / kBinBlock;  // staged samples per thread
   // the stage holds TOD values in the TOD precision: an FP32 stage cannot hold d / tau exactly
   constexpr bool kScaleAtUse = sizeof(T) < sizeof(double);
+  const int pk = PK >= 0 ? PK : P.psi_kind;
   extern __shared__ double smem_d[];
   const BinLds<T> L = bin_lds<NV, T>(smem_d, PLAN, P.max_tile_pix);
   T* stage = L.stage;
@@ -1145,7 +1149,7 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
       const int kl = k0 + kPerLane * lane;
       const bool active = kl < k1;
       LaneEntries en = {};
-      if (active) load_lane_entries<POL>(P, S.sorted_begin + kl, en);  // kl: a multiple of kSortAlign
+      if (active) load_lane_entries<POL>(P, pk, S.sorted_begin + kl, en);  // kl: a multiple of kSortAlign
       load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), PLAN || bsrc == BSRC_DATA_OVER_TAU,
                     bsrc == BSRC_WORK);
       if (lane == 0) clp[wave] = -1;
@@ -1207,7 +1211,7 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
               if (kScaleAtUse && bsrc == BSRC_DATA_OVER_TAU) y *= P.chunks[schunk[gpr]].inv_tau;
             }
             double c = 0.0, sn = 0.0;
-            if (POL) weights_from_raw<T>(P, entry_psi_raw(P, en, i), c, sn);
+            if (POL) weights_from_raw<T>(P, pk, entry_psi_raw(pk, en, i), c, sn);
             double v[NV];
             contrib<T, NV>(P, y, c, sn, v);
             if (lp != cur_lp) {
@@ -1349,7 +1353,7 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
     }
     __syncthreads();
     if (!PLAN && pm_out && (epi == EPI_UPDATE || epi == EPI_REPLACE))
-      tile_project<T, (NV == 3 ? 3 : 1)>(P, tl, acc, L, sbn, pm_out);
+      tile_project<T, (NV == 3 ? 3 : 1), PK>(P, tl, acc, L, sbn, pm_out);
   }
 }
 
@@ -1748,8 +1752,20 @@ static hipError_t launch_bin_t(const DevPlan& P, int bsrc, const void* src, int 
                                double* w_out, int32_t* hits_out, uint8_t* sol_out, hipStream_t s, void* pm_out) {
   constexpr bool plan = NV == 2 || NV == 7;
   const size_t lds = bin_lds_bytes<NV, T>(plan, P.max_tile_pix, plan || bsrc == BSRC_DATA_OVER_TAU);
-  hipLaunchKernelGGL((k_bin<T, NV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, bsrc,
-                     (const T*)src, epi, m_in, out, w_out, hits_out, sol_out, (T*)pm_out);
+#define MM_BIN(PKV)                                                                                   \
+  hipLaunchKernelGGL((k_bin<T, NV, PKV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, bsrc, \
+                     (const T*)src, epi, m_in, out, w_out, hits_out, sol_out, (T*)pm_out)
+  // the I/Q/U iteration kernels take the angle kind at compile time
+  if constexpr (NV != 3) {
+    MM_BIN(-1);
+  } else {
+    switch (P.psi_kind) {
+      case 1: MM_BIN(1); break;
+      case 2: MM_BIN(2); break;
+      default: MM_BIN(3); break;
+    }
+  }
+#undef MM_BIN
   return hipGetLastError();
 }
 
