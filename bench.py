@@ -19,6 +19,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -93,6 +94,11 @@ def load_traffic(workload: str, khash: str):
 PASS_KERNELS = ["k_pass_a<", "k_pass_b<", "k_pass_c<", "k_bin<", "k_project<"]
 
 
+def _is_plan_bin(name: str) -> bool:
+    """The plan's precompute binning kernels (k_bin with 2 or 7 accumulated values)."""
+    return re.search(r"k_bin<[^,<>]+, (2|7)[,>]", name) is not None
+
+
 def _counter_rows(run_dir: str):
     import csv
     import glob
@@ -115,7 +121,7 @@ def write_traffic(args, fetch_dir: str, write_dir: str) -> None:
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = [r for r in _counter_rows(d) if r["Counter_Name"] == counter]
         start = max(int(r["Dispatch_Id"]) for r in rows
-                    if "k_bin<" in r["Kernel_Name"] and (", 7>" in r["Kernel_Name"] or ", 2>" in r["Kernel_Name"]))
+                    if _is_plan_bin(r["Kernel_Name"]))
         vals = {}
         for r in rows:
             if int(r["Dispatch_Id"]) <= start:
@@ -158,7 +164,7 @@ def summarize_counters(run_dirs: list) -> None:
     for d in run_dirs:
         rows = _counter_rows(d)
         start = max(int(r["Dispatch_Id"]) for r in rows
-                    if "k_bin<" in r["Kernel_Name"] and (", 7>" in r["Kernel_Name"] or ", 2>" in r["Kernel_Name"]))
+                    if _is_plan_bin(r["Kernel_Name"]))
         acc, disp = {}, {}
         for r in rows:
             if int(r["Dispatch_Id"]) <= start or "mm::" not in r["Kernel_Name"]:
@@ -193,7 +199,7 @@ def summarize_trace(trace_dir: str) -> None:
     with open(files[0]) as fh:
         rows = list(csv.DictReader(fh))
     start = max(int(r["Dispatch_Id"]) for r in rows
-                if "k_bin<" in r["Kernel_Name"] and (", 7>" in r["Kernel_Name"] or ", 2>" in r["Kernel_Name"]))
+                if _is_plan_bin(r["Kernel_Name"]))
     acc = {}
     for r in rows:
         if int(r["Dispatch_Id"]) <= start or "mm::" not in r["Kernel_Name"]:
