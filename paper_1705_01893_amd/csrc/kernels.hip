@@ -1158,20 +1158,21 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
       // the other bitmap was last read before the previous sub-batch's final barrier
       if (threadIdx.x < kSubBatch / 64) L.smask[((sbn + 1) & 1) * (kSubBatch / 64) + threadIdx.x] = 0ull;
       if (!PLAN) {
-        // two rounds of SPW / 2 loads in flight per thread
+        // FP32 I/Q/U: one round of SPW loads in flight per thread; otherwise two rounds of SPW / 2
+        constexpr int kRounds = (sizeof(T) == 4 && NV == 3) ? 1 : 2, kPer = SPW / kRounds;
 #pragma unroll 1
-        for (int h = 0; h < 2; ++h) {
-          double v[SPW / 2];
+        for (int h = 0; h < kRounds; ++h) {
+          T v[kPer];
 #pragma unroll
-          for (int u = 0; u < SPW / 2; ++u) {
-            const int q = threadIdx.x + (h * (SPW / 2) + u) * kBinBlock;
+          for (int u = 0; u < kPer; ++u) {
+            const int q = threadIdx.x + (h * kPer + u) * kBinBlock;
             const int gq = seg_lookup(si, q);  // lane reads with every lane active
             if constexpr (sizeof(T) == 4) {
               // FP32: positions past the sub-batch read its first sample (a valid address) and
               // are not stored, so no per-element branch separates the loads (FP64 measured
               // faster with the branch)
               const int g = q < cnt ? gq : 0;
-              v[u] = (double)src[sstart[g] + (q < cnt ? q - (int)spos[g] : 0)];
+              v[u] = src[sstart[g] + (q < cnt ? q - (int)spos[g] : 0)];
             } else {
               v[u] = 0.0;
               if (q < cnt) {
@@ -1182,9 +1183,9 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
             }
           }
 #pragma unroll
-          for (int u = 0; u < SPW / 2; ++u) {
-            const int q = threadIdx.x + (h * (SPW / 2) + u) * kBinBlock;
-            if (q < cnt) stage[q] = (T)v[u];
+          for (int u = 0; u < kPer; ++u) {
+            const int q = threadIdx.x + (h * kPer + u) * kBinBlock;
+            if (q < cnt) stage[q] = v[u];
           }
         }
         __syncthreads();
