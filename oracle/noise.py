@@ -6,8 +6,8 @@ benchmark's CPU-baseline leg.
 Readings of the paper used here (each also listed with the design notes):
 
 * The noise covariance of one detector chunk is taken to be exactly circulant,
-  i.e. diagonal in the discrete Fourier basis of that chunk (Section 2 says it
-  is approximately diagonal in the frequency domain).  Its eigenvalue at rfft
+  i.e. diagonal in the discrete Fourier basis of that chunk (Section 2 treats
+  stationary noise as nearly so).  Its eigenvalue at rfft
   bin k is N_k, in per-sample-variance units: white noise of per-sample
   standard deviation sigma has N_k = sigma^2 at every k.
 * The power law is the one of the simulation section (Section 2.3),

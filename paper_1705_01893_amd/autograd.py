@@ -29,9 +29,9 @@ import torch
 from . import mm
 
 
-def _noise_changed(plan, sigma, fknee, alpha) -> bool:
+def _noise_changed(plan, sigma, fknee, alpha, tau) -> bool:
     cur = getattr(plan, "_noise", None)
-    new = (tuple(sigma), tuple(fknee), tuple(alpha))
+    new = (tuple(sigma), tuple(fknee), tuple(alpha), None if tau is None else tuple(tau))
     if cur != new:
         plan._noise = new
         return True
@@ -42,17 +42,20 @@ class MessengerSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, d: torch.Tensor, sigma: torch.Tensor, fknee: torch.Tensor, alpha: torch.Tensor,
                 plan: mm.Plan, lambdas: Sequence[float], iters: Sequence[int], adjoint: str = "cg",
-                adjoint_iters: int = 500, adjoint_rtol: float = 1e-10):
+                adjoint_iters: int = 500, adjoint_rtol: float = 1e-10, tau=None):
         s = sigma.detach().double().cpu().numpy()
         f = fknee.detach().double().cpu().numpy()
         a = alpha.detach().double().cpu().numpy()
-        if _noise_changed(plan, s, f, a):
-            mm.mm_plan_set_noise(plan, s, f, a)
+        # the messenger variance: the given one, else whatever the plan was last given (its
+        # default sigma^2 when it never was)
+        t = np.asarray(tau, dtype=np.float64).reshape(-1) if tau is not None else plan.tau
+        if _noise_changed(plan, s, f, a, t):
+            mm.mm_plan_set_noise(plan, s, f, a, t)
         m = torch.zeros(plan.map_shape, dtype=torch.float64, device=d.device)
         dd = d.detach().to(plan.tod_dtype).contiguous()
         mm.mm_solve(plan, dd, lambdas, iters, m)
         ctx.plan = plan
-        ctx.noise = (s, f, a)
+        ctx.noise = (s, f, a, t)
         ctx.sched = (list(lambdas), list(iters))
         ctx.adjoint = (adjoint, adjoint_iters, adjoint_rtol)
         ctx.d_dtype = d.dtype
@@ -86,10 +89,12 @@ class MessengerSolve(torch.autograd.Function):
             mm.mm_noise_grad(plan, dd, m, z, gr)
             gr = gr.to(device=ctx.theta[0], dtype=ctx.theta[1])
             grad_s, grad_f, grad_a = gr[:, 0].contiguous(), gr[:, 1].contiguous(), gr[:, 2].contiguous()
-        return grad_d, grad_s, grad_f, grad_a, None, None, None, None, None, None
+        return grad_d, grad_s, grad_f, grad_a, None, None, None, None, None, None, None
 
 
 def messenger_solve(d, sigma, fknee, alpha, plan, lambdas, iters, adjoint: str = "cg", adjoint_iters: int = 500,
-                    adjoint_rtol: float = 1e-10):
-    """Differentiable solved map (see MessengerSolve)."""
-    return MessengerSolve.apply(d, sigma, fknee, alpha, plan, lambdas, iters, adjoint, adjoint_iters, adjoint_rtol)
+                    adjoint_rtol: float = 1e-10, tau=None):
+    """Differentiable solved map (see MessengerSolve).  ``tau`` (per chunk, not differentiated)
+    sets the messenger variance; by default the plan keeps the one it was built or last set with."""
+    return MessengerSolve.apply(d, sigma, fknee, alpha, plan, lambdas, iters, adjoint, adjoint_iters, adjoint_rtol,
+                                tau)

@@ -142,6 +142,8 @@ class Plan:
         self.handle = ctypes.c_void_p(handle)
         self._keep = (desc_arrays, tensors)
         self.ncomp, self.npix, self.nchunk, self.nsamp, self.precision = ncomp, npix, nchunk, nsamp, precision
+        # messenger variance per chunk as last given to the library (None: its default sigma^2)
+        self.tau = desc_arrays.get("tau")
 
     @property
     def tod_dtype(self):
@@ -317,6 +319,7 @@ def mm_plan_set_noise(plan: Plan, sigma, fknee, alpha, tau=None, stream=None) ->
     _check(lib().mm_plan_set_noise(plan.handle, *[a.ctypes.data_as(P) for a in arrs],
                                    t.ctypes.data_as(P) if t is not None else None, _stream(stream)),
            "mm_plan_set_noise")
+    plan.tau = t
 
 
 def mm_tod_apply(plan: Plan, which: int, x: torch.Tensor, out: torch.Tensor, lam: float = 1.0, stream=None) -> None:

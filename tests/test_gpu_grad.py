@@ -211,3 +211,31 @@ def test_mixed_precision_gradient(dev):
     ref = noise_param_grad(S, t.d.astype(np.float64), m_gls, z, t.fsample, t.sigma, t.fknee, t.alpha)
     got = np.stack([sig.grad.numpy(), fk.grad.numpy(), al.grad.numpy()], axis=1)
     np.testing.assert_allclose(got, ref, rtol=1e-3, atol=1e-4 * np.abs(ref).max())
+
+
+def test_forward_keeps_plan_tau(dev):
+    """A plan built with a messenger variance below sigma^2 keeps it through the differentiable
+    forward (the split N = N-bar + T of Section 2.1 changes the cooled iterates): the forward map
+    equals the oracle's finite schedule with that tau, and a later plain solve still uses it."""
+    say("[forward tau]")
+    t = tiny_problem(44, ncomp=3, lengths=(128, 256), nx=8)
+    tau = 0.5 * t.sigma ** 2
+    psi = torch.from_numpy(t.psi).to(dev)
+    plan = mm.mm_plan(ncomp=3, npix=t.npix, nx=t.nx, chunk_off=t.chunk_off, fsample=t.fsample, sigma=t.sigma,
+                      fknee=t.fknee, alpha=t.alpha, pix=torch.from_numpy(t.pix).to(dev), psi=psi, tau=tau)
+    S = make_setup(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, t.npix, 3, tau=tau)
+    lams, its = [20.0, 4.0, 1.0], [2, 2, 2]
+    seq = [math.inf] + [lv for lv, k in zip(lams, its) for _ in range(k)]
+    m_ref = np.zeros((3, t.npix))
+    for lam in seq:
+        m_ref = messenger_step(S, t.d, m_ref, lam)
+    d = torch.from_numpy(t.d).to(dev)
+    th = [torch.from_numpy(np.asarray(v, dtype=np.float64)).to(dev) for v in (t.sigma, t.fknee, t.alpha)]
+    m = messenger_solve(d, *th, plan, lams, its)
+    torch.cuda.synchronize()
+    assert np.linalg.norm(m.cpu().numpy() - m_ref) / np.linalg.norm(m_ref) < 1e-10
+    m2 = torch.zeros_like(m)
+    mm.mm_solve(plan, d, lams, its, m2)
+    torch.cuda.synchronize()
+    assert np.linalg.norm(m2.cpu().numpy() - m_ref) / np.linalg.norm(m_ref) < 1e-10
+    plan.close()

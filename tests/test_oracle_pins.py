@@ -67,6 +67,24 @@ def test_cooling_schedule_levels():
     np.testing.assert_allclose(ratios, 10 ** (4 / 9), rtol=1e-13)
 
 
+@pytest.mark.parametrize("tau0, expect", [(None, 3.0), (0.5, 4.0)])
+def test_lambda_max_rule_hand_values(tau0, expect):
+    """Section 3.1: the top level puts lambda tau at the largest noise power of any chunk.
+
+    Two chunks of n = 8 samples at f_s = 8 Hz (bins f_k = k Hz, k = 0..4, f_0 clamped to f_1):
+      chunk 0: sigma = 1, f_knee = 1, alpha = -2: N = 1 + f^-2 -> 2, 2, 1.25, 1.111, 1.0625;
+               largest 2 at the low end, tau = sigma^2 = 1 (or 0.5) -> ratio 2 (or 4);
+      chunk 1: sigma = 2, f_knee = 2, alpha = +1: N = 4 (1 + f/2) -> 6, 6, 8, 10, 12;
+               largest 12 at Nyquist, tau = 4 -> ratio 3.
+    The rule takes the larger ratio: 3 (or 4 when chunk 0 has tau = 0.5).  Taking the smaller,
+    dividing by tau twice or reading only one end of the spectrum all give another value."""
+    off = np.array([0, 8, 16])
+    tau = None if tau0 is None else np.array([tau0, 4.0])
+    S = make_setup(off, np.array([8.0, 8.0]), np.array([1.0, 2.0]), np.array([1.0, 2.0]),
+                   np.array([-2.0, 1.0]), np.zeros(16, np.int32), None, 1, 1, tau=tau)
+    assert lambda_max_rule(S) == pytest.approx(expect, rel=1e-15)
+
+
 # ------------------------------------------------------------------------------------------------
 # closed forms for the noise operator and chi^2
 
