@@ -417,7 +417,7 @@ def main():
                       tune=mm.MM_TUNE_MEASURE if args.tune == "measure" else mm.MM_TUNE_STATIC,
                       binning=mm.MM_BIN_ATOMIC if args.binning == "atomic" else mm.MM_BIN_SORTED)
     t_plan = time.perf_counter() - t0
-    log(f"plan built in {t_plan:.1f} s ({mm.mm_plan_workspace_bytes(plan) / 2**30:.2f} GiB of device tables)")
+    log(f"plan built in {t_plan:.1f} s ({plan.workspace.numel() / 2**30:.2f} GiB of workspace)")
     ns = prob.nsamp_total
     m_a = torch.zeros((prob.ncomp, prob.npix), dtype=torch.float64, device=dev)
     m_b = torch.zeros_like(m_a)

@@ -31,12 +31,14 @@
  *  Memory       Arguments documented "device" are device pointers on the
  *               current HIP device; "host" are host pointers.  All are
  *               borrowed: the library never frees or keeps them past the
- *               call, except pix / psi, which a plan reads at every iteration
- *               and which must stay valid and unchanged until mm_plan_destroy.
- *               A plan allocates and owns its own device tables
- *               (mm_plan_workspace_bytes reports how much).
+ *               call, except pix / psi and the workspace, which a plan reads
+ *               at every iteration and which must stay valid (pix / psi also
+ *               unchanged) until mm_plan_destroy.  A plan allocates no device
+ *               memory: every table and work buffer lies in the caller's
+ *               workspace, whose size mm_plan_workspace_bytes reports.
  *  Streams      Every call is ordered on the given stream and returns without
- *               waiting for it, except mm_plan (waits for its precompute),
+ *               waiting for it, except mm_plan_workspace_bytes and
+ *               mm_plan (they wait for their passes over the pointing),
  *               mm_chi2 (returns a host scalar) and mm_cg_solve when rtol > 0.
  *               Pass 0 for the default stream.  A plan is not thread-safe; use
  *               it from one host thread and one stream at a time.
@@ -117,6 +119,9 @@ enum { MM_BIN_SORTED = 0, MM_BIN_ATOMIC = 1 };                            /* bin
  *               map with FP64 atomics in time order (a measured alternative: the
  *               rounding varies from run to run).  The plan precompute (hits, W)
  *               always uses the sorted reduction.
+ *  with_adjoint 1 reserves a second TOD-sized buffer in the workspace for
+ *               mm_noise_grad and for mm_solve with a map right-hand side; 0
+ *               leaves it out (those calls then return MM_E_ARG).
  */
 typedef struct {
   int32_t ncomp;
@@ -138,6 +143,7 @@ typedef struct {
   int64_t psi_table_len;
   int32_t tune;
   int32_t binning;
+  int32_t with_adjoint;
 } mm_plan_desc;
 
 /* Cooling schedule (Section 3.1): optionally one lambda = inf step, then
@@ -150,19 +156,40 @@ typedef struct {
 } mm_schedule;
 
 /*
- * Build a plan: validates the descriptor, sorts the pointing by pixel tile for
- * deterministic binning (host), selects transform splits, and runs the
- * precompute kernels on `stream`: hit counts, the weight blocks
+ * Device bytes of the workspace a plan of this description needs (the
+ * problem statement of Section 2: chunk table, pointing, noise law).  The
+ * size depends on the pointing through the pixel-tile lists of the
+ * deterministic binning, so the call validates the description and walks the
+ * device pointing on `stream` (two passes over pix, one over psi; it waits for
+ * them): pixel indices must be < npix, angles finite with |psi| < 1e5 (or
+ * table indices < psi_table_len), MM_E_ARG otherwise.  It allocates a small
+ * device buffer for its counters and the chunk table (freed before it
+ * returns).  The result is the same for every call with the same description
+ * and pointing, on any stream.
+ */
+mm_status mm_plan_workspace_bytes(const mm_plan_desc* desc, mm_stream_t stream, size_t* bytes);
+
+/*
+ * Build a plan in the caller's workspace (device, 256-byte aligned,
+ * workspace_bytes >= what mm_plan_workspace_bytes reports, MM_E_NOMEM
+ * otherwise): validates the descriptor, sorts the pointing by pixel tile for
+ * deterministic binning (on the device), selects transform splits (timing
+ * candidates in the workspace with MM_TUNE_MEASURE), and runs the precompute
+ * kernels on `stream`: hit counts, the weight blocks
  * W_p = sum_{j at p} a_j a_j^T / tau_c (P^T T^-1 P of Section 2.1) and their
  * inverses.  A pixel is solvable when it has hits and, for 3x3 blocks,
  * det(W_p) / (W_p,00 W_p,11 W_p,22) >= 1e-8 (its angles separate Q from U);
  * unsolvable pixels are held at 0.
- * Waits for the stream.  MM_E_SINGULAR if no pixel is solvable.
+ * Waits for the stream.  MM_E_SINGULAR if no pixel is solvable.  The workspace
+ * belongs to the plan until mm_plan_destroy, which waits for the device.
  */
-mm_status mm_plan(const mm_plan_desc* desc, mm_stream_t stream, mm_plan_t* out);
+mm_status mm_plan(const mm_plan_desc* desc, void* workspace, size_t workspace_bytes, mm_stream_t stream,
+                  mm_plan_t* out);
 mm_status mm_plan_destroy(mm_plan_t plan);
-/* Device bytes held by the plan (tables, sorted pointing, one TOD-sized work buffer). */
-mm_status mm_plan_workspace_bytes(mm_plan_t plan, size_t* bytes);
+/* Binning structures of the plan (host out[7]): pixel tiles, tile width and
+ * height (pixels), sub-batches, time-contiguous segments, pixel-sorted entries
+ * (padded), and the workspace bytes in use. */
+mm_status mm_plan_binning_stats(mm_plan_t plan, int64_t* out);
 /* Copy the bit-exact hit counts (int32 [npix]) into hits_dev (device). */
 mm_status mm_plan_hits(mm_plan_t plan, int32_t* hits_dev, mm_stream_t stream);
 /* Copy the solvable mask (uint8 [npix]) into mask_dev (device). */
@@ -196,12 +223,16 @@ mm_status mm_messenger_iter(mm_plan_t plan, const void* d, double lambda, const 
  * the same schedule as the previous one replays that graph without capture.
  * The plan keeps only the latest graph: a call that captures a new one first
  * waits on the host until the previous graph's last launch has completed, then
- * destroys it.  m0: device start map or NULL for zero.  m_out: device result.  chi2_hist_dev: device array of
+ * destroys it.  Exactly one of d (device TOD) and rhs_map (device map g) is
+ * given.  With rhs_map the solve runs on the lifted data N T^-1 P W^-1 g (see
+ * mm_lift_rhs), so it converges to (P^T N^-1 P)^-1 g: the adjoint solve of a
+ * map gradient, with the cooling behaviour of real data (needs with_adjoint).
+ * m0: device start map or NULL for zero.  m_out: device result.  chi2_hist_dev: device array of
  * (first_inf + sum(iters) + 1) doubles or NULL; entry i is chi^2(m_i) of the
  * map entering iteration i, the last entry chi^2 of the final map.
  */
-mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, const double* m0,
-                   double* m_out, double* chi2_hist_dev, mm_stream_t stream);
+mm_status mm_solve(mm_plan_t plan, const void* d, const double* rhs_map, const mm_schedule* sched,
+                   const double* m0, double* m_out, double* chi2_hist_dev, mm_stream_t stream);
 
 /*
  * Geometric cooling levels (Section 3.1): lambda_l = lambda_max^((nlevel-1-l)/(nlevel-1)),
@@ -219,7 +250,8 @@ mm_status mm_cooling_levels(mm_plan_t plan, int32_t nlevel, double lambda_max, d
  * the host every 10 iterations, which waits for the stream) if rtol > 0.
  * chi2_hist_dev (device, maxiter+1 doubles, or NULL) gets chi^2 of each iterate
  * from the recursion chi^2(x) = d^T N^-1 d - x^T b - x^T r (needs d).
- * rz_hist_dev (device, maxiter+1 doubles, or NULL) gets r^T W^-1 r.
+ * rz_hist_dev (device, maxiter+1 doubles, or NULL) gets r^T W^-1 r; without it
+ * the plan keeps the history itself, which limits maxiter to 16383.
  * iters_done (host, or NULL) gets the number of iterations run.
  */
 mm_status mm_cg_solve(mm_plan_t plan, const void* d, const double* rhs_map, int32_t maxiter,
@@ -279,8 +311,8 @@ mm_status mm_tod_apply(mm_plan_t plan, int32_t which, double lambda, const doubl
  * with r = d - P m, Zhat = rfft of P z and z = A^-1 (dL/dm) the adjoint map
  * (obtain it with mm_lift_rhs + mm_solve, or mm_cg_solve with rhs_map).
  * omega_k is the multiplicity of rfft bin k.  d: device TOD; m, z: device
- * maps; grad_dev: device [nchunk][3] doubles.  Needs a second TOD-sized work
- * buffer (allocated on first use).  MM_E_LEN when two rows of two residuals
+ * maps; grad_dev: device [nchunk][3] doubles.  Needs the plan's second
+ * TOD-sized buffer (with_adjoint).  MM_E_LEN when two rows of two residuals
  * do not fit one workgroup's LDS.
  */
 mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const double* z, double* grad_dev,

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmm.so")
-SOURCES = ["kernels.hip", "plan.cpp", "tune.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "sort.hip", "plan.cpp", "tune.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -149,6 +149,15 @@ mm_status dot(mm_plan_s* pl, const double* a, const double* b, double* out, hipS
   return MM_OK;
 }
 
+// out = N T^-1 P W^-1 g in time order (the lifted right-hand side of an adjoint solve)
+mm_status lift(mm_plan_s* pl, const double* g, void* out, hipStream_t s) {
+  double* u = pl->d_map[5];
+  MM_TRY_HIP(launch_winv_apply(pl->dp, g, u, s));
+  MM_TRY(sweep_filter(pl, nullptr, u, SRC_PM, B_FILTER, GAIN_LIFT, 1.0, 1.0, s));
+  MM_TRY_HIP(launch_unshift(pl->dp, pl->d_work, out, s));
+  return MM_OK;
+}
+
 bool valid_lambda(double lam) { return std::isinf(lam) ? lam > 0 : (lam >= 1.0 && std::isfinite(lam)); }
 
 }  // namespace
@@ -201,9 +210,15 @@ mm_status mm_get_timing(mm_plan_t plan, double* ms, int64_t* launches) {
   return st;
 }
 
-mm_status mm_plan(const mm_plan_desc* desc, mm_stream_t stream, mm_plan_t* out) {
+mm_status mm_plan_workspace_bytes(const mm_plan_desc* desc, mm_stream_t stream, size_t* bytes) {
   g_last_error.clear();
-  return build_plan(desc, S(stream), out);
+  return workspace_query(desc, S(stream), nullptr, 0, bytes);
+}
+
+mm_status mm_plan(const mm_plan_desc* desc, void* workspace, size_t workspace_bytes, mm_stream_t stream,
+                  mm_plan_t* out) {
+  g_last_error.clear();
+  return build_plan(desc, workspace, workspace_bytes, S(stream), out);
 }
 
 mm_status mm_plan_destroy(mm_plan_t plan) {
@@ -212,9 +227,15 @@ mm_status mm_plan_destroy(mm_plan_t plan) {
   return MM_OK;
 }
 
-mm_status mm_plan_workspace_bytes(mm_plan_t plan, size_t* bytes) {
-  if (!plan || !bytes) return fail(MM_E_ARG, "null argument");
-  *bytes = plan->bytes;
+mm_status mm_plan_binning_stats(mm_plan_t plan, int64_t* out) {
+  if (!plan || !out) return fail(MM_E_ARG, "null argument");
+  out[0] = plan->ntiles;
+  out[1] = plan->tile_w;
+  out[2] = plan->tile_h;
+  out[3] = plan->nsbs;
+  out[4] = plan->nsegs;
+  out[5] = plan->nsorted;
+  out[6] = (int64_t)plan->ws_used;
   return MM_OK;
 }
 
@@ -285,9 +306,11 @@ mm_status mm_cooling_levels(mm_plan_t plan, int32_t nlevel, double lambda_max, d
   return MM_OK;
 }
 
-mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, const double* m0, double* m_out,
-                   double* chi2_hist_dev, mm_stream_t stream) {
-  if (!plan || !d || !sched || !m_out) return fail(MM_E_ARG, "null argument");
+mm_status mm_solve(mm_plan_t plan, const void* d, const double* rhs_map, const mm_schedule* sched, const double* m0,
+                   double* m_out, double* chi2_hist_dev, mm_stream_t stream) {
+  if (!plan || !sched || !m_out) return fail(MM_E_ARG, "null argument");
+  if ((d == nullptr) == (rhs_map == nullptr)) return fail(MM_E_ARG, "give exactly one of d and rhs_map");
+  if (rhs_map && !plan->d_work2) return fail(MM_E_ARG, "a map right-hand side needs a plan built with_adjoint");
   if (sched->nlevel < 0 || (sched->nlevel > 0 && (!sched->lambda || !sched->iters)))
     return fail(MM_E_ARG, "invalid schedule");
   std::vector<double> lams;
@@ -297,7 +320,10 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, cons
     for (int i = 0; i < sched->iters[l]; ++i) lams.push_back(sched->lambda[l]);
   }
   const int64_t n = mapn(plan);
+  // with a map right-hand side g the data are the lifted TOD N T^-1 P W^-1 g (second TOD buffer)
+  const void* dd = rhs_map ? plan->d_work2 : d;
   auto body = [&](hipStream_t cs) -> mm_status {
+    if (rhs_map) MM_TRY(lift(plan, rhs_map, plan->d_work2, cs));
     // start map into m_out (fill kernel, no memset nodes in the graph)
     if (m0) {
       if (m0 != m_out) MM_TRY_HIP(launch_copy(m_out, m0, n, cs));
@@ -307,8 +333,8 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, cons
     // iterate in place: every pass reads the map before the binning epilogue rewrites it
     const size_t nit = lams.size();
     for (size_t i = 0; i < nit; ++i)
-      MM_TRY(iterate(plan, d, lams[i], m_out, m_out, chi2_hist_dev ? chi2_hist_dev + i : nullptr, cs, i > 0));
-    if (chi2_hist_dev) MM_TRY(chi2_device(plan, d, m_out, 1.0, chi2_hist_dev + nit, nullptr, cs, nit > 0));
+      MM_TRY(iterate(plan, dd, lams[i], m_out, m_out, chi2_hist_dev ? chi2_hist_dev + i : nullptr, cs, i > 0));
+    if (chi2_hist_dev) MM_TRY(chi2_device(plan, dd, m_out, 1.0, chi2_hist_dev + nit, nullptr, cs, nit > 0));
     return MM_OK;
   };
   // per-pass timing records events between the passes: run on the caller's stream, uncaptured
@@ -316,6 +342,7 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const mm_schedule* sched, cons
   // replay the previous graph when the call is identical (same buffers, same schedule)
   std::vector<double> key;
   key.push_back((double)(uintptr_t)d);
+  key.push_back((double)(uintptr_t)rhs_map);
   key.push_back((double)(uintptr_t)m0);
   key.push_back((double)(uintptr_t)m_out);
   key.push_back((double)(uintptr_t)chi2_hist_dev);
@@ -385,12 +412,7 @@ mm_status mm_apply(mm_plan_t plan, int32_t which, double lambda, const double* x
 
 mm_status mm_lift_rhs(mm_plan_t plan, const double* g, void* out, mm_stream_t stream) {
   if (!plan || !g || !out) return fail(MM_E_ARG, "null argument");
-  hipStream_t s = S(stream);
-  double* u = plan->d_map[5];
-  MM_TRY_HIP(launch_winv_apply(plan->dp, g, u, s));
-  MM_TRY(sweep_filter(plan, nullptr, u, SRC_PM, B_FILTER, GAIN_LIFT, 1.0, 1.0, s));
-  MM_TRY_HIP(launch_unshift(plan->dp, plan->d_work, out, s));
-  return MM_OK;
+  return lift(plan, g, out, S(stream));
 }
 
 mm_status mm_plan_set_noise(mm_plan_t plan, const double* sigma, const double* fknee, const double* alpha,
@@ -418,11 +440,7 @@ mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const do
   // kBlock * Ept (= 64 KB of LDS)
   if (plan->lds_g > 65536) return fail(MM_E_LEN, "chunk rows too long for the two-spectrum gradient pass");
   hipStream_t s = S(stream);
-  if (!plan->d_work2) {
-    void* p = nullptr;
-    MM_TRY(plan_alloc(plan, (size_t)plan->nwork * (plan->precision == MM_FP64 ? 8 : 4), &p));
-    plan->d_work2 = p;
-  }
+  if (!plan->d_work2) return fail(MM_E_ARG, "the plan was built without with_adjoint (no second TOD buffer)");
   const bool pm = plan->pm_mode != 0;
   if (pm) MM_TRY_HIP(launch_project(plan->dp, m, plan->d_pm, s));
   MM_TRY_HIP(launch_interleave(plan->dp, m, s));  // no-op without an interleaved copy
@@ -456,24 +474,8 @@ mm_status mm_cg_solve(mm_plan_t plan, const void* d, const double* rhs_map, int3
   double* sc = plan->d_scal;  // 0: p.q  1: chi2(0)  2: x.b  3: x.r
   double* rzh = rz_hist_dev;
   if (!rzh) {
-    const size_t need = (size_t)maxiter + 1;
-    if (plan->hist_cap < need) {
-      void* h = nullptr;
-      if (hipMalloc(&h, need * sizeof(double)) != hipSuccess) return fail(MM_E_NOMEM, "device allocation failed (CG history)");
-      if (plan->d_hist) {
-        // the old history may still be read by queued work
-        const hipError_t es = hipStreamSynchronize(s);
-        if (es != hipSuccess) {
-          (void)hipFree(h);
-          return fail(MM_E_HIP, std::string("stream synchronize: ") + hipGetErrorString(es));
-        }
-        (void)hipFree(plan->d_hist);
-      }
-      plan->d_hist = (double*)h;
-      plan->hist_cap = need;
-      plan->extra_allocs.clear();
-      plan->extra_allocs.push_back(h);
-    }
+    if ((int64_t)maxiter + 1 > kCgHistCap)
+      return fail(MM_E_ARG, "maxiter above " + std::to_string(kCgHistCap - 1) + " needs a caller history (rz_hist_dev)");
     rzh = plan->d_hist;
   }
   // b = P^T N^-1 d (or the given map)

@@ -152,6 +152,62 @@ struct DevPlan {
                              // (gather access with ncomp = 3; null otherwise)
 };
 
+// ---------------------------------------------------------------------------------------------
+// device-side construction of the binning structures (sort.hip)
+
+// Pixel tiles: rectangles of tw x th pixels over a map of rows of nxm pixels, ntx per tile row.
+struct TileGeom {
+  int32_t nxm, tw, th, ntx, ntiles;
+};
+// Counters of the analysis passes (integers: independent of scheduling).
+struct SortCounters {
+  unsigned long long sx, sy, nst;  // summed |dx|, |dy| of the sampled steps, number of steps
+  unsigned long long non;          // on-map samples
+  unsigned long long nruns;        // runs (time-contiguous stretches inside one tile and chunk)
+  unsigned int flags;              // 1 pixel >= npix, 2 angle not finite or too large,
+                                   // 4 angle index beyond the table, 8 reserved sizes exceeded
+  unsigned int pad;
+};
+// The samples cut into slabs walked in time order, one thread per slab.
+struct SlabWalk {
+  const int32_t* pix;
+  const int64_t* off;  // device chunk table, nchunk + 1 entries
+  int32_t nchunk;
+  int64_t ns, slab, nslabs;
+};
+// Plan-time temporaries of the sort.
+struct SortTemp {
+  int64_t* starts;      // [nslabs][ntiles]
+  int64_t* tile_runs;   // [ntiles]
+  int64_t* runbase;     // [ntiles + 1]
+  int64_t* rstart;      // [nruns]
+  int64_t* rend;        // [nruns]
+  int32_t* rchunk;      // [nruns]
+  int64_t *nsb, *nseg, *nsort, *sbbase, *segbase, *sortbase;  // [ntiles] each
+};
+// What the sort leaves in the plan.
+struct SortOut {
+  Tile* tiles;
+  SubBatch* sbs;
+  Segment* segs;
+  uint16_t* perm;
+  uint16_t* lp;
+  uint8_t* psi_sorted;
+  int64_t cap_sb, cap_seg, cap_sort;
+  int64_t* totals;      // [3]: sub-batches, segments, sorted entries
+};
+
+hipError_t launch_sort_clear(SortCounters* ctr, hipStream_t s);
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
+hipError_t launch_sort_stats(const SlabWalk& w, int64_t npix, int64_t nxm, const void* psi, int psi_kind,
+                             int64_t table_len, SortCounters* ctr, hipStream_t s);
+hipError_t launch_sort_count(const SlabWalk& w, const TileGeom& g, SortCounters* ctr, int64_t* starts,
+                             hipStream_t s);
+hipError_t launch_sort_lists(const SlabWalk& w, const TileGeom& g, int64_t nym, const SortTemp& T, const SortOut& O,
+                             SortCounters* ctr, hipStream_t s);
+hipError_t launch_sort_pixels(const int32_t* pix, const void* psi, int psi_esz, const TileGeom& g, const SortOut& O,
+                              hipStream_t s);
+
 // pass-A sources
 // pass-A sources: gather P m directly, or read a TOD-sized buffer holding P m written in
 // pixel-tile order (by the binning epilogue or the projection kernel)

@@ -13,6 +13,21 @@
 namespace mm {
 
 constexpr int kScratchMaps = 6;
+constexpr int64_t kCgHistCap = 16384;  // CG history entries a plan holds for callers that give none
+
+// Bump allocation of 256-byte-aligned pieces from a byte range; with a null base it only
+// measures (cap unlimited), which is how the workspace size is computed.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = ~size_t(0);
+  size_t used = 0;
+  void* take(size_t bytes) {
+    const size_t a = (used + 255) / 256 * 256;
+    if (a > cap || bytes > cap - a) return nullptr;
+    used = a + bytes;
+    return base ? (void*)(base + a) : (void*)(uintptr_t)(a + 256);  // non-null when measuring
+  }
+};
 
 extern thread_local std::string g_last_error;
 mm_status fail(mm_status s, const std::string& msg);
@@ -34,13 +49,12 @@ struct mm_plan_s {
   size_t lds_ac = 0, lds_c = 0, lds_b = 0, lds_g = 0;  // dynamic LDS: column passes A, C; row passes
   std::vector<int32_t> class_layout;      // per transform class: chosen candidate index
   std::vector<int32_t> class_ncand;       // per transform class: number of candidates
-  int64_t ntiles = 0, nsegs = 0;
+  int64_t ntiles = 0, nsegs = 0, nsbs = 0, nsorted = 0;
   int32_t tile_w = 0, tile_h = 0;
-  // device
+  // device: every buffer lies in the caller's workspace
   mm::DevPlan dp;
-  std::vector<void*> allocs;
-  std::vector<void*> extra_allocs;
-  size_t bytes = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0, ws_used = 0;
   mm::ItemAC* d_itemsAC = nullptr;
   mm::ItemB* d_itemsB = nullptr;
   int32_t* d_chunk_item_begin = nullptr;
@@ -55,7 +69,8 @@ struct mm_plan_s {
   double* d_scal = nullptr;
   double* d_part = nullptr;
   double* d_map[mm::kScratchMaps] = {};
-  void* d_work2 = nullptr;   // second TOD-sized buffer (noise-parameter gradient), on demand
+  void* d_work2 = nullptr;    // second TOD-sized buffer (gradients, map right-hand sides); null
+                              // unless the plan was built with_adjoint
   // P m in time order, written in pixel-tile order (large maps: the column pass reads it instead
   // of gathering the map)
   int pm_mode = 0;
@@ -65,8 +80,7 @@ struct mm_plan_s {
   double* d_batom = nullptr;
   int64_t max_n = 0;
   mm::DevChunk* d_chunks = nullptr;
-  double* d_hist = nullptr;  // grows on demand (CG rz history)
-  size_t hist_cap = 0;
+  double* d_hist = nullptr;  // CG r^T z history when the caller gives none (kCgHistCap entries)
   int64_t nsolvable = 0;
   hipStream_t cap_stream = nullptr;
   std::vector<double> solve_key;        // arguments of the last captured solve (replayed when equal)
@@ -109,13 +123,20 @@ void make_class(int64_t M, const Layout& L, std::vector<double2>& tw, DevClass& 
 bool row_fuse(int M1, bool f64);
 void append_col_items(int32_t c, const DevChunk& ch, std::vector<ItemAC>& itemsAC);
 void append_row_items(int32_t c, const DevChunk& ch, std::vector<ItemB>& itemsB, bool fuse);
-// index of the fastest candidate, timed on the GPU (0 for short chunks or on any failure);
-// cached per process by (M, precision)
-int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream_t s);
+// whether a length with ncand candidates is timed, and the device scratch the timing takes
+bool tune_wanted(int64_t M, size_t ncand);
+size_t tune_scratch_bytes(int64_t M, bool f64, const std::vector<Layout>& cands);
+// index of the fastest candidate, timed on the GPU in the given scratch (0 for short chunks or
+// on any failure); cached per process by (M, precision)
+int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream_t s, void* scratch,
+                size_t scratch_bytes);
 
-mm_status build_plan(const mm_plan_desc* desc, hipStream_t s, mm_plan_s** out);
+// device bytes a plan of this description needs; `scratch` (device, scratch_bytes) serves the
+// analysis passes, or null to have them allocate their own
+mm_status workspace_query(const mm_plan_desc* desc, hipStream_t s, void* scratch, size_t scratch_bytes,
+                          size_t* bytes);
+mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStream_t s, mm_plan_s** out);
 void destroy_plan(mm_plan_s* pl);
-mm_status plan_alloc(mm_plan_s* pl, size_t bytes, void** out);
 mm_status plan_set_noise(mm_plan_s* pl, const double* sigma, const double* fknee, const double* alpha,
                          const double* tau, hipStream_t s);
 }  // namespace mm

@@ -192,37 +192,27 @@ namespace {
 std::mutex g_tune_mu;
 std::map<std::pair<int64_t, int>, int> g_tune_cache;  // (M, precision) -> candidate index
 
-struct DevBuf {
-  void* p = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-  bool alloc(size_t n) { return hipMalloc(&p, n ? n : 8) == hipSuccess; }
-};
-
-template <typename X>
-bool put(DevBuf& b, const std::vector<X>& v, hipStream_t s) {
-  if (!b.alloc(v.size() * sizeof(X))) return false;
-  return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, s) == hipSuccess;
-}
-
 // Passes A-C (filter on) over K copies of a length-2M chunk under one layout: the device
-// tables and work lists, kept for repeated timing.
+// tables and work lists (carved from the tuner's scratch), kept for repeated timing.
 struct LayoutRun {
-  DevBuf bch, bcl, btw, btw32, bac, bb, bspec;
+  std::vector<double2> tw;
+  std::vector<float2> tw32;
+  std::vector<DevClass> cls;
+  std::vector<DevChunk> chunks;
+  std::vector<ItemAC> itemsAC;
+  std::vector<ItemB> itemsB;
   DevPlan P;
+  const ItemAC* dac = nullptr;
+  const ItemB* db = nullptr;
   int nac = 0, nb = 0;
   size_t lds_ac = 0, lds_c = 0, lds_b = 0;
 
-  bool prepare(int64_t M, bool f64, const Layout& L, int64_t K, hipStream_t s) {
-    std::vector<double2> tw;
-    std::vector<DevClass> cls(1);
+  void tables(int64_t M, bool f64, const Layout& L, int64_t K) {
+    cls.resize(1);
     make_class(M, L, tw, cls[0]);
-    std::vector<float2> tw32(tw.size());
+    tw32.resize(tw.size());
     for (size_t i = 0; i < tw.size(); ++i) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
-    std::vector<DevChunk> chunks(K);
-    std::vector<ItemAC> itemsAC;
-    std::vector<ItemB> itemsB;
+    chunks.resize(K);
     for (int64_t c = 0; c < K; ++c) {
       DevChunk& ch = chunks[c];
       std::memset(&ch, 0, sizeof(ch));
@@ -247,9 +237,35 @@ struct LayoutRun {
       append_col_items((int32_t)c, ch, itemsAC);
       append_row_items((int32_t)c, ch, itemsB, row_fuse(L.M1, f64));
     }
-    if (!put(bch, chunks, s) || !put(bcl, cls, s) || !put(btw, tw, s) || !put(btw32, tw32, s) ||
-        !put(bac, itemsAC, s) || !put(bb, itemsB, s))
+  }
+
+  // device bytes of the tables (what prepare carves)
+  size_t bytes(int64_t M, bool f64, const Layout& L, int64_t K) {
+    tables(M, f64, L, K);
+    Arena a;
+    a.take(chunks.size() * sizeof(DevChunk));
+    a.take(sizeof(DevClass));
+    a.take(tw.size() * sizeof(double2));
+    a.take(tw32.size() * sizeof(float2));
+    a.take(itemsAC.size() * sizeof(ItemAC));
+    a.take(itemsB.size() * sizeof(ItemB));
+    return a.used;
+  }
+
+  bool prepare(int64_t M, bool f64, const Layout& L, int64_t K, const double* spec, Arena& ar, hipStream_t s) {
+    tables(M, f64, L, K);
+    auto put = [&](const void* src, size_t n, void** dst) {
+      *dst = ar.take(n);
+      return *dst && (n == 0 || hipMemcpyAsync(*dst, src, n, hipMemcpyHostToDevice, s) == hipSuccess);
+    };
+    void *pch, *pcl, *ptw, *ptw32, *pac, *pb;
+    if (!put(chunks.data(), chunks.size() * sizeof(DevChunk), &pch) || !put(cls.data(), sizeof(DevClass), &pcl) ||
+        !put(tw.data(), tw.size() * sizeof(double2), &ptw) || !put(tw32.data(), tw32.size() * sizeof(float2), &ptw32) ||
+        !put(itemsAC.data(), itemsAC.size() * sizeof(ItemAC), &pac) ||
+        !put(itemsB.data(), itemsB.size() * sizeof(ItemB), &pb))
       return false;
+    dac = (const ItemAC*)pac;
+    db = (const ItemB*)pb;
     nac = (int)itemsAC.size();
     nb = (int)itemsB.size();
     std::memset(&P, 0, sizeof(P));
@@ -259,15 +275,12 @@ struct LayoutRun {
     for (int8_t r : L.r2) P.all_pow2 &= (r == 2 || r == 4 || r == 8);
     P.nsamp = K * 2 * M;
     P.nchunk = (int32_t)K;
-    P.chunks = (const DevChunk*)bch.p;
-    P.classes = (const DevClass*)bcl.p;
-    P.tw64 = (const double2*)btw.p;
-    P.tw32 = (const float2*)btw32.p;
-    if (f64) {
-      if (!bspec.alloc((size_t)K * (M + 1) * sizeof(double))) return false;
-      P.spec = (const double*)bspec.p;
-      if (launch_spectrum(P, (double*)bspec.p, s) != hipSuccess) return false;
-    }
+    P.chunks = (const DevChunk*)pch;
+    P.classes = (const DevClass*)pcl;
+    P.tw64 = (const double2*)ptw;
+    P.tw32 = (const float2*)ptw32;
+    // the power-law values only need to be finite: every candidate reads the same table
+    P.spec = spec;
     const size_t csz = f64 ? sizeof(double2) : sizeof(float2);
     const bool wl = !(f64 && P.all_pow2) && wave_cols(L.M2, L.cb, (int)csz);
     P.col_wave = wl ? 1 : 0;
@@ -278,17 +291,44 @@ struct LayoutRun {
   }
 
   bool run(void* din, void* dwork, hipStream_t s) const {
-    return launch_pass_a(P, (const ItemAC*)bac.p, nac, din, nullptr, SRC_D, dwork, lds_ac, s) == hipSuccess &&
-           launch_pass_b(P, (const ItemB*)bb.p, nb, dwork, B_FILTER, GAIN_MESSENGER, 1.0, 1.0, nullptr, lds_b, s) ==
-               hipSuccess &&
-           launch_pass_c(P, (const ItemAC*)bac.p, nac, dwork, lds_c, s) == hipSuccess;
+    return launch_pass_a(P, dac, nac, din, nullptr, SRC_D, dwork, lds_ac, s) == hipSuccess &&
+           launch_pass_b(P, db, nb, dwork, B_FILTER, GAIN_MESSENGER, 1.0, 1.0, nullptr, lds_b, s) == hipSuccess &&
+           launch_pass_c(P, dac, nac, dwork, lds_c, s) == hipSuccess;
   }
 };
 
+// copies of the chunk timed per launch, and the bytes of one copy in the work buffers
+void tune_shape(int64_t M, bool f64, int64_t* K, size_t* buf_bytes) {
+  *K = std::max<int64_t>(1, kTuneElements / M);
+  const int64_t Mp = (M + kWorkAlign - 1) / kWorkAlign * kWorkAlign;
+  *buf_bytes = (size_t)(*K) * Mp * (f64 ? sizeof(double2) : sizeof(float2));
+}
+
 }  // namespace
 
-int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream_t s) {
-  if (cands.size() <= 1 || M < kTuneMinM) return 0;
+bool tune_wanted(int64_t M, size_t ncand) { return ncand > 1 && M >= kTuneMinM; }
+
+size_t tune_scratch_bytes(int64_t M, bool f64, const std::vector<Layout>& cands) {
+  if (!tune_wanted(M, cands.size())) return 0;
+  int64_t K;
+  size_t bb;
+  tune_shape(M, f64, &K, &bb);
+  Arena a;
+  a.take(bb);
+  a.take(bb);
+  if (f64) a.take((size_t)K * (M + 1) * sizeof(double));
+  const int ncand = (int)std::min<size_t>(cands.size(), kTuneMaxCandidates);
+  size_t t = a.used;
+  for (int i = 0; i < ncand; ++i) {
+    LayoutRun r;
+    t = (t + 255) / 256 * 256 + r.bytes(M, f64, cands[i], K);
+  }
+  return t + 256;
+}
+
+int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream_t s, void* scratch,
+                size_t scratch_bytes) {
+  if (!tune_wanted(M, cands.size())) return 0;
   const std::pair<int64_t, int> key(M, f64 ? 0 : 1);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -296,48 +336,50 @@ int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream
     if (it != g_tune_cache.end()) return it->second;
   }
   const int ncand = (int)std::min<size_t>(cands.size(), kTuneMaxCandidates);
-  // enough copies of the chunk to fill the GPU several times over
-  const int64_t K = std::max<int64_t>(1, kTuneElements / M);
-  const int64_t Mp = (M + kWorkAlign - 1) / kWorkAlign * kWorkAlign;
-  const size_t bytes = (size_t)K * Mp * (f64 ? sizeof(double2) : sizeof(float2));
+  int64_t K;
+  size_t bb;
+  tune_shape(M, f64, &K, &bb);
+  Arena ar;
+  ar.base = (char*)scratch;
+  ar.cap = scratch_bytes;
+  void* din = ar.take(bb);
+  void* dwork = ar.take(bb);
+  double* spec = nullptr;
+  if (f64) spec = (double*)ar.take((size_t)K * (M + 1) * sizeof(double));
+  if (!din || !dwork || (f64 && !spec)) return 0;
   int best = 0;
-  {
-    DevBuf din, dwork;
-    if (!din.alloc(bytes) || !dwork.alloc(bytes) || hipMemsetAsync(din.p, 0, bytes, s) != hipSuccess) {
-      (void)hipGetLastError();
-      return 0;
-    }
-    // every candidate prepared and warmed up, then timed round-robin (best of kTuneReps each), so
-    // that clock and cache drift during the plan affects all of them alike
-    std::vector<std::unique_ptr<LayoutRun>> runs;
-    std::vector<double> t(ncand, -1.0);
-    bool ok = true;
+  // every candidate prepared and warmed up, then timed round-robin (best of kTuneReps each), so
+  // that clock and cache drift during the plan affects all of them alike
+  std::vector<std::unique_ptr<LayoutRun>> runs;
+  std::vector<double> t(ncand, -1.0);
+  bool ok = launch_fill_i64((int64_t*)din, (int64_t)(bb / sizeof(int64_t)), 0, s) == hipSuccess;
+  for (int i = 0; ok && i < ncand; ++i) {
+    runs.emplace_back(new LayoutRun);
+    ok = runs[i]->prepare(M, f64, cands[i], K, spec, ar, s);
+    if (ok && f64 && i == 0) ok = launch_spectrum(runs[0]->P, spec, s) == hipSuccess;
+    ok = ok && runs[i]->run(din, dwork, s);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  for (int rep = 0; ok && rep < kTuneReps; ++rep)
     for (int i = 0; ok && i < ncand; ++i) {
-      runs.emplace_back(new LayoutRun);
-      ok = runs[i]->prepare(M, f64, cands[i], K, s) && runs[i]->run(din.p, dwork.p, s);
+      float ms = 0.f;
+      ok = hipEventRecord(e0, s) == hipSuccess && runs[i]->run(din, dwork, s) &&
+           hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      if (ok && (t[i] < 0 || ms < t[i])) t[i] = ms;
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
-    for (int rep = 0; ok && rep < kTuneReps; ++rep)
-      for (int i = 0; ok && i < ncand; ++i) {
-        float ms = 0.f;
-        ok = hipEventRecord(e0, s) == hipSuccess && runs[i]->run(din.p, dwork.p, s) &&
-             hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-        if (ok && (t[i] < 0 || ms < t[i])) t[i] = ms;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipGetLastError();
+  if (ok) {
+    double tbest = t[0];
+    for (int i = 1; i < ncand; ++i)
+      if (t[i] < tbest * 0.98) {  // a clear win over the better-ranked layouts
+        tbest = t[i];
+        best = i;
       }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    (void)hipStreamSynchronize(s);
-    (void)hipGetLastError();
-    if (ok) {
-      double tbest = t[0];
-      for (int i = 1; i < ncand; ++i)
-        if (t[i] < tbest * 0.98) {  // a clear win over the better-ranked layouts
-          tbest = t[i];
-          best = i;
-        }
-    }
   }
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tune_cache[key] = best;

@@ -47,7 +47,7 @@ class _Desc(ctypes.Structure):
         ("pix", ctypes.c_void_p), ("psi", ctypes.c_void_p),
         ("psi_kind", ctypes.c_int32), ("map_access", ctypes.c_int32),
         ("psi_table", ctypes.POINTER(ctypes.c_float)), ("psi_table_len", ctypes.c_int64),
-        ("tune", ctypes.c_int32), ("binning", ctypes.c_int32),
+        ("tune", ctypes.c_int32), ("binning", ctypes.c_int32), ("with_adjoint", ctypes.c_int32),
     ]
 
 
@@ -68,9 +68,10 @@ def lib() -> ctypes.CDLL:
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1705_01893_amd.build`")
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-    L.mm_plan.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.POINTER(vp)]
+    L.mm_plan_workspace_bytes.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mm_plan.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.mm_plan_destroy.argtypes = [vp]
-    L.mm_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mm_plan_binning_stats.argtypes = [vp, ctypes.POINTER(i64)]
     L.mm_plan_hits.argtypes = [vp, vp, vp]
     L.mm_plan_solvable.argtypes = [vp, vp, vp]
     L.mm_plan_nsolvable.argtypes = [vp, ctypes.POINTER(i64)]
@@ -78,7 +79,7 @@ def lib() -> ctypes.CDLL:
     L.mm_plan_chunk_layout.argtypes = [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
                                        ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.mm_messenger_iter.argtypes = [vp, vp, dbl, vp, vp, vp, vp]
-    L.mm_solve.argtypes = [vp, vp, ctypes.POINTER(_Sched), vp, vp, vp, vp]
+    L.mm_solve.argtypes = [vp, vp, vp, ctypes.POINTER(_Sched), vp, vp, vp, vp]
     L.mm_cooling_levels.argtypes = [vp, i32, dbl, ctypes.POINTER(dbl)]
     L.mm_cg_solve.argtypes = [vp, vp, vp, i32, dbl, vp, vp, vp, vp, ctypes.POINTER(i32), vp]
     L.mm_chi2.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp]
@@ -90,7 +91,7 @@ def lib() -> ctypes.CDLL:
     L.mm_noise_grad.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mm_set_timing.argtypes = [vp, i32]
     L.mm_get_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
-    for name in ("mm_plan_set_noise", "mm_tod_apply", "mm_noise_grad", "mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_hits", "mm_plan_solvable",
+    for name in ("mm_plan_set_noise", "mm_tod_apply", "mm_noise_grad", "mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_binning_stats", "mm_plan_hits", "mm_plan_solvable",
                  "mm_plan_nsolvable", "mm_plan_map_access", "mm_plan_chunk_layout", "mm_messenger_iter", "mm_solve", "mm_cooling_levels", "mm_cg_solve",
                  "mm_chi2", "mm_apply", "mm_lift_rhs"):
         getattr(L, name).restype = ctypes.c_int
@@ -135,12 +136,13 @@ def _host_f64(x, n, name):
 
 
 class Plan:
-    """A built plan (owns the C handle; keeps the pointing tensors alive)."""
+    """A built plan: owns the C handle and the workspace tensor, keeps the pointing tensors alive."""
 
     def __init__(self, handle: int, desc_arrays: dict, ncomp: int, npix: int, nchunk: int, nsamp: int,
-                 precision: int, tensors: list):
+                 precision: int, tensors: list, workspace: torch.Tensor):
         self.handle = ctypes.c_void_p(handle)
         self._keep = (desc_arrays, tensors)
+        self.workspace = workspace
         self.ncomp, self.npix, self.nchunk, self.nsamp, self.precision = ncomp, npix, nchunk, nsamp, precision
         # messenger variance per chunk as last given to the library (None: its default sigma^2)
         self.tau = desc_arrays.get("tau")
@@ -157,6 +159,7 @@ class Plan:
         if self.handle:
             lib().mm_plan_destroy(self.handle)
             self.handle = ctypes.c_void_p(None)
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -165,11 +168,12 @@ class Plan:
             pass
 
 
-def mm_plan(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, pix: torch.Tensor,
-            psi: Optional[torch.Tensor] = None, psi_table=None, tau=None, nx: int = 0,
-            precision: int = MM_FP64, map_access: int = MM_MAP_AUTO, tune: int = MM_TUNE_MEASURE,
-            binning: int = MM_BIN_SORTED, stream=None) -> Plan:
-    """Build a plan (mm_plan).  pix (int32) and psi (float64 / float32 / uint16) are device tensors."""
+def plan_desc(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, pix: torch.Tensor,
+              psi: Optional[torch.Tensor] = None, psi_table=None, tau=None, nx: int = 0,
+              precision: int = MM_FP64, map_access: int = MM_MAP_AUTO, tune: int = MM_TUNE_MEASURE,
+              binning: int = MM_BIN_SORTED, with_adjoint: bool = False):
+    """The mm_plan_desc of a problem and the host arrays it points to (keep both alive together).
+    pix (int32) and psi (float64 / float32 / uint16) are device tensors."""
     off = np.ascontiguousarray(np.asarray(chunk_off, dtype=np.int64).reshape(-1))
     nchunk = off.size - 1
     nsamp = int(off[-1])
@@ -183,6 +187,7 @@ def mm_plan(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, p
     d.map_access = map_access
     d.tune = tune
     d.binning = binning
+    d.with_adjoint = int(bool(with_adjoint))
     d.chunk_off = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     for k in ("fsample", "sigma", "fknee", "alpha"):
         setattr(d, k, arrs[k].ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
@@ -200,15 +205,41 @@ def mm_plan(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, p
         arrs["psi_table"] = tab
         d.psi_table = tab.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         d.psi_table_len = tab.size
-    h = ctypes.c_void_p()
-    _check(lib().mm_plan(ctypes.byref(d), _stream(stream), ctypes.byref(h)), "mm_plan")
-    return Plan(h.value, arrs, ncomp, npix, nchunk, nsamp, precision, [pix, psi])
+    return d, arrs
 
 
-def mm_plan_workspace_bytes(plan: Plan) -> int:
+def mm_plan_workspace_bytes(stream=None, **kw) -> int:
+    """Workspace bytes of the plan the keyword arguments (those of mm_plan) describe."""
+    d, arrs = plan_desc(**kw)
     v = ctypes.c_size_t()
-    _check(lib().mm_plan_workspace_bytes(plan.handle, ctypes.byref(v)), "mm_plan_workspace_bytes")
+    _check(lib().mm_plan_workspace_bytes(ctypes.byref(d), _stream(stream), ctypes.byref(v)),
+           "mm_plan_workspace_bytes")
     return v.value
+
+
+def mm_plan(*, stream=None, **kw) -> Plan:
+    """Build a plan (mm_plan) in a workspace tensor sized by mm_plan_workspace_bytes (torch owns the
+    device memory).  Keyword arguments: those of plan_desc."""
+    d, arrs = plan_desc(**kw)
+    st = _stream(stream)
+    v = ctypes.c_size_t()
+    _check(lib().mm_plan_workspace_bytes(ctypes.byref(d), st, ctypes.byref(v)), "mm_plan_workspace_bytes")
+    pix, psi = kw["pix"], kw.get("psi")
+    ws = torch.empty(max(int(v.value), 1), dtype=torch.uint8, device=pix.device)
+    h = ctypes.c_void_p()
+    _check(lib().mm_plan(ctypes.byref(d), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), st,
+                         ctypes.byref(h)), "mm_plan")
+    nsamp = int(arrs["off"][-1])
+    return Plan(h.value, arrs, kw["ncomp"], kw["npix"], arrs["off"].size - 1, nsamp,
+                kw.get("precision", MM_FP64), [pix, psi], ws)
+
+
+def mm_plan_binning_stats(plan: Plan) -> dict:
+    """Pixel tiles, tile width and height, sub-batches, segments, sorted entries and workspace bytes in use."""
+    out = (ctypes.c_int64 * 7)()
+    _check(lib().mm_plan_binning_stats(plan.handle, out), "mm_plan_binning_stats")
+    keys = ("tiles", "tile_w", "tile_h", "sub_batches", "segments", "sorted_entries", "workspace_used")
+    return {k: int(v) for k, v in zip(keys, out)}
 
 
 def mm_plan_hits(plan: Plan, hits: torch.Tensor, stream=None) -> None:
@@ -259,9 +290,10 @@ def mm_cooling_levels(plan: Plan, nlevel: int, lambda_max: float = 0.0) -> list:
     return list(out)
 
 
-def mm_solve(plan: Plan, d: torch.Tensor, lambdas: Sequence[float], iters: Sequence[int], m_out: torch.Tensor,
-             first_inf: bool = True, m0: Optional[torch.Tensor] = None, chi2_hist: Optional[torch.Tensor] = None,
-             stream=None) -> None:
+def mm_solve(plan: Plan, d: Optional[torch.Tensor], lambdas: Sequence[float], iters: Sequence[int],
+             m_out: torch.Tensor, first_inf: bool = True, m0: Optional[torch.Tensor] = None,
+             chi2_hist: Optional[torch.Tensor] = None, rhs_map: Optional[torch.Tensor] = None, stream=None) -> None:
+    """Cooled messenger solve on the data d, or (d None) on a map right-hand side rhs_map."""
     lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
     its = np.ascontiguousarray(np.asarray(iters, dtype=np.int32))
     if lam.size != its.size:
@@ -271,8 +303,8 @@ def mm_solve(plan: Plan, d: torch.Tensor, lambdas: Sequence[float], iters: Seque
     sc.lambda_ = lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     sc.iters = its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     nh = int(bool(first_inf)) + int(its.sum()) + 1
-    _check(lib().mm_solve(plan.handle, _ptr(d, "d", plan.tod_dtype, plan.nsamp), ctypes.byref(sc),
-                          _map_ptr(plan, m0, "m0"), _map_ptr(plan, m_out, "m_out"),
+    _check(lib().mm_solve(plan.handle, _ptr(d, "d", plan.tod_dtype, plan.nsamp), _map_ptr(plan, rhs_map, "rhs_map"),
+                          ctypes.byref(sc), _map_ptr(plan, m0, "m0"), _map_ptr(plan, m_out, "m_out"),
                           _ptr(chi2_hist, "chi2_hist", torch.float64, nh), _stream(stream)), "mm_solve")
 
 

@@ -65,6 +65,7 @@ def _desc(**over):
     d.map_access = over.pop("map_access", 0)
     d.tune = over.pop("tune", 0)
     d.binning = over.pop("binning", 0)
+    d.with_adjoint = over.pop("with_adjoint", 0)
     assert not over
     return d, arr
 
@@ -75,6 +76,7 @@ def _desc(**over):
     (dict(map_access=3), mm.MM_E_ARG),
     (dict(tune=2), mm.MM_E_ARG),
     (dict(binning=2), mm.MM_E_ARG),
+    (dict(with_adjoint=2), mm.MM_E_ARG),
     (dict(npix=0), mm.MM_E_ARG),
     (dict(npix=15, nx=4), mm.MM_E_ARG),
     (dict(pix=None), mm.MM_E_ARG),
@@ -86,17 +88,23 @@ def _desc(**over):
     (dict(arrays=dict(off=np.array([1, 65, 129], np.int64))), mm.MM_E_ARG),
 ])
 def test_plan_validation(case, status):
+    """Both the workspace query and the plan reject the description before any device work."""
     d, keep = _desc(**case)
     h = ctypes.c_void_p()
-    st = mm.lib().mm_plan(ctypes.byref(d), None, ctypes.byref(h))
+    st = mm.lib().mm_plan(ctypes.byref(d), None, 0, None, ctypes.byref(h))
     assert st == status, mm.lib().mm_last_error()
     assert h.value is None
     assert len(mm.lib().mm_last_error()) > 0
+    v = ctypes.c_size_t(12345)
+    st = mm.lib().mm_plan_workspace_bytes(ctypes.byref(d), None, ctypes.byref(v))
+    assert st == status, mm.lib().mm_last_error()
+    assert v.value == 12345
 
 
 def test_null_plan_is_rejected():
     lib = mm.lib()
     assert lib.mm_plan_destroy(None) == mm.MM_E_ARG
     v = ctypes.c_size_t()
-    assert lib.mm_plan_workspace_bytes(None, ctypes.byref(v)) == mm.MM_E_ARG
+    assert lib.mm_plan_workspace_bytes(None, None, ctypes.byref(v)) == mm.MM_E_ARG
+    assert lib.mm_plan_binning_stats(None, None) == mm.MM_E_ARG
     assert lib.mm_messenger_iter(None, None, 1.0, None, None, None, None) == mm.MM_E_ARG

@@ -36,7 +36,7 @@ def _plan(t, dev, precision=mm.MM_FP64):
     psi = torch.from_numpy(t.psi).to(dev) if t.ncomp == 3 else None
     return mm.mm_plan(ncomp=t.ncomp, npix=t.npix, nx=t.nx, chunk_off=t.chunk_off, fsample=t.fsample, sigma=t.sigma,
                       fknee=t.fknee, alpha=t.alpha, pix=torch.from_numpy(t.pix).to(dev), psi=psi,
-                      precision=precision)
+                      precision=precision, with_adjoint=True)
 
 
 def _setup(t, sigma=None, fknee=None, alpha=None):

@@ -56,7 +56,7 @@ def plan_for(t, dev, access=mm.MM_MAP_PROJECTED, precision=mm.MM_FP64):
     psi = torch.from_numpy(np.ascontiguousarray(t.psi)).to(dev) if t.ncomp == 3 else None
     return mm.mm_plan(ncomp=t.ncomp, npix=t.npix, nx=t.nx, chunk_off=t.chunk_off, fsample=t.fsample,
                       sigma=t.sigma, fknee=t.fknee, alpha=t.alpha, pix=torch.from_numpy(t.pix).to(dev), psi=psi,
-                      precision=precision, map_access=access)
+                      precision=precision, map_access=access, with_adjoint=True)
 
 
 def setup(t):
