@@ -37,7 +37,7 @@
  *               memory: every table and work buffer lies in the caller's
  *               workspace, whose size mm_plan_workspace_bytes reports.
  *  Streams      Every call is ordered on the given stream and returns without
- *               waiting for it, except mm_plan_workspace_bytes and
+ *               waiting for it, except mm_plan_workspace_bytes(_noalloc) and
  *               mm_plan (they wait for their passes over the pointing),
  *               mm_chi2 (returns a host scalar) and mm_cg_solve when rtol > 0.
  *               Pass 0 for the default stream.  A plan is not thread-safe; use
@@ -168,6 +168,17 @@ typedef struct {
  * and pointing, on any stream.
  */
 mm_status mm_plan_workspace_bytes(const mm_plan_desc* desc, mm_stream_t stream, size_t* bytes);
+
+/*
+ * mm_plan_workspace_bytes for callers that cannot allocate device memory
+ * (code under graph capture elsewhere on the device, serving loops, harnesses
+ * that forbid hipMalloc).  Same result, but its counters and the chunk table
+ * live in a fixed 1 MiB device array of the library (one per GPU, held until
+ * the process ends), so nchunk is limited to 131039 (MM_E_ARG beyond).  Calls
+ * on one GPU share that array: calls that overlap on one GPU (other host
+ * threads, other streams) race and must be serialized by the caller.
+ */
+mm_status mm_plan_workspace_bytes_noalloc(const mm_plan_desc* desc, mm_stream_t stream, size_t* bytes);
 
 /*
  * Build a plan in the caller's workspace (device, 256-byte aligned,

@@ -215,6 +215,15 @@ mm_status mm_plan_workspace_bytes(const mm_plan_desc* desc, mm_stream_t stream, 
   return workspace_query(desc, S(stream), nullptr, 0, bytes);
 }
 
+mm_status mm_plan_workspace_bytes_noalloc(const mm_plan_desc* desc, mm_stream_t stream, size_t* bytes) {
+  g_last_error.clear();
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  void* scratch = e == hipSuccess ? static_scratch(dev, &e) : nullptr;
+  if (!scratch) return fail(MM_E_HIP, std::string("fixed scratch lookup: ") + hipGetErrorString(e));
+  return workspace_query(desc, S(stream), scratch, kStaticScratchBytes, bytes);
+}
+
 mm_status mm_plan(const mm_plan_desc* desc, void* workspace, size_t workspace_bytes, mm_stream_t stream,
                   mm_plan_t* out) {
   g_last_error.clear();

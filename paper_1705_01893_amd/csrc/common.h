@@ -197,6 +197,10 @@ struct SortOut {
   int64_t* totals;      // [3]: sub-batches, segments, sorted entries
 };
 
+constexpr int kMaxDevices = 64;
+// bytes of the fixed device array used by the allocation-free workspace query
+constexpr size_t kStaticScratchBytes = size_t(1) << 20;
+
 hipError_t launch_sort_clear(SortCounters* ctr, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 hipError_t launch_sort_stats(const SlabWalk& w, int64_t npix, int64_t nxm, const void* psi, int psi_kind,
@@ -207,6 +211,8 @@ hipError_t launch_sort_lists(const SlabWalk& w, const TileGeom& g, int64_t nym, 
                              SortCounters* ctr, hipStream_t s);
 hipError_t launch_sort_pixels(const int32_t* pix, const void* psi, int psi_esz, const TileGeom& g, const SortOut& O,
                               hipStream_t s);
+// address of the fixed scratch array on `device` (which must be current); looked up once per device
+void* static_scratch(int device, hipError_t* err);
 
 // pass-A sources
 // pass-A sources: gather P m directly, or read a TOD-sized buffer holding P m written in

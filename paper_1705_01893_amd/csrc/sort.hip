@@ -19,8 +19,11 @@
 //
 // A slab is a contiguous range of samples walked by one thread in time order, so every
 // count is an integer and every list position follows from prefix sums: the result does
-// not depend on scheduling.
+// not depend on scheduling.  The scratch array at the end serves the allocation-free
+// workspace query.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 
 #include "common.h"
 
@@ -524,6 +527,34 @@ hipError_t launch_sort_pixels(const int32_t* pix, const void* psi, int psi_esz, 
   hipLaunchKernelGGL(k_sort_pixels, dim3(grid > 0 ? grid : 1), dim3(kSortBlock), 0, s, pix, psi, psi_esz, g,
                      O.tiles, O.sbs, O.segs, O.perm, O.lp, O.psi_sorted);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// The fixed device array of the allocation-free workspace query: the chunk table and the
+// counters of the analysis passes.  Each device gets its own copy; its address is looked up
+// once per device (with that device current) and kept.
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+void* static_scratch(int device, hipError_t* err) {
+  static std::mutex mu;
+  static void* ptrs[kMaxDevices] = {};
+  *err = hipSuccess;
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      *err = e;
+      return nullptr;
+    }
+    ptrs[device] = p;
+  }
+  return ptrs[device];
 }
 
 }  // namespace mm

@@ -69,6 +69,7 @@ def lib() -> ctypes.CDLL:
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.mm_plan_workspace_bytes.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mm_plan_workspace_bytes_noalloc.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.POINTER(ctypes.c_size_t)]
     L.mm_plan.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.mm_plan_destroy.argtypes = [vp]
     L.mm_plan_binning_stats.argtypes = [vp, ctypes.POINTER(i64)]
@@ -91,7 +92,8 @@ def lib() -> ctypes.CDLL:
     L.mm_noise_grad.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mm_set_timing.argtypes = [vp, i32]
     L.mm_get_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
-    for name in ("mm_plan_set_noise", "mm_tod_apply", "mm_noise_grad", "mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_binning_stats", "mm_plan_hits", "mm_plan_solvable",
+    for name in ("mm_plan_set_noise", "mm_tod_apply", "mm_noise_grad", "mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_workspace_bytes_noalloc",
+                 "mm_plan_binning_stats", "mm_plan_hits", "mm_plan_solvable",
                  "mm_plan_nsolvable", "mm_plan_map_access", "mm_plan_chunk_layout", "mm_messenger_iter", "mm_solve", "mm_cooling_levels", "mm_cg_solve",
                  "mm_chi2", "mm_apply", "mm_lift_rhs"):
         getattr(L, name).restype = ctypes.c_int
