@@ -1,15 +1,18 @@
 #!/usr/bin/env python3
 """Throughput of the messenger-field mapmaking iteration on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload iqu256]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large2048] [--forms mixed,fp64]
 
-A step is one messenger iteration (eqn. mcompact of the paper: gather P m,
-forward transforms, noise filter, inverse transforms, binning P^T and the
-per-pixel 3x3 update) over the whole time-ordered data set of the workload,
-already resident in HBM.  The value is samples per second.  One JSON line is
-printed; it carries the roofline of the dominant pass (algorithmic bytes per
-launch over the pass's average duration from HIP events on the launch stream)
-and the CPU oracle timed on a bounded sample on the host.
+A step is one messenger iteration (eqn. mcompact of the paper: P m, forward transforms, noise
+filter, inverse transforms, binning P^T and the per-pixel 3x3 update) over the whole
+time-ordered data set of the workload, already resident in HBM.  The default workload is the
+largest single-GPU share: 1024 detectors x 2^22 samples (4.3e9), a 2048x2048 I/Q/U map, FP32
+TOD and a uint16 angle-table index, generated on the GPU.  Both forms run, one plan at a time:
+the FP32-mixed form gives `value`, the plain FP64 form (the stored TOD promoted) is reported
+beside it.  One JSON line is printed; it carries the roofline of the mixed form's dominant pass
+(algorithmic bytes per launch over the pass's mean duration from HIP events on the launch
+stream), the time to chi^2 targets of the cooled messenger in both forms and of preconditioned
+CG, and the CPU oracle timed on a bounded sample on the host (one thread, and all cores).
 """
 
 from __future__ import annotations
@@ -39,31 +42,6 @@ def kernel_hash() -> str:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
-
-
-def pass_bytes(prob, tod_bytes: int, psi_bytes: int, projected: bool) -> list:
-    """Algorithmic HBM bytes of one launch of each pass (compulsory streams, each once).
-
-    Gather access: pass A reads d, pix and the on-map angles and gathers the map (counted
-    once, with the binning pass's map traffic).  Projected access: pass A reads d and the
-    P m buffer; the binning pass also writes P m of the new map for its on-map samples."""
-    ns = prob.nsamp_total
-    non = int((prob.pix >= 0).sum())
-    ncomp, npix = prob.ncomp, prob.npix
-    nw = 1 if ncomp == 1 else 6
-    if projected:
-        a = 3 * ns * tod_bytes                                              # d, P m, X write
-    else:
-        a = ns * tod_bytes + ns * 4 + non * psi_bytes + ns * tod_bytes      # d, pix, psi (on map), X write
-    b = 2 * ns * tod_bytes                                                  # X read + write
-    if tod_bytes == 8:
-        b += (ns // 2 + prob.nchunk) * 8                                    # tabulated noise power law
-    c = 2 * ns * tod_bytes                                                  # X read + y write
-    d = non * (tod_bytes + 2 + 2 + psi_bytes) + npix * 8 * (2 * ncomp + nw) + npix  # y, perm, lp, psi; maps
-    if projected:
-        d += non * tod_bytes                                                # P m of the new map
-    p = non * (2 + 2 + psi_bytes + tod_bytes) + npix * 8 * ncomp            # perm, lp, psi, P m; map
-    return [a, b, c, d, p]
 
 
 def layout_summary(mm, plan) -> list:
@@ -109,7 +87,7 @@ def _counter_rows(run_dir: str):
         return list(csv.DictReader(fh))
 
 
-def write_traffic(args, fetch_dir: str, write_dir: str) -> None:
+def write_traffic(args, form: str, fetch_dir: str, write_dir: str) -> None:
     """HBM bytes per launch of each pass from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch).
 
     Only the workload's dispatches count: those after the plan's precompute binning launch (the
@@ -143,13 +121,13 @@ def write_traffic(args, fetch_dir: str, write_dir: str) -> None:
         w = per.get(i, {}).get("WRITE_SIZE")
         passes.append({"pass": name, "fetch_bytes": f, "write_bytes": w,
                        "bytes_per_launch": (f + w) if f is not None and w is not None else None})
-    name = args.workload + ("_mixed" if args.mixed else "")
+    name = f"{args.workload}_{form}"
     out = {"workload": name, "kernel_hash": kernel_hash(),
            "calibration": {"FETCH_SIZE": scale["FETCH_SIZE"], "WRITE_SIZE": scale["WRITE_SIZE"],
                            "reference": "torch copy of 1 GiB (bench.py --copy-calibration)"},
            "passes": passes,
            "commands": [f"rocprofv3 --pmc {c} --kernel-trace -d <dir> -o run -- python3 bench.py --workload "
-                        f"{args.workload}{' --mixed' if args.mixed else ''} --steps 2 --warmup 1 --no-cpu --no-chi2 "
+                        f"{args.workload} --forms {form} --steps 2 --warmup 1 --no-cpu --no-chi2 "
                         "--copy-calibration" for c in ("FETCH_SIZE", "WRITE_SIZE")]}
     path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     with open(path, "w") as fh:
@@ -216,32 +194,176 @@ def summarize_trace(trace_dir: str) -> None:
         print(f"| {k} | {n} | {t / n:.1f} | {100 * t / total:.1f}% |")
 
 
-def cpu_baseline(prob, seconds: float):
-    """The oracle's messenger step on the same workload, single-threaded NumPy, bounded in time."""
-    from threadpoolctl import threadpool_limits
-    import oracle
-    from oracle.messenger import messenger_step, setup_from_problem
-    import numpy as np
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        S = setup_from_problem(prob)
-        t_setup = time.perf_counter() - t0
-        m = np.zeros((prob.ncomp, prob.npix))
-        d = prob.d
-        times = []
-        t_start = time.perf_counter()
-        while True:
-            t0 = time.perf_counter()
-            m = messenger_step(S, d, m, 1.0)
-            times.append(time.perf_counter() - t0)
-            if time.perf_counter() - t_start > seconds or len(times) >= 50:
-                break
-    per = float(np.median(times))
-    return {"value": prob.nsamp_total / per, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{len(times)} lambda=1 iterations of the float64 NumPy oracle over the full "
-                       f"{prob.nsamp_total}-sample workload (median {per:.3f} s/iteration; plan setup "
-                       f"{t_setup:.1f} s not included), one host thread")}
 
+
+# ---------------------------------------------------------------------------------------------
+# algorithmic bytes: each TOD-sized stream a pass of the four-pass deterministic design must read
+# or write once, per sample of the workload (the survey's per-pass table; no plan-side tables)
+
+def pass_bytes_per_sample(tod_bytes: int, psi_bytes: int) -> list:
+    """A: d, pix, psi read + transform buffer written; B: buffer read + written; C: buffer read +
+    y written; D: y, pix, psi read.  (The map-sized traffic, ~1% here, is left out.)"""
+    return [2 * tod_bytes + 4 + psi_bytes, 2 * tod_bytes, 2 * tod_bytes, tod_bytes + 4 + psi_bytes]
+
+
+def host_info() -> dict:
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["cores_available"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["cores_available"] = os.cpu_count()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    info["ram_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+# ---------------------------------------------------------------------------------------------
+# inputs
+
+def make_inputs(cfg, dev, log):
+    """The workload in device memory: the large workload is generated on the GPU, the others on the
+    host and copied over (both give a synth.device.DeviceProblem)."""
+    import numpy as np
+    import torch
+    from synth.device import DeviceProblem, make_problem_device
+    if cfg.name == "large2048":
+        return make_problem_device(cfg, dev)
+    from synth import make_problem
+    prob = make_problem(cfg, workers=16)
+    psi = None
+    if prob.psi_index is not None:
+        psi = torch.from_numpy(prob.psi_index.view(np.int16)).to(dev).view(torch.uint16)
+    elif prob.psi is not None:
+        psi = torch.from_numpy(prob.psi).to(dev)
+    return DeviceProblem(cfg=cfg, chunks=np.arange(cfg.ndet), chunk_off=prob.chunk_off, fsample=prob.fsample,
+                         sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=torch.from_numpy(prob.pix).to(dev),
+                         psi=psi, psi_table=prob.psi_table, d=torch.from_numpy(prob.d).to(dev), m_true=prob.m_true)
+
+
+def form_inputs(P, form):
+    """TOD and angles of one form: FP32-mixed takes FP32 TOD and FP32 angles (or the uint16 index),
+    FP64 takes the stored values promoted to FP64 (the uint16 index as it is)."""
+    import torch
+    if form == "mixed":
+        d = P.d if P.d.dtype == torch.float32 else P.d.float()
+        psi = P.psi if (P.psi is None or P.psi.dtype in (torch.uint16, torch.float32)) else P.psi.float()
+    else:
+        d = P.d if P.d.dtype == torch.float64 else P.d.double()
+        psi = P.psi if (P.psi is None or P.psi.dtype in (torch.uint16, torch.float64)) else P.psi.double()
+    return d, psi
+
+
+def build_plan(mm, P, form, psi, **over):
+    kw = dict(ncomp=P.ncomp, npix=P.npix, nx=P.cfg.nx, chunk_off=P.chunk_off, fsample=P.fsample, sigma=P.sigma,
+              fknee=P.fknee, alpha=P.alpha, pix=P.pix, psi=psi, psi_table=P.psi_table,
+              precision=mm.MM_MIXED if form == "mixed" else mm.MM_FP64)
+    kw.update(over)
+    return mm.mm_plan(**kw)
+
+
+# ---------------------------------------------------------------------------------------------
+# one form: plan, warm-up, the timed K iterations, per-pass durations
+
+def run_form(mm, torch, P, form, args, log):
+    import numpy as np
+    dev = P.pix.device
+    d, psi = form_inputs(P, form)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = build_plan(mm, P, form, psi,
+                      map_access={"auto": mm.MM_MAP_AUTO, "gather": mm.MM_MAP_GATHER,
+                                  "projected": mm.MM_MAP_PROJECTED}[args.map_access],
+                      tune=mm.MM_TUNE_MEASURE if args.tune == "measure" else mm.MM_TUNE_STATIC,
+                      binning=mm.MM_BIN_ATOMIC if args.binning == "atomic" else mm.MM_BIN_SORTED)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    stats = mm.mm_plan_binning_stats(plan)
+    log(f"[{form}] plan built in {t_plan:.2f} s ({plan.workspace.numel() / 2**30:.1f} GiB workspace; "
+        f"{stats['sub_batches']} sub-batches, {stats['segments']} segments)")
+    ns = P.nsamp_total
+    m_a = torch.zeros((P.ncomp, P.npix), dtype=torch.float64, device=dev)
+    m_b = torch.zeros_like(m_a)
+    projected = mm.mm_plan_map_access(plan) == mm.MM_MAP_PROJECTED
+    # start from the binned map, as the cooled solve does
+    mm.mm_messenger_iter(plan, d, math.inf, m_a, m_a)
+    if args.warmup > 0:
+        mm.mm_solve(plan, d, [1.0], [args.warmup], m_b, first_inf=False, m0=m_a)
+        m_a, m_b = m_b, m_a
+    torch.cuda.synchronize()
+    # timed region: K chained iterations at lambda = 1 as the solver runs them (one HIP graph; with
+    # projected access only the first iteration runs the projection pass).  The graph of this exact
+    # call is captured by an untimed call first; the timed call replays it.
+    stream = torch.cuda.current_stream()
+    mm.mm_solve(plan, d, [1.0], [args.steps], m_b, first_inf=False, m0=m_a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    mm.mm_solve(plan, d, [1.0], [args.steps], m_b, first_inf=False, m0=m_a)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ms_step = total_ms / args.steps
+    log(f"[{form}] timed {args.steps} iterations (graph replay): {ms_step:.4f} ms each")
+    # per-pass durations: the same K iterations uncaptured, HIP events around every pass on the launch
+    # stream (mm_set_timing); not part of the timed region above
+    mm.mm_set_timing(plan, True)
+    ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev2.record(stream)
+    mm.mm_solve(plan, d, [1.0], [args.steps], m_b, first_inf=False, m0=m_a)
+    ev3.record(stream)
+    torch.cuda.synchronize()
+    timed_passes_ms = ev2.elapsed_time(ev3)
+    pass_ms, pass_n = mm.mm_get_timing(plan)
+    mm.mm_set_timing(plan, False)
+    tod_bytes = 4 if form == "mixed" else 8
+    psi_bytes = 0 if psi is None else psi.element_size()
+    per = pass_bytes_per_sample(tod_bytes, psi_bytes)
+    avg = [pass_ms[i] / max(pass_n[i], 1) for i in range(5)]
+    dom = int(np.argmax(avg[:4]))
+    alg = [b * ns for b in per]
+    achieved = alg[dom] / (avg[dom] * 1e-3) / 1e9
+    khash = kernel_hash()
+    traffic = load_traffic(f"{P.cfg.name}_{form}", khash)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (traffic["passes"][dom]["bytes_per_launch"] if traffic else None),
+            "kernel": PASS_NAMES[dom], "bytes_per_sample": per[dom], "samples_per_launch": ns}
+    non = int((P.pix >= 0).sum().item())
+    out = {
+        "form": form, "value": round(ns / (ms_step * 1e-3), 1), "ms_per_step": round(ms_step, 5),
+        "roofline": roof,
+        "sweep_roofline_frac": round(sum(per) * ns / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "sweep_bytes_per_sample": sum(per),
+        # the bytes no schedule can avoid: d, pix and the on-map angles, each read once per iteration
+        "compulsory_frac": round((ns * (tod_bytes + 4) + non * psi_bytes) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "ms_per_step_with_pass_events": round(timed_passes_ms / args.steps, 5),
+        "map_access": "projected" if projected else "gather",
+        "passes": [{"pass": PASS_NAMES[i], "avg_ms": round(avg[i], 5), "launches": int(pass_n[i]),
+                    "alg_bytes": alg[i] if i < 4 else None,
+                    "GBs": round(alg[i] / (avg[i] * 1e-3) / 1e9, 1) if (i < 4 and avg[i] > 0) else None}
+                   for i in range(5)],
+        "plan_s": round(t_plan, 2), "workspace_GiB": round(plan.workspace.numel() / 2 ** 30, 2),
+        "binning_lists": stats, "kernel_hash": khash, "layouts": layout_summary(mm, plan),
+    }
+    plan.close()
+    del plan, d
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+# time to a chi^2 target
 
 def _first_at_or_below(hist, target):
     import numpy as np
@@ -249,101 +371,197 @@ def _first_at_or_below(hist, target):
     return int(idx[0]) if idx.size else None
 
 
-def time_to_chi2(mm, torch, prob, cfg, dev, plans, d_by_plan, deltas=(1e-5, 1e-4, 1e-3)):
-    """Wall time (HIP events around the replayed graph / the CG loop) to reach chi2_ref (1 + delta).
-
-    chi2_ref: the lower of a long FP64 messenger run (16 x 10 then 300 iterations at lambda = 1)
-    and FP64 PCG run to 2000 iterations.  Compared: the cooled messenger in FP64 and FP32-mixed
-    with the workload's schedule (plus a lambda = 1 tail), and FP64 PCG from zero.
-    """
-    import numpy as np
-    p64 = plans["fp64"]
-    d64 = d_by_plan["fp64"]
-    shape = (prob.ncomp, prob.npix)
+def time_to_chi2(mm, torch, P, log, tail: int, cg_max: int, deltas=(1e-5, 1e-4, 1e-3)):
+    """Wall time (HIP events around a replayed solve graph, or around the CG loop) to reach
+    chi2_ref (1 + delta).  chi2_ref is the lower of the FP64 messenger run below continued at
+    lambda = 1 and FP64 PCG to a relative residual of 1e-10.  Compared: the cooled messenger in
+    FP64 and FP32-mixed (the workload's schedule, then `tail` iterations at lambda = 1) and FP64
+    PCG from zero.  One plan at a time."""
+    dev = P.pix.device
+    cfg = P.cfg
+    shape = (P.ncomp, P.npix)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    # reference chi^2
-    lv = mm.mm_cooling_levels(p64, 16, 0.0)
-    m = torch.zeros(shape, dtype=torch.float64, device=dev)
-    mm.mm_solve(p64, d64, lv + [1.0], [10] * 16 + [300], m)
-    chi_m = mm.mm_chi2(p64, d64, m)
-    mc = torch.zeros_like(m)
-    mm.mm_cg_solve(p64, mc, 2000, d=d64, rtol=1e-12)
-    chi_c = mm.mm_chi2(p64, d64, mc)
-    ref = min(chi_m, chi_c)
-    out = {"chi2_ref": ref, "chi2_ref_source": "messenger 16x10+300" if chi_m <= chi_c else "pcg 2000",
-           "nsamp": prob.nsamp_total, "targets": {}}
-    levels = mm.mm_cooling_levels(p64, cfg.nlevel, cfg.lambda_max or 0.0)
-    tail = 200
-    lams = levels + [1.0]
-    its = [cfg.iters_per_level] * cfg.nlevel + [tail]
-    nit = 1 + sum(its)
-    runs = {}
+    runs, times, its_of = {}, {}, {}
+    out = {"nsamp": P.nsamp_total, "targets": {}}
+    cg_hist = None
+    chi_cg = None
+    lams = its = None
     for form in ("fp64", "mixed"):
-        if form not in plans:
-            continue
-        pl, dd = plans[form], d_by_plan[form]
+        d, psi = form_inputs(P, form)
+        plan = build_plan(mm, P, form, psi)
+        if lams is None:
+            levels = mm.mm_cooling_levels(plan, cfg.nlevel, cfg.lambda_max or 0.0)
+            lams = levels + [1.0]
+            its = [cfg.iters_per_level] * cfg.nlevel + [tail]
+        nit = 1 + sum(its)
+        m = torch.zeros(shape, dtype=torch.float64, device=dev)
         h = torch.zeros(nit + 1, dtype=torch.float64, device=dev)
-        mm.mm_solve(pl, dd, lams, its, m, chi2_hist=h)
+        mm.mm_solve(plan, d, lams, its, m, chi2_hist=h)
         torch.cuda.synchronize()
         runs[form] = h.cpu().numpy()
-    maxcg = 500
-    hc = torch.zeros(maxcg + 1, dtype=torch.float64, device=dev)
-    mm.mm_cg_solve(p64, mc, maxcg, d=d64, chi2_hist=hc)
-    torch.cuda.synchronize()
-    cg_hist = hc.cpu().numpy()
+        log(f"[chi2] {form} messenger history: {nit} iterations")
+        if form == "fp64":
+            mc = torch.zeros(shape, dtype=torch.float64, device=dev)
+            hc = torch.zeros(cg_max + 1, dtype=torch.float64, device=dev)
+            n_cg = mm.mm_cg_solve(plan, mc, cg_max, d=d, chi2_hist=hc, rtol=1e-10)
+            torch.cuda.synchronize()
+            cg_hist = hc.cpu().numpy()[: n_cg + 1]
+            chi_cg = mm.mm_chi2(plan, d, mc)
+            log(f"[chi2] fp64 PCG: {n_cg} iterations")
+            ref = min(float(runs["fp64"][-1]), chi_cg)
+            out["chi2_ref"] = ref
+            out["chi2_ref_source"] = (f"messenger FP64, schedule + {tail} at lambda=1" if runs["fp64"][-1] <= chi_cg
+                                      else f"FP64 PCG, {n_cg} iterations (relative residual 1e-10)")
+        ref = out["chi2_ref"]
 
-    def timed_solve(pl, dd, niters):
-        # schedule prefix of niters iterations (first the lambda = inf step)
-        rem = niters - 1
-        lam_p, it_p = [], []
-        for lam, k in zip(lams, its):
-            if rem <= 0:
-                break
-            take = min(k, rem)
-            lam_p.append(lam)
-            it_p.append(take)
-            rem -= take
-        mm.mm_solve(pl, dd, lam_p, it_p, m)  # capture
-        torch.cuda.synchronize()
-        e0, e1 = ev(), ev()
-        e0.record()
-        mm.mm_solve(pl, dd, lam_p, it_p, m)  # replay
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1)
-
-    for delta in deltas:
-        target = ref * (1 + delta)
-        row = {}
-        for form, hist in runs.items():
-            i = _first_at_or_below(hist, target)  # hist[i] = chi2 of the map after i iterations
-            row[f"messenger_{form}"] = ({"iterations": i, "ms": round(timed_solve(plans[form], d_by_plan[form], i), 3)}
-                                        if i is not None and i > 0 else {"iterations": None, "ms": None})
-        i = _first_at_or_below(cg_hist, target)
-        if i is not None and i > 0:
+        def timed_solve(niters):
+            # schedule prefix of niters iterations (the lambda = inf step first)
+            rem = niters - 1
+            lam_p, it_p = [], []
+            for lam, k in zip(lams, its):
+                if rem <= 0:
+                    break
+                take = min(k, rem)
+                lam_p.append(lam)
+                it_p.append(take)
+                rem -= take
+            mm.mm_solve(plan, d, lam_p, it_p, m)  # capture
+            torch.cuda.synchronize()
             e0, e1 = ev(), ev()
             e0.record()
-            mm.mm_cg_solve(p64, mc, i, d=d64)
+            mm.mm_solve(plan, d, lam_p, it_p, m)  # replay
             e1.record()
             torch.cuda.synchronize()
-            row["cg_fp64"] = {"iterations": i, "ms": round(e0.elapsed_time(e1), 3)}
-        else:
-            row["cg_fp64"] = {"iterations": None, "ms": None, "chi2_after_500": float(cg_hist[-1])}
-        out["targets"][f"{delta:g}"] = row
+            return e0.elapsed_time(e1)
+
+        for delta in deltas:
+            i = _first_at_or_below(runs[form], ref * (1 + delta))  # hist[i]: chi^2 after i iterations
+            row = out["targets"].setdefault(f"{delta:g}", {})
+            row[f"messenger_{form}"] = ({"iterations": i, "ms": round(timed_solve(i), 3)}
+                                        if i is not None and i > 0 else {"iterations": None, "ms": None})
+            if form == "fp64":
+                j = _first_at_or_below(cg_hist, ref * (1 + delta))
+                if j is not None and j > 0:
+                    mc.zero_()
+                    e0, e1 = ev(), ev()
+                    e0.record()
+                    mm.mm_cg_solve(plan, mc, j, d=d)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    row["cg_fp64"] = {"iterations": j, "ms": round(e0.elapsed_time(e1), 3)}
+                else:
+                    row["cg_fp64"] = {"iterations": None, "ms": None, "chi2_last": float(cg_hist[-1])}
+        plan.close()
+        del plan, d
+        torch.cuda.empty_cache()
     out["schedule"] = f"1 + {cfg.nlevel}x{cfg.iters_per_level} + {tail} at lambda=1"
+    out["chi2_final"] = {k: float(v[-1]) for k, v in runs.items()}
+    out["chi2_cg_final"] = chi_cg
     return out
 
+
+# ---------------------------------------------------------------------------------------------
+# the CPU oracle on a bounded sample of the workload
+
+_BARRIER = None
+
+
+def _oracle_init(barrier):
+    global _BARRIER
+    _BARRIER = barrier
+
+
+def _oracle_worker(path, niter, wait):
+    """One process: the oracle's plan set-up, then `niter` timed messenger steps (after all the
+    processes of a group have set up, when `wait`)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.messenger import make_setup, messenger_step
+    z = np.load(path)
+    with threadpool_limits(limits=1):
+        S = make_setup(z["chunk_off"], z["fsample"], z["sigma"], z["fknee"], z["alpha"], z["pix"],
+                       z["psi"] if z["psi"].size else None, int(z["npix"]), int(z["ncomp"]))
+        d = z["d"]
+        m = np.zeros((S.ncomp, S.npix))
+        if wait:
+            _BARRIER.wait()
+        times = []
+        for _ in range(niter):
+            t0 = time.perf_counter()
+            m = messenger_step(S, d, m, 1.0)
+            times.append(time.perf_counter() - t0)
+    return int(z["chunk_off"][-1]), times
+
+
+def cpu_baseline(P, seconds: float, log):
+    """The oracle's messenger step (lambda = 1, float64 NumPy) on detector chunks of the workload
+    itself, copied from the device: on one host thread over the first 16 chunks, and on all
+    available cores as one process per core, each on chunks of its own, timed together."""
+    import multiprocessing as mp
+    import tempfile
+    from concurrent.futures import ProcessPoolExecutor
+    import numpy as np
+    info = host_info()
+    ncores = max(1, min(16, info.get("cores_available") or 1))
+    nsub = min(16, P.nchunk)
+    tmp = tempfile.mkdtemp(prefix="mm_oracle_")
+    ctx = mp.get_context("spawn")
+
+    def dump(name, idx):
+        h = P.host_chunks(idx)
+        path = os.path.join(tmp, name + ".npz")
+        np.savez(path, npix=P.npix, ncomp=P.ncomp, psi=h["psi"] if h["psi"] is not None else np.zeros(0),
+                 **{k: v for k, v in h.items() if k != "psi"})
+        return path, int(h["chunk_off"][-1])
+
+    try:
+        # one thread, 16 chunks
+        path, ns1 = dump("single", list(range(nsub)))
+        with ProcessPoolExecutor(max_workers=1, mp_context=ctx) as ex:
+            n1, times1 = ex.submit(_oracle_worker, path, 3, False).result(timeout=max(600.0, 40 * seconds))
+        per1 = float(np.median(times1))
+        log(f"[cpu] oracle, one thread, {nsub} chunks: {per1:.2f} s per iteration")
+        # all cores: one process per core, chunk groups of their own, timed together
+        per_worker = max(1, min(4, P.nchunk // ncores))
+        paths = []
+        for w in range(ncores):
+            idx = [(w * per_worker + k) % P.nchunk for k in range(per_worker)]
+            paths.append(dump(f"w{w}", idx)[0])
+        bar = ctx.Barrier(ncores)
+        with ProcessPoolExecutor(max_workers=ncores, mp_context=ctx, initializer=_oracle_init,
+                                 initargs=(bar,)) as ex:
+            futs = [ex.submit(_oracle_worker, p_, 2, True) for p_ in paths]
+            res = [f.result(timeout=max(900.0, 60 * seconds)) for f in futs]
+        rate_all = sum(n / float(np.median(t)) for n, t in res)
+        log(f"[cpu] oracle, {ncores} processes: {rate_all:.3e} samples/s together")
+    finally:
+        import shutil
+        shutil.rmtree(tmp, ignore_errors=True)
+    return {"value": round(rate_all, 1), "unit": "samples/s", "cores": ncores, "kind": "oracle",
+            "sample": (f"float64 NumPy oracle, lambda=1 messenger iterations on chunks of this workload with the "
+                       f"full {P.cfg.nx}x{P.cfg.nx} map: {ncores} single-threaded processes at once, each on "
+                       f"{per_worker} chunk(s) of its own (median of 2 iterations each), summed; the rate is per "
+                       f"sample, so it extrapolates linearly to all {P.nsamp_total} samples"),
+            "single_thread": {"value": round(ns1 / per1, 1), "unit": "samples/s", "cores": 1,
+                              "sample": f"{nsub} chunks ({ns1} samples), median of 3 iterations, {per1:.2f} s each"},
+            "host": info}
+
+
+# ---------------------------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="iqu256")
+    ap.add_argument("--workload", default="large2048")
+    ap.add_argument("--forms", default="mixed,fp64",
+                    help="comma list of forms to time: mixed (FP32 TOD/transforms), fp64; the first gives value")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--mixed", action="store_true", help="run the FP32-mixed form (FP32 TOD and angles)")
     ap.add_argument("--no-chi2", action="store_true", help="skip the time-to-chi2-target comparison")
+    ap.add_argument("--chi2-tail", type=int, default=60, help="lambda = 1 iterations after the schedule")
+    ap.add_argument("--cg-max", type=int, default=150)
     ap.add_argument("--map-access", choices=["auto", "gather", "projected"], default="auto",
                     help="how the time-domain sweeps read P m (the plan's rule by default)")
     ap.add_argument("--binning", choices=["sorted", "atomic"], default="sorted",
@@ -354,15 +572,18 @@ def main():
                     help="also run one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no GPU run: read two rocprofv3 --pmc outputs (FETCH_SIZE, WRITE_SIZE) of a "
-                         "--copy-calibration run of this workload and write profiles/traffic_<workload>.json")
+                         "--copy-calibration run of one form and write profiles/traffic_<workload>_<form>.json")
     ap.add_argument("--summarize-counters", metavar="PMC_DIR", nargs="+",
                     help="print per-kernel shader-counter ratios from rocprofv3 --pmc runs of SQ_ counters")
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
                     help="no GPU run: per-kernel launch count and mean duration of the workload's dispatches "
                          "in a rocprofv3 --kernel-trace output (markdown table)")
     args = ap.parse_args()
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    if any(f not in ("mixed", "fp64") for f in forms) or not forms:
+        ap.error("--forms takes mixed and/or fp64")
     if args.write_traffic:
-        write_traffic(args, *args.write_traffic)
+        write_traffic(args, forms[0], *args.write_traffic)
         return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
@@ -376,9 +597,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from synth import config_by_name, make_problem
+    from synth import config_by_name
     from paper_1705_01893_amd import mm
 
     if not torch.cuda.is_available():
@@ -389,73 +609,13 @@ def main():
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
     log(f"generating {cfg.name}")
     t0 = time.perf_counter()
-    prob = make_problem(cfg, workers=16)
+    P = make_inputs(cfg, dev, log)
+    torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
-    log(f"generated {prob.nsamp_total} samples in {t_gen:.1f} s")
-    mixed = args.mixed or cfg.tod_dtype == "f32"
-    precision = mm.MM_MIXED if mixed else mm.MM_FP64
-    tod_np = prob.d.astype(np.float32 if mixed else np.float64)
-    d = torch.from_numpy(tod_np).to(dev)
-    pix = torch.from_numpy(prob.pix).to(dev)
-    psi = None
-    psi_bytes = 0
-    if prob.ncomp == 3:
-        if prob.psi_index is not None:
-            psi = torch.from_numpy(prob.psi_index.view(np.int16)).to(dev).view(torch.uint16)
-            psi_bytes = 2
-        else:
-            ps = prob.psi.astype(np.float32) if mixed else prob.psi.astype(np.float64)
-            psi = torch.from_numpy(ps).to(dev)
-            psi_bytes = ps.dtype.itemsize
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan = mm.mm_plan(ncomp=prob.ncomp, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off,
-                      fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=pix,
-                      psi=psi, psi_table=prob.psi_table, precision=precision,
-                      map_access={"auto": mm.MM_MAP_AUTO, "gather": mm.MM_MAP_GATHER,
-                                  "projected": mm.MM_MAP_PROJECTED}[args.map_access],
-                      tune=mm.MM_TUNE_MEASURE if args.tune == "measure" else mm.MM_TUNE_STATIC,
-                      binning=mm.MM_BIN_ATOMIC if args.binning == "atomic" else mm.MM_BIN_SORTED)
-    t_plan = time.perf_counter() - t0
-    log(f"plan built in {t_plan:.1f} s ({plan.workspace.numel() / 2**30:.2f} GiB of workspace)")
-    ns = prob.nsamp_total
-    m_a = torch.zeros((prob.ncomp, prob.npix), dtype=torch.float64, device=dev)
-    m_b = torch.zeros_like(m_a)
-    access = mm.mm_plan_map_access(plan)
-    projected = access == mm.MM_MAP_PROJECTED
-    log(f"map access: {'projected P m buffer' if projected else 'per-sample gather'}")
-    # start from the binned map, as the cooled solve does
-    mm.mm_messenger_iter(plan, d, math.inf, m_a, m_a)
-    if args.warmup > 0:
-        mm.mm_solve(plan, d, [1.0], [args.warmup], m_b, first_inf=False, m0=m_a)
-        m_a, m_b = m_b, m_a
-    torch.cuda.synchronize()
-
-    # timed region: K chained iterations at lambda = 1 as the solver runs them (one HIP graph;
-    # with projected access only the first iteration runs the projection pass).  The graph for
-    # this exact call is captured by an untimed call first; the timed call replays it.
-    stream = torch.cuda.current_stream()
-    mm.mm_solve(plan, d, [1.0], [args.steps], m_b, first_inf=False, m0=m_a)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    mm.mm_solve(plan, d, [1.0], [args.steps], m_b, first_inf=False, m0=m_a)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    log(f"timed {args.steps} iterations (graph replay): {total_ms / args.steps:.4f} ms each")
-    # per-pass durations: the same K iterations uncaptured, HIP events around every pass on the
-    # launch stream (mm_set_timing); not part of the timed region above
-    mm.mm_set_timing(plan, True)
-    ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev2.record(stream)
-    mm.mm_solve(plan, d, [1.0], [args.steps], m_b, first_inf=False, m0=m_a)
-    ev3.record(stream)
-    torch.cuda.synchronize()
-    timed_passes_ms = ev2.elapsed_time(ev3)
-    pass_ms, pass_n = mm.mm_get_timing(plan)
-    mm.mm_set_timing(plan, False)
-    log(f"per-pass run: {timed_passes_ms / args.steps:.4f} ms per iteration with events between passes")
+    ns = P.nsamp_total
+    log(f"generated {ns} samples in {t_gen:.1f} s")
+    results = [run_form(mm, torch, P, f, args, log) for f in forms]
+    head = results[0]
     # what a plain device-to-device copy reaches on this GPU (read + write bytes per second):
     # the practical ceiling of a streaming pass, beside the published HBM peak
     csrc = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -476,80 +636,39 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    ms_step = total_ms / args.steps
-    value = ns / (ms_step * 1e-3)
-
-    tod_bytes = 4 if mixed else 8
-    pb = pass_bytes(prob, tod_bytes, psi_bytes, projected)
-    avg = [pass_ms[i] / max(pass_n[i], 1) for i in range(5)]
-    dom = int(np.argmax(avg[:4]))  # the per-iteration passes
-    achieved = pb[dom] / (avg[dom] * 1e-3) / 1e9
-    khash = kernel_hash()
-    traffic = load_traffic(cfg.name + ("_mixed" if args.mixed else ""), khash)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (traffic["passes"][dom]["bytes_per_launch"] if traffic else None),
-            "kernel": PASS_NAMES[dom]}
-    sweep_bytes = sum(pb[:4]) + pb[4] * pass_n[4] / args.steps
-    extra = {
-        "ms_per_step_with_pass_events": round(timed_passes_ms / args.steps, 5),
-        "map_access": "projected" if projected else "gather",
-        "binning": args.binning,
-        "passes": [{"pass": PASS_NAMES[i], "avg_ms": round(avg[i], 5), "launches": int(pass_n[i]),
-                    "alg_bytes": pb[i], "GBs": round(pb[i] / (avg[i] * 1e-3) / 1e9, 1) if avg[i] > 0 else None}
-                   for i in range(5)],
-        "sweep_roofline_frac": round(sweep_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        # the bytes no schedule can avoid: d, pix and the on-map angles, each read once per iteration
-        "compulsory_frac": round((prob.nsamp_total * (tod_bytes + 4) + int((prob.pix >= 0).sum()) * psi_bytes)
-                                 / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "copy_GBs": round(copy_gbs, 1), "copy_frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
-        "plan_s": round(t_plan, 2), "generate_s": round(t_gen, 2), "kernel_hash": khash,
-        "layouts": layout_summary(mm, plan),
-    }
     chi2_block = None
     if not args.no_chi2:
-        plans = {("mixed" if mixed else "fp64"): plan}
-        d_by = {("mixed" if mixed else "fp64"): d}
-        other = None
-        if not mixed:
-            # the FP32-mixed form of the same workload: FP32 TOD and angles
-            d32 = d.float().contiguous()
-            psi32 = psi.float().contiguous() if (psi is not None and psi.dtype == torch.float64) else psi
-            other = "mixed"
-            plans[other] = mm.mm_plan(ncomp=prob.ncomp, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off,
-                                      fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha,
-                                      pix=pix, psi=psi32, psi_table=prob.psi_table, precision=mm.MM_MIXED)
-            d_by[other] = d32
-        else:
-            # the plain FP64 form of the same workload: the stored FP32 TOD and angles promoted
-            d64 = d.double().contiguous()
-            psi64 = psi.double().contiguous() if (psi is not None and psi.dtype == torch.float32) else psi
-            other = "fp64"
-            plans[other] = mm.mm_plan(ncomp=prob.ncomp, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off,
-                                      fsample=prob.fsample, sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha,
-                                      pix=pix, psi=psi64, psi_table=prob.psi_table, precision=mm.MM_FP64)
-            d_by[other] = d64
         log("time to chi^2 target")
-        chi2_block = time_to_chi2(mm, torch, prob, cfg, dev, plans, d_by)
-        plans[other].close()
-        del d_by
+        chi2_block = time_to_chi2(mm, torch, P, log, args.chi2_tail, args.cg_max)
     cpu = None
     if not args.no_cpu:
         log("oracle on the host")
-        cpu = cpu_baseline(prob, args.cpu_seconds)
-    cfg_desc = {"workload": (f"{cfg.name}: {cfg.ndet} detectors x {ns // cfg.ndet if cfg.nsamp == cfg.nsamp_min else 'uneven'} "
-                             f"samples ({ns} total), {cfg.nx}x{cfg.nx} map, ncomp={cfg.ncomp}, "
-                             f"{'FP32-mixed' if mixed else 'FP64'}"),
-                "nsamp": ns, "npix": prob.npix, "ncomp": prob.ncomp, "nchunk": prob.nchunk}
+        cpu = cpu_baseline(P, args.cpu_seconds, log)
+    per_chunk = ns // P.nchunk if len(set(int(x) for x in (P.chunk_off[1:] - P.chunk_off[:-1]))) == 1 else None
+    if P.psi is None:
+        psi_desc = "temperature only"
+    elif P.psi_table is not None:
+        psi_desc = "uint16 angle-table index"
+    else:
+        psi_desc = str(P.psi.dtype).replace("torch.", "") + " angles"
+    form_name = {"mixed": "FP32-mixed", "fp64": "FP64"}
+    cfg_desc = {"workload": (f"{cfg.name}: {P.nchunk} detectors x {per_chunk if per_chunk else 'uneven'} samples "
+                             f"({ns} total), {cfg.nx}x{cfg.nx} map, ncomp={P.ncomp}, {psi_desc}; value: "
+                             f"{form_name[head['form']]}"
+                             + (f", {', '.join(form_name[r['form']] for r in results[1:])} in detail.forms"
+                                if len(results) > 1 else "")),
+                "nsamp": ns, "npix": P.npix, "ncomp": P.ncomp, "nchunk": P.nchunk}
     out = {
-        "metric": "TOD samples/s per messenger iteration", "value": round(value, 1), "unit": "samples/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "metric": "TOD samples/s per messenger iteration", "value": head["value"], "unit": "samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if mixed else "f64", "data": "synthetic", "config": cfg_desc,
-        "roofline": roof, "cpu_baseline": cpu, "time_to_chi2": chi2_block, "detail": extra,
+        "dtype": "f32" if head["form"] == "mixed" else "f64", "data": "synthetic", "config": cfg_desc,
+        "roofline": head["roofline"], "cpu_baseline": cpu, "time_to_chi2": chi2_block,
+        "detail": {"forms": results, "copy_GBs": round(copy_gbs, 1),
+                   "copy_frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4), "generate_s": round(t_gen, 2),
+                   "binning": args.binning},
     }
     print(json.dumps(out))
-    plan.close()
 
 
 if __name__ == "__main__":
