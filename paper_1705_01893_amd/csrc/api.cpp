@@ -445,8 +445,8 @@ mm_status mm_tod_apply(mm_plan_t plan, int32_t which, double lambda, const doubl
 mm_status mm_noise_grad(mm_plan_t plan, const void* d, const double* m, const double* z, double* grad_dev,
                         mm_stream_t stream) {
   if (!plan || !d || !m || !z || !grad_dev) return fail(MM_E_ARG, "null argument");
-  // two rows of both residuals per workgroup: 4 M1 complex values, at most the transform capacity
-  // kBlock * Ept (= 64 KB of LDS)
+  // two rows of both residuals per workgroup: 4 M1 complex values in LDS (at most 64 KB); each
+  // residual's rows are transformed by a call of their own
   if (plan->lds_g > 65536) return fail(MM_E_LEN, "chunk rows too long for the two-spectrum gradient pass");
   hipStream_t s = S(stream);
   if (!plan->d_work2) return fail(MM_E_ARG, "the plan was built without with_adjoint (no second TOD buffer)");

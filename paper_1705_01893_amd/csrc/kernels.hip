@@ -1418,7 +1418,10 @@ __global__ __launch_bounds__(kBlockB) void k_grad_b(DevPlan P, const ItemB* __re
       }
     }
     __syncthreads();
-    lds_fft<T, false, false, kBlockB>(lds, M1, 2 * nrow, 0, cl.rad1, cl.nr1, twtab<T>(P) + cl.tw1);
+    // the rows of r, then those of P z: each call holds at most the row pass's two rows, within
+    // the NT * Ept values a transform call covers
+    lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, twtab<T>(P) + cl.tw1);
+    lds_fft<T, false, false, kBlockB>(lds + off2, M1, nrow, 0, cl.rad1, cl.nr1, twtab<T>(P) + cl.tw1);
     double acc[3] = {0.0, 0.0, 0.0};
     for (int sl = 0; sl < nrow; ++sl) {
       const int row = sl == 0 ? ra : rb;

@@ -169,3 +169,121 @@ def test_large2048_shape_reduced():
     assert np.linalg.norm(m2.cpu().numpy() - r2) / np.linalg.norm(r2) < 1e-5
     assert c2.item() == pytest.approx(chi2(S, prob.d, r1), rel=1e-6)
     plan.close()
+
+
+def test_iqu256_full_schedule():
+    """The benchmark-sized FP64 workload (16 x 2^20, 256x256 I/Q/U) through its whole cooled
+    schedule, 1 + 10 x 10 iterations in one mm_solve graph (Section 3.1): the final map and every
+    chi^2 of the history against the oracle iterating the same schedule."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests.oracle_sweeps import Binned, problem_chunks
+    dev = torch.device("cuda:0")
+    cfg = config_by_name("iqu256")
+    print("[fullsize] generating iqu256", flush=True)
+    prob = make_problem(cfg, workers=16)
+    plan = mm.mm_plan(ncomp=3, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off, fsample=prob.fsample,
+                      sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=torch.from_numpy(prob.pix).to(dev),
+                      psi=torch.from_numpy(prob.psi).to(dev))
+    levels = mm.mm_cooling_levels(plan, cfg.nlevel, 0.0)
+    d = torch.from_numpy(prob.d).to(dev)
+    m = torch.zeros((3, prob.npix), dtype=torch.float64, device=dev)
+    nit = 1 + cfg.nlevel * cfg.iters_per_level
+    h = torch.zeros(nit + 1, dtype=torch.float64, device=dev)
+    mm.mm_solve(plan, d, levels, [cfg.iters_per_level] * cfg.nlevel, m, chi2_hist=h)
+    torch.cuda.synchronize()
+    print("[fullsize] oracle schedule", flush=True)
+    B = Binned(prob.nchunk, problem_chunks(prob), prob.npix, 3, group=1)
+    ref_h = [B.chi2(np.zeros((3, prob.npix)))]
+    mr = B.m_bin
+    for lam in [lv for lv in levels for _ in range(cfg.iters_per_level)]:
+        mr, c = B.step(mr, lam)
+        ref_h.append(c)
+    ref_h.append(B.chi2(mr))
+    e = np.linalg.norm(m.cpu().numpy() - mr) / np.linalg.norm(mr)
+    eh = float(np.max(np.abs(h.cpu().numpy() - np.array(ref_h)) / np.abs(ref_h)))
+    print(f"[fullsize] 1 + 10x10 schedule: map {e:.2e}, chi^2 history {eh:.2e}", flush=True)
+    assert e < 1e-10 and eh < 1e-10
+    plan.close()
+
+
+def test_batched1024_two_chained_iterations():
+    """The 512-chunk uneven FP32-mixed workload at full size (4.4e8 samples) in projected map access:
+    the lambda = inf step and two lambda < inf iterations chained in one mm_solve (each binning pass
+    writes P m of its new map for the next sweep), on every pixel, with the chi^2 history."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests.oracle_sweeps import Binned, problem_chunks
+    dev = torch.device("cuda:0")
+    cfg = config_by_name("batched1024")
+    print("[fullsize] generating batched1024", flush=True)
+    prob = make_problem(cfg, workers=16)
+    plan = mm.mm_plan(ncomp=3, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off, fsample=prob.fsample,
+                      sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=torch.from_numpy(prob.pix).to(dev),
+                      psi=torch.from_numpy(prob.psi).to(dev), precision=mm.MM_MIXED)
+    assert mm.mm_plan_map_access(plan) == mm.MM_MAP_PROJECTED
+    lams = [mm.mm_cooling_levels(plan, cfg.nlevel, 0.0)[cfg.nlevel // 2], 1.0]
+    d = torch.from_numpy(prob.d).to(dev)
+    m = torch.zeros((3, prob.npix), dtype=torch.float64, device=dev)
+    h = torch.zeros(4, dtype=torch.float64, device=dev)
+    mm.mm_solve(plan, d, lams, [1, 1], m, chi2_hist=h)
+    torch.cuda.synchronize()
+    plan.close()
+    print("[fullsize] oracle", flush=True)
+    B = Binned(prob.nchunk, problem_chunks(prob), prob.npix, 3)
+    ref_h = [B.chi2(np.zeros((3, prob.npix)))]
+    mr = B.m_bin
+    for lam in lams:
+        mr, c = B.step(mr, lam)
+        ref_h.append(c)
+    ref_h.append(B.chi2(mr))
+    e = np.linalg.norm(m.cpu().numpy() - mr) / np.linalg.norm(mr)
+    eh = float(np.max(np.abs(h.cpu().numpy() - np.array(ref_h)) / np.abs(ref_h)))
+    print(f"[fullsize] chained iterations at lambda={lams}: map {e:.2e}, chi^2 history {eh:.2e}", flush=True)
+    assert e < 1e-5 and eh < 1e-6
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_grad512_full_size_kernels(form):
+    """The differentiation workload at its size (64 x 2^20, 512x512 I/Q/U): the noise-parameter
+    gradient kernel and dL/dd = N^-1 P z at a given map m (the sky) and adjoint map z (seeded),
+    against the oracle's implicit-gradient formulas on every chunk."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle.grad import data_grad, noise_param_grad
+    from tests.oracle_sweeps import group_setup, problem_chunks
+    dev = torch.device("cuda:0")
+    cfg = config_by_name("grad512")
+    print(f"[fullsize] generating grad512 ({form})", flush=True)
+    prob = make_problem(cfg, workers=16)
+    mixed = form == "mixed"
+    psi = prob.psi if mixed else prob.psi.astype(np.float64)
+    plan = mm.mm_plan(ncomp=3, npix=prob.npix, nx=cfg.nx, chunk_off=prob.chunk_off, fsample=prob.fsample,
+                      sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=torch.from_numpy(prob.pix).to(dev),
+                      psi=torch.from_numpy(psi).to(dev), precision=mm.MM_MIXED if mixed else mm.MM_FP64,
+                      with_adjoint=True)
+    d = torch.from_numpy(prob.d if mixed else prob.d.astype(np.float64)).to(dev)
+    z = np.random.default_rng(5120).standard_normal((3, prob.npix)) * 1e-3
+    g = torch.zeros((prob.nchunk, 3), dtype=torch.float64, device=dev)
+    mm.mm_noise_grad(plan, d, torch.from_numpy(prob.m_true).to(dev), torch.from_numpy(z).to(dev), g)
+    y = torch.zeros_like(d)
+    mm.mm_tod_apply(plan, 0, torch.from_numpy(z).to(dev), y)
+    torch.cuda.synchronize()
+    plan.close()
+    print("[fullsize] oracle", flush=True)
+    S, hh = group_setup(problem_chunks(prob), list(range(prob.nchunk)), prob.npix, 3)
+    ref = noise_param_grad(S, prob.d, prob.m_true, z, prob.fsample, prob.sigma, prob.fknee, prob.alpha)
+    got = g.cpu().numpy()
+    scale = np.abs(ref).max(axis=0)
+    err = np.abs(got - ref) / scale
+    ref_y = data_grad(S, z)
+    ey = np.linalg.norm(y.cpu().numpy().astype(np.float64) - ref_y) / np.linalg.norm(ref_y)
+    print(f"[fullsize] grad512 {form}: noise-parameter gradient max error / largest entry per parameter "
+          f"{err.max(axis=0)}, dL/dd rel-L2 {ey:.2e}", flush=True)
+    # FP32-mixed: the residual d - P m is held in FP32, and its low-frequency 1/f wander (up to
+    # ~1e4 times the white level at f_1 = fs / 2^20 for slopes near -3) sets an absolute rounding
+    # floor that is white: the high-frequency bins, which carry the largest weights 1/N^2 of the
+    # gradient, see it at ~1e-4 of their amplitude (measured 1.8e-4 for sigma, 4e-5 for fknee
+    # and alpha); hence 1e-3 of the largest entry per parameter.  FP64: rounding only.
+    bar, ybar = (1e-3, 1e-5) if mixed else (1e-10, 1e-10)
+    assert err.max() < bar and ey < ybar

@@ -239,3 +239,39 @@ def test_forward_keeps_plan_tau(dev):
     torch.cuda.synchronize()
     assert np.linalg.norm(m2.cpu().numpy() - m_ref) / np.linalg.norm(m_ref) < 1e-10
     plan.close()
+
+
+@pytest.mark.parametrize("precision", [mm.MM_FP64, mm.MM_MIXED])
+def test_noise_grad_long_rows(dev, precision):
+    """Layouts whose rows are long enough that the two rows of both residuals exceed what one
+    transform call covers (4 M1 > 256 threads x values per thread): every candidate layout of a
+    2^17-sample chunk against the oracle's gradient formula."""
+    say(f"[noise_grad long rows] precision={precision}")
+    f64 = precision == mm.MM_FP64
+    t = tiny_problem(48, ncomp=3, lengths=(1 << 17, 1 << 16), nx=16, psi_dtype=np.float64 if f64 else np.float32,
+                     tod_dtype=np.float64 if f64 else np.float32)
+    S = _setup(t)
+    m = random_map(11, 3, t.npix)
+    z = random_map(12, 3, t.npix)
+    ref = noise_param_grad(S, t.d.astype(np.float64), m, z, t.fsample, t.sigma, t.fknee, t.alpha)
+    psi = torch.from_numpy(t.psi).to(dev)
+    seen = set()
+    for pick in range(12):
+        plan = mm.mm_plan(ncomp=3, npix=t.npix, nx=t.nx, chunk_off=t.chunk_off, fsample=t.fsample, sigma=t.sigma,
+                          fknee=t.fknee, alpha=t.alpha, pix=torch.from_numpy(t.pix).to(dev), psi=psi,
+                          precision=precision, with_adjoint=True, tune=mm.MM_TUNE_PICK0 + pick)
+        lay = mm.mm_plan_chunk_layout(plan, 0)
+        key = (lay["M1"], lay["M2"], lay["cb"])
+        if key not in seen:
+            seen.add(key)
+            out = torch.zeros((plan.nchunk, 3), dtype=torch.float64, device=dev)
+            mm.mm_noise_grad(plan, torch.from_numpy(t.d).to(dev), torch.from_numpy(m).to(dev),
+                             torch.from_numpy(z).to(dev), out)
+            torch.cuda.synchronize()
+            err = float(np.max(np.abs(out.cpu().numpy() - ref) / np.abs(ref).max(axis=0)))
+            say(f"  layout {key}: max error / largest entry {err:.2e}")
+            assert err < (1e-10 if f64 else 1e-3), key
+        plan.close()
+        if pick + 1 >= lay["ncand"]:
+            break
+    assert max(k[0] for k in seen) * 4 > 256 * (8 if f64 else 16)
