@@ -246,6 +246,19 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const double* rhs_map, const m
                    const double* m0, double* m_out, double* chi2_hist_dev, mm_stream_t stream);
 
 /*
+ * The cooled messenger solve in its map-sized form (Section 2.1, eqns. md and F;
+ * Section 4.1): each level first forms m_d(lambda) = W^-1 P^T (lambda^-1 N-bar + T)^-1 d
+ * (one sweep that reads the data), and its iterations then apply
+ * m_{i+1} = m_d(lambda) + F(lambda) m_i, F(lambda) m = m - W^-1 P^T (lambda^-1 N-bar + T)^-1 P m,
+ * without reading d.  Equal to mm_solve's iterates in exact arithmetic (Woodbury); the
+ * lambda = inf step is the binned map as there.  Same schedule, start map and graph
+ * capture/replay as mm_solve (the one cached graph is shared); no chi^2 history (the
+ * iterations never form d - P m: use mm_chi2 on the result).
+ */
+mm_status mm_solve_mapsized(mm_plan_t plan, const void* d, const mm_schedule* sched, const double* m0,
+                            double* m_out, mm_stream_t stream);
+
+/*
  * Geometric cooling levels (Section 3.1): lambda_l = lambda_max^((nlevel-1-l)/(nlevel-1)),
  * ending at exactly 1.  lambda_max <= 0 selects the rule lambda_max = max_c N_c(f_0) / tau_c
  * (lambda tau spans the noise power).  out: host array of nlevel doubles.

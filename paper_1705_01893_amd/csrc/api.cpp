@@ -160,6 +160,67 @@ mm_status lift(mm_plan_s* pl, const double* g, void* out, hipStream_t s) {
 
 bool valid_lambda(double lam) { return std::isinf(lam) ? lam > 0 : (lam >= 1.0 && std::isfinite(lam)); }
 
+// the schedule as one lambda per iteration (lambda = inf first when asked)
+mm_status expand_schedule(const mm_schedule* sched, std::vector<double>& lams) {
+  if (sched->nlevel < 0 || (sched->nlevel > 0 && (!sched->lambda || !sched->iters)))
+    return fail(MM_E_ARG, "invalid schedule");
+  if (sched->first_inf) lams.push_back(INFINITY);
+  for (int l = 0; l < sched->nlevel; ++l) {
+    if (sched->iters[l] < 0 || !valid_lambda(sched->lambda[l])) return fail(MM_E_ARG, "invalid schedule level");
+    for (int i = 0; i < sched->iters[l]; ++i) lams.push_back(sched->lambda[l]);
+  }
+  return MM_OK;
+}
+
+// Run a solve body on `stream`: captured into the plan's one cached HIP graph (replayed when the
+// key, i.e. the buffers and the schedule, equals the previous call's), or directly when per-pass
+// timing is on (events between the passes cannot be recorded inside a capture).
+template <typename F>
+mm_status run_graph(mm_plan_s* plan, const std::vector<double>& key, mm_stream_t stream, F&& body) {
+  // per-pass timing records events between the passes: run on the caller's stream, uncaptured
+  if (plan->timing) return body(S(stream));
+  if (plan->solve_exec && key == plan->solve_key) {
+    MM_TRY_HIP(hipGraphLaunch(plan->solve_exec, S(stream)));
+    MM_TRY_HIP(hipEventRecord(plan->solve_done, S(stream)));
+    return MM_OK;
+  }
+  hipStream_t cs = plan->cap_stream;
+  MM_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  plan->capturing = true;
+  mm_status st = body(cs);
+  plan->capturing = false;
+  hipGraph_t graph = nullptr;
+  hipError_t ee = hipStreamEndCapture(cs, &graph);
+  if (st != MM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph capture: ") + hipGetErrorString(ee));
+  hipGraphExec_t exec = nullptr;
+  ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ee));
+  // one cached solve graph: the previous one is destroyed once its last launch has completed
+  if (plan->solve_exec) {
+    (void)hipEventSynchronize(plan->solve_done);
+    (void)hipGraphExecDestroy(plan->solve_exec);
+    plan->solve_exec = nullptr;
+    plan->solve_key.clear();
+  }
+  if (!plan->solve_done && (ee = hipEventCreateWithFlags(&plan->solve_done, hipEventDisableTiming)) != hipSuccess) {
+    plan->solve_done = nullptr;
+    (void)hipGraphExecDestroy(exec);
+    return fail(MM_E_HIP, std::string("event create: ") + hipGetErrorString(ee));
+  }
+  plan->solve_exec = exec;  // owned by the plan from here on; replayed only once the key is set
+  ee = hipGraphLaunch(exec, S(stream));
+  if (ee == hipSuccess) ee = hipEventRecord(plan->solve_done, S(stream));
+  if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph launch: ") + hipGetErrorString(ee));
+  plan->solve_key = key;
+  return MM_OK;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -320,14 +381,8 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const double* rhs_map, const m
   if (!plan || !sched || !m_out) return fail(MM_E_ARG, "null argument");
   if ((d == nullptr) == (rhs_map == nullptr)) return fail(MM_E_ARG, "give exactly one of d and rhs_map");
   if (rhs_map && !plan->d_work2) return fail(MM_E_ARG, "a map right-hand side needs a plan built with_adjoint");
-  if (sched->nlevel < 0 || (sched->nlevel > 0 && (!sched->lambda || !sched->iters)))
-    return fail(MM_E_ARG, "invalid schedule");
   std::vector<double> lams;
-  if (sched->first_inf) lams.push_back(INFINITY);
-  for (int l = 0; l < sched->nlevel; ++l) {
-    if (sched->iters[l] < 0 || !valid_lambda(sched->lambda[l])) return fail(MM_E_ARG, "invalid schedule level");
-    for (int i = 0; i < sched->iters[l]; ++i) lams.push_back(sched->lambda[l]);
-  }
+  MM_TRY(expand_schedule(sched, lams));
   const int64_t n = mapn(plan);
   // with a map right-hand side g the data are the lifted TOD N T^-1 P W^-1 g (second TOD buffer)
   const void* dd = rhs_map ? plan->d_work2 : d;
@@ -346,55 +401,57 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const double* rhs_map, const m
     if (chi2_hist_dev) MM_TRY(chi2_device(plan, dd, m_out, 1.0, chi2_hist_dev + nit, nullptr, cs, nit > 0));
     return MM_OK;
   };
-  // per-pass timing records events between the passes: run on the caller's stream, uncaptured
-  if (plan->timing) return body(S(stream));
-  // replay the previous graph when the call is identical (same buffers, same schedule)
-  std::vector<double> key;
-  key.push_back((double)(uintptr_t)d);
-  key.push_back((double)(uintptr_t)rhs_map);
-  key.push_back((double)(uintptr_t)m0);
-  key.push_back((double)(uintptr_t)m_out);
-  key.push_back((double)(uintptr_t)chi2_hist_dev);
+  std::vector<double> key = {0.0, (double)(uintptr_t)d, (double)(uintptr_t)rhs_map, (double)(uintptr_t)m0,
+                             (double)(uintptr_t)m_out, (double)(uintptr_t)chi2_hist_dev};
   key.insert(key.end(), lams.begin(), lams.end());
-  if (plan->solve_exec && key == plan->solve_key) {
-    MM_TRY_HIP(hipGraphLaunch(plan->solve_exec, S(stream)));
-    MM_TRY_HIP(hipEventRecord(plan->solve_done, S(stream)));
+  return run_graph(plan, key, stream, body);
+}
+
+mm_status mm_solve_mapsized(mm_plan_t plan, const void* d, const mm_schedule* sched, const double* m0,
+                            double* m_out, mm_stream_t stream) {
+  if (!plan || !d || !sched || !m_out) return fail(MM_E_ARG, "null argument");
+  std::vector<double> lams;
+  MM_TRY(expand_schedule(sched, lams));
+  const int64_t n = mapn(plan);
+  double* md = plan->d_map[3];
+  double* b = plan->d_map[4];
+  auto body = [&](hipStream_t cs) -> mm_status {
+    if (m0) {
+      if (m0 != m_out) MM_TRY_HIP(launch_copy(m_out, m0, n, cs));
+    } else {
+      MM_TRY_HIP(launch_fill(m_out, n, 0.0, cs));
+    }
+    DevPlan P = plan->dp;
+    P.md = md;
+    const size_t nit = lams.size();
+    for (size_t i = 0; i < nit; ++i) {
+      const double lam = lams[i];
+      if (std::isinf(lam)) {  // m_d(inf) = W^-1 P^T T^-1 d and F(inf) = 0: the binned map
+        MM_TRY(iterate(plan, d, lam, m_out, m_out, nullptr, cs, i > 0));
+        continue;
+      }
+      if (i == 0 || lams[i - 1] != lam) {
+        // a new level: m_d(lambda) = W^-1 P^T (lambda^-1 N-bar + T)^-1 d, the one sweep of the level
+        // that reads the data (it leaves the map-derived P m / interleaved copy untouched)
+        MM_TRY(apply_op(plan, GAIN_MESSENGER, lam, nullptr, d, b, cs));
+        MM_TRY_HIP(launch_winv_apply(plan->dp, b, md, cs));
+      }
+      // m <- m_d + F(lambda) m = m_d + m - W^-1 P^T (lambda^-1 N-bar + T)^-1 P m
+      MM_TRY(sweep_filter(plan, nullptr, m_out, SRC_PM, B_FILTER, GAIN_MESSENGER, lam, 1.0, cs, i > 0));
+      MM_TRY_HIP(timed(plan, 3, cs, [&] {
+        if (plan->bin_atomic) {
+          hipError_t e = launch_fill(plan->d_batom, n, 0.0, cs);
+          if (e == hipSuccess) e = launch_bin_atomic(P, BSRC_WORK, plan->d_work, plan->d_batom, plan->max_n, cs);
+          return e != hipSuccess ? e : launch_update(P, EPI_MAPSIZED, m_out, plan->d_batom, m_out, cs);
+        }
+        return launch_bin(P, BSRC_WORK, plan->d_work, EPI_MAPSIZED, m_out, m_out, nullptr, nullptr, cs, plan->d_pm);
+      }));
+    }
     return MM_OK;
-  }
-  hipStream_t cs = plan->cap_stream;
-  MM_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  plan->capturing = true;
-  mm_status st = body(cs);
-  plan->capturing = false;
-  hipGraph_t graph = nullptr;
-  hipError_t ee = hipStreamEndCapture(cs, &graph);
-  if (st != MM_OK) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return st;
-  }
-  if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph capture: ") + hipGetErrorString(ee));
-  hipGraphExec_t exec = nullptr;
-  ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ee));
-  // one cached solve graph: the previous one is destroyed once its last launch has completed
-  if (plan->solve_exec) {
-    (void)hipEventSynchronize(plan->solve_done);
-    (void)hipGraphExecDestroy(plan->solve_exec);
-    plan->solve_exec = nullptr;
-    plan->solve_key.clear();
-  }
-  if (!plan->solve_done && (ee = hipEventCreateWithFlags(&plan->solve_done, hipEventDisableTiming)) != hipSuccess) {
-    plan->solve_done = nullptr;
-    (void)hipGraphExecDestroy(exec);
-    return fail(MM_E_HIP, std::string("event create: ") + hipGetErrorString(ee));
-  }
-  plan->solve_exec = exec;  // owned by the plan from here on; replayed only once the key is set
-  ee = hipGraphLaunch(exec, S(stream));
-  if (ee == hipSuccess) ee = hipEventRecord(plan->solve_done, S(stream));
-  if (ee != hipSuccess) return fail(MM_E_HIP, std::string("graph launch: ") + hipGetErrorString(ee));
-  plan->solve_key = key;
-  return MM_OK;
+  };
+  std::vector<double> key = {1.0, (double)(uintptr_t)d, (double)(uintptr_t)m0, (double)(uintptr_t)m_out};
+  key.insert(key.end(), lams.begin(), lams.end());
+  return run_graph(plan, key, stream, body);
 }
 
 mm_status mm_chi2(mm_plan_t plan, const void* d, const double* m, double lambda, double* chi2_host,

@@ -150,6 +150,7 @@ struct DevPlan {
   const uint8_t* solvable;   // [npix]
   double2* mapi;             // I/Q/U map interleaved, [npix][2] = (I, Q), (U, 0): one line per gather
                              // (gather access with ncomp = 3; null otherwise)
+  const double* md;          // m_d(lambda) of the map-sized form (EPI_MAPSIZED launches only)
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -226,7 +227,8 @@ enum {
 enum { GAIN_MESSENGER = 0, GAIN_NINV = 1, GAIN_LIFT = 2 };
 // binning sources / epilogues
 enum { BSRC_WORK = 0, BSRC_DATA_OVER_TAU = 1, BSRC_PLAN = 2 };
-enum { EPI_WRITE_B = 0, EPI_UPDATE = 1, EPI_REPLACE = 2, EPI_PLAN = 3 };
+// EPI_MAPSIZED: m_out = m_d + m_in - W^-1 b (DevPlan::md), the map-sized form of an iteration
+enum { EPI_WRITE_B = 0, EPI_UPDATE = 1, EPI_REPLACE = 2, EPI_PLAN = 3, EPI_MAPSIZED = 4 };
 
 // ---------------------------------------------------------------------------------------------
 // kernel launchers (kernels.hip)

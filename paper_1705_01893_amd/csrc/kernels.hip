@@ -1341,19 +1341,22 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
           double r = 0.0;
-          if (ok) r = (epi == EPI_UPDATE) ? m_in[q * np + p] + u[q] : u[q];
+          if (ok)
+            r = (epi == EPI_UPDATE)     ? m_in[q * np + p] + u[q]
+                : (epi == EPI_MAPSIZED) ? P.md[q * np + p] + m_in[q * np + p] - u[q]
+                                        : u[q];
           out[q * np + p] = r;
           rr[q] = r;
           if (!PLAN && pm_out) acc[l * NV + q] = r;  // the tile's new map values, for P m below
         }
-        if (NV == 3 && P.mapi && (epi == EPI_UPDATE || epi == EPI_REPLACE)) {
+        if (NV == 3 && P.mapi && (epi == EPI_UPDATE || epi == EPI_REPLACE || epi == EPI_MAPSIZED)) {
           P.mapi[2 * p] = make_double2(rr[0], rr[NV > 1 ? 1 : 0]);
           P.mapi[2 * p + 1] = make_double2(rr[NV > 2 ? 2 : 0], 0.0);
         }
       }
     }
     __syncthreads();
-    if (!PLAN && pm_out && (epi == EPI_UPDATE || epi == EPI_REPLACE))
+    if (!PLAN && pm_out && (epi == EPI_UPDATE || epi == EPI_REPLACE || epi == EPI_MAPSIZED))
       tile_project<T, (NV == 3 ? 3 : 1), PK>(P, tl, acc, L, sbn, pm_out);
   }
 }
@@ -1832,8 +1835,9 @@ __global__ __launch_bounds__(256) void k_bin_atomic(DevPlan P, int bsrc, const T
   }
 }
 
-// The binning epilogue's per-pixel step from a binned vector b: m_out = m_in + W^-1 b (EPI_UPDATE)
-// or W^-1 b (EPI_REPLACE) on solvable pixels, 0 elsewhere; refreshes the interleaved map.
+// The binning epilogue's per-pixel step from a binned vector b: m_out = m_in + W^-1 b (EPI_UPDATE),
+// W^-1 b (EPI_REPLACE) or m_d + m_in - W^-1 b (EPI_MAPSIZED) on solvable pixels, 0 elsewhere;
+// refreshes the interleaved map.
 template <int NC>
 __global__ __launch_bounds__(256) void k_update(DevPlan P, int epi, const double* __restrict__ m_in,
                                                 const double* __restrict__ b, double* __restrict__ out) {
@@ -1854,7 +1858,10 @@ __global__ __launch_bounds__(256) void k_update(DevPlan P, int epi, const double
     double r[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      if (ok) r[q] = (epi == EPI_UPDATE) ? m_in[q * np + p] + u[q] : u[q];
+      if (ok)
+        r[q] = (epi == EPI_UPDATE)     ? m_in[q * np + p] + u[q]
+               : (epi == EPI_MAPSIZED) ? P.md[q * np + p] + m_in[q * np + p] - u[q]
+                                       : u[q];
       out[q * np + p] = r[q];
     }
     if (NC == 3 && P.mapi) {

@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.mm_messenger_iter.argtypes = [vp, vp, dbl, vp, vp, vp, vp]
     L.mm_solve.argtypes = [vp, vp, vp, ctypes.POINTER(_Sched), vp, vp, vp, vp]
+    L.mm_solve_mapsized.argtypes = [vp, vp, ctypes.POINTER(_Sched), vp, vp, vp]
     L.mm_cooling_levels.argtypes = [vp, i32, dbl, ctypes.POINTER(dbl)]
     L.mm_cg_solve.argtypes = [vp, vp, vp, i32, dbl, vp, vp, vp, vp, ctypes.POINTER(i32), vp]
     L.mm_chi2.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp]
@@ -94,7 +95,7 @@ def lib() -> ctypes.CDLL:
     L.mm_get_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for name in ("mm_plan_set_noise", "mm_tod_apply", "mm_noise_grad", "mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_workspace_bytes_noalloc",
                  "mm_plan_binning_stats", "mm_plan_hits", "mm_plan_solvable",
-                 "mm_plan_nsolvable", "mm_plan_map_access", "mm_plan_chunk_layout", "mm_messenger_iter", "mm_solve", "mm_cooling_levels", "mm_cg_solve",
+                 "mm_plan_nsolvable", "mm_plan_map_access", "mm_plan_chunk_layout", "mm_messenger_iter", "mm_solve", "mm_solve_mapsized", "mm_cooling_levels", "mm_cg_solve",
                  "mm_chi2", "mm_apply", "mm_lift_rhs"):
         getattr(L, name).restype = ctypes.c_int
     L.mm_status_str.argtypes = [ctypes.c_int]
@@ -308,6 +309,23 @@ def mm_solve(plan: Plan, d: Optional[torch.Tensor], lambdas: Sequence[float], it
     _check(lib().mm_solve(plan.handle, _ptr(d, "d", plan.tod_dtype, plan.nsamp), _map_ptr(plan, rhs_map, "rhs_map"),
                           ctypes.byref(sc), _map_ptr(plan, m0, "m0"), _map_ptr(plan, m_out, "m_out"),
                           _ptr(chi2_hist, "chi2_hist", torch.float64, nh), _stream(stream)), "mm_solve")
+
+
+def mm_solve_mapsized(plan: Plan, d: torch.Tensor, lambdas: Sequence[float], iters: Sequence[int],
+                      m_out: torch.Tensor, first_inf: bool = True, m0: Optional[torch.Tensor] = None,
+                      stream=None) -> None:
+    """Cooled messenger solve in the map-sized form m <- m_d(lambda) + F(lambda) m."""
+    lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+    its = np.ascontiguousarray(np.asarray(iters, dtype=np.int32))
+    if lam.size != its.size:
+        raise ValueError("lambdas and iters must have equal length")
+    sc = _Sched()
+    sc.nlevel, sc.first_inf = lam.size, int(bool(first_inf))
+    sc.lambda_ = lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    sc.iters = its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    _check(lib().mm_solve_mapsized(plan.handle, _ptr(d, "d", plan.tod_dtype, plan.nsamp), ctypes.byref(sc),
+                                   _map_ptr(plan, m0, "m0"), _map_ptr(plan, m_out, "m_out"), _stream(stream)),
+           "mm_solve_mapsized")
 
 
 def mm_cg_solve(plan: Plan, m_out: torch.Tensor, maxiter: int, d: Optional[torch.Tensor] = None,
