@@ -122,6 +122,10 @@ enum { MM_BIN_SORTED = 0, MM_BIN_ATOMIC = 1 };                            /* bin
  *  with_adjoint 1 reserves a second TOD-sized buffer in the workspace for
  *               mm_noise_grad and for mm_solve with a map right-hand side; 0
  *               leaves it out (those calls then return MM_E_ARG).
+ *  tile_pixels  pixels per binning tile: 0 picks about npix / 2048, within
+ *               16..512; 16..1024 asks for that many.  Larger tiles hold longer
+ *               time-contiguous runs of each scan (fewer partly used cache lines
+ *               when the binning pass reads the filtered TOD) but take more LDS.
  */
 typedef struct {
   int32_t ncomp;
@@ -144,6 +148,7 @@ typedef struct {
   int32_t tune;
   int32_t binning;
   int32_t with_adjoint;
+  int32_t tile_pixels;
 } mm_plan_desc;
 
 /* Cooling schedule (Section 3.1): optionally one lambda = inf step, then
@@ -291,6 +296,25 @@ mm_status mm_cg_solve(mm_plan_t plan, const void* d, const double* rhs_map, int3
  */
 mm_status mm_chi2(mm_plan_t plan, const void* d, const double* m, double lambda, double* chi2_host,
                   double* per_chunk_dev, mm_stream_t stream);
+
+/*
+ * chi^2 per Fourier mode, a diagnostic of the noise model (Section 3.1 reads
+ * chi^2 mode by mode; each mode's term |r-hat_k|^2 / (n N'_k) has unit mean when
+ * the noise model is right): for the nsel chunks listed in `chunks` (host),
+ * with r = d - P m and N' = N + (lambda - 1) T (lambda = 1: eqn. chi2),
+ *   modes_dev (device, sum over the listed chunks of n_i/2 + 1 doubles, chunk i
+ *   after those before it): term k = omega_k |r-hat_k|^2 / (n N'_k), k = 0..n/2,
+ *   omega_k = 1 for k = 0 and n/2, else 2 (they sum to the chunk's chi^2);
+ *   bins_dev (device, [nsel][nbins][2]): per log-spaced bin, the sum of the terms
+ *   and the number of real modes they stand for (sum of omega_k).
+ * Bins: k = 0 in bin 0; k >= 1 in bin 1 + s o + floor(s (k - 2^o) / 2^o),
+ * o = floor(log2 k), s = per_octave (1..64); nbins must equal
+ * 1 + s (floor(log2 max_i n_i/2) + 1) (MM_E_ARG otherwise).  One forward sweep
+ * over the whole TOD plus the listed chunks' row transforms; deterministic.
+ */
+mm_status mm_chi2_modes(mm_plan_t plan, const void* d, const double* m, double lambda, int32_t nsel,
+                        const int64_t* chunks, int32_t per_octave, double* modes_dev, double* bins_dev, int32_t nbins,
+                        mm_stream_t stream);
 
 /*
  * Apply the map-space operators once (building blocks for adjoint solves and

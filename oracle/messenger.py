@@ -109,6 +109,41 @@ def chi2_of_residual(S: Setup, r: np.ndarray, lam: float = 1.0, per_chunk: bool 
     return out if per_chunk else float(out.sum())
 
 
+def mode_bin(k: int, per_octave: int) -> int:
+    """Log-spaced bin of real Fourier bin k: 0 for k = 0, else 1 + s*o + floor(s*(k - 2^o)/2^o)
+    with o = floor(log2 k) and s bins per octave."""
+    if k == 0:
+        return 0
+    o = k.bit_length() - 1
+    return 1 + per_octave * o + (per_octave * (k - (1 << o))) // (1 << o)
+
+
+def chi2_modes(S: Setup, d: np.ndarray, m: np.ndarray, chunks, per_octave: int, lam: float = 1.0):
+    """chi^2 mode by mode for the listed chunks (Section 3.1 examines it per Fourier mode: each
+    term |r-hat_k|^2 / (n N'_k) has unit mean under the right noise model).
+
+    Returns (terms, bins): terms[i] = omega_k |r-hat_k|^2 / (n N'_k) for k = 0..n/2 of chunk i
+    (they sum to its chi^2), and bins [len(chunks), nbins, 2] with the sum of the terms in each
+    log-spaced bin (mode_bin) and the number of real modes they stand for (sum of omega_k).
+    """
+    r = residual(S, d, m)
+    nm = max(int(S.noise.chunk_off[c + 1] - S.noise.chunk_off[c]) // 2 for c in chunks)
+    nbins = 1 + per_octave * nm.bit_length()
+    terms, bins = [], np.zeros((len(chunks), nbins, 2))
+    for i, c in enumerate(chunks):
+        a, b = int(S.noise.chunk_off[c]), int(S.noise.chunk_off[c + 1])
+        n = b - a
+        rh = np.fft.rfft(r[a:b])
+        w = chi2_weights(n)
+        t = w * (rh.real ** 2 + rh.imag ** 2) / (n * (S.noise.spectra[c] + (lam - 1.0) * S.noise.tau[c]))
+        terms.append(t)
+        for k in range(n // 2 + 1):
+            j = mode_bin(k, per_octave)
+            bins[i, j, 0] += t[k]
+            bins[i, j, 1] += w[k]
+    return terms, bins
+
+
 def chi2(S: Setup, d: np.ndarray, m: np.ndarray, per_chunk: bool = False):
     """chi^2(m) = (d - P m)^T N^-1 (d - P m), eqn. (chi2), evaluated over Fourier modes."""
     return chi2_of_residual(S, residual(S, d, m), 1.0, per_chunk)

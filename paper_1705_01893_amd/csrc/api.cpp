@@ -69,8 +69,8 @@ hipError_t bin_atomic_update(mm_plan_s* pl, int bsrc, const void* src, int epi, 
 
 // r = src(d, m) -> filtered y in the work buffer (passes A, B, C).  Returns with the
 // chi^2 partials in d_chi2_part when ops includes B_CHI2.
-mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, int ops, int gain, double lam,
-                       double chi2_lam, hipStream_t s, bool map_current = false) {
+// pass A of a sweep: r = src(d, m) column-transformed into the work buffer
+mm_status sweep_pass_a(mm_plan_s* pl, const void* d, const double* m, int src, hipStream_t s, bool map_current) {
   // large maps: P m comes from the projection buffer (projected here unless it already holds P m);
   // otherwise I/Q/U maps are gathered from their interleaved copy (made here unless current)
   // atomic binning writes no P m for the next sweep
@@ -85,6 +85,12 @@ mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, i
     return launch_pass_a(pl->dp, pl->d_itemsAC, (int)pl->itemsAC.size(), d, m, src, pl->d_work, pl->lds_ac, s,
                          pl->d_pm);
   }));
+  return MM_OK;
+}
+
+mm_status sweep_filter(mm_plan_s* pl, const void* d, const double* m, int src, int ops, int gain, double lam,
+                       double chi2_lam, hipStream_t s, bool map_current = false) {
+  MM_TRY(sweep_pass_a(pl, d, m, src, s, map_current));
   MM_TRY_HIP(timed(pl, 1, s, [&] {
     return launch_pass_b(pl->dp, pl->d_itemsB, (int)pl->itemsB.size(), pl->d_work, ops, gain, lam, chi2_lam,
                          pl->d_chi2_part, pl->lds_b, s);
@@ -465,6 +471,37 @@ mm_status mm_chi2(mm_plan_t plan, const void* d, const double* m, double lambda,
   MM_TRY_HIP(hipStreamSynchronize(s));
   if (!std::isfinite(v)) return fail(MM_E_NONFINITE, "chi^2 is not finite");
   *chi2_host = v;
+  return MM_OK;
+}
+
+mm_status mm_chi2_modes(mm_plan_t plan, const void* d, const double* m, double lambda, int32_t nsel,
+                        const int64_t* chunks, int32_t per_octave, double* modes_dev, double* bins_dev, int32_t nbins,
+                        mm_stream_t stream) {
+  if (!plan || !d || !m || !chunks || !modes_dev || !bins_dev) return fail(MM_E_ARG, "null argument");
+  if (nsel < 1) return fail(MM_E_ARG, "no chunk listed");
+  if (per_octave < 1 || per_octave > 64) return fail(MM_E_ARG, "per_octave must be 1..64");
+  if (!(lambda >= 1.0) || !std::isfinite(lambda)) return fail(MM_E_ARG, "lambda must be finite and >= 1");
+  int64_t maxM = 1;
+  for (int32_t i = 0; i < nsel; ++i) {
+    if (chunks[i] < 0 || chunks[i] >= plan->nchunk) return fail(MM_E_ARG, "chunk index out of range");
+    maxM = std::max<int64_t>(maxM, (plan->off[chunks[i] + 1] - plan->off[chunks[i]]) / 2);
+  }
+  int lg = 0;
+  while ((int64_t(2) << lg) <= maxM) ++lg;  // floor(log2 maxM)
+  const int need = 1 + per_octave * (lg + 1);
+  if (nbins != need) return fail(MM_E_ARG, "nbins must be " + std::to_string(need) + " for these chunks");
+  hipStream_t s = S(stream);
+  MM_TRY(sweep_pass_a(plan, d, m, SRC_D_MINUS_PM, s, false));
+  int64_t off = 0;
+  for (int32_t i = 0; i < nsel; ++i) {
+    const int64_t c = chunks[i];
+    const int64_t M = (plan->off[c + 1] - plan->off[c]) / 2;
+    const int b0 = plan->chunk_item_begin[c], b1 = plan->chunk_item_begin[c + 1];
+    MM_TRY_HIP(launch_pass_b(plan->dp, plan->d_itemsB + b0, b1 - b0, plan->d_work, B_CHI2, GAIN_NINV, 1.0, lambda,
+                             plan->d_chi2_part, plan->lds_b, s, modes_dev + off));
+    MM_TRY_HIP(launch_modes_bin(modes_dev + off, M, per_octave, nbins, bins_dev + 2 * (int64_t)nbins * i, s));
+    off += M + 1;
+  }
   return MM_OK;
 }
 

@@ -14,7 +14,8 @@ constexpr int kBinBlock = 256;     // threads per workgroup of the binning pass
 constexpr int kWaves = kBinBlock / 64;
 constexpr int kMaxStages = 24;     // radix stages of one sub-transform
 constexpr int kSubBatch = 4096;    // samples staged in LDS per binning step (<= 65536: uint16 indices)
-constexpr int kMaxTilePix = 512;   // pixels per binning tile (LDS accumulators)
+constexpr int kMaxTilePix = 512;   // pixels per binning tile by default (LDS accumulators)
+constexpr int kMaxTilePixAsked = 1024;  // the largest tile a descriptor may ask for
 
 // complex elements per thread in the LDS transforms (tile capacity = kBlock * ept = 64 KB)
 template <typename T> struct Ept;
@@ -236,12 +237,17 @@ enum { EPI_WRITE_B = 0, EPI_UPDATE = 1, EPI_REPLACE = 2, EPI_PLAN = 3, EPI_MAPSI
 hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m,
                          int src, void* work, size_t lds_bytes, hipStream_t s, const void* pmbuf = nullptr);
 hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void* work, int ops, int gain,
-                         double lam, double chi2_lam, double* chi2_part, size_t lds_bytes, hipStream_t s);
+                         double lam, double chi2_lam, double* chi2_part, size_t lds_bytes, hipStream_t s,
+                         double* modes = nullptr);
+// one chunk's per-mode chi^2 terms (k = 0 .. M) summed in log-spaced bins: out [nbins][2] (sum, modes)
+hipError_t launch_modes_bin(const double* modes, int64_t M, int per_octave, int nbins, double* out, hipStream_t s);
 hipError_t launch_pass_c(const DevPlan& P, const ItemAC* items, int nitems, void* work, size_t lds_bytes,
                          hipStream_t s);
 hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,
                       double* w_out, int32_t* hits_out, hipStream_t s, void* pm_out = nullptr);
 hipError_t launch_interleave(const DevPlan& P, const double* m, hipStream_t s);
+// LDS bytes the binning kernels of a plan take per workgroup (tiles of tile_pix pixels)
+size_t binning_lds_bytes(int ncomp, int precision, int tile_pix);
 // binning by FP64 atomics (the measured alternative): b += P^T src over all samples (b zeroed by
 // the caller), then the per-pixel update of the binning epilogue from b
 hipError_t launch_bin_atomic(const DevPlan& P, int bsrc, const void* src, double* b, int64_t max_n, hipStream_t s);

@@ -185,6 +185,7 @@ __device__ __forceinline__ float powerlaw<float>(const DevChunk& ch, int k) {
 struct BinCtx {
   int gain, chi2;
   double lam, inv_lam, chi2_lam;
+  double* modes;  // per-mode chi^2 terms of the launch's chunk, indexed by real bin k (or null)
 };
 
 // power-law part sigma^2 (f_k/fknee)^alpha of the noise spectrum at real bin k: tabulated at plan
@@ -501,6 +502,10 @@ __device__ __forceinline__ void b_pair(cx<T>* lds, const DevPlan& P, const DevCh
   bin_factors_pl<T>(ch, bc, plk, gk, cwk);
   bin_factors_pl<T>(ch, bc, plm, gm, cwm);
   if (ops & B_CHI2) chi += 2.0 * (norm2(Rk) * cwk + norm2(Rm) * cwm);
+  if (bc.modes) {
+    bc.modes[k] = 2.0 * norm2(Rk) * cwk;
+    bc.modes[ch.M - k] = 2.0 * norm2(Rm) * cwm;
+  }
   if (ops & B_FILTER) {
     const cx<T> Yk = cscale(Rk, gk), Ym = cscale(Rm, gm);
     cx<T> Ep, D;
@@ -530,6 +535,10 @@ __device__ __forceinline__ void b_dc(cx<T>* lds, const DevPlan& P, const DevChun
   bin_factors<T>(P, ch, bc, 0, 0, g0, c0);
   bin_factors<T>(P, ch, bc, ch.M, ch.M, gM, cM);
   if (ops & B_CHI2) chi += (double)R0 * (double)R0 * c0 + (double)RM * (double)RM * cM;
+  if (bc.modes) {
+    bc.modes[0] = (double)R0 * (double)R0 * c0;
+    bc.modes[ch.M] = (double)RM * (double)RM * cM;
+  }
   if (ops & B_FILTER) {
     const T Y0 = R0 * g0, YM = RM * gM;
     cx<T> z;
@@ -548,6 +557,7 @@ __device__ __forceinline__ void b_self(cx<T>* lds, const DevPlan& P, const DevCh
   double cw;
   bin_factors<T>(P, ch, bc, k, ta, g, cw);
   if (ops & B_CHI2) chi += 2.0 * norm2(Z) * cw;
+  if (bc.modes) bc.modes[k] = 2.0 * norm2(Z) * cw;
   if (ops & B_FILTER) {
     cx<T> y;
     y.x = Z.x * g;
@@ -1521,6 +1531,55 @@ hipError_t launch_grad(const DevPlan& P, const ItemB* items, int nitems, const i
 }
 
 // ---------------------------------------------------------------------------------------------
+// chi^2 per Fourier mode, summed in log-spaced bins (a diagnostic of the noise model)
+//
+// Real bin k of a chunk falls in bin 0 for k = 0 and otherwise, with o = floor(log2 k) and s bins
+// per octave, in bin 1 + s o + floor(s (k - 2^o) / 2^o).  Bin b >= 1 therefore holds
+// k - 2^o in [ceil(j 2^o / s), ceil((j + 1) 2^o / s)) with o = (b - 1) / s, j = (b - 1) mod s.
+// One workgroup per (listed chunk, bin): the chunk's terms in that range summed in a fixed order,
+// and the number of real modes they stand for (2 per bin, 1 for k = 0 and k = n/2).
+
+__global__ __launch_bounds__(256) void k_modes_bin(const double* __restrict__ modes, int64_t M, int per_octave,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;  // the chunk's terms cover k = 0 .. M
+  int64_t lo, hi;
+  if (b == 0) {
+    lo = 0;
+    hi = 1;
+  } else {
+    const int o = (b - 1) / per_octave, j = (b - 1) % per_octave;
+    const int64_t p2 = (int64_t)1 << o;
+    lo = p2 + (j * p2 + per_octave - 1) / per_octave;
+    hi = p2 + ((j + 1) * p2 + per_octave - 1) / per_octave;
+  }
+  if (hi > M + 1) hi = M + 1;
+  double sacc = 0.0;
+  for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) sacc += modes[k];
+  red[threadIdx.x] = sacc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double cnt = 0.0;
+    if (hi > lo) {
+      cnt = 2.0 * (double)(hi - lo);
+      if (lo == 0) cnt -= 1.0;
+      if (hi == M + 1) cnt -= 1.0;
+    }
+    out[2 * b] = red[0];
+    out[2 * b + 1] = cnt;
+  }
+}
+
+hipError_t launch_modes_bin(const double* modes, int64_t M, int per_octave, int nbins, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_modes_bin, dim3(nbins), dim3(256), 0, s, modes, M, per_octave, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 // plan: tabulate the power-law part of every chunk's noise spectrum (FP64 form)
 
 __global__ void k_spectrum(DevPlan P, double* __restrict__ spec) {
@@ -1707,11 +1766,12 @@ hipError_t launch_pass_a(const DevPlan& P, const ItemAC* items, int nitems, cons
 }
 
 hipError_t launch_pass_b(const DevPlan& P, const ItemB* items, int nitems, void* work, int ops, int gain, double lam,
-                         double chi2_lam, double* chi2_part, size_t lds, hipStream_t s) {
+                         double chi2_lam, double* chi2_part, size_t lds, hipStream_t s, double* modes) {
   if (nitems <= 0) return hipSuccess;
   BinCtx bc;
   bc.gain = gain;
   bc.chi2 = (ops & B_CHI2) ? 1 : 0;
+  bc.modes = modes;
   bc.lam = lam;
   bc.inv_lam = 1.0 / lam;
   bc.chi2_lam = chi2_lam;
@@ -1929,6 +1989,19 @@ hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipSt
                          (float*)pm_out);
   }
   return hipGetLastError();
+}
+
+size_t binning_lds_bytes(int ncomp, int precision, int tile_pix) {
+  const bool f64 = precision == 0;
+  const size_t plan = ncomp == 1 ? (f64 ? bin_lds_bytes<2, double>(true, tile_pix, true)
+                                        : bin_lds_bytes<2, float>(true, tile_pix, true))
+                                 : (f64 ? bin_lds_bytes<7, double>(true, tile_pix, true)
+                                        : bin_lds_bytes<7, float>(true, tile_pix, true));
+  const size_t it = ncomp == 1 ? (f64 ? bin_lds_bytes<1, double>(false, tile_pix, true)
+                                      : bin_lds_bytes<1, float>(false, tile_pix, true))
+                               : (f64 ? bin_lds_bytes<3, double>(false, tile_pix, true)
+                                      : bin_lds_bytes<3, float>(false, tile_pix, true));
+  return plan > it ? plan : it;
 }
 
 hipError_t launch_bin(const DevPlan& P, int bsrc, const void* src, int epi, const double* m_in, double* out,

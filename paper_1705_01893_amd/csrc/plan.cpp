@@ -74,6 +74,8 @@ mm_status validate(const mm_plan_desc* desc) {
   if (D.tune != MM_TUNE_MEASURE && D.tune != MM_TUNE_STATIC && !pick_mode) return fail(MM_E_ARG, "unknown tune mode");
   if (D.binning != MM_BIN_SORTED && D.binning != MM_BIN_ATOMIC) return fail(MM_E_ARG, "unknown binning mode");
   if (D.with_adjoint != 0 && D.with_adjoint != 1) return fail(MM_E_ARG, "with_adjoint must be 0 or 1");
+  if (D.tile_pixels != 0 && (D.tile_pixels < 16 || D.tile_pixels > kMaxTilePixAsked))
+    return fail(MM_E_ARG, "tile_pixels must be 0 (automatic) or 16.." + std::to_string(kMaxTilePixAsked));
   if (D.chunk_off[0] != 0) return fail(MM_E_ARG, "chunk_off[0] must be 0");
   std::string why;
   for (int64_t c = 0; c < D.nchunk; ++c) {
@@ -191,7 +193,8 @@ void prep_transforms(const mm_plan_desc& D, Prep& P) {
 void tile_shape(const mm_plan_desc& D, const SortCounters& c, Prep& P) {
   P.nxm = D.nx > 0 ? D.nx : D.npix;
   P.nym = D.npix / P.nxm;
-  const int64_t target = std::max<int64_t>(16, std::min<int64_t>(kMaxTilePix, D.npix / 2048));
+  const int64_t target = D.tile_pixels > 0 ? std::min<int64_t>(D.tile_pixels, D.npix)
+                                           : std::max<int64_t>(16, std::min<int64_t>(kMaxTilePix, D.npix / 2048));
   double mx = c.nst ? (double)c.sx / (double)c.nst : 1.0;
   double my = c.nst ? (double)c.sy / (double)c.nst : 1.0;
   if (mx + my <= 0.0) mx = my = 1.0;
@@ -267,6 +270,16 @@ mm_status analyse(const mm_plan_desc& D, Prep& P, int64_t* doff, SortCounters* d
   if (c.flags & 4u) return fail(MM_E_ARG, "an angle index lies beyond the angle table");
   tile_shape(D, c, P);
   if (P.ntiles > (int64_t)INT32_MAX) return fail(MM_E_ARG, "too many pixel tiles");
+  {
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      return fail(MM_E_HIP, "device LDS query failed");
+    const size_t need = binning_lds_bytes(D.ncomp, D.precision, (int)(P.tw * P.th));
+    if (need > (size_t)lds_max)
+      return fail(MM_E_ARG, "binning tiles of " + std::to_string(P.tw * P.th) + " pixels need " + std::to_string(need) +
+                                " bytes of LDS per workgroup; the device allows " + std::to_string(lds_max));
+  }
   e = launch_sort_count(w, geom(P), dctr, nullptr, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&c, dctr, sizeof(c), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

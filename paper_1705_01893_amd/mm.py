@@ -48,6 +48,7 @@ class _Desc(ctypes.Structure):
         ("psi_kind", ctypes.c_int32), ("map_access", ctypes.c_int32),
         ("psi_table", ctypes.POINTER(ctypes.c_float)), ("psi_table_len", ctypes.c_int64),
         ("tune", ctypes.c_int32), ("binning", ctypes.c_int32), ("with_adjoint", ctypes.c_int32),
+        ("tile_pixels", ctypes.c_int32),
     ]
 
 
@@ -86,6 +87,7 @@ def lib() -> ctypes.CDLL:
     L.mm_cg_solve.argtypes = [vp, vp, vp, i32, dbl, vp, vp, vp, vp, ctypes.POINTER(i32), vp]
     L.mm_chi2.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp]
     L.mm_apply.argtypes = [vp, i32, dbl, vp, vp, vp, vp]
+    L.mm_chi2_modes.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(i64), i32, vp, vp, i32, vp]
     L.mm_lift_rhs.argtypes = [vp, vp, vp, vp]
     L.mm_plan_set_noise.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                      ctypes.POINTER(dbl), vp]
@@ -96,7 +98,7 @@ def lib() -> ctypes.CDLL:
     for name in ("mm_plan_set_noise", "mm_tod_apply", "mm_noise_grad", "mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_workspace_bytes_noalloc",
                  "mm_plan_binning_stats", "mm_plan_hits", "mm_plan_solvable",
                  "mm_plan_nsolvable", "mm_plan_map_access", "mm_plan_chunk_layout", "mm_messenger_iter", "mm_solve", "mm_solve_mapsized", "mm_cooling_levels", "mm_cg_solve",
-                 "mm_chi2", "mm_apply", "mm_lift_rhs"):
+                 "mm_chi2", "mm_chi2_modes", "mm_apply", "mm_lift_rhs"):
         getattr(L, name).restype = ctypes.c_int
     L.mm_status_str.argtypes = [ctypes.c_int]
     L.mm_status_str.restype = ctypes.c_char_p
@@ -174,7 +176,7 @@ class Plan:
 def plan_desc(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, pix: torch.Tensor,
               psi: Optional[torch.Tensor] = None, psi_table=None, tau=None, nx: int = 0,
               precision: int = MM_FP64, map_access: int = MM_MAP_AUTO, tune: int = MM_TUNE_MEASURE,
-              binning: int = MM_BIN_SORTED, with_adjoint: bool = False):
+              binning: int = MM_BIN_SORTED, with_adjoint: bool = False, tile_pixels: int = 0):
     """The mm_plan_desc of a problem and the host arrays it points to (keep both alive together).
     pix (int32) and psi (float64 / float32 / uint16) are device tensors."""
     off = np.ascontiguousarray(np.asarray(chunk_off, dtype=np.int64).reshape(-1))
@@ -191,6 +193,7 @@ def plan_desc(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha,
     d.tune = tune
     d.binning = binning
     d.with_adjoint = int(bool(with_adjoint))
+    d.tile_pixels = int(tile_pixels)
     d.chunk_off = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     for k in ("fsample", "sigma", "fknee", "alpha"):
         setattr(d, k, arrs[k].ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
@@ -349,6 +352,29 @@ def mm_chi2(plan: Plan, d: torch.Tensor, m: torch.Tensor, lam: float = 1.0,
                          float(lam), ctypes.byref(v), _ptr(per_chunk, "per_chunk", torch.float64, plan.nchunk),
                          _stream(stream)), "mm_chi2")
     return v.value
+
+
+def chi2_modes_nbins(plan: Plan, chunks, per_octave: int) -> int:
+    """Number of log-spaced bins mm_chi2_modes fills for these chunks (its documented rule)."""
+    maxm = max(int(plan._keep[0]["off"][c + 1] - plan._keep[0]["off"][c]) // 2 for c in chunks)
+    return 1 + per_octave * (maxm.bit_length())
+
+
+def mm_chi2_modes(plan: Plan, d: torch.Tensor, m: torch.Tensor, chunks, per_octave: int = 4, lam: float = 1.0,
+                  stream=None):
+    """Per-mode chi^2 terms of the listed chunks (concatenated, n_i/2 + 1 each) and their log-binned
+    sums [nsel, nbins, 2] (sum of terms, number of real modes)."""
+    ch = np.ascontiguousarray(np.asarray(chunks, dtype=np.int64).reshape(-1))
+    off = plan._keep[0]["off"]
+    nmodes = int(sum((off[c + 1] - off[c]) // 2 + 1 for c in ch))
+    nb = chi2_modes_nbins(plan, ch, per_octave)
+    modes = torch.empty(nmodes, dtype=torch.float64, device=d.device)
+    bins = torch.empty((ch.size, nb, 2), dtype=torch.float64, device=d.device)
+    _check(lib().mm_chi2_modes(plan.handle, _ptr(d, "d", plan.tod_dtype, plan.nsamp), _map_ptr(plan, m, "m"),
+                               float(lam), int(ch.size), ch.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                               int(per_octave), modes.data_ptr(), bins.data_ptr(), int(nb), _stream(stream)),
+           "mm_chi2_modes")
+    return modes, bins
 
 
 def mm_apply(plan: Plan, which: int, out: torch.Tensor, x: Optional[torch.Tensor] = None,

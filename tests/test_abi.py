@@ -66,6 +66,7 @@ def _desc(**over):
     d.tune = over.pop("tune", 0)
     d.binning = over.pop("binning", 0)
     d.with_adjoint = over.pop("with_adjoint", 0)
+    d.tile_pixels = over.pop("tile_pixels", 0)
     assert not over
     return d, arr
 
@@ -77,6 +78,8 @@ def _desc(**over):
     (dict(tune=2), mm.MM_E_ARG),
     (dict(binning=2), mm.MM_E_ARG),
     (dict(with_adjoint=2), mm.MM_E_ARG),
+    (dict(tile_pixels=8), mm.MM_E_ARG),
+    (dict(tile_pixels=4096), mm.MM_E_ARG),
     (dict(npix=0), mm.MM_E_ARG),
     (dict(npix=15, nx=4), mm.MM_E_ARG),
     (dict(pix=None), mm.MM_E_ARG),

@@ -390,3 +390,52 @@ def test_pcg_operator_is_symmetric():
     x[:, ~S.solvable] = 0
     y[:, ~S.solvable] = 0
     assert np.sum(x * apply_A(S, y)) == pytest.approx(np.sum(y * apply_A(S, x)), rel=1e-11)
+
+
+# ------------------------------------------------------------------------------------------------
+# chi^2 per Fourier mode (the diagnostic of Section 3.1)
+
+def test_mode_bin_hand_values():
+    """Two bins per octave: k = 0 | 1 | (empty) | 2 | 3 | 4, 5 | 6, 7 | 8 ..."""
+    from oracle.messenger import mode_bin
+    got = [mode_bin(k, 2) for k in range(10)]
+    assert got == [0, 1, 3, 4, 5, 5, 6, 6, 7, 7]
+    assert [mode_bin(k, 1) for k in (1, 2, 3, 4, 7, 8, 1023, 1024)] == [1, 2, 2, 3, 3, 4, 10, 11]
+
+
+def test_chi2_modes_pure_cosine_closed_form():
+    """A residual that is one cosine at bin k0 puts all of chi^2 in bin(k0), with the closed form
+    A^2 n / (2 N_k0) (n/2 from the rfft amplitude, a multiplicity of 2); the bins' mode counts add
+    up to n."""
+    from oracle.messenger import chi2_modes, mode_bin
+    n, k0, A = 64, 11, 1.7
+    N = noise_psd(n, 5.0, 1.1, 0.7, -1.7)
+    nm = NoiseModel(chunk_off=np.array([0, n]), spectra=[N], tau=np.array([1.1 ** 2]))
+    pt = Pointing(np.full(n, -1, np.int32), None, npix=1, ncomp=1)
+    S = oracle.Setup(pointing=pt, noise=nm, W=np.zeros((1, 1, 1)), W_inv=np.zeros((1, 1, 1)),
+                     solvable=np.zeros(1, bool), hits=np.zeros(1, np.int64))
+    d = A * np.cos(2 * np.pi * k0 * np.arange(n) / n)
+    terms, bins = chi2_modes(S, d, np.zeros((1, 1)), [0], per_octave=3)
+    expect = A * A * n / (2 * N[k0])
+    assert terms[0][k0] == pytest.approx(expect, rel=1e-12)
+    assert bins[0, mode_bin(k0, 3), 0] == pytest.approx(expect, rel=1e-12)
+    assert bins[0, :, 0].sum() == pytest.approx(expect, rel=1e-12)
+    assert bins[0, :, 1].sum() == n
+
+
+def test_chi2_modes_unit_mean_for_white_noise():
+    """Data that are white noise of the modelled variance (N = sigma^2 at every bin when f_knee is
+    far below f_1): every bin's mean term is 1 within 5 standard errors (each real mode's term is
+    chi^2 with one degree of freedom: variance 2 per mode)."""
+    from oracle.messenger import chi2_modes
+    rng = np.random.default_rng(4)
+    n = 4096
+    nm = NoiseModel.from_params(np.array([0, n]), [100.0], [1.3], [1e-9], [-1.0])
+    pt = Pointing(np.full(n, -1, np.int32), None, npix=1, ncomp=1)
+    S = oracle.Setup(pointing=pt, noise=nm, W=np.zeros((1, 1, 1)), W_inv=np.zeros((1, 1, 1)),
+                     solvable=np.zeros(1, bool), hits=np.zeros(1, np.int64))
+    d = rng.standard_normal(n) * 1.3
+    _, bins = chi2_modes(S, d, np.zeros((1, 1)), [0], per_octave=2)
+    for s, cnt in bins[0]:
+        if cnt >= 8:
+            assert abs(s / cnt - 1.0) < 5 * np.sqrt(2.0 / cnt)
