@@ -6,9 +6,10 @@ law of every detector and the numeric type of the time-ordered data.  The
 cooling-schedule fields record how many levels and iterations a solve runs;
 how the levels are placed is the solver's business.
 
-The five named workloads mirror the simulations of Section 2.3 of the paper
-(cross-linked rasters, 1/f plus white noise, polarized detectors) at the sizes
-used for parity and throughput measurement.  ``scaled`` derives small variants
+The named workloads mirror the simulations of Section 2.3 of the paper
+(cross-linked rasters, 1/f plus white noise, polarized detectors; two of them
+with the differencing beams of Section 3.2) at the sizes used for parity and
+throughput measurement.  ``scaled`` derives small variants
 with the same structure for tests that must finish in seconds.
 """
 
@@ -48,6 +49,8 @@ class WorkloadConfig:
     # sky amplitudes (rms of the temperature and of each polarization component)
     rms_t: float = 10.0
     rms_p: float = 1.0
+    # differential pointing: separation (pixels) of the second beam, 0 for a single beam
+    diff_sep: float = 0.0
 
     @property
     def npix(self) -> int:
@@ -88,6 +91,18 @@ CONFIGS = [
                    fsample=200.0, nx=2048, ncomp=3, tod_dtype="f32", psi_kind="u16", scan="crossed",
                    sig_lo=0.8, sig_hi=1.2, fk_lo=0.1, fk_hi=2.0, al_lo=-3.0, al_hi=-1.0,
                    frac_high_knee=0.05, fknee_high=5.0, nlevel=15, iters_per_level=5),
+    # Differential beams (Section 3.2): two beams 8 pixels apart (the paper's 18 arcmin on a
+    # 600-pixel map, scaled to 256), each sample their difference; temperature only, FP64,
+    # 16 detectors x 2^20 on the crossed rasters, a 16 x 10 schedule.
+    WorkloadConfig(name="diff256", index=5, ndet=16, nsamp=1 << 20, nsamp_min=1 << 20, fsample=200.0,
+                   nx=256, ncomp=1, tod_dtype="f64", psi_kind="none", scan="crossed",
+                   sig_lo=0.8, sig_hi=1.2, fk_lo=0.1, fk_hi=2.0, al_lo=-3.0, al_hi=-1.0,
+                   nlevel=16, iters_per_level=10, diff_sep=8.0),
+    # Differential I/Q/U, FP32-mixed: 64 detectors x 2^20 on a 512 x 512 map, beams 16 pixels apart.
+    WorkloadConfig(name="diff512", index=6, ndet=64, nsamp=1 << 20, nsamp_min=1 << 20, fsample=200.0,
+                   nx=512, ncomp=3, tod_dtype="f32", psi_kind="f32", scan="crossed",
+                   sig_lo=0.8, sig_hi=1.2, fk_lo=0.1, fk_hi=2.0, al_lo=-3.0, al_hi=-1.0,
+                   nlevel=16, iters_per_level=10, diff_sep=16.0),
 ]
 
 

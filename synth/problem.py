@@ -4,7 +4,8 @@ Recipe (every random draw is seeded from one SeedSequence tree, so a problem
 is reproducible and each chunk's noise does not depend on how many chunks are
 generated before it):
 
-* seed tree: ``SeedSequence(170501893).spawn(5)[cfg.index]`` and then its
+* seed tree: child ``cfg.index`` of ``SeedSequence(170501893)`` (spawned five or more at
+  once: the first five children do not depend on how many are spawned) and then its
   children, in order: sky, noise parameters, chunk lengths, detector offsets,
   then one child per chunk for that chunk's noise realisation;
 * sky: flat-sky Gaussian random field on the nx*nx grid with power falling as
@@ -29,7 +30,7 @@ from typing import List, Optional
 import numpy as np
 
 from .configs import WorkloadConfig
-from .scans import chunk_pointing
+from .scans import chunk_pointing, chunk_pointing_differential
 
 ROOT_SEED = 170501893
 
@@ -50,6 +51,11 @@ class Problem:
     d: Optional[np.ndarray] = None           # float64 / float32 [N_s]
     m_true: Optional[np.ndarray] = None      # float64 [ncomp, npix]
     noise: Optional[np.ndarray] = None       # float64 [N_s] (kept only when asked for)
+    # differential pointing (Section 3.2): the second beam's pixels and angles, and the weights
+    # of the two beams in each sample (None for a single beam)
+    pix_b: Optional[np.ndarray] = None
+    psi_b: Optional[np.ndarray] = None
+    weights: Optional[tuple] = None
     extra: dict = field(default_factory=dict)
 
     @property
@@ -81,7 +87,7 @@ class Problem:
 
 
 def _seed_tree(cfg: WorkloadConfig):
-    top = np.random.SeedSequence(ROOT_SEED).spawn(5)[cfg.index]
+    top = np.random.SeedSequence(ROOT_SEED).spawn(max(5, cfg.index + 1))[cfg.index]
     kids = top.spawn(4 + cfg.ndet)
     return kids[0], kids[1], kids[2], kids[3], kids[4:]
 
@@ -183,7 +189,10 @@ def make_problem(cfg: WorkloadConfig, with_noise: bool = True, noise_scale: floa
 
     ``noise_scale`` multiplies the noise realisation (0 gives noise-free data for
     unbiasedness checks); ``keep_noise`` stores the realisation in ``Problem.noise``.
+    With ``cfg.diff_sep > 0`` every sample is the difference of two beams (weights +1 and -1,
+    same angle): d = sky(beam A) - sky(beam B) + noise.
     """
+    diff = cfg.diff_sep > 0
     ss_sky, ss_par, ss_len, ss_off, ss_chunks = _seed_tree(cfg)
     lengths = chunk_lengths(cfg, ss_len)
     chunk_off = np.zeros(cfg.ndet + 1, dtype=np.int64)
@@ -210,21 +219,33 @@ def make_problem(cfg: WorkloadConfig, with_noise: bool = True, noise_scale: floa
     tod_dtype = np.float64 if cfg.tod_dtype == "f64" else np.float32
     d = np.empty(ns, dtype=tod_dtype)
     noise_all = np.empty(ns, dtype=np.float64) if keep_noise else None
+    if diff and cfg.psi_kind == "u16":
+        raise ValueError("differential workloads store their angles directly")
+    pix_b = np.empty(ns, dtype=np.int32) if diff else None
+    psi_b = np.empty_like(psi_store) if (diff and psi_store is not None) else None
 
     def work(c: int):
         sl = slice(int(chunk_off[c]), int(chunk_off[c + 1]))
         n = int(lengths[c])
-        cpix, cpsi, chalf = chunk_pointing(cfg, c, n, offsets[c])
+        if diff:
+            cpix, cpix_b, cpsi, chalf = chunk_pointing_differential(cfg, c, n, offsets[c])
+            pix_b[sl] = cpix_b
+        else:
+            cpix, cpsi, chalf = chunk_pointing(cfg, c, n, offsets[c])
         pix[sl] = cpix
         psi_used = None
         if cfg.psi_kind in ("f64", "f32"):
             psi_store[sl] = cpsi
             psi_used = psi_store[sl]
+            if diff:
+                psi_b[sl] = cpsi
         elif cfg.psi_kind == "u16":
             idx = (2 * c + chalf).astype(np.uint16)
             psi_index[sl] = idx
             psi_used = psi_table[idx]
         sig = _signal(m_true, cpix, psi_used)
+        if diff:
+            sig = sig - _signal(m_true, cpix_b, psi_used)
         if with_noise and noise_scale != 0.0:
             nz = chunk_noise(n, float(fsample[c]), float(sigma[c]), float(fknee[c]), float(alpha[c]),
                              ss_chunks[c]) * noise_scale
@@ -243,4 +264,5 @@ def make_problem(cfg: WorkloadConfig, with_noise: bool = True, noise_scale: floa
 
     return Problem(cfg=cfg, chunk_off=chunk_off, fsample=fsample, sigma=sigma, fknee=fknee,
                    alpha=alpha, pix=pix, psi=psi_store, psi_index=psi_index, psi_table=psi_table,
-                   d=d, m_true=m_true, noise=noise_all)
+                   d=d, m_true=m_true, noise=noise_all, pix_b=pix_b, psi_b=psi_b,
+                   weights=(1.0, -1.0) if diff else None)

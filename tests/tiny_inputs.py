@@ -78,3 +78,30 @@ def tiny_problem(seed: int, lengths=(64, 48), nx: int = 4, ncomp: int = 3, fknee
 
 def random_map(seed: int, ncomp: int, npix: int, scale: float = 1.0) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((ncomp, npix)) * scale
+
+
+def tiny_composite(seed: int, b_mode: str = "shift", lengths=(64, 48), nx: int = 5, ncomp: int = 3,
+                   weights=(1.0, -1.0), flag_b: float = 0.1, **kw):
+    """A ``tiny_problem`` plus a second pointing component for P = w_A P_A + w_B P_B.
+
+    b_mode: "shift" (beam B two pixels to the right of beam A in even chunks and one pixel
+    below it in odd ones, wrapping, so that the differences link every pixel; a fraction
+    ``flag_b`` of B's entries off the map), "none" (P_B = 0: every B index -1), "same"
+    (B = A: the same pixels and angles).  B's angles are drawn independently for "shift".
+    Returns (tiny, pix_b, psi_b, weights)."""
+    t = tiny_problem(seed, lengths=lengths, nx=nx, ncomp=ncomp, **kw)
+    rng = np.random.default_rng(seed + 1000)
+    if b_mode == "none":
+        pix_b = np.full_like(t.pix, -1)
+        psi_b = None if t.psi is None else t.psi.copy()
+    elif b_mode == "same":
+        pix_b = t.pix.copy()
+        psi_b = None if t.psi is None else t.psi.copy()
+    else:
+        on = t.pix >= 0
+        x, y = t.pix % nx, t.pix // nx
+        odd = (np.searchsorted(t.chunk_off, np.arange(len(t.pix)), side="right") - 1) % 2 == 1
+        pix_b = np.where(on, np.where(odd, ((y + 1) % nx) * nx + x, y * nx + (x + 2) % nx), -1).astype(np.int32)
+        pix_b[rng.random(len(pix_b)) < flag_b] = -1
+        psi_b = None if t.psi is None else rng.uniform(0.0, np.pi, size=len(pix_b)).astype(t.psi.dtype)
+    return t, pix_b, psi_b, tuple(float(w) for w in weights)
