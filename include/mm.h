@@ -126,6 +126,24 @@ enum { MM_BIN_SORTED = 0, MM_BIN_ATOMIC = 1 };                            /* bin
  *               16..512; 16..1024 asks for that many.  Larger tiles hold longer
  *               time-contiguous runs of each scan (fewer partly used cache lines
  *               when the binning pass reads the filtered TOD) but take more LDS.
+ *  pix_b, psi_b, weight_a, weight_b
+ *               composite pointing P = P_A + P_B (Section 2.2, Appendix B): NULL
+ *               pix_b is the single pencil beam.  Otherwise every sample j also
+ *               sees the map through a second component at pixel pix_b[j] (device,
+ *               N_s int32, < 0: no second entry) with angle psi_b[j] (device, same
+ *               type as psi; NULL when ncomp == 1):
+ *                 (P m)_j = weight_a a(psi_j) m[pix_j] + weight_b a(psi_b_j) m[pix_b_j],
+ *               a(psi) = (1, cos 2psi, sin 2psi).  A differential instrument has
+ *               weights +1 and -1.  The messenger covariance is split T_A = T_B =
+ *               T/2, so the per-pixel blocks the iteration inverts are
+ *               W_AB = 2 (weight_a^2 P_A^T T^-1 P_A + weight_b^2 P_B^T T^-1 P_B)
+ *               (eqn. mdiffcompact), and the lambda = inf step is a weighted Jacobi
+ *               step (no longer the binned map).  Hits count the entries of both
+ *               components.  Needs map_access AUTO or PROJECTED (it takes the
+ *               projected access, with a 2 N_s-sample buffer) and binning SORTED;
+ *               mm_lift_rhs, mm_tod_apply(which = 2) and mm_solve with a map
+ *               right-hand side return MM_E_ARG (their lifting needs
+ *               W = P^T T^-1 P).  Weights must be finite.
  */
 typedef struct {
   int32_t ncomp;
@@ -149,6 +167,10 @@ typedef struct {
   int32_t binning;
   int32_t with_adjoint;
   int32_t tile_pixels;
+  const int32_t* pix_b;
+  const void* psi_b;
+  double weight_a;
+  double weight_b;
 } mm_plan_desc;
 
 /* Cooling schedule (Section 3.1): optionally one lambda = inf step, then

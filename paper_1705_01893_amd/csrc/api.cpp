@@ -115,7 +115,9 @@ mm_status chi2_device(mm_plan_s* pl, const void* d, const double* m, double lam,
 // m_in: the previous iteration's binning epilogue wrote it
 mm_status iterate(mm_plan_s* pl, const void* d, double lam, const double* m_in, double* m_out, double* chi2_dev,
                   hipStream_t s, bool chained = false) {
-  if (std::isinf(lam)) {
+  // single beam: at lambda = inf the step is the binned map W^-1 P^T T^-1 d whatever m_in is (the
+  // filter is T^-1); composite pointing keeps the general step there (F(inf) != 0), with gain 1/tau
+  if (std::isinf(lam) && !pl->composite) {
     if (chi2_dev) MM_TRY(chi2_device(pl, d, m_in, 1.0, chi2_dev, nullptr, s, chained));
     MM_TRY_HIP(timed(pl, 3, s, [&] {
       if (pl->bin_atomic) return bin_atomic_update(pl, BSRC_DATA_OVER_TAU, d, EPI_REPLACE, m_in, m_out, s);
@@ -155,8 +157,10 @@ mm_status dot(mm_plan_s* pl, const double* a, const double* b, double* out, hipS
   return MM_OK;
 }
 
-// out = N T^-1 P W^-1 g in time order (the lifted right-hand side of an adjoint solve)
+// out = N T^-1 P W^-1 g in time order (the lifted right-hand side of an adjoint solve); needs
+// W = P^T T^-1 P, which composite pointing (W_AB) does not have
 mm_status lift(mm_plan_s* pl, const double* g, void* out, hipStream_t s) {
+  if (pl->composite) return fail(MM_E_ARG, "the lifted right-hand side needs single-beam pointing");
   double* u = pl->d_map[5];
   MM_TRY_HIP(launch_winv_apply(pl->dp, g, u, s));
   MM_TRY(sweep_filter(pl, nullptr, u, SRC_PM, B_FILTER, GAIN_LIFT, 1.0, 1.0, s));
@@ -387,6 +391,7 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const double* rhs_map, const m
   if (!plan || !sched || !m_out) return fail(MM_E_ARG, "null argument");
   if ((d == nullptr) == (rhs_map == nullptr)) return fail(MM_E_ARG, "give exactly one of d and rhs_map");
   if (rhs_map && !plan->d_work2) return fail(MM_E_ARG, "a map right-hand side needs a plan built with_adjoint");
+  if (rhs_map && plan->composite) return fail(MM_E_ARG, "a map right-hand side needs single-beam pointing");
   std::vector<double> lams;
   MM_TRY(expand_schedule(sched, lams));
   const int64_t n = mapn(plan);
@@ -432,7 +437,7 @@ mm_status mm_solve_mapsized(mm_plan_t plan, const void* d, const mm_schedule* sc
     const size_t nit = lams.size();
     for (size_t i = 0; i < nit; ++i) {
       const double lam = lams[i];
-      if (std::isinf(lam)) {  // m_d(inf) = W^-1 P^T T^-1 d and F(inf) = 0: the binned map
+      if (std::isinf(lam)) {  // m_d(inf) + F(inf) m: the residual-form step at lambda = inf
         MM_TRY(iterate(plan, d, lam, m_out, m_out, nullptr, cs, i > 0));
         continue;
       }
@@ -529,6 +534,7 @@ mm_status mm_tod_apply(mm_plan_t plan, int32_t which, double lambda, const doubl
   if (!plan || !x || !out) return fail(MM_E_ARG, "null argument");
   if (which < 0 || which > 2) return fail(MM_E_ARG, "which must be 0, 1 or 2");
   if (which == 1 && (!(lambda >= 1.0) || !std::isfinite(lambda))) return fail(MM_E_ARG, "lambda must be >= 1");
+  if (which == 2 && plan->composite) return fail(MM_E_ARG, "the lifting filter needs single-beam pointing");
   const int gain = which == 0 ? GAIN_NINV : (which == 1 ? GAIN_MESSENGER : GAIN_LIFT);
   hipStream_t s = S(stream);
   MM_TRY(sweep_filter(plan, nullptr, x, SRC_PM, B_FILTER, gain, which == 1 ? lambda : 1.0, 1.0, s));

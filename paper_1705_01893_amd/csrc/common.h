@@ -112,15 +112,19 @@ struct SubBatch {
   int64_t sorted_begin;      // offset into perm / lp / psi_sorted
   int32_t seg_begin, seg_end;  // at most kMaxSegs segments
   int32_t count;             // samples in the sub-batch
-  int32_t pad;
+  int32_t na;                // stage positions below na hold first-component entries (composite
+                             // pointing: those of the second follow them); count otherwise
 };
 constexpr int kMaxSegs = 512;  // segments per sub-batch (LDS segment table)
 constexpr int kSortAlign = 16;  // alignment (elements) of each sub-batch in the pixel-sorted arrays
 constexpr int kPerLane = 16;    // consecutive pixel-sorted samples one lane accumulates
+// Composite pointing (two entries per sample) runs over 2 N_s pointing entries: entry v < N_s is
+// sample v's first component, entry N_s + j its second; chunk c + nchunk holds the second
+// components of chunk c.  Segments, runs and sub-batches are cut over that entry order.
 struct Segment {             // 16 bytes: read by both walks of the binning pass every iteration
-  int64_t start;             // first sample
+  int64_t start;             // first pointing entry (the sample index for a single beam)
   int32_t pos;               // position of the first sample in the LDS stage
-  int32_t chunk;
+  int32_t chunk;             // chunk of the entries (nchunk + c: second components of chunk c)
 };
 
 struct DevPlan {
@@ -152,6 +156,12 @@ struct DevPlan {
   double2* mapi;             // I/Q/U map interleaved, [npix][2] = (I, Q), (U, 0): one line per gather
                              // (gather access with ncomp = 3; null otherwise)
   const double* md;          // m_d(lambda) of the map-sized form (EPI_MAPSIZED launches only)
+  // composite pointing P = wa P_A + wb P_B (0 / 1, 0 for a single beam): the projection buffer
+  // holds P_A m and P_B m (times their weights) in two halves, pmb_off complex values apart
+  int32_t composite;
+  int32_t pad1;
+  double wa, wb;
+  int64_t pmb_off;
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -170,12 +180,15 @@ struct SortCounters {
                                    // 4 angle index beyond the table, 8 reserved sizes exceeded
   unsigned int pad;
 };
-// The samples cut into slabs walked in time order, one thread per slab.
+// The pointing entries cut into slabs walked in order, one thread per slab.  Entry v reads
+// pix[v] below ns_a and pix_b[v - ns_a] from there (composite pointing: ns = 2 ns_a, and the
+// chunk table lists the second components' chunks after the first ones).
 struct SlabWalk {
   const int32_t* pix;
-  const int64_t* off;  // device chunk table, nchunk + 1 entries
+  const int32_t* pix_b;  // null for a single beam (ns == ns_a)
+  const int64_t* off;    // device chunk table, nchunk + 1 entries
   int32_t nchunk;
-  int64_t ns, slab, nslabs;
+  int64_t ns, ns_a, slab, nslabs;
 };
 // Plan-time temporaries of the sort.
 struct SortTemp {
@@ -205,14 +218,14 @@ constexpr size_t kStaticScratchBytes = size_t(1) << 20;
 
 hipError_t launch_sort_clear(SortCounters* ctr, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
-hipError_t launch_sort_stats(const SlabWalk& w, int64_t npix, int64_t nxm, const void* psi, int psi_kind,
-                             int64_t table_len, SortCounters* ctr, hipStream_t s);
+hipError_t launch_sort_stats(const SlabWalk& w, int64_t npix, int64_t nxm, const void* psi, const void* psi_b,
+                             int psi_kind, int64_t table_len, SortCounters* ctr, hipStream_t s);
 hipError_t launch_sort_count(const SlabWalk& w, const TileGeom& g, SortCounters* ctr, int64_t* starts,
                              hipStream_t s);
 hipError_t launch_sort_lists(const SlabWalk& w, const TileGeom& g, int64_t nym, const SortTemp& T, const SortOut& O,
                              SortCounters* ctr, hipStream_t s);
-hipError_t launch_sort_pixels(const int32_t* pix, const void* psi, int psi_esz, const TileGeom& g, const SortOut& O,
-                              hipStream_t s);
+hipError_t launch_sort_pixels(const SlabWalk& w, const void* psi, const void* psi_b, int psi_esz, const TileGeom& g,
+                              const SortOut& O, hipStream_t s);
 // address of the fixed scratch array on `device` (which must be current); looked up once per device
 void* static_scratch(int device, hipError_t* err);
 

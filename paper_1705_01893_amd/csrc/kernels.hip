@@ -374,7 +374,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* _
 #pragma unroll 1
     for (int g = 0; g < E; g += G) {
       int2 pp[G];
-      cx<T> dd[G], pb[G];
+      cx<T> dd[G], pb[G], pb2[G];
       uint4 raw[G];
       bool ok[G];
       // every load of the group goes out before any is used: elements outside the item read the
@@ -391,9 +391,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* _
         dd[u].y = T(0);
         pb[u].x = T(0);
         pb[u].y = T(0);
+        pb2[u].x = T(0);
+        pb2[u].y = T(0);
         if (src != SRC_PM && src != SRC_PMBUF) dd[u] = ((const cx<T>*)d)[ci];
         if (src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF) {
           pb[u] = ((const cx<T>*)pmbuf)[ci];
+          if (P.pmb_off) pb2[u] = ((const cx<T>*)pmbuf)[ci + P.pmb_off];  // composite: P_B m
         } else if (!NG && src != SRC_D) {
           const int2 q = ((const int2*)P.pix)[ci];
           pp[u] = ok[u] ? q : make_int2(-1, -1);
@@ -435,10 +438,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* _
             z.x = (T)pm[u][0];
             z.y = (T)pm[u][1];
           } else if (src == SRC_PMBUF) {
-            z = pb[u];
+            z.x = (T)((double)pb[u].x + (double)pb2[u].x);
+            z.y = (T)((double)pb[u].y + (double)pb2[u].y);
           } else if (src == SRC_D_MINUS_PMBUF) {
-            z.x = (T)((double)dd[u].x - (double)pb[u].x);
-            z.y = (T)((double)dd[u].y - (double)pb[u].y);
+            z.x = (T)((double)dd[u].x - ((double)pb[u].x + (double)pb2[u].x));
+            z.y = (T)((double)dd[u].y - ((double)pb[u].y + (double)pb2[u].y));
           } else if (!NG) {
             z.x = (T)((double)dd[u].x - pm[u][0]);
             z.y = (T)((double)dd[u].y - pm[u][1]);
@@ -987,22 +991,31 @@ __device__ __forceinline__ BinLds<S> bin_lds(double* base, bool plan, int tpix) 
 }
 
 // Load the segment table of sub-batch S and mark its starts in bitmap `sm` (zeroed beforehand).
-// Segment starts are sample indices in time order; in_work moves them to the work buffer, where
-// chunk c starts at real position 2 xoff_c instead of off_c.
+// Segment starts are pointing-entry indices: the sample index in time order, plus N_s for the
+// second components of composite pointing.  Unless `entries` keeps them (to address the
+// two-part projection buffer), they become sample indices; in_work then moves them to the work
+// buffer, where chunk c starts at real position 2 xoff_c instead of off_c.  The chunks kept for
+// the caller are the samples' chunks.
 template <typename SL>
 __device__ __forceinline__ void load_segments(const DevPlan& P, const SubBatch& S, const BinLds<SL>& L,
-                                              unsigned long long* sm, bool with_chunk, bool in_work) {
+                                              unsigned long long* sm, bool with_chunk, bool in_work,
+                                              bool entries = false) {
   const int nseg = S.seg_end - S.seg_begin;
   for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
     const Segment g = P.segs[S.seg_begin + i];
     int64_t start = g.start;
+    int chunk = g.chunk;
+    if (chunk >= P.nchunk) {
+      chunk -= P.nchunk;
+      if (!entries) start -= P.nsamp;
+    }
     if (in_work) {
-      const DevChunk& ch = P.chunks[g.chunk];
+      const DevChunk& ch = P.chunks[chunk];
       start += 2 * ch.xoff - ch.off;
     }
     L.sstart[i] = start;
     L.spos[i] = (uint16_t)g.pos;
-    if (with_chunk) L.schunk[i] = g.chunk;
+    if (with_chunk) L.schunk[i] = chunk;
     atomicOr(&sm[g.pos >> 6], 1ull << (g.pos & 63));
   }
 }
@@ -1048,7 +1061,8 @@ __device__ __forceinline__ uint64_t entry_psi_raw(int pk, const LaneEntries& e, 
 // P m for every on-map sample of one tile, written to a TOD-sized buffer in time order.
 // mt: the tile's map values in LDS, [local pixel][NC].  For each sub-batch the values are formed
 // in pixel-sorted order, scattered to their staging positions in LDS and written out along the
-// sub-batch's time-contiguous segments (coalesced within each segment).
+// sub-batch's time-contiguous segments (coalesced within each segment).  Composite pointing:
+// each component's weighted projection goes to its half of the buffer (entry index).
 template <typename T, int NC, int PK>
 __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt, const BinLds<T>& L, int& sbn,
                              T* __restrict__ pm_out) {
@@ -1077,12 +1091,14 @@ __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt,
               weights_from_raw<T>(P, pk, entry_psi_raw(pk, en, i), c, sn);
               v += c * mt[l * 3 + 1] + sn * mt[l * 3 + 2];
             }
-            L.stage[entry_u16(en.pmw, i)] = (T)v;
+            const int q = entry_u16(en.pmw, i);
+            if (P.composite) v *= q < S.na ? P.wa : P.wb;
+            L.stage[q] = (T)v;
           }
         }
       }
     }
-    load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), false, false);
+    load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), false, false, true);
     __syncthreads();
     const SegIndex si = seg_index(L.smask + (sbn & 1) * (kSubBatch / 64));
     // the other bitmap was last read before the previous sub-batch's final barrier
@@ -1220,6 +1236,11 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
             } else {
               y = stage[pr];
               if (kScaleAtUse && bsrc == BSRC_DATA_OVER_TAU) y *= P.chunks[schunk[gpr]].inv_tau;
+            }
+            if (P.composite) {
+              // the entry's component weight w; the weight blocks take w^2 / (tau / 2) (T_A = T_B = T/2)
+              const double w = pr < S.na ? P.wa : P.wb;
+              y *= PLAN ? 2.0 * w * w : w;
             }
             double c = 0.0, sn = 0.0;
             if (POL) weights_from_raw<T>(P, pk, entry_psi_raw(pk, en, i), c, sn);

@@ -76,6 +76,14 @@ mm_status validate(const mm_plan_desc* desc) {
   if (D.with_adjoint != 0 && D.with_adjoint != 1) return fail(MM_E_ARG, "with_adjoint must be 0 or 1");
   if (D.tile_pixels != 0 && (D.tile_pixels < 16 || D.tile_pixels > kMaxTilePixAsked))
     return fail(MM_E_ARG, "tile_pixels must be 0 (automatic) or 16.." + std::to_string(kMaxTilePixAsked));
+  if (D.pix_b) {
+    if (D.ncomp == 3 && !D.psi_b) return fail(MM_E_ARG, "composite I/Q/U pointing needs the second angles (psi_b)");
+    if (!std::isfinite(D.weight_a) || !std::isfinite(D.weight_b))
+      return fail(MM_E_ARG, "composite pointing weights must be finite");
+    if (D.map_access == MM_MAP_GATHER)
+      return fail(MM_E_ARG, "composite pointing reads P m from the projection buffer (map_access AUTO or PROJECTED)");
+    if (D.binning != MM_BIN_SORTED) return fail(MM_E_ARG, "composite pointing needs sorted binning");
+  }
   if (D.chunk_off[0] != 0) return fail(MM_E_ARG, "chunk_off[0] must be 0");
   std::string why;
   for (int64_t c = 0; c < D.nchunk; ++c) {
@@ -109,6 +117,9 @@ struct Prep {
   bool f64 = true;
   size_t tsz = 8, pes = 0;
   int64_t ns = 0, nchunk = 0, mapn = 0;
+  // pointing entries and their chunks: N_s and nchunk, doubled with composite pointing
+  bool composite = false;
+  int64_t nent = 0, nchunk_ent = 0;
   int nw = 1;
   std::vector<int32_t> chunk_class;
   std::vector<ClassInfo> classes;
@@ -129,6 +140,9 @@ void prep_transforms(const mm_plan_desc& D, Prep& P) {
   P.pes = D.ncomp == 3 ? psi_elem_size(D.psi_kind) : 0;
   P.nchunk = D.nchunk;
   P.ns = D.chunk_off[D.nchunk];
+  P.composite = D.pix_b != nullptr;
+  P.nent = P.composite ? 2 * P.ns : P.ns;
+  P.nchunk_ent = P.composite ? 2 * P.nchunk : P.nchunk;
   P.mapn = (int64_t)D.ncomp * D.npix;
   P.nw = D.ncomp == 1 ? 1 : 6;
   P.chunk_class.resize(D.nchunk);
@@ -180,7 +194,7 @@ void prep_transforms(const mm_plan_desc& D, Prep& P) {
   P.bin_atomic = D.binning == MM_BIN_ATOMIC;
   // maps larger than the L2 of one XCD (4 MB) are gathered badly by the strided column pass:
   // then P m is produced in pixel-tile order instead
-  P.pm_mode = D.map_access == MM_MAP_PROJECTED ||
+  P.pm_mode = D.map_access == MM_MAP_PROJECTED || P.composite ||
               (D.map_access == MM_MAP_AUTO && P.mapn * (int64_t)sizeof(double) > ((int64_t)4 << 20));
   P.mapi = !P.pm_mode && D.ncomp == 3;
 }
@@ -233,35 +247,54 @@ TileGeom geom(const Prep& P) {
 constexpr int64_t kFineSlab = int64_t(1) << 14;       // samples per thread of the analysis walks
 constexpr int64_t kSlabMatrix = int64_t(1) << 25;     // entries of the per-slab, per-tile run counts
 
-// Bytes of the analysis header at the start of the workspace: the device chunk table and the
-// counters (with the sort's totals).
-size_t header_bytes(int64_t nchunk) {
+// Bytes of the analysis header at the start of the workspace: the device chunk table of the
+// pointing entries (nchunk_ent + 1 offsets) and the counters (with the sort's totals).
+size_t header_bytes(int64_t nchunk_ent) {
   Arena a;
-  a.take((size_t)(nchunk + 1) * sizeof(int64_t));
+  a.take((size_t)(nchunk_ent + 1) * sizeof(int64_t));
   a.take(256);
   return a.used;
+}
+
+// The chunk table of the pointing entries: the caller's, followed for composite pointing by the
+// same chunks shifted by N_s (the second components).
+std::vector<int64_t> entry_chunk_table(const mm_plan_desc& D, const Prep& P) {
+  std::vector<int64_t> off(D.chunk_off, D.chunk_off + D.nchunk + 1);
+  if (P.composite)
+    for (int64_t c = 1; c <= D.nchunk; ++c) off.push_back(P.ns + D.chunk_off[c]);
+  return off;
+}
+
+SlabWalk entry_walk(const mm_plan_desc& D, const Prep& P, const int64_t* doff) {
+  SlabWalk w;
+  w.pix = D.pix;
+  w.pix_b = P.composite ? D.pix_b : nullptr;
+  w.off = doff;
+  w.nchunk = (int32_t)P.nchunk_ent;
+  w.ns = P.nent;
+  w.ns_a = P.ns;
+  w.slab = kFineSlab;
+  w.nslabs = (P.nent + kFineSlab - 1) / kFineSlab;
+  return w;
 }
 
 // Analysis passes over the device pointing: validation, scan statistics (tile shape), on-map
 // samples and runs.  doff / dctr: device chunk table and counters.  Waits for the stream.
 mm_status analyse(const mm_plan_desc& D, Prep& P, int64_t* doff, SortCounters* dctr, hipStream_t s) {
-  if (hipMemcpyAsync(doff, D.chunk_off, (size_t)(D.nchunk + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s) !=
-      hipSuccess)
+  const std::vector<int64_t> off = entry_chunk_table(D, P);
+  if (hipMemcpyAsync(doff, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(MM_E_HIP, "chunk table upload failed");
-  SlabWalk w;
-  w.pix = D.pix;
-  w.off = doff;
-  w.nchunk = (int32_t)D.nchunk;
-  w.ns = P.ns;
-  w.slab = kFineSlab;
-  w.nslabs = (P.ns + kFineSlab - 1) / kFineSlab;
+  const SlabWalk w = entry_walk(D, P, doff);
   hipError_t e = launch_sort_clear(dctr, s);
   if (e == hipSuccess)
     e = launch_sort_stats(w, D.npix, D.nx > 0 ? D.nx : D.npix, D.ncomp == 3 ? D.psi : nullptr,
-                          D.ncomp == 3 ? D.psi_kind : 0, D.psi_table_len, dctr, s);
+                          D.ncomp == 3 && P.composite ? D.psi_b : nullptr, D.ncomp == 3 ? D.psi_kind : 0,
+                          D.psi_table_len, dctr, s);
   SortCounters c;
   if (e == hipSuccess) e = hipMemcpyAsync(&c, dctr, sizeof(c), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  // waited on in every case: the host chunk table must outlive its upload
+  const hipError_t es = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = es;
   if (e != hipSuccess)
     return fail(MM_E_HIP, std::string("pointing analysis failed (are pix and psi device pointers?): ") +
                               hipGetErrorString(e));
@@ -298,9 +331,9 @@ mm_status analyse(const mm_plan_desc& D, Prep& P, int64_t* doff, SortCounters* d
   if (P.cap_seg > (int64_t)INT32_MAX || P.cap_sb > (int64_t)INT32_MAX)
     return fail(MM_E_ARG, "the pointing has too many time-contiguous segments per tile");
   // slabs of the run-list walk: enough threads, within the per-slab, per-tile count budget
-  const int64_t want = std::max<int64_t>(1, (P.ns + kFineSlab - 1) / kFineSlab);
+  const int64_t want = std::max<int64_t>(1, (P.nent + kFineSlab - 1) / kFineSlab);
   P.nslabs = std::max<int64_t>(1, std::min<int64_t>(want, kSlabMatrix / std::max<int64_t>(1, P.ntiles)));
-  P.slab = (P.ns + P.nslabs - 1) / P.nslabs;
+  P.slab = (P.nent + P.nslabs - 1) / P.nslabs;
   return MM_OK;
 }
 
@@ -363,7 +396,7 @@ bool carve_sort_temp(Arena& a, const Prep& P, SortTemp& T) {
 
 bool carve(Arena& a, const mm_plan_desc& D, const Prep& P, Bufs& B) {
   const int64_t npix = D.npix;
-  bool ok = take(a, (size_t)P.nchunk + 1, &B.off);
+  bool ok = take(a, (size_t)P.nchunk_ent + 1, &B.off);
   void* c = a.take(256);
   B.ctr = (SortCounters*)c;
   ok = ok && c && take(a, (size_t)P.nchunk, &B.chunks) && take(a, P.classes.size(), &B.classes) &&
@@ -390,7 +423,7 @@ bool carve(Arena& a, const mm_plan_desc& D, const Prep& P, Bufs& B) {
   char* w = nullptr;
   ok = take(a, (size_t)(2 * P.xwork) * P.tsz, &w);
   B.work = w;
-  if (ok && P.pm_mode) ok = take(a, (size_t)P.ns * P.tsz, (char**)&B.pm);
+  if (ok && P.pm_mode) ok = take(a, (size_t)P.nent * P.tsz, (char**)&B.pm);
   if (ok && P.adjoint) ok = take(a, (size_t)(2 * P.xwork) * P.tsz, (char**)&B.work2);
   if (!ok) return false;
   const size_t tod_bytes = a.used - tod0;
@@ -479,21 +512,22 @@ mm_status workspace_query(const mm_plan_desc* desc, hipStream_t s, void* scratch
   const mm_plan_desc& D = *desc;
   Prep P;
   prep_transforms(D, P);
-  const size_t hb = header_bytes(D.nchunk);
+  const size_t hb = header_bytes(P.nchunk_ent);
   void* own = nullptr;
   if (!scratch) {
     if (hipMalloc(&own, hb) != hipSuccess) return fail(MM_E_NOMEM, "device allocation failed (analysis counters)");
     scratch = own;
   } else if (hb > scratch_bytes) {
     return fail(MM_E_ARG, "the fixed scratch of " + std::to_string(scratch_bytes) +
-                              " bytes holds the chunk table of at most " +
+                              " bytes holds a chunk table of at most " +
                               std::to_string((scratch_bytes - 256) / sizeof(int64_t) - 1) +
-                              " chunks; this description has " + std::to_string(D.nchunk));
+                              " entries; this description needs " + std::to_string(P.nchunk_ent) +
+                              " (twice the chunks with composite pointing)");
   }
   Arena h;
   h.base = (char*)scratch;
   h.cap = hb;
-  int64_t* doff = (int64_t*)h.take((size_t)(D.nchunk + 1) * sizeof(int64_t));
+  int64_t* doff = (int64_t*)h.take((size_t)(P.nchunk_ent + 1) * sizeof(int64_t));
   SortCounters* dctr = (SortCounters*)h.take(256);
   st = analyse(D, P, doff, dctr, s);
   if (own) (void)hipFree(own);
@@ -536,13 +570,13 @@ mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStr
   pl->ws_bytes = ws_bytes;
 
   // ---- analysis of the pointing in the workspace's header, then the full layout
-  if (header_bytes(D.nchunk) > ws_bytes)
+  if (header_bytes(P.nchunk_ent) > ws_bytes)
     return fail(MM_E_NOMEM, "the workspace is smaller than mm_plan_workspace_bytes reports");
   {
     Arena h;
     h.base = (char*)ws;
     h.cap = ws_bytes;
-    int64_t* doff = (int64_t*)h.take((size_t)(D.nchunk + 1) * sizeof(int64_t));
+    int64_t* doff = (int64_t*)h.take((size_t)(P.nchunk_ent + 1) * sizeof(int64_t));
     SortCounters* dctr = (SortCounters*)h.take(256);
     if ((st = analyse(D, P, doff, dctr, s)) != MM_OK) return st;
   }
@@ -578,11 +612,7 @@ mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStr
   O.cap_sort = P.cap_sort;
   O.totals = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(B.ctr) + 128);
   {
-    SlabWalk w;
-    w.pix = D.pix;
-    w.off = B.off;
-    w.nchunk = (int32_t)D.nchunk;
-    w.ns = ns;
+    SlabWalk w = entry_walk(D, P, B.off);
     w.slab = P.slab;
     w.nslabs = P.nslabs;
     hipError_t e = launch_fill_i64(B.T.starts, P.nslabs * P.ntiles, 0, s);
@@ -604,7 +634,8 @@ mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStr
     pl->nsbs = hb.totals[0];
     pl->nsegs = hb.totals[1];
     pl->nsorted = hb.totals[2];
-    e = launch_sort_pixels(D.pix, D.ncomp == 3 ? D.psi : nullptr, (int)P.pes, g, O, s);
+    e = launch_sort_pixels(w, D.ncomp == 3 ? D.psi : nullptr, D.ncomp == 3 && P.composite ? D.psi_b : nullptr,
+                           (int)P.pes, g, O, s);
     if (e != hipSuccess) return fail(MM_E_HIP, std::string("pixel sort launch: ") + hipGetErrorString(e));
   }
 
@@ -776,6 +807,11 @@ mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStr
   Pd.winv = B.winv;
   Pd.solvable = B.sol;
   Pd.mapi = B.mapi;
+  Pd.composite = P.composite ? 1 : 0;
+  Pd.wa = P.composite ? D.weight_a : 1.0;
+  Pd.wb = P.composite ? D.weight_b : 0.0;
+  Pd.pmb_off = P.composite ? ns / 2 : 0;
+  pl->composite = P.composite;
   pl->d_winv = B.winv;
   pl->d_solvable = B.sol;
   pl->d_hits = B.hits;
@@ -791,8 +827,8 @@ mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStr
   pl->bin_atomic = P.bin_atomic;
   pl->d_batom = B.batom;
   for (int64_t c = 0; c < D.nchunk; ++c) pl->max_n = std::max<int64_t>(pl->max_n, D.chunk_off[c + 1] - D.chunk_off[c]);
-  if (pl->pm_mode) {  // off-map samples: P m = 0 (the buffer held plan-time temporaries)
-    if (launch_fill_i64((int64_t*)pl->d_pm, (int64_t)((size_t)ns * P.tsz / sizeof(int64_t)), 0, s) != hipSuccess)
+  if (pl->pm_mode) {  // off-map entries: P m = 0 (the buffer held plan-time temporaries)
+    if (launch_fill_i64((int64_t*)pl->d_pm, (int64_t)((size_t)P.nent * P.tsz / sizeof(int64_t)), 0, s) != hipSuccess)
       return fail(MM_E_HIP, "clearing the projection buffer failed");
   }
   if ((st = plan_precompute(pl, s)) != MM_OK) return st;

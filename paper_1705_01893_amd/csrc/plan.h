@@ -74,6 +74,7 @@ struct mm_plan_s {
   // P m in time order, written in pixel-tile order (large maps: the column pass reads it instead
   // of gathering the map)
   int pm_mode = 0;
+  bool composite = false;  // P = P_A + P_B (second pointing component given)
   void* d_pm = nullptr;
   // binning by FP64 atomics (measured alternative): binned vector, longest chunk
   bool bin_atomic = false;

@@ -19,7 +19,8 @@
 //
 // A slab is a contiguous range of samples walked by one thread in time order, so every
 // count is an integer and every list position follows from prefix sums: the result does
-// not depend on scheduling.  The scratch array at the end serves the allocation-free
+// not depend on scheduling.  With composite pointing the walks run over the 2 N_s pointing
+// entries (the first components, then the second ones), each a "sample" of its own here.  The scratch array at the end serves the allocation-free
 // workspace query.
 #include <hip/hip_runtime.h>
 
@@ -43,6 +44,19 @@ __device__ __forceinline__ int chunk_of(const int64_t* __restrict__ off, int nch
   return lo;
 }
 
+// the pixel of pointing entry j: first components below na, second ones from there
+struct PixSrc {
+  const int32_t* a;
+  const int32_t* b;
+  int64_t na;
+};
+__device__ __forceinline__ int32_t pix_at(const PixSrc& q, int64_t j) { return j < q.na ? q.a[j] : q.b[j - q.na]; }
+template <typename E>
+__device__ __forceinline__ E psi_at(const void* a, const void* b, int64_t na, int64_t j) {
+  return j < na ? ((const E*)a)[j] : ((const E*)b)[j - na];
+}
+inline PixSrc pix_src(const SlabWalk& w) { return PixSrc{w.pix, w.pix_b, w.ns_a}; }
+
 __device__ __forceinline__ int tile_of(int32_t p, const TileGeom& g) {
   const uint32_t y = (uint32_t)p / (uint32_t)g.nxm, x = (uint32_t)p - y * (uint32_t)g.nxm;
   return (int)((y / (uint32_t)g.th) * (uint32_t)g.ntx + x / (uint32_t)g.tw);
@@ -62,10 +76,11 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
 // Scan statistics, on-map count and validation.  The statistics follow every fourth pair of
 // consecutive samples inside a chunk (j - off_c = 1 mod 4) whose two pixels are on the map and
 // at most 16 pixels apart in x and in y (scan-line turnarounds left out).
-__global__ __launch_bounds__(256) void k_sort_stats(const int32_t* __restrict__ pix, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(256) void k_sort_stats(PixSrc pix, const int64_t* __restrict__ off,
                                                     int nchunk, int64_t ns, int64_t slab, int64_t nslabs,
                                                     int64_t npix, int64_t nxm, const void* __restrict__ psi,
-                                                    int psi_kind, int64_t table_len, SortCounters* ctr) {
+                                                    const void* __restrict__ psi_b, int psi_kind, int64_t table_len,
+                                                    SortCounters* ctr) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   unsigned long long sx = 0, sy = 0, nst = 0, non = 0;
   unsigned int flags = 0;
@@ -81,11 +96,11 @@ __global__ __launch_bounds__(256) void k_sort_stats(const int32_t* __restrict__ 
           cbeg = cend;
           cend = off[c + 1];
         }
-        const int32_t p = pix[j];
+        const int32_t p = pix_at(pix, j);
         if ((int64_t)p >= npix) flags |= 1u;
         non += p >= 0 ? 1ull : 0ull;
         if (j > cbeg && ((j - cbeg) & 3) == 1 && p >= 0) {
-          const int32_t a = pix[j - 1];
+          const int32_t a = pix_at(pix, j - 1);
           if (a >= 0 && (int64_t)a < npix && (int64_t)p < npix) {
             const int64_t ax = a % nxm, ay = a / nxm, bx = p % nxm, by = p / nxm;
             const int64_t dx = ax > bx ? ax - bx : bx - ax, dy = ay > by ? ay - by : by - ay;
@@ -97,13 +112,13 @@ __global__ __launch_bounds__(256) void k_sort_stats(const int32_t* __restrict__ 
           }
         }
         if (psi_kind == 1) {
-          const double v = ((const double*)psi)[j];
+          const double v = psi_at<double>(psi, psi_b, pix.na, j);
           if (!(fabs(v) < kMaxAngle)) flags |= 2u;
         } else if (psi_kind == 2) {
-          const float v = ((const float*)psi)[j];
+          const float v = psi_at<float>(psi, psi_b, pix.na, j);
           if (!(fabs((double)v) < kMaxAngle)) flags |= 2u;
         } else if (psi_kind == 3) {
-          if ((int64_t)((const uint16_t*)psi)[j] >= table_len) flags |= 4u;
+          if ((int64_t)psi_at<uint16_t>(psi, psi_b, pix.na, j) >= table_len) flags |= 4u;
         }
       }
     }
@@ -128,7 +143,7 @@ __global__ __launch_bounds__(256) void k_sort_stats(const int32_t* __restrict__ 
 // Run starts.  Sample j starts a run when it is on the map and its tile differs from that of
 // sample j - 1 (off the map, or the previous chunk's last sample, count as no tile).  With
 // `starts` (row s of an nslabs x ntiles matrix) the starts are also counted per tile.
-__global__ __launch_bounds__(256) void k_sort_count(const int32_t* __restrict__ pix, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(256) void k_sort_count(PixSrc pix, const int64_t* __restrict__ off,
                                                     int nchunk, int64_t ns, int64_t slab, int64_t nslabs, TileGeom g,
                                                     SortCounters* ctr, int64_t* __restrict__ starts) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -141,7 +156,7 @@ __global__ __launch_bounds__(256) void k_sort_count(const int32_t* __restrict__ 
       int64_t cend = off[c + 1];
       int prev_t = -1;
       if (j0 > off[c]) {
-        const int32_t p = pix[j0 - 1];
+        const int32_t p = pix_at(pix, j0 - 1);
         prev_t = p >= 0 ? tile_of(p, g) : -1;
       }
       int64_t* row = starts ? starts + s * (int64_t)g.ntiles : nullptr;
@@ -153,7 +168,7 @@ __global__ __launch_bounds__(256) void k_sort_count(const int32_t* __restrict__ 
           cend = off[c + 1];
           prev_t = -1;
         }
-        const int32_t p = pix[j];
+        const int32_t p = pix_at(pix, j);
         const int t = p >= 0 ? tile_of(p, g) : -1;
         if (t >= 0 && t != prev_t) {
           ++nr;
@@ -224,7 +239,7 @@ __global__ __launch_bounds__(1024) void k_scan_i64(const int64_t* __restrict__ i
 // the number of tile-t runs that start before slab s (k_sort_slab_prefix); the slab's thread
 // advances it as it meets run starts.  A run's end (one past its last sample) is written by the
 // slab holding its last sample, at the slot of the tile's latest run.
-__global__ __launch_bounds__(256) void k_sort_runs(const int32_t* __restrict__ pix, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(256) void k_sort_runs(PixSrc pix, const int64_t* __restrict__ off,
                                                    int nchunk, int64_t ns, int64_t slab, int64_t nslabs, TileGeom g,
                                                    int64_t* __restrict__ cur, const int64_t* __restrict__ runbase,
                                                    int64_t* __restrict__ rstart, int64_t* __restrict__ rend,
@@ -239,7 +254,7 @@ __global__ __launch_bounds__(256) void k_sort_runs(const int32_t* __restrict__ p
   int64_t cend = off[c + 1];
   int prev_t = -1;
   if (j0 > off[c]) {
-    const int32_t p = pix[j0 - 1];
+    const int32_t p = pix_at(pix, j0 - 1);
     prev_t = p >= 0 ? tile_of(p, g) : -1;
   }
   // row[ct] cached in a register while the walk stays in one tile
@@ -260,7 +275,7 @@ __global__ __launch_bounds__(256) void k_sort_runs(const int32_t* __restrict__ p
       cend = off[c + 1];
       prev_t = -1;
     }
-    const int32_t p = pix[j];
+    const int32_t p = pix_at(pix, j);
     const int t = p >= 0 ? tile_of(p, g) : -1;
     if (prev_t >= 0 && t != prev_t && j > j0) rend[runbase[prev_t] + slot_of(prev_t) - 1] = j;
     if (t >= 0 && t != prev_t) {
@@ -276,7 +291,7 @@ __global__ __launch_bounds__(256) void k_sort_runs(const int32_t* __restrict__ p
   if (prev_t >= 0) {
     bool ends = true;
     if (j1 < ns && j1 != cend) {
-      const int32_t p = pix[j1];
+      const int32_t p = pix_at(pix, j1);
       ends = !(p >= 0 && tile_of(p, g) == prev_t);
     }
     if (ends) rend[runbase[prev_t] + slot_of(prev_t) - 1] = j1;
@@ -288,8 +303,10 @@ __global__ __launch_bounds__(256) void k_sort_runs(const int32_t* __restrict__ p
 // kSubBatch samples or when the next segment would be its (kMaxSegs + 1)-th.  A segment is the
 // part of a run inside one sub-batch.  Count mode (write == 0) gives each tile's sub-batch,
 // segment and padded sorted-entry counts; write mode writes the records at the scanned offsets
-// (and flags an overflow of the reserved sizes instead of writing past them).
-__global__ __launch_bounds__(256) void k_sort_batches(int write, TileGeom g, int64_t nym,
+// (and flags an overflow of the reserved sizes instead of writing past them).  Runs come in entry
+// order, so a sub-batch's first-component entries (below ns_a) precede its second-component ones;
+// SubBatch::na counts the former.
+__global__ __launch_bounds__(256) void k_sort_batches(int write, TileGeom g, int64_t nym, int64_t ns_a,
                                                       const int64_t* __restrict__ runbase,
                                                       const int64_t* __restrict__ rstart,
                                                       const int64_t* __restrict__ rend,
@@ -307,13 +324,13 @@ __global__ __launch_bounds__(256) void k_sort_batches(int write, TileGeom g, int
   int64_t sb = write ? sbbase[t] : 0, sg = write ? segbase[t] : 0, so = write ? sortbase[t] : 0;
   const int64_t sb0 = sb;
   bool open = false, bad = false;
-  int cnt = 0, ns_ = 0;
+  int cnt = 0, ns_ = 0, cnt_a = 0;
   SubBatch cur = {};
   auto close = [&]() {
     if (write) {
       cur.seg_end = (int32_t)sg;
       cur.count = cnt;
-      cur.pad = 0;
+      cur.na = cnt_a;
       if (sb < cap_sb) sbs[sb] = cur; else bad = true;
     }
     ++sb;
@@ -331,6 +348,7 @@ __global__ __launch_bounds__(256) void k_sort_batches(int write, TileGeom g, int
         cur.sorted_begin = so;
         cur.seg_begin = (int32_t)sg;
         cnt = 0;
+        cnt_a = 0;
         ns_ = 0;
       }
       const int64_t take = (e - j) < (int64_t)(kSubBatch - cnt) ? (e - j) : (int64_t)(kSubBatch - cnt);
@@ -348,6 +366,7 @@ __global__ __launch_bounds__(256) void k_sort_batches(int write, TileGeom g, int
       ++sg;
       ++ns_;
       cnt += (int)take;
+      if (j < ns_a) cnt_a += (int)take;
       j += take;
       if (cnt == kSubBatch) close();
     }
@@ -380,8 +399,8 @@ __global__ __launch_bounds__(256) void k_sort_batches(int write, TileGeom g, int
 // order kept; perm = q, lp = local pixel, psi_sorted = the sample's stored angle.  The entries
 // past count up to the next multiple of kSortAlign are zero.
 constexpr int kSortBlock = 256;
-__global__ __launch_bounds__(kSortBlock) void k_sort_pixels(const int32_t* __restrict__ pix,
-                                                            const void* __restrict__ psi, int psi_esz, TileGeom g,
+__global__ __launch_bounds__(kSortBlock) void k_sort_pixels(PixSrc pix, const void* __restrict__ psi,
+                                                            const void* __restrict__ psi_b, int psi_esz, TileGeom g,
                                                             const Tile* __restrict__ tiles,
                                                             const SubBatch* __restrict__ sbs,
                                                             const Segment* __restrict__ segs,
@@ -415,7 +434,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pixels(const int32_t* __res
               hi = mid;
           }
           const int64_t j = sstart[lo] + (q - spos[lo]);
-          const int32_t p = pix[j];
+          const int32_t p = pix_at(pix, j);
           const int y = p / (int)g.nxm, x = p - y * (int)g.nxm;
           const int l = (y - tl.y0) * tl.tw + (x - tl.x0);
           key[q] = ((uint32_t)l << 12) | (uint32_t)q;
@@ -456,11 +475,11 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pixels(const int32_t* __res
         if (psi_esz) {
           uint8_t* dst = psi_sorted + (base + i) * psi_esz;
           if (psi_esz == 8) {
-            *(uint64_t*)dst = i < cnt ? ((const uint64_t*)psi)[jq[q]] : 0ull;
+            *(uint64_t*)dst = i < cnt ? psi_at<uint64_t>(psi, psi_b, pix.na, jq[q]) : 0ull;
           } else if (psi_esz == 4) {
-            *(uint32_t*)dst = i < cnt ? ((const uint32_t*)psi)[jq[q]] : 0u;
+            *(uint32_t*)dst = i < cnt ? psi_at<uint32_t>(psi, psi_b, pix.na, jq[q]) : 0u;
           } else {
-            *(uint16_t*)dst = i < cnt ? ((const uint16_t*)psi)[jq[q]] : (uint16_t)0;
+            *(uint16_t*)dst = i < cnt ? psi_at<uint16_t>(psi, psi_b, pix.na, jq[q]) : (uint16_t)0;
           }
         }
       }
@@ -487,16 +506,16 @@ hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sort_stats(const SlabWalk& w, int64_t npix, int64_t nxm, const void* psi, int psi_kind,
-                             int64_t table_len, SortCounters* ctr, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_stats, dim3(slab_grid(w.nslabs)), dim3(256), 0, s, w.pix, w.off, w.nchunk, w.ns, w.slab,
-                     w.nslabs, npix, nxm, psi, psi_kind, table_len, ctr);
+hipError_t launch_sort_stats(const SlabWalk& w, int64_t npix, int64_t nxm, const void* psi, const void* psi_b,
+                             int psi_kind, int64_t table_len, SortCounters* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_stats, dim3(slab_grid(w.nslabs)), dim3(256), 0, s, pix_src(w), w.off, w.nchunk, w.ns,
+                     w.slab, w.nslabs, npix, nxm, psi, psi_b, psi_kind, table_len, ctr);
   return hipGetLastError();
 }
 
 hipError_t launch_sort_count(const SlabWalk& w, const TileGeom& g, SortCounters* ctr, int64_t* starts, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_count, dim3(slab_grid(w.nslabs)), dim3(256), 0, s, w.pix, w.off, w.nchunk, w.ns, w.slab,
-                     w.nslabs, g, ctr, starts);
+  hipLaunchKernelGGL(k_sort_count, dim3(slab_grid(w.nslabs)), dim3(256), 0, s, pix_src(w), w.off, w.nchunk, w.ns,
+                     w.slab, w.nslabs, g, ctr, starts);
   return hipGetLastError();
 }
 
@@ -506,26 +525,26 @@ hipError_t launch_sort_lists(const SlabWalk& w, const TileGeom& g, int64_t nym, 
   hipLaunchKernelGGL(k_sort_slab_prefix, dim3(tb), dim3(256), 0, s, T.starts, w.nslabs, g.ntiles, T.tile_runs);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, s, T.tile_runs, T.runbase, (int64_t)g.ntiles,
                      T.runbase + g.ntiles);
-  hipLaunchKernelGGL(k_sort_runs, dim3(slab_grid(w.nslabs)), dim3(256), 0, s, w.pix, w.off, w.nchunk, w.ns, w.slab,
-                     w.nslabs, g, T.starts, T.runbase, T.rstart, T.rend, T.rchunk);
-  hipLaunchKernelGGL(k_sort_batches, dim3(tb), dim3(256), 0, s, 0, g, nym, T.runbase, T.rstart, T.rend, T.rchunk,
+  hipLaunchKernelGGL(k_sort_runs, dim3(slab_grid(w.nslabs)), dim3(256), 0, s, pix_src(w), w.off, w.nchunk, w.ns,
+                     w.slab, w.nslabs, g, T.starts, T.runbase, T.rstart, T.rend, T.rchunk);
+  hipLaunchKernelGGL(k_sort_batches, dim3(tb), dim3(256), 0, s, 0, g, nym, w.ns_a, T.runbase, T.rstart, T.rend, T.rchunk,
                      T.nsb, T.nseg, T.nsort, (const int64_t*)nullptr, (const int64_t*)nullptr,
                      (const int64_t*)nullptr, (Tile*)nullptr, (SubBatch*)nullptr, (Segment*)nullptr, (int64_t)0,
                      (int64_t)0, (int64_t)0, ctr);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, s, T.nsb, T.sbbase, (int64_t)g.ntiles, O.totals + 0);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, s, T.nseg, T.segbase, (int64_t)g.ntiles, O.totals + 1);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, s, T.nsort, T.sortbase, (int64_t)g.ntiles, O.totals + 2);
-  hipLaunchKernelGGL(k_sort_batches, dim3(tb), dim3(256), 0, s, 1, g, nym, T.runbase, T.rstart, T.rend, T.rchunk,
-                     (int64_t*)nullptr, (int64_t*)nullptr, (int64_t*)nullptr, T.sbbase, T.segbase, T.sortbase,
+  hipLaunchKernelGGL(k_sort_batches, dim3(tb), dim3(256), 0, s, 1, g, nym, w.ns_a, T.runbase, T.rstart, T.rend,
+                     T.rchunk, (int64_t*)nullptr, (int64_t*)nullptr, (int64_t*)nullptr, T.sbbase, T.segbase, T.sortbase,
                      O.tiles, O.sbs, O.segs, O.cap_sb, O.cap_seg, O.cap_sort, ctr);
   return hipGetLastError();
 }
 
-hipError_t launch_sort_pixels(const int32_t* pix, const void* psi, int psi_esz, const TileGeom& g, const SortOut& O,
-                              hipStream_t s) {
+hipError_t launch_sort_pixels(const SlabWalk& w, const void* psi, const void* psi_b, int psi_esz, const TileGeom& g,
+                              const SortOut& O, hipStream_t s) {
   const int grid = g.ntiles < 65536 ? g.ntiles : 65536;
-  hipLaunchKernelGGL(k_sort_pixels, dim3(grid > 0 ? grid : 1), dim3(kSortBlock), 0, s, pix, psi, psi_esz, g,
-                     O.tiles, O.sbs, O.segs, O.perm, O.lp, O.psi_sorted);
+  hipLaunchKernelGGL(k_sort_pixels, dim3(grid > 0 ? grid : 1), dim3(kSortBlock), 0, s, pix_src(w), psi, psi_b,
+                     psi_esz, g, O.tiles, O.sbs, O.segs, O.perm, O.lp, O.psi_sorted);
   return hipGetLastError();
 }
 

@@ -49,6 +49,8 @@ class _Desc(ctypes.Structure):
         ("psi_table", ctypes.POINTER(ctypes.c_float)), ("psi_table_len", ctypes.c_int64),
         ("tune", ctypes.c_int32), ("binning", ctypes.c_int32), ("with_adjoint", ctypes.c_int32),
         ("tile_pixels", ctypes.c_int32),
+        ("pix_b", ctypes.c_void_p), ("psi_b", ctypes.c_void_p),
+        ("weight_a", ctypes.c_double), ("weight_b", ctypes.c_double),
     ]
 
 
@@ -176,9 +178,13 @@ class Plan:
 def plan_desc(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha, pix: torch.Tensor,
               psi: Optional[torch.Tensor] = None, psi_table=None, tau=None, nx: int = 0,
               precision: int = MM_FP64, map_access: int = MM_MAP_AUTO, tune: int = MM_TUNE_MEASURE,
-              binning: int = MM_BIN_SORTED, with_adjoint: bool = False, tile_pixels: int = 0):
+              binning: int = MM_BIN_SORTED, with_adjoint: bool = False, tile_pixels: int = 0,
+              pix_b: Optional[torch.Tensor] = None, psi_b: Optional[torch.Tensor] = None,
+              weights=(1.0, -1.0)):
     """The mm_plan_desc of a problem and the host arrays it points to (keep both alive together).
-    pix (int32) and psi (float64 / float32 / uint16) are device tensors."""
+    pix (int32) and psi (float64 / float32 / uint16) are device tensors.  pix_b / psi_b (same
+    types) add the second component of a composite pointing P = w_a P_A + w_b P_B with
+    weights = (w_a, w_b); they are ignored without pix_b."""
     off = np.ascontiguousarray(np.asarray(chunk_off, dtype=np.int64).reshape(-1))
     nchunk = off.size - 1
     nsamp = int(off[-1])
@@ -211,6 +217,13 @@ def plan_desc(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha,
         arrs["psi_table"] = tab
         d.psi_table = tab.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         d.psi_table_len = tab.size
+    if pix_b is not None:
+        d.pix_b = _ptr(pix_b, "pix_b", torch.int32, nsamp)
+        if psi_b is not None:
+            if psi is None or psi_b.dtype != psi.dtype:
+                raise TypeError("psi_b must have the type of psi")
+            d.psi_b = _ptr(psi_b, "psi_b", None, nsamp)
+        d.weight_a, d.weight_b = float(weights[0]), float(weights[1])
     return d, arrs
 
 
@@ -237,7 +250,7 @@ def mm_plan(*, stream=None, **kw) -> Plan:
                          ctypes.byref(h)), "mm_plan")
     nsamp = int(arrs["off"][-1])
     return Plan(h.value, arrs, kw["ncomp"], kw["npix"], arrs["off"].size - 1, nsamp,
-                kw.get("precision", MM_FP64), [pix, psi], ws)
+                kw.get("precision", MM_FP64), [pix, psi, kw.get("pix_b"), kw.get("psi_b")], ws)
 
 
 def mm_plan_binning_stats(plan: Plan) -> dict:

@@ -67,6 +67,10 @@ def _desc(**over):
     d.binning = over.pop("binning", 0)
     d.with_adjoint = over.pop("with_adjoint", 0)
     d.tile_pixels = over.pop("tile_pixels", 0)
+    d.pix_b = over.pop("pix_b", None)
+    d.psi_b = over.pop("psi_b", None)
+    d.weight_a = over.pop("weight_a", 1.0)
+    d.weight_b = over.pop("weight_b", -1.0)
     assert not over
     return d, arr
 
@@ -89,6 +93,12 @@ def _desc(**over):
     (dict(arrays=dict(sig=np.array([1.0, -1.0]))), mm.MM_E_ARG),
     (dict(arrays=dict(tau=np.array([1.0, 1.5]))), mm.MM_E_ARG),  # tau above sigma^2
     (dict(arrays=dict(off=np.array([1, 65, 129], np.int64))), mm.MM_E_ARG),
+    # composite pointing: second angles, finite weights, projected access and sorted binning required
+    (dict(ncomp=3, psi=0x2000, psi_kind=1, pix_b=0x3000), mm.MM_E_ARG),
+    (dict(pix_b=0x3000, weight_b=float("nan")), mm.MM_E_ARG),
+    (dict(pix_b=0x3000, weight_a=float("inf")), mm.MM_E_ARG),
+    (dict(pix_b=0x3000, map_access=1), mm.MM_E_ARG),
+    (dict(pix_b=0x3000, binning=1), mm.MM_E_ARG),
 ])
 def test_plan_validation(case, status):
     """Both the workspace query and the plan reject the description before any device work."""

@@ -1,0 +1,231 @@
+"""GPU parity of composite pointing P = w_A P_A + w_B P_B (Section 2.2, Section 3.2, Appendix B)
+against the CPU FP64 oracle (``oracle.composite``).
+
+Cases: hit counts and the solvable mask (bit-exact); one iteration at lambda = inf (the
+weighted Jacobi step), a mid-schedule lambda and lambda = 1 from a map that is zero on the
+unsolvable pixels; a cooled solve with its chi^2 history; the map-sized form; conjugate
+gradients on the composite operator; chi^2 per chunk.  Shapes: tiny ragged chunks (several
+pixel tiles, both angle types, general and differential weights, the second component partly
+flagged, absent or equal to the first), and the differential-beam workloads at reduced size.
+Bars: FP64 rel-L2 1e-10 (chi^2 rel 1e-10), FP32-mixed rel-L2 1e-5 (chi^2 rel 1e-6).
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.cg import pcg_solve  # noqa: E402
+from oracle.composite import composite_step_mapsized, make_composite_setup  # noqa: E402
+from oracle.messenger import chi2, chi2_of_residual, messenger_step, residual  # noqa: E402
+from paper_1705_01893_amd import mm  # noqa: E402
+from synth import config_by_name, make_problem  # noqa: E402
+from tests.tiny_inputs import random_map, tiny_composite  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL, MIX_TOL, MIX_CHI2 = 1e-10, 1e-5, 1e-6
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+class Case:
+    """One composite problem: host arrays, the oracle setup, and the device tensors."""
+
+    def __init__(self, chunk_off, fsample, sigma, fknee, alpha, pix, psi, pix_b, psi_b, d, npix, nx, ncomp,
+                 weights, dev):
+        self.chunk_off, self.fsample, self.sigma, self.fknee, self.alpha = chunk_off, fsample, sigma, fknee, alpha
+        self.pix, self.psi, self.pix_b, self.psi_b, self.d = pix, psi, pix_b, psi_b, d
+        self.npix, self.nx, self.ncomp, self.weights = npix, nx, ncomp, weights
+        self.S = make_composite_setup(chunk_off, fsample, sigma, fknee, alpha, pix, psi, pix_b, psi_b, npix, ncomp,
+                                      w_a=weights[0], w_b=weights[1])
+        t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self.dpix, self.dpsi, self.dpix_b, self.dpsi_b = t(pix), t(psi), t(pix_b), t(psi_b)
+        self.dev = dev
+
+    def plan(self, precision, **kw):
+        return mm.mm_plan(ncomp=self.ncomp, npix=self.npix, nx=self.nx, chunk_off=self.chunk_off,
+                          fsample=self.fsample, sigma=self.sigma, fknee=self.fknee, alpha=self.alpha, pix=self.dpix,
+                          psi=self.dpsi, pix_b=self.dpix_b, psi_b=self.dpsi_b, weights=self.weights,
+                          precision=precision, **kw)
+
+    def tod(self, precision):
+        dt = np.float64 if precision == mm.MM_FP64 else np.float32
+        return torch.from_numpy(np.ascontiguousarray(np.asarray(self.d).astype(dt))).to(self.dev)
+
+    def start_map(self, seed, scale=1.0):
+        m = random_map(seed, self.ncomp, self.npix, scale)
+        m[:, ~self.S.solvable] = 0.0
+        return m
+
+
+def tiny_case(dev, seed, b_mode, ncomp, weights, lengths, nx, psi_dtype=np.float64):
+    t, pb, sb, w = tiny_composite(seed, b_mode=b_mode, lengths=lengths, nx=nx, ncomp=ncomp, weights=weights,
+                                  psi_dtype=psi_dtype)
+    return Case(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, pb, sb, t.d, t.npix, nx, ncomp, w,
+                dev)
+
+
+def synth_case(dev, name, ndet, nsamp, nx, sep):
+    cfg = config_by_name(name).scaled(f"{name}_test", ndet=ndet, nsamp=nsamp, nx=nx, diff_sep=sep)
+    p = make_problem(cfg)
+    return Case(p.chunk_off, p.fsample, p.sigma, p.fknee, p.alpha, p.pix, p.psi, p.pix_b, p.psi_b, p.d, p.npix, nx,
+                p.ncomp, p.weights, dev)
+
+
+TINY = {
+    # name: (b_mode, ncomp, weights, lengths, nx, psi dtype).  The I/Q/U cases have weight blocks
+    # of condition number below 5, except no_B_sparse (up to 1.8e7), which runs in FP64 only.
+    "diff_T": ("shift", 1, (1.0, -1.0), (256, 512, 128), 12, np.float64),
+    "diff_IQU_f32psi": ("shift", 3, (1.0, -1.0), (2 * 3 * 5 * 8 * 4, 2 * 45 * 8, 2 * 27 * 4 * 4, 2 * 125 * 4), 10,
+                        np.float32),
+    "weighted_IQU": ("shift", 3, (0.8, -1.1), (2 * 4096, 2 * 6000), 20, np.float64),
+    "no_B": ("none", 3, (1.0, -1.0), (2048, 1536), 8, np.float64),
+    "no_B_sparse": ("none", 3, (1.0, -1.0), (256, 384), 8, np.float64),
+    "B_equals_A": ("same", 1, (1.0, 1.0), (30, 18, 50), 4, np.float64),
+}
+
+
+@pytest.mark.parametrize("name", list(TINY))
+def test_hits_and_solvable_bit_exact(dev, name):
+    say(f"[composite hits] {name}")
+    b_mode, ncomp, w, lengths, nx, pdt = TINY[name]
+    c = tiny_case(dev, 401, b_mode, ncomp, w, lengths, nx, pdt)
+    plan = c.plan(mm.MM_FP64)
+    hits = torch.zeros(c.npix, dtype=torch.int32, device=dev)
+    mask = torch.zeros(c.npix, dtype=torch.uint8, device=dev)
+    mm.mm_plan_hits(plan, hits)
+    mm.mm_plan_solvable(plan, mask)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(hits.cpu().numpy(), c.S.hits)
+    np.testing.assert_array_equal(mask.cpu().numpy().astype(bool), c.S.solvable)
+    assert mm.mm_plan_map_access(plan) == mm.MM_MAP_PROJECTED
+
+
+@pytest.mark.parametrize("name", list(TINY))
+@pytest.mark.parametrize("precision", [mm.MM_FP64, mm.MM_MIXED])
+@pytest.mark.parametrize("lam", [math.inf, 23.0, 1.0])
+def test_one_iteration(dev, name, precision, lam):
+    say(f"[composite iter] {name} precision={precision} lam={lam}")
+    if name == "no_B_sparse" and precision == mm.MM_MIXED:
+        pytest.skip("the FP32 angle weights of the mixed form (errors ~1e-7) are amplified by weight blocks "
+                    "of condition number up to 1.8e7 beyond the mixed bar; FP64 covers this case")
+    b_mode, ncomp, w, lengths, nx, pdt = TINY[name]
+    c = tiny_case(dev, 402, b_mode, ncomp, w, lengths, nx, pdt)
+    plan = c.plan(precision)
+    m0 = c.start_map(5)
+    d = c.tod(precision)
+    mi = torch.from_numpy(m0).to(dev)
+    mo = torch.zeros_like(mi)
+    c2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    mm.mm_messenger_iter(plan, d, lam, mi, mo, c2)
+    torch.cuda.synchronize()
+    d_used = d.cpu().numpy().astype(np.float64)
+    ref = messenger_step(c.S, d_used, m0, lam)
+    tol, ctol = (F64_TOL, F64_TOL) if precision == mm.MM_FP64 else (MIX_TOL, MIX_CHI2)
+    e = rel(mo.cpu().numpy(), ref)
+    say(f"  map rel {e:.2e}")
+    assert e < tol
+    assert c2.item() == pytest.approx(chi2(c.S, d_used, m0), rel=ctol)
+
+
+@pytest.mark.parametrize("name, ndet, nsamp, nx, sep", [("diff256", 4, 1 << 15, 96, 4.0),
+                                                      ("diff512", 6, 1 << 15, 80, 5.0)])
+@pytest.mark.parametrize("precision", [mm.MM_FP64, mm.MM_MIXED])
+def test_cooled_solve_and_chi2_history(dev, name, ndet, nsamp, nx, sep, precision):
+    """A lambda = inf step then three geometric levels of three iterations, iterate for iterate."""
+    say(f"[composite solve] {name} ndet={ndet} nx={nx} precision={precision}")
+    c = synth_case(dev, name, ndet, nsamp, nx, sep)
+    plan = c.plan(precision)
+    d = c.tod(precision)
+    d_used = d.cpu().numpy().astype(np.float64)
+    lams = [40.0, 6.3, 1.0]
+    its = [3, 3, 3]
+    m = torch.zeros((c.ncomp, c.npix), dtype=torch.float64, device=dev)
+    hist = torch.zeros(1 + sum(its) + 1, dtype=torch.float64, device=dev)
+    mm.mm_solve(plan, d, lams, its, m, first_inf=True, chi2_hist=hist)
+    torch.cuda.synchronize()
+    seq = [math.inf] + [l for l, k in zip(lams, its) for _ in range(k)]
+    ref = np.zeros((c.ncomp, c.npix))
+    ref_hist = []
+    for lam in seq:
+        ref_hist.append(chi2(c.S, d_used, ref))
+        ref = messenger_step(c.S, d_used, ref, lam)
+    ref_hist.append(chi2(c.S, d_used, ref))
+    tol, ctol = (F64_TOL, F64_TOL) if precision == mm.MM_FP64 else (MIX_TOL, MIX_CHI2)
+    e = rel(m.cpu().numpy(), ref)
+    eh = float(np.max(np.abs(hist.cpu().numpy() - ref_hist) / np.asarray(ref_hist)))
+    say(f"  map rel {e:.2e}, chi2 history max rel {eh:.2e}")
+    assert e < tol and eh < ctol
+    # the same schedule in the map-sized form of Appendix B
+    m2 = torch.zeros_like(m)
+    mm.mm_solve_mapsized(plan, d, lams, its, m2, first_inf=True)
+    torch.cuda.synchronize()
+    ref2 = np.zeros((c.ncomp, c.npix))
+    for lam in seq:
+        ref2 = composite_step_mapsized(c.S, d_used, ref2, lam)
+    e2 = rel(m2.cpu().numpy(), ref2)
+    say(f"  map-sized rel {e2:.2e}")
+    assert e2 < tol
+    # chi^2 per chunk of the final map at lambda = 1 and lambda = 5
+    pc = torch.zeros(len(c.chunk_off) - 1, dtype=torch.float64, device=dev)
+    for lam in (1.0, 5.0):
+        mm.mm_chi2(plan, d, m, lam, per_chunk=pc)
+        want = chi2_of_residual(c.S, residual(c.S, d_used, m.cpu().numpy()), lam, per_chunk=True)
+        assert float(np.max(np.abs(pc.cpu().numpy() - want) / want)) < ctol
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", [mm.MM_FP64, mm.MM_MIXED])
+def test_cg_on_the_composite_operator(dev, precision):
+    say(f"[composite cg] precision={precision}")
+    c = synth_case(dev, "diff256", 4, 1 << 14, 64, 3.0)
+    plan = c.plan(precision)
+    d = c.tod(precision)
+    d_used = d.cpu().numpy().astype(np.float64)
+    m = torch.zeros((c.ncomp, c.npix), dtype=torch.float64, device=dev)
+    n = 12
+    got = mm.mm_cg_solve(plan, m, n, d=d)
+    torch.cuda.synchronize()
+    assert got == n
+    ref, _ = pcg_solve(c.S, d_used, n)
+    e = rel(m.cpu().numpy(), ref)
+    say(f"  cg rel {e:.2e}")
+    # CG amplifies rounding with the iteration count: FP64 at 1e-10 after 12 steps, mixed at 1e-4
+    assert e < (F64_TOL if precision == mm.MM_FP64 else 1e-4)
+
+
+def test_single_beam_only_calls_are_refused(dev):
+    c = tiny_case(dev, 403, "shift", 1, (1.0, -1.0), (256, 128), 8)
+    plan = c.plan(mm.MM_FP64, with_adjoint=True)
+    g = torch.ones((1, c.npix), dtype=torch.float64, device=dev)
+    out = torch.zeros(int(c.chunk_off[-1]), dtype=torch.float64, device=dev)
+    with pytest.raises(mm.MMError) as ei:
+        mm.mm_lift_rhs(plan, g, out)
+    assert ei.value.status == mm.MM_E_ARG
+    with pytest.raises(mm.MMError) as ei:
+        mm.mm_tod_apply(plan, 2, g, out)
+    assert ei.value.status == mm.MM_E_ARG
+    m = torch.zeros_like(g)
+    with pytest.raises(mm.MMError) as ei:
+        mm.mm_solve(plan, None, [1.0], [1], m, rhs_map=g)
+    assert ei.value.status == mm.MM_E_ARG
