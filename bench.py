@@ -200,10 +200,12 @@ def summarize_trace(trace_dir: str) -> None:
 # algorithmic bytes: each TOD-sized stream a pass of the four-pass deterministic design must read
 # or write once, per sample of the workload (the survey's per-pass table; no plan-side tables)
 
-def pass_bytes_per_sample(tod_bytes: int, psi_bytes: int) -> list:
+def pass_bytes_per_sample(tod_bytes: int, psi_bytes: int, nbeam: int = 1) -> list:
     """A: d, pix, psi read + transform buffer written; B: buffer read + written; C: buffer read +
-    y written; D: y, pix, psi read.  (The map-sized traffic, ~1% here, is left out.)"""
-    return [2 * tod_bytes + 4 + psi_bytes, 2 * tod_bytes, 2 * tod_bytes, tod_bytes + 4 + psi_bytes]
+    y written; D: y, pix, psi read.  (The map-sized traffic, ~1% here, is left out.)  Composite
+    pointing (nbeam = 2) gathers and bins through two pixel / angle pairs per sample."""
+    ptg = nbeam * (4 + psi_bytes)
+    return [2 * tod_bytes + ptg, 2 * tod_bytes, 2 * tod_bytes, tod_bytes + ptg]
 
 
 def host_info() -> dict:
@@ -246,9 +248,18 @@ def make_inputs(cfg, dev, log):
         psi = torch.from_numpy(prob.psi_index.view(np.int16)).to(dev).view(torch.uint16)
     elif prob.psi is not None:
         psi = torch.from_numpy(prob.psi).to(dev)
+    on_dev = lambda a: None if a is None else torch.from_numpy(a).to(dev)  # noqa: E731
     return DeviceProblem(cfg=cfg, chunks=np.arange(cfg.ndet), chunk_off=prob.chunk_off, fsample=prob.fsample,
                          sigma=prob.sigma, fknee=prob.fknee, alpha=prob.alpha, pix=torch.from_numpy(prob.pix).to(dev),
-                         psi=psi, psi_table=prob.psi_table, d=torch.from_numpy(prob.d).to(dev), m_true=prob.m_true)
+                         psi=psi, psi_table=prob.psi_table, d=torch.from_numpy(prob.d).to(dev), m_true=prob.m_true,
+                         pix_b=on_dev(prob.pix_b), psi_b=on_dev(prob.psi_b), weights=prob.weights)
+
+
+def _form_angles(a, form):
+    import torch
+    if a is None or a.dtype == torch.uint16:
+        return a
+    return a.float() if form == "mixed" else a.double()
 
 
 def form_inputs(P, form):
@@ -257,17 +268,17 @@ def form_inputs(P, form):
     import torch
     if form == "mixed":
         d = P.d if P.d.dtype == torch.float32 else P.d.float()
-        psi = P.psi if (P.psi is None or P.psi.dtype in (torch.uint16, torch.float32)) else P.psi.float()
     else:
         d = P.d if P.d.dtype == torch.float64 else P.d.double()
-        psi = P.psi if (P.psi is None or P.psi.dtype in (torch.uint16, torch.float64)) else P.psi.double()
-    return d, psi
+    return d, _form_angles(P.psi, form)
 
 
 def build_plan(mm, P, form, psi, **over):
     kw = dict(ncomp=P.ncomp, npix=P.npix, nx=P.cfg.nx, chunk_off=P.chunk_off, fsample=P.fsample, sigma=P.sigma,
               fknee=P.fknee, alpha=P.alpha, pix=P.pix, psi=psi, psi_table=P.psi_table,
               precision=mm.MM_MIXED if form == "mixed" else mm.MM_FP64)
+    if P.pix_b is not None:  # differential beams: the second pointing component
+        kw.update(pix_b=P.pix_b, psi_b=_form_angles(P.psi_b, form), weights=P.weights)
     kw.update(over)
     return mm.mm_plan(**kw)
 
@@ -328,7 +339,7 @@ def run_form(mm, torch, P, form, args, log):
     mm.mm_set_timing(plan, False)
     tod_bytes = 4 if form == "mixed" else 8
     psi_bytes = 0 if psi is None else psi.element_size()
-    per = pass_bytes_per_sample(tod_bytes, psi_bytes)
+    per = pass_bytes_per_sample(tod_bytes, psi_bytes, 2 if P.pix_b is not None else 1)
     avg = [pass_ms[i] / max(pass_n[i], 1) for i in range(5)]
     dom = int(np.argmax(avg[:4]))
     alg = [b * ns for b in per]
@@ -339,14 +350,16 @@ def run_form(mm, torch, P, form, args, log):
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (traffic["passes"][dom]["bytes_per_launch"] if traffic else None),
             "kernel": PASS_NAMES[dom], "bytes_per_sample": per[dom], "samples_per_launch": ns}
-    non = int((P.pix >= 0).sum().item())
+    non = int((P.pix >= 0).sum().item()) + (0 if P.pix_b is None else int((P.pix_b >= 0).sum().item()))
     out = {
         "form": form, "value": round(ns / (ms_step * 1e-3), 1), "ms_per_step": round(ms_step, 5),
         "roofline": roof,
         "sweep_roofline_frac": round(sum(per) * ns / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "sweep_bytes_per_sample": sum(per),
-        # the bytes no schedule can avoid: d, pix and the on-map angles, each read once per iteration
-        "compulsory_frac": round((ns * (tod_bytes + 4) + non * psi_bytes) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the bytes no schedule can avoid: d, pix (both beams' for composite pointing) and the
+        # on-map angles, each read once per iteration
+        "compulsory_frac": round((ns * (tod_bytes + 4 * (2 if P.pix_b is not None else 1)) + non * psi_bytes)
+                                 / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "ms_per_step_with_pass_events": round(timed_passes_ms / args.steps, 5),
         "map_access": "projected" if projected else "gather",
         "passes": [{"pass": PASS_NAMES[i], "avg_ms": round(avg[i], 5), "launches": int(pass_n[i]),
@@ -476,11 +489,17 @@ def _oracle_worker(path, niter, wait):
     processes of a group have set up, when `wait`)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
+    from oracle.composite import make_composite_setup
     from oracle.messenger import make_setup, messenger_step
     z = np.load(path)
     with threadpool_limits(limits=1):
-        S = make_setup(z["chunk_off"], z["fsample"], z["sigma"], z["fknee"], z["alpha"], z["pix"],
-                       z["psi"] if z["psi"].size else None, int(z["npix"]), int(z["ncomp"]))
+        args = (z["chunk_off"], z["fsample"], z["sigma"], z["fknee"], z["alpha"], z["pix"],
+                z["psi"] if z["psi"].size else None)
+        if "pix_b" in z:
+            S = make_composite_setup(*args, z["pix_b"], z["psi_b"] if z["psi_b"].size else None, int(z["npix"]),
+                                     int(z["ncomp"]), w_a=float(z["weights"][0]), w_b=float(z["weights"][1]))
+        else:
+            S = make_setup(*args, int(z["npix"]), int(z["ncomp"]))
         d = z["d"]
         m = np.zeros((S.ncomp, S.npix))
         if wait:
@@ -510,8 +529,12 @@ def cpu_baseline(P, seconds: float, log):
     def dump(name, idx):
         h = P.host_chunks(idx)
         path = os.path.join(tmp, name + ".npz")
+        extra = {}
+        if "pix_b" in h:
+            extra = dict(psi_b=h["psi_b"] if h["psi_b"] is not None else np.zeros(0),
+                         weights=np.asarray(P.weights, dtype=np.float64))
         np.savez(path, npix=P.npix, ncomp=P.ncomp, psi=h["psi"] if h["psi"] is not None else np.zeros(0),
-                 **{k: v for k, v in h.items() if k != "psi"})
+                 **extra, **{k: v for k, v in h.items() if k not in ("psi", "psi_b")})
         return path, int(h["chunk_off"][-1])
 
     try:
@@ -651,6 +674,8 @@ def main():
         psi_desc = "uint16 angle-table index"
     else:
         psi_desc = str(P.psi.dtype).replace("torch.", "") + " angles"
+    if P.pix_b is not None:
+        psi_desc += f"; differential beams {cfg.diff_sep:g} pixels apart, weights {P.weights[0]:+g} / {P.weights[1]:+g}"
     form_name = {"mixed": "FP32-mixed", "fp64": "FP64"}
     cfg_desc = {"workload": (f"{cfg.name}: {P.nchunk} detectors x {per_chunk if per_chunk else 'uneven'} samples "
                              f"({ns} total), {cfg.nx}x{cfg.nx} map, ncomp={P.ncomp}, {psi_desc}; value: "

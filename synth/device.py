@@ -43,6 +43,10 @@ class DeviceProblem:
     psi_table: Optional[np.ndarray]
     d: torch.Tensor                # TOD in the workload's type
     m_true: np.ndarray             # float64 [ncomp, npix] (host)
+    # differential pointing: second beam's pixels / angles on the device, beam weights (or None)
+    pix_b: Optional[torch.Tensor] = None
+    psi_b: Optional[torch.Tensor] = None
+    weights: Optional[tuple] = None
     extra: dict = field(default_factory=dict)
 
     @property
@@ -66,7 +70,8 @@ class DeviceProblem:
 
     def host_chunks(self, idx: Sequence[int]):
         """pix, stored angle values (table lookups resolved, float32/64) and d of the given chunks,
-        copied to the host, with their chunk table: the inputs the oracle reads."""
+        copied to the host, with their chunk table: the inputs the oracle reads (and the second
+        beam's pix_b / psi_b for differential pointing)."""
         sl = [self.chunk(c) for c in idx]
         pix = np.concatenate([self.pix[s].cpu().numpy() for s in sl])
         d = np.concatenate([self.d[s].cpu().numpy() for s in sl])
@@ -77,8 +82,13 @@ class DeviceProblem:
         lens = np.array([s.stop - s.start for s in sl], dtype=np.int64)
         off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
         ix = np.asarray(idx)
-        return dict(chunk_off=off, fsample=self.fsample[ix], sigma=self.sigma[ix], fknee=self.fknee[ix],
-                    alpha=self.alpha[ix], pix=pix, psi=psi, d=d)
+        out = dict(chunk_off=off, fsample=self.fsample[ix], sigma=self.sigma[ix], fknee=self.fknee[ix],
+                   alpha=self.alpha[ix], pix=pix, psi=psi, d=d)
+        if self.pix_b is not None:
+            out["pix_b"] = np.concatenate([self.pix_b[s].cpu().numpy() for s in sl])
+            out["psi_b"] = (None if self.psi_b is None else
+                            np.concatenate([self.psi_b[s].cpu().numpy() for s in sl]))
+        return out
 
 
 def _raster_positions(nh: int, w: int, rotate: bool, dev):

@@ -142,6 +142,11 @@ def test_one_iteration(dev, name, precision, lam):
     d_used = d.cpu().numpy().astype(np.float64)
     ref = messenger_step(c.S, d_used, m0, lam)
     tol, ctol = (F64_TOL, F64_TOL) if precision == mm.MM_FP64 else (MIX_TOL, MIX_CHI2)
+    if name == "no_B_sparse":
+        # FP64 rounding of the binned sums (~1e-16 relative) is amplified by up to the largest
+        # condition number of a solvable weight block (1.8e7 here): allow 10 kappa eps
+        kappa = max(np.linalg.cond(c.S.W[p]) for p in np.nonzero(c.S.solvable)[0])
+        tol = max(tol, 10.0 * kappa * np.finfo(np.float64).eps)
     e = rel(mo.cpu().numpy(), ref)
     say(f"  map rel {e:.2e}")
     assert e < tol
