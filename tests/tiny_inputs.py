@@ -105,3 +105,14 @@ def tiny_composite(seed: int, b_mode: str = "shift", lengths=(64, 48), nx: int =
         pix_b[rng.random(len(pix_b)) < flag_b] = -1
         psi_b = None if t.psi is None else rng.uniform(0.0, np.pi, size=len(pix_b)).astype(t.psi.dtype)
     return t, pix_b, psi_b, tuple(float(w) for w in weights)
+
+
+def gap_mask(seed: int, chunk_off, frac: float = 0.1, run: int = 6) -> np.ndarray:
+    """Gaps as runs of `run` consecutive samples placed at random, about `frac` of the samples."""
+    rng = np.random.default_rng(seed)
+    ns = int(chunk_off[-1])
+    g = np.zeros(ns, dtype=bool)
+    nrun = max(1, int(frac * ns / run))
+    for s0 in rng.integers(0, max(1, ns - run), size=nrun):
+        g[s0:s0 + run] = True
+    return g
