@@ -144,6 +144,10 @@ enum { MM_BIN_SORTED = 0, MM_BIN_ATOMIC = 1 };                            /* bin
  *               mm_lift_rhs, mm_tod_apply(which = 2) and mm_solve with a map
  *               right-hand side return MM_E_ARG (their lifting needs
  *               W = P^T T^-1 P).  Weights must be finite.
+ *  with_gapfill 1 reserves two more TOD-sized buffers (the fields d_0 and t_0 of
+ *               mm_solve_gapfill) and takes the projected map access; 0 leaves
+ *               them out.  Not with composite pointing or map_access GATHER.
+ *  pad_         unused (zero).
  */
 typedef struct {
   int32_t ncomp;
@@ -171,6 +175,8 @@ typedef struct {
   const void* psi_b;
   double weight_a;
   double weight_b;
+  int32_t with_gapfill;
+  int32_t pad_;
 } mm_plan_desc;
 
 /* Cooling schedule (Section 3.1): optionally one lambda = inf step, then
@@ -284,6 +290,29 @@ mm_status mm_solve(mm_plan_t plan, const void* d, const double* rhs_map, const m
  */
 mm_status mm_solve_mapsized(mm_plan_t plan, const void* d, const mm_schedule* sched, const double* m0,
                             double* m_out, mm_stream_t stream);
+
+/*
+ * The cooled solve with gap filling: composite noise N = N_0 + N_1 (Appendix C), N_1 diagonal
+ * in time with infinite variance in the gaps and eps_c = sigma_c^2 - tau_c elsewhere, N_0 =
+ * N - eps_c I (so that outside the gaps the noise is the chunk's law N).  Every iteration sets
+ * the four fields of the appendix to their conditional means in its order:
+ *   t_1 = d outside the gaps, d_0 inside (T_1 = eps I, the largest allowed);
+ *   d_0 = t_1 + A (t_0 - t_1),  A = eps / (eps + N-bar_0) per Fourier bin;
+ *   t_0 = P m + tau (lambda^-1 N-bar_0 + T_0)^-1 (d_0 - P m);
+ *   m   = W^-1 P^T T_0^-1 t_0 (W^-1 P^T T_0^-1 P = I on the solvable pixels),
+ * with T_0 = tau I and N-bar_0 = N_0 - T_0 = sigma^2 (f/f_knee)^alpha (the DC bin clamped), lambda
+ * on T_0 as in Section 2.1.  The fixed point at lambda = 1 is the generalised least-squares
+ * map of the samples outside the gaps; d_0 is the gap-filled data.  Start: d_0 = d outside the
+ * gaps and 0 inside, t_0 = d_0, m = m0 (NULL: zero).
+ * The plan needs with_gapfill, single-beam pointing and 0 < tau_c < sigma_c^2 (tau_c < sigma_c^2
+ * sets eps_c > 0); MM_E_ARG otherwise.  d: device TOD (the plan's precision).  gaps: device
+ * N_s bytes, nonzero for a sample whose data are unusable (its pointing still counts in W and
+ * P m); the data there are never read.  d0_out: device TOD receiving d_0 (time order), or NULL.
+ * Each iteration runs two filter sweeps (the d_0 and the t_0 updates), two time-domain steps
+ * and the binning pass.  Runs uncaptured on `stream`; no chi^2 history.
+ */
+mm_status mm_solve_gapfill(mm_plan_t plan, const void* d, const uint8_t* gaps, const mm_schedule* sched,
+                           const double* m0, double* m_out, void* d0_out, mm_stream_t stream);
 
 /*
  * Geometric cooling levels (Section 3.1): lambda_l = lambda_max^((nlevel-1-l)/(nlevel-1)),

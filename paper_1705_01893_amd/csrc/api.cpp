@@ -465,6 +465,55 @@ mm_status mm_solve_mapsized(mm_plan_t plan, const void* d, const mm_schedule* sc
   return run_graph(plan, key, stream, body);
 }
 
+mm_status mm_solve_gapfill(mm_plan_t plan, const void* d, const uint8_t* gaps, const mm_schedule* sched,
+                           const double* m0, double* m_out, void* d0_out, mm_stream_t stream) {
+  if (!plan || !d || !gaps || !sched || !m_out) return fail(MM_E_ARG, "null argument");
+  if (!plan->d_gd0) return fail(MM_E_ARG, "gap filling needs a plan built with_gapfill");
+  for (int64_t c = 0; c < plan->nchunk; ++c)
+    if (!(plan->tau[c] < plan->sigma[c] * plan->sigma[c]))
+      return fail(MM_E_ARG, "gap filling needs tau_c < sigma_c^2 (eps_c = sigma_c^2 - tau_c > 0), chunk " +
+                                std::to_string(c));
+  std::vector<double> lams;
+  MM_TRY(expand_schedule(sched, lams));
+  hipStream_t s = S(stream);
+  const int64_t n = mapn(plan);
+  if (m0) {
+    if (m0 != m_out) MM_TRY_HIP(launch_copy(m_out, m0, n, s));
+  } else {
+    MM_TRY_HIP(launch_fill(m_out, n, 0.0, s));
+  }
+  DevPlan P = plan->dp;
+  P.gap_d0 = plan->d_gd0;
+  P.gaps = gaps;
+  MM_TRY_HIP(launch_gap_init(P, d, gaps, plan->d_gd0, plan->d_gt0, s));
+  for (size_t i = 0; i < lams.size(); ++i) {
+    // d_0 = t_1 + A (t_0 - t_1)
+    MM_TRY_HIP(timed(plan, 0, s, [&] {
+      return launch_pass_a(P, plan->d_itemsAC, (int)plan->itemsAC.size(), d, nullptr, SRC_GAP, plan->d_work,
+                           plan->lds_ac, s, plan->d_gt0);
+    }));
+    MM_TRY_HIP(timed(plan, 1, s, [&] {
+      return launch_pass_b(P, plan->d_itemsB, (int)plan->itemsB.size(), plan->d_work, B_FILTER, GAIN_GAPFILL, 1.0,
+                           1.0, plan->d_chi2_part, plan->lds_b, s);
+    }));
+    MM_TRY_HIP(timed(plan, 2, s, [&] {
+      return launch_pass_c(P, plan->d_itemsAC, (int)plan->itemsAC.size(), plan->d_work, plan->lds_c, s);
+    }));
+    MM_TRY_HIP(launch_gap_d0(P, d, gaps, plan->d_work, plan->d_gd0, s));
+    // t_0 = P m + tau (lambda^-1 N-bar_0 + T_0)^-1 (d_0 - P m), then m = W^-1 P^T T_0^-1 t_0 (the
+    // binning pass updates m by W^-1 P^T of the filtered residual and writes P m of the result)
+    MM_TRY(sweep_filter(plan, plan->d_gd0, m_out, SRC_D_MINUS_PM, B_FILTER, GAIN_MESSENGER_PL, lams[i], 1.0, s,
+                        i > 0));
+    MM_TRY_HIP(launch_gap_t0(P, plan->d_pm, plan->d_work, plan->d_gt0, s));
+    MM_TRY_HIP(timed(plan, 3, s, [&] {
+      return launch_bin(plan->dp, BSRC_WORK, plan->d_work, EPI_UPDATE, m_out, m_out, nullptr, nullptr, s,
+                        plan->d_pm);
+    }));
+  }
+  if (d0_out) MM_TRY_HIP(launch_copy_bytes(d0_out, plan->d_gd0, plan->ns * (int64_t)(plan->precision ? 4 : 8), s));
+  return MM_OK;
+}
+
 mm_status mm_chi2(mm_plan_t plan, const void* d, const double* m, double lambda, double* chi2_host,
                   double* per_chunk_dev, mm_stream_t stream) {
   if (!plan || !d || !m || !chi2_host) return fail(MM_E_ARG, "null argument");

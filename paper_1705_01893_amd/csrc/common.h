@@ -162,6 +162,9 @@ struct DevPlan {
   int32_t pad1;
   double wa, wb;
   int64_t pmb_off;
+  // gap filling (SRC_GAP launches only): the filled data d_0 and the gap flags, time order
+  const void* gap_d0;
+  const uint8_t* gaps;
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -232,13 +235,17 @@ void* static_scratch(int device, hipError_t* err);
 // pass-A sources
 // pass-A sources: gather P m directly, or read a TOD-sized buffer holding P m written in
 // pixel-tile order (by the binning epilogue or the projection kernel)
-enum { SRC_D_MINUS_PM = 0, SRC_PM = 1, SRC_D = 2, SRC_D_MINUS_PMBUF = 3, SRC_PMBUF = 4 };
+// SRC_GAP: t_0 - t_1 of gap filling, t_1 = d outside the gaps and d_0 inside (t_0 from the
+// buffer argument, d_0 and the flags from DevPlan)
+enum { SRC_D_MINUS_PM = 0, SRC_PM = 1, SRC_D = 2, SRC_D_MINUS_PMBUF = 3, SRC_PMBUF = 4, SRC_GAP = 5 };
 // pass-B operations (bit set)
 enum {
   B_CHI2 = 1,         // accumulate chi^2(., chi2_lambda) partials
   B_FILTER = 2,       // multiply by a gain, inverse-transform and write back
 };
-enum { GAIN_MESSENGER = 0, GAIN_NINV = 1, GAIN_LIFT = 2 };
+// GAIN_GAPFILL: eps / (eps + N-bar_0) with eps = sigma^2 - tau (the d_0 update of gap filling);
+// GAIN_MESSENGER_PL: the messenger gain with N-bar = the power-law part alone (N-bar_0 there)
+enum { GAIN_MESSENGER = 0, GAIN_NINV = 1, GAIN_LIFT = 2, GAIN_GAPFILL = 3, GAIN_MESSENGER_PL = 4 };
 // binning sources / epilogues
 enum { BSRC_WORK = 0, BSRC_DATA_OVER_TAU = 1, BSRC_PLAN = 2 };
 // EPI_MAPSIZED: m_out = m_d + m_in - W^-1 b (DevPlan::md), the map-sized form of an iteration
@@ -268,6 +275,12 @@ hipError_t launch_update(const DevPlan& P, int epi, const double* m_in, const do
 // the filtered TOD of the work buffer (chunk bases at xoff) copied to time order
 hipError_t launch_unshift(const DevPlan& P, const void* work, void* out, hipStream_t s);
 hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipStream_t s);
+// gap filling's time-domain steps (time-order TOD buffers; y of the work buffer at chunk bases xoff):
+// d_0 = d outside the gaps and 0 inside, t_0 = d_0; then d_0 = t_1 + y; then t_0 = P m + tau y
+hipError_t launch_gap_init(const DevPlan& P, const void* d, const uint8_t* gaps, void* d0, void* t0, hipStream_t s);
+hipError_t launch_gap_d0(const DevPlan& P, const void* d, const uint8_t* gaps, const void* work, void* d0,
+                         hipStream_t s);
+hipError_t launch_gap_t0(const DevPlan& P, const void* pm, const void* work, void* t0, hipStream_t s);
 hipError_t launch_spectrum(const DevPlan& P, double* spec, hipStream_t s);
 hipError_t launch_grad(const DevPlan& P, const ItemB* items, int nitems, const int32_t* chunk_item_begin,
                        const void* Xr, const void* Xz, double* part, double* out, size_t lds, hipStream_t s);

@@ -228,6 +228,11 @@ __device__ __forceinline__ void bin_factors_pl(const DevChunk& ch, const BinCtx&
   if (bc.gain == GAIN_MESSENGER) {
     const T nbar = (T)ch.nbar0 + pl;
     gg = recip<T>(tau + nbar * (T)bc.inv_lam);
+  } else if (bc.gain == GAIN_MESSENGER_PL) {
+    gg = recip<T>(tau + pl * (T)bc.inv_lam);
+  } else if (bc.gain == GAIN_GAPFILL) {
+    const T eps = (T)ch.nbar0;  // sigma^2 - tau
+    gg = eps * recip<T>(eps + pl);
   } else if (bc.gain == GAIN_NINV) {
     gg = recip<T>(N);
   } else {
@@ -350,7 +355,9 @@ __device__ __forceinline__ int xcd_run_order(int b, int grid) {
 // NG: the source needs no map gather (d, P m from its buffer, or their difference).  PK: the
 // angles of the gather form, fixed at compile time so that no run-time branch on them separates
 // the loads (0 none: temperature only; 1 float64, 2 float32, 3 uint16 table index; -1: not used)
-template <typename T, bool P2, bool NG, int PK>
+// X2 (no-gather sources only): a second TOD stream read beside the first, P_B m of composite
+// pointing or d_0 and the gap flags of gap filling (kept out of the plain variants' registers).
+template <typename T, bool P2, bool NG, int PK, bool X2 = false>
 __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* __restrict__ items, int nitems,
                                                    const T* __restrict__ d, const double* __restrict__ m, int src,
                                                    cx<T>* __restrict__ X, const T* __restrict__ pmbuf) {
@@ -374,7 +381,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* _
 #pragma unroll 1
     for (int g = 0; g < E; g += G) {
       int2 pp[G];
-      cx<T> dd[G], pb[G], pb2[G];
+      constexpr int G2 = X2 ? G : 1;
+      cx<T> dd[G], pb[G], pb2[G2];
+      uint16_t gf[G2];
       uint4 raw[G];
       bool ok[G];
       // every load of the group goes out before any is used: elements outside the item read the
@@ -391,12 +400,21 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* _
         dd[u].y = T(0);
         pb[u].x = T(0);
         pb[u].y = T(0);
-        pb2[u].x = T(0);
-        pb2[u].y = T(0);
+        if constexpr (X2) {
+          pb2[u].x = T(0);
+          pb2[u].y = T(0);
+          gf[u] = 0;
+        }
         if (src != SRC_PM && src != SRC_PMBUF) dd[u] = ((const cx<T>*)d)[ci];
         if (src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF) {
           pb[u] = ((const cx<T>*)pmbuf)[ci];
-          if (P.pmb_off) pb2[u] = ((const cx<T>*)pmbuf)[ci + P.pmb_off];  // composite: P_B m
+          if constexpr (X2) pb2[u] = ((const cx<T>*)pmbuf)[ci + P.pmb_off];  // composite: P_B m
+        } else if (X2 && src == SRC_GAP) {
+          if constexpr (X2) {
+            pb[u] = ((const cx<T>*)pmbuf)[ci];      // t_0
+            pb2[u] = ((const cx<T>*)P.gap_d0)[ci];  // d_0
+            gf[u] = ((const uint16_t*)P.gaps)[ci];  // the pair's two gap flags
+          }
         } else if (!NG && src != SRC_D) {
           const int2 q = ((const int2*)P.pix)[ci];
           pp[u] = ok[u] ? q : make_int2(-1, -1);
@@ -438,11 +456,25 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* _
             z.x = (T)pm[u][0];
             z.y = (T)pm[u][1];
           } else if (src == SRC_PMBUF) {
-            z.x = (T)((double)pb[u].x + (double)pb2[u].x);
-            z.y = (T)((double)pb[u].y + (double)pb2[u].y);
+            z = pb[u];
+            if constexpr (X2) {
+              z.x = (T)((double)pb[u].x + (double)pb2[u].x);
+              z.y = (T)((double)pb[u].y + (double)pb2[u].y);
+            }
           } else if (src == SRC_D_MINUS_PMBUF) {
-            z.x = (T)((double)dd[u].x - ((double)pb[u].x + (double)pb2[u].x));
-            z.y = (T)((double)dd[u].y - ((double)pb[u].y + (double)pb2[u].y));
+            double px = (double)pb[u].x, py = (double)pb[u].y;
+            if constexpr (X2) {
+              px += (double)pb2[u].x;
+              py += (double)pb2[u].y;
+            }
+            z.x = (T)((double)dd[u].x - px);
+            z.y = (T)((double)dd[u].y - py);
+          } else if (X2 && src == SRC_GAP) {
+            // t_0 - t_1, t_1 = d outside the gaps, d_0 inside
+            if constexpr (X2) {
+              z.x = (T)((double)pb[u].x - (double)((gf[u] & 0xffu) ? pb2[u].x : dd[u].x));
+              z.y = (T)((double)pb[u].y - (double)((gf[u] >> 8) ? pb2[u].y : dd[u].y));
+            }
           } else if (!NG) {
             z.x = (T)((double)dd[u].x - pm[u][0]);
             z.y = (T)((double)dd[u].y - pm[u][1]);
@@ -1752,18 +1784,22 @@ __global__ void k_cg_chi2(const double* chi2_0, const double* xb, const double* 
 template <typename T, bool P2>
 static void launch_pass_a_t(const DevPlan& P, const ItemAC* items, int nitems, const void* d, const double* m,
                             int src, void* work, size_t lds, hipStream_t s, const void* pmbuf) {
-  const bool ng = src == SRC_D || src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF;
-#define MM_PASS_A(NGV, PKV)                                                                          \
-  hipLaunchKernelGGL((k_pass_a<T, P2, NGV, PKV>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, \
+  const bool ng = src == SRC_D || src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF || src == SRC_GAP;
+  // a second stream: gap filling's d_0, or the P_B m half of a composite plan's projection buffer
+  const bool x2 = src == SRC_GAP || (P.pmb_off != 0 && (src == SRC_PMBUF || src == SRC_D_MINUS_PMBUF));
+#define MM_PASS_A(NGV, PKV, X2V)                                                                          \
+  hipLaunchKernelGGL((k_pass_a<T, P2, NGV, PKV, X2V>), dim3(col_grid(nitems)), dim3(kBlock), lds, s, P, items, \
                      nitems, (const T*)d, m, src, (cx<T>*)work, (const T*)pmbuf)
-  if (ng) {
-    MM_PASS_A(true, -1);
+  if (ng && x2) {
+    MM_PASS_A(true, -1, true);
+  } else if (ng) {
+    MM_PASS_A(true, -1, false);
   } else {
     switch (P.ncomp == 1 ? 0 : P.psi_kind) {
-      case 0: MM_PASS_A(false, 0); break;
-      case 1: MM_PASS_A(false, 1); break;
-      case 2: MM_PASS_A(false, 2); break;
-      default: MM_PASS_A(false, 3); break;
+      case 0: MM_PASS_A(false, 0, false); break;
+      case 1: MM_PASS_A(false, 1, false); break;
+      case 2: MM_PASS_A(false, 2, false); break;
+      default: MM_PASS_A(false, 3, false); break;
     }
   }
 #undef MM_PASS_A
@@ -1873,6 +1909,84 @@ __global__ void k_unshift(DevPlan P, const T* __restrict__ work, T* __restrict__
     T* dst = out + ch.off;
     for (int t = threadIdx.x; t < ch.n; t += blockDim.x) dst[t] = src[t];
   }
+}
+
+// gap filling, time-domain steps (one workgroup per chunk at a time, like k_unshift)
+template <typename T>
+__global__ void k_gap_init(DevPlan P, const T* __restrict__ d, const uint8_t* __restrict__ gaps, T* __restrict__ d0,
+                           T* __restrict__ t0) {
+  for (int c = blockIdx.x; c < P.nchunk; c += gridDim.x) {
+    const DevChunk& ch = P.chunks[c];
+    for (int t = threadIdx.x; t < ch.n; t += blockDim.x) {
+      const int64_t j = ch.off + t;
+      const T v = gaps[j] ? T(0) : d[j];
+      d0[j] = v;
+      t0[j] = v;
+    }
+  }
+}
+
+// d_0 = t_1 + y, t_1 = d outside the gaps and d_0 inside (y: the filtered t_0 - t_1)
+template <typename T>
+__global__ void k_gap_d0(DevPlan P, const T* __restrict__ d, const uint8_t* __restrict__ gaps,
+                         const T* __restrict__ work, T* __restrict__ d0) {
+  for (int c = blockIdx.x; c < P.nchunk; c += gridDim.x) {
+    const DevChunk& ch = P.chunks[c];
+    const T* y = work + 2 * ch.xoff;
+    for (int t = threadIdx.x; t < ch.n; t += blockDim.x) {
+      const int64_t j = ch.off + t;
+      const double t1 = gaps[j] ? (double)d0[j] : (double)d[j];
+      d0[j] = (T)(t1 + (double)y[t]);
+    }
+  }
+}
+
+// t_0 = P m + tau y (y: the messenger-filtered d_0 - P m)
+template <typename T>
+__global__ void k_gap_t0(DevPlan P, const T* __restrict__ pm, const T* __restrict__ work, T* __restrict__ t0) {
+  for (int c = blockIdx.x; c < P.nchunk; c += gridDim.x) {
+    const DevChunk& ch = P.chunks[c];
+    const T* y = work + 2 * ch.xoff;
+    const double tau = ch.tau;
+    for (int t = threadIdx.x; t < ch.n; t += blockDim.x) {
+      const int64_t j = ch.off + t;
+      t0[j] = (T)((double)pm[j] + tau * (double)y[t]);
+    }
+  }
+}
+
+hipError_t launch_gap_init(const DevPlan& P, const void* d, const uint8_t* gaps, void* d0, void* t0, hipStream_t s) {
+  const int g = P.nchunk < 65536 ? P.nchunk : 65536;
+  if (P.precision == 0)
+    hipLaunchKernelGGL(k_gap_init<double>, dim3(g), dim3(256), 0, s, P, (const double*)d, gaps, (double*)d0,
+                       (double*)t0);
+  else
+    hipLaunchKernelGGL(k_gap_init<float>, dim3(g), dim3(256), 0, s, P, (const float*)d, gaps, (float*)d0,
+                       (float*)t0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gap_d0(const DevPlan& P, const void* d, const uint8_t* gaps, const void* work, void* d0,
+                         hipStream_t s) {
+  const int g = P.nchunk < 65536 ? P.nchunk : 65536;
+  if (P.precision == 0)
+    hipLaunchKernelGGL(k_gap_d0<double>, dim3(g), dim3(256), 0, s, P, (const double*)d, gaps, (const double*)work,
+                       (double*)d0);
+  else
+    hipLaunchKernelGGL(k_gap_d0<float>, dim3(g), dim3(256), 0, s, P, (const float*)d, gaps, (const float*)work,
+                       (float*)d0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gap_t0(const DevPlan& P, const void* pm, const void* work, void* t0, hipStream_t s) {
+  const int g = P.nchunk < 65536 ? P.nchunk : 65536;
+  if (P.precision == 0)
+    hipLaunchKernelGGL(k_gap_t0<double>, dim3(g), dim3(256), 0, s, P, (const double*)pm, (const double*)work,
+                       (double*)t0);
+  else
+    hipLaunchKernelGGL(k_gap_t0<float>, dim3(g), dim3(256), 0, s, P, (const float*)pm, (const float*)work,
+                       (float*)t0);
+  return hipGetLastError();
 }
 
 hipError_t launch_unshift(const DevPlan& P, const void* work, void* out, hipStream_t s) {

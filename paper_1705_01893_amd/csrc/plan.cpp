@@ -76,6 +76,10 @@ mm_status validate(const mm_plan_desc* desc) {
   if (D.with_adjoint != 0 && D.with_adjoint != 1) return fail(MM_E_ARG, "with_adjoint must be 0 or 1");
   if (D.tile_pixels != 0 && (D.tile_pixels < 16 || D.tile_pixels > kMaxTilePixAsked))
     return fail(MM_E_ARG, "tile_pixels must be 0 (automatic) or 16.." + std::to_string(kMaxTilePixAsked));
+  if (D.with_gapfill != 0 && D.with_gapfill != 1) return fail(MM_E_ARG, "with_gapfill must be 0 or 1");
+  if (D.with_gapfill && D.pix_b) return fail(MM_E_ARG, "gap filling needs single-beam pointing");
+  if (D.with_gapfill && D.map_access == MM_MAP_GATHER)
+    return fail(MM_E_ARG, "gap filling reads P m from the projection buffer (map_access AUTO or PROJECTED)");
   if (D.pix_b) {
     if (D.ncomp == 3 && !D.psi_b) return fail(MM_E_ARG, "composite I/Q/U pointing needs the second angles (psi_b)");
     if (!std::isfinite(D.weight_a) || !std::isfinite(D.weight_b))
@@ -126,7 +130,7 @@ struct Prep {
   int64_t xwork = 0, spec_total = 0;
   size_t capAC = 0, capB = 0, capG = 0, capTW = 0;
   size_t tune_bytes = 0;
-  bool pm_mode = false, adjoint = false, bin_atomic = false, mapi = false;
+  bool pm_mode = false, adjoint = false, bin_atomic = false, mapi = false, gapfill = false;
   // tiles and counts
   int64_t nxm = 0, nym = 0, tw = 0, th = 0, ntx = 0, nty = 0, ntiles = 0;
   int64_t non = 0, nruns = 0;
@@ -194,7 +198,8 @@ void prep_transforms(const mm_plan_desc& D, Prep& P) {
   P.bin_atomic = D.binning == MM_BIN_ATOMIC;
   // maps larger than the L2 of one XCD (4 MB) are gathered badly by the strided column pass:
   // then P m is produced in pixel-tile order instead
-  P.pm_mode = D.map_access == MM_MAP_PROJECTED || P.composite ||
+  P.gapfill = D.with_gapfill != 0;
+  P.pm_mode = D.map_access == MM_MAP_PROJECTED || P.composite || P.gapfill ||
               (D.map_access == MM_MAP_AUTO && P.mapn * (int64_t)sizeof(double) > ((int64_t)4 << 20));
   P.mapi = !P.pm_mode && D.ncomp == 3;
 }
@@ -374,6 +379,8 @@ struct Bufs {
   void* work = nullptr;
   void* pm = nullptr;
   void* work2 = nullptr;
+  void* gd0 = nullptr;
+  void* gt0 = nullptr;
   char* transient = nullptr;
   size_t transient_bytes = 0;
   SortTemp T = {};
@@ -425,6 +432,8 @@ bool carve(Arena& a, const mm_plan_desc& D, const Prep& P, Bufs& B) {
   B.work = w;
   if (ok && P.pm_mode) ok = take(a, (size_t)P.nent * P.tsz, (char**)&B.pm);
   if (ok && P.adjoint) ok = take(a, (size_t)(2 * P.xwork) * P.tsz, (char**)&B.work2);
+  if (ok && P.gapfill)
+    ok = take(a, (size_t)P.ns * P.tsz, (char**)&B.gd0) && take(a, (size_t)P.ns * P.tsz, (char**)&B.gt0);
   if (!ok) return false;
   const size_t tod_bytes = a.used - tod0;
   Arena m;
@@ -817,6 +826,8 @@ mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStr
   pl->d_hits = B.hits;
   pl->d_work = B.work;
   pl->d_work2 = B.work2;
+  pl->d_gd0 = B.gd0;
+  pl->d_gt0 = B.gt0;
   pl->d_chi2_part = B.chi2part;
   pl->d_scal = B.scal;
   pl->d_part = B.part;

@@ -75,6 +75,8 @@ struct mm_plan_s {
   // of gathering the map)
   int pm_mode = 0;
   bool composite = false;  // P = P_A + P_B (second pointing component given)
+  void* d_gd0 = nullptr;   // gap filling: the fields d_0 and t_0 (TOD-sized, time order)
+  void* d_gt0 = nullptr;
   void* d_pm = nullptr;
   // binning by FP64 atomics (measured alternative): binned vector, longest chunk
   bool bin_atomic = false;

@@ -51,6 +51,7 @@ class _Desc(ctypes.Structure):
         ("tile_pixels", ctypes.c_int32),
         ("pix_b", ctypes.c_void_p), ("psi_b", ctypes.c_void_p),
         ("weight_a", ctypes.c_double), ("weight_b", ctypes.c_double),
+        ("with_gapfill", ctypes.c_int32), ("pad_", ctypes.c_int32),
     ]
 
 
@@ -85,6 +86,7 @@ def lib() -> ctypes.CDLL:
     L.mm_messenger_iter.argtypes = [vp, vp, dbl, vp, vp, vp, vp]
     L.mm_solve.argtypes = [vp, vp, vp, ctypes.POINTER(_Sched), vp, vp, vp, vp]
     L.mm_solve_mapsized.argtypes = [vp, vp, ctypes.POINTER(_Sched), vp, vp, vp]
+    L.mm_solve_gapfill.argtypes = [vp, vp, vp, ctypes.POINTER(_Sched), vp, vp, vp, vp]
     L.mm_cooling_levels.argtypes = [vp, i32, dbl, ctypes.POINTER(dbl)]
     L.mm_cg_solve.argtypes = [vp, vp, vp, i32, dbl, vp, vp, vp, vp, ctypes.POINTER(i32), vp]
     L.mm_chi2.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp]
@@ -99,7 +101,8 @@ def lib() -> ctypes.CDLL:
     L.mm_get_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for name in ("mm_plan_set_noise", "mm_tod_apply", "mm_noise_grad", "mm_set_timing", "mm_get_timing", "mm_plan", "mm_plan_destroy", "mm_plan_workspace_bytes", "mm_plan_workspace_bytes_noalloc",
                  "mm_plan_binning_stats", "mm_plan_hits", "mm_plan_solvable",
-                 "mm_plan_nsolvable", "mm_plan_map_access", "mm_plan_chunk_layout", "mm_messenger_iter", "mm_solve", "mm_solve_mapsized", "mm_cooling_levels", "mm_cg_solve",
+                 "mm_plan_nsolvable", "mm_plan_map_access", "mm_plan_chunk_layout", "mm_messenger_iter", "mm_solve", "mm_solve_mapsized",
+                 "mm_solve_gapfill", "mm_cooling_levels", "mm_cg_solve",
                  "mm_chi2", "mm_chi2_modes", "mm_apply", "mm_lift_rhs"):
         getattr(L, name).restype = ctypes.c_int
     L.mm_status_str.argtypes = [ctypes.c_int]
@@ -180,7 +183,7 @@ def plan_desc(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha,
               precision: int = MM_FP64, map_access: int = MM_MAP_AUTO, tune: int = MM_TUNE_MEASURE,
               binning: int = MM_BIN_SORTED, with_adjoint: bool = False, tile_pixels: int = 0,
               pix_b: Optional[torch.Tensor] = None, psi_b: Optional[torch.Tensor] = None,
-              weights=(1.0, -1.0)):
+              weights=(1.0, -1.0), with_gapfill: bool = False):
     """The mm_plan_desc of a problem and the host arrays it points to (keep both alive together).
     pix (int32) and psi (float64 / float32 / uint16) are device tensors.  pix_b / psi_b (same
     types) add the second component of a composite pointing P = w_a P_A + w_b P_B with
@@ -200,6 +203,7 @@ def plan_desc(*, ncomp: int, npix: int, chunk_off, fsample, sigma, fknee, alpha,
     d.binning = binning
     d.with_adjoint = int(bool(with_adjoint))
     d.tile_pixels = int(tile_pixels)
+    d.with_gapfill = int(bool(with_gapfill))
     d.chunk_off = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     for k in ("fsample", "sigma", "fknee", "alpha"):
         setattr(d, k, arrs[k].ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
@@ -342,6 +346,26 @@ def mm_solve_mapsized(plan: Plan, d: torch.Tensor, lambdas: Sequence[float], ite
     _check(lib().mm_solve_mapsized(plan.handle, _ptr(d, "d", plan.tod_dtype, plan.nsamp), ctypes.byref(sc),
                                    _map_ptr(plan, m0, "m0"), _map_ptr(plan, m_out, "m_out"), _stream(stream)),
            "mm_solve_mapsized")
+
+
+def mm_solve_gapfill(plan: Plan, d: torch.Tensor, gaps: torch.Tensor, lambdas: Sequence[float], iters: Sequence[int],
+                     m_out: torch.Tensor, first_inf: bool = True, m0: Optional[torch.Tensor] = None,
+                     d0_out: Optional[torch.Tensor] = None, stream=None) -> None:
+    """Cooled solve with gap filling (composite noise N = N_0 + N_1); gaps: device uint8 per sample
+    (nonzero: unusable data); d0_out receives the gap-filled TOD."""
+    lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+    its = np.ascontiguousarray(np.asarray(iters, dtype=np.int32))
+    if lam.size != its.size:
+        raise ValueError("lambdas and iters must have equal length")
+    sc = _Sched()
+    sc.nlevel, sc.first_inf = lam.size, int(bool(first_inf))
+    sc.lambda_ = lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    sc.iters = its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    _check(lib().mm_solve_gapfill(plan.handle, _ptr(d, "d", plan.tod_dtype, plan.nsamp),
+                                  _ptr(gaps, "gaps", torch.uint8, plan.nsamp), ctypes.byref(sc),
+                                  _map_ptr(plan, m0, "m0"), _map_ptr(plan, m_out, "m_out"),
+                                  _ptr(d0_out, "d0_out", plan.tod_dtype, plan.nsamp), _stream(stream)),
+           "mm_solve_gapfill")
 
 
 def mm_cg_solve(plan: Plan, m_out: torch.Tensor, maxiter: int, d: Optional[torch.Tensor] = None,

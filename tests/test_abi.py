@@ -71,6 +71,7 @@ def _desc(**over):
     d.psi_b = over.pop("psi_b", None)
     d.weight_a = over.pop("weight_a", 1.0)
     d.weight_b = over.pop("weight_b", -1.0)
+    d.with_gapfill = over.pop("with_gapfill", 0)
     assert not over
     return d, arr
 
@@ -99,6 +100,10 @@ def _desc(**over):
     (dict(pix_b=0x3000, weight_a=float("inf")), mm.MM_E_ARG),
     (dict(pix_b=0x3000, map_access=1), mm.MM_E_ARG),
     (dict(pix_b=0x3000, binning=1), mm.MM_E_ARG),
+    # gap filling: a flag, single-beam pointing, projected access
+    (dict(with_gapfill=2), mm.MM_E_ARG),
+    (dict(with_gapfill=1, pix_b=0x3000), mm.MM_E_ARG),
+    (dict(with_gapfill=1, map_access=1), mm.MM_E_ARG),
 ])
 def test_plan_validation(case, status):
     """Both the workspace query and the plan reject the description before any device work."""
