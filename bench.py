@@ -376,6 +376,47 @@ def run_form(mm, torch, P, form, args, log):
 
 
 # ---------------------------------------------------------------------------------------------
+# gap filling (composite noise N = N_0 + N_1): throughput of the four-field iteration
+
+def gapfill_rate(mm, torch, P, form, args, log, eps_frac: float = 0.2, run: int = 200):
+    """K gap-filling iterations at lambda = 1 on the workload with a fraction args.gapfill of its
+    samples in gaps (runs of `run` samples at seeded random places), after W warm-up iterations.
+    The plan moves eps = eps_frac sigma^2 of each chunk's white level into N_1 (tau = sigma^2 - eps)."""
+    import numpy as np
+    dev = P.pix.device
+    d, psi = form_inputs(P, form)
+    ns = P.nsamp_total
+    rng = np.random.default_rng(1705)
+    nrun = max(1, int(args.gapfill * ns / run))
+    starts = torch.from_numpy(rng.integers(0, ns - run, size=nrun)).to(dev)
+    gaps = torch.zeros(ns, dtype=torch.uint8, device=dev)
+    idx = (starts[:, None] + torch.arange(run, device=dev)[None, :]).reshape(-1)
+    gaps[idx] = 1
+    del idx, starts
+    tau = (1.0 - eps_frac) * np.asarray(P.sigma) ** 2
+    plan = build_plan(mm, P, form, psi, tau=tau, with_gapfill=True)
+    m = torch.zeros((P.ncomp, P.npix), dtype=torch.float64, device=dev)
+    mm.mm_solve_gapfill(plan, d, gaps, [1.0], [max(args.warmup, 1)], m, first_inf=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    mm.mm_solve_gapfill(plan, d, gaps, [1.0], [args.steps], m, first_inf=False, m0=m)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    frac = float(gaps.float().mean().item())
+    log(f"[gapfill {form}] {ms:.3f} ms per iteration ({frac:.3f} of the samples in gaps)")
+    plan.close()
+    del plan, gaps
+    torch.cuda.empty_cache()
+    return {"form": form, "value": round(ns / (ms * 1e-3), 1), "unit": "samples/s", "ms_per_step": round(ms, 5),
+            "gap_fraction": round(frac, 4), "gap_run": run, "eps_over_sigma2": eps_frac,
+            "note": "each iteration: the d_0 filter sweep, the t_0 / map filter sweep, two time-domain field "
+                    "updates and the binning pass (eager launches)"}
+
+
+# ---------------------------------------------------------------------------------------------
 # time to a chi^2 target
 
 def _first_at_or_below(hist, target):
@@ -591,6 +632,8 @@ def main():
                     help="deterministic sorted reduction (default) or the FP64-atomic alternative")
     ap.add_argument("--tune", choices=["measure", "static"], default="measure",
                     help="transform layouts: timed at plan time (default) or the fixed rule")
+    ap.add_argument("--gapfill", type=float, default=0.0, metavar="FRAC",
+                    help="also time gap-filling iterations with this fraction of the samples in gaps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -639,6 +682,12 @@ def main():
     log(f"generated {ns} samples in {t_gen:.1f} s")
     results = [run_form(mm, torch, P, f, args, log) for f in forms]
     head = results[0]
+    gapfill = None
+    if args.gapfill > 0:
+        if P.pix_b is not None:
+            log("gap filling needs single-beam pointing: skipped")
+        else:
+            gapfill = [gapfill_rate(mm, torch, P, f, args, log) for f in forms]
     # what a plain device-to-device copy reaches on this GPU (read + write bytes per second):
     # the practical ceiling of a streaming pass, beside the published HBM peak
     csrc = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -689,7 +738,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if head["form"] == "mixed" else "f64", "data": "synthetic", "config": cfg_desc,
         "roofline": head["roofline"], "cpu_baseline": cpu, "time_to_chi2": chi2_block,
-        "detail": {"forms": results, "copy_GBs": round(copy_gbs, 1),
+        "detail": {"forms": results, "gapfill": gapfill, "copy_GBs": round(copy_gbs, 1),
                    "copy_frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4), "generate_s": round(t_gen, 2),
                    "binning": args.binning},
     }
