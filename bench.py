@@ -93,7 +93,7 @@ def write_traffic(args, form: str, fetch_dir: str, write_dir: str) -> None:
     Only the workload's dispatches count: those after the plan's precompute binning launch (the
     transform-layout tuner's timing launches come before it) and outside the time-to-chi^2 part
     (not run with --no-chi2).  Counters are scaled by what they read for the plain 1 GiB copy of
-    --copy-calibration (torch's copy kernel, the largest WRITE_SIZE of a non-library kernel)."""
+    --copy-calibration (the runtime's copy kernel behind torch's 1 GiB device copy)."""
     per = {}
     scale = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
@@ -106,10 +106,14 @@ def write_traffic(args, form: str, fetch_dir: str, write_dir: str) -> None:
                 continue
             key = (r["Kernel_Name"], r["Dispatch_Id"])
             vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
-        copies = [v for (k, _), v in vals.items() if "copy" in k.lower() and "mm::" not in k]
+        # the runtime's copy kernel of torch's 1 GiB device copies (the most common reading among
+        # them: other, smaller copies run in the same process)
+        copies = [v for (k, _), v in vals.items() if "copybuffer" in k.lower()]
         if not copies:
             raise SystemExit("no copy kernel in the counters: profile a --copy-calibration run")
-        scale[counter] = (1 << 30) / (max(copies) * 1024.0)
+        big = [v for v in copies if v >= 0.25 * max(copies)]
+        mode = max(set(big), key=big.count)
+        scale[counter] = (1 << 30) / (mode * 1024.0)
         for i, kname in enumerate(PASS_KERNELS):
             vs = [v for (k, _), v in vals.items() if kname in k]
             if vs:
@@ -426,7 +430,7 @@ def _first_at_or_below(hist, target):
 
 
 def time_to_chi2(mm, torch, P, log, tail: int, cg_max: int, deltas=(1e-5, 1e-4, 1e-3)):
-    """Wall time (HIP events around a replayed solve graph, or around the CG loop) to reach
+    """Wall time (HIP events around a replayed solve graph, for both solvers) to reach
     chi2_ref (1 + delta).  chi2_ref is the lower of the FP64 messenger run below continued at
     lambda = 1 and FP64 PCG to a relative residual of 1e-10.  Compared: the cooled messenger in
     FP64 and FP32-mixed (the workload's schedule, then `tail` iterations at lambda = 1) and FP64
@@ -496,10 +500,11 @@ def time_to_chi2(mm, torch, P, log, tail: int, cg_max: int, deltas=(1e-5, 1e-4, 
             if form == "fp64":
                 j = _first_at_or_below(cg_hist, ref * (1 + delta))
                 if j is not None and j > 0:
-                    mc.zero_()
+                    mm.mm_cg_solve(plan, mc, j, d=d)  # capture (a fixed count runs as one graph)
+                    torch.cuda.synchronize()
                     e0, e1 = ev(), ev()
                     e0.record()
-                    mm.mm_cg_solve(plan, mc, j, d=d)
+                    mm.mm_cg_solve(plan, mc, j, d=d)  # replay
                     e1.record()
                     torch.cuda.synchronize()
                     row["cg_fp64"] = {"iterations": j, "ms": round(e0.elapsed_time(e1), 3)}

@@ -332,7 +332,10 @@ mm_status mm_cooling_levels(mm_plan_t plan, int32_t nlevel, double lambda_max, d
  * from the recursion chi^2(x) = d^T N^-1 d - x^T b - x^T r (needs d).
  * rz_hist_dev (device, maxiter+1 doubles, or NULL) gets r^T W^-1 r; without it
  * the plan keeps the history itself, which limits maxiter to 16383.
- * iters_done (host, or NULL) gets the number of iterations run.
+ * iters_done (host, or NULL) gets the number of iterations run.  With rtol = 0
+ * (a fixed count) the solve is captured into the plan's one cached HIP graph and
+ * replayed by a later call with the same buffers and count (as mm_solve's schedule);
+ * with rtol > 0 it runs uncaptured.
  */
 mm_status mm_cg_solve(mm_plan_t plan, const void* d, const double* rhs_map, int32_t maxiter,
                       double rtol, const double* m0, double* m_out, double* chi2_hist_dev,

@@ -620,7 +620,6 @@ mm_status mm_cg_solve(mm_plan_t plan, const void* d, const double* rhs_map, int3
   if ((d == nullptr) == (rhs_map == nullptr)) return fail(MM_E_ARG, "give exactly one of d and rhs_map");
   if (chi2_hist_dev && !d) return fail(MM_E_ARG, "the chi^2 history needs the data");
   if (!(rtol >= 0)) return fail(MM_E_ARG, "rtol must be >= 0");
-  hipStream_t s = S(stream);
   const int64_t n = mapn(plan);
   double* x = m_out;
   double* b = plan->d_map[0];
@@ -636,57 +635,72 @@ mm_status mm_cg_solve(mm_plan_t plan, const void* d, const double* rhs_map, int3
       return fail(MM_E_ARG, "maxiter above " + std::to_string(kCgHistCap - 1) + " needs a caller history (rz_hist_dev)");
     rzh = plan->d_hist;
   }
-  // b = P^T N^-1 d (or the given map)
-  if (d)
-    MM_TRY(apply_op(plan, GAIN_NINV, 1.0, nullptr, d, b, s));
-  else
-    MM_TRY_HIP(launch_copy(b, rhs_map, n, s));
-  // x0, r0 = b - A x0
-  if (m0) {
-    if (m0 != x) MM_TRY_HIP(launch_copy(x, m0, n, s));
-    MM_TRY(apply_op(plan, GAIN_NINV, 1.0, x, nullptr, q, s));
-    MM_TRY_HIP(launch_sub(r, b, q, n, s));
-  } else {
-    MM_TRY_HIP(launch_fill(x, n, 0.0, s));
-    MM_TRY_HIP(launch_copy(r, b, n, s));
-  }
-  MM_TRY_HIP(launch_winv_apply(plan->dp, r, z, s));
-  MM_TRY_HIP(launch_copy(p, z, n, s));
-  MM_TRY(dot(plan, r, z, rzh + 0, s));
-  auto record_chi2 = [&](int i) -> mm_status {
-    MM_TRY(dot(plan, x, b, sc + 2, s));
-    MM_TRY(dot(plan, x, r, sc + 3, s));
-    MM_TRY_HIP(launch_cg_chi2(sc + 1, sc + 2, sc + 3, chi2_hist_dev + i, s));
-    return MM_OK;
-  };
-  if (chi2_hist_dev) {
-    MM_TRY_HIP(launch_fill(zero, n, 0.0, s));
-    MM_TRY(chi2_device(plan, d, zero, 1.0, sc + 1, nullptr, s));
-    MM_TRY(record_chi2(0));
-  }
-  const int nb = dot_blocks(plan->npix);
   int it = 0;
-  double rz0 = -1.0;
-  for (it = 0; it < maxiter; ++it) {
-    MM_TRY(apply_op(plan, GAIN_NINV, 1.0, p, nullptr, q, s));
-    MM_TRY(dot(plan, p, q, sc + 0, s));
-    MM_TRY_HIP(launch_cg_update_xr(plan->dp, x, r, z, p, q, rzh + it, sc + 0, plan->d_part, nb, s));
-    MM_TRY_HIP(launch_reduce(plan->d_part, nb, rzh + it + 1, s));
-    MM_TRY_HIP(launch_cg_update_p(p, z, rzh + it + 1, rzh + it, n, s));
-    if (chi2_hist_dev) MM_TRY(record_chi2(it + 1));
-    if (rtol > 0 && ((it + 1) % 10 == 0 || it + 1 == maxiter)) {
-      double h[2];
-      if (rz0 < 0) {
-        MM_TRY_HIP(hipMemcpyAsync(&h[0], rzh, sizeof(double), hipMemcpyDeviceToHost, s));
-      }
-      MM_TRY_HIP(hipMemcpyAsync(&h[1], rzh + it + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-      MM_TRY_HIP(hipStreamSynchronize(s));
-      if (rz0 < 0) rz0 = h[0];
-      if (h[1] <= rtol * rtol * rz0) {
-        ++it;
-        break;
+  // the whole solve on stream s; with rtol > 0 the host reads r^T z every 10 iterations
+  auto body = [&](hipStream_t s) -> mm_status {
+    // b = P^T N^-1 d (or the given map)
+    if (d)
+      MM_TRY(apply_op(plan, GAIN_NINV, 1.0, nullptr, d, b, s));
+    else
+      MM_TRY_HIP(launch_copy(b, rhs_map, n, s));
+    // x0, r0 = b - A x0
+    if (m0) {
+      if (m0 != x) MM_TRY_HIP(launch_copy(x, m0, n, s));
+      MM_TRY(apply_op(plan, GAIN_NINV, 1.0, x, nullptr, q, s));
+      MM_TRY_HIP(launch_sub(r, b, q, n, s));
+    } else {
+      MM_TRY_HIP(launch_fill(x, n, 0.0, s));
+      MM_TRY_HIP(launch_copy(r, b, n, s));
+    }
+    MM_TRY_HIP(launch_winv_apply(plan->dp, r, z, s));
+    MM_TRY_HIP(launch_copy(p, z, n, s));
+    MM_TRY(dot(plan, r, z, rzh + 0, s));
+    auto record_chi2 = [&](int i) -> mm_status {
+      MM_TRY(dot(plan, x, b, sc + 2, s));
+      MM_TRY(dot(plan, x, r, sc + 3, s));
+      MM_TRY_HIP(launch_cg_chi2(sc + 1, sc + 2, sc + 3, chi2_hist_dev + i, s));
+      return MM_OK;
+    };
+    if (chi2_hist_dev) {
+      MM_TRY_HIP(launch_fill(zero, n, 0.0, s));
+      MM_TRY(chi2_device(plan, d, zero, 1.0, sc + 1, nullptr, s));
+      MM_TRY(record_chi2(0));
+    }
+    const int nb = dot_blocks(plan->npix);
+    double rz0 = -1.0;
+    for (it = 0; it < maxiter; ++it) {
+      MM_TRY(apply_op(plan, GAIN_NINV, 1.0, p, nullptr, q, s));
+      MM_TRY(dot(plan, p, q, sc + 0, s));
+      MM_TRY_HIP(launch_cg_update_xr(plan->dp, x, r, z, p, q, rzh + it, sc + 0, plan->d_part, nb, s));
+      MM_TRY_HIP(launch_reduce(plan->d_part, nb, rzh + it + 1, s));
+      MM_TRY_HIP(launch_cg_update_p(p, z, rzh + it + 1, rzh + it, n, s));
+      if (chi2_hist_dev) MM_TRY(record_chi2(it + 1));
+      if (rtol > 0 && ((it + 1) % 10 == 0 || it + 1 == maxiter)) {
+        double h[2];
+        if (rz0 < 0) {
+          MM_TRY_HIP(hipMemcpyAsync(&h[0], rzh, sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        MM_TRY_HIP(hipMemcpyAsync(&h[1], rzh + it + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        MM_TRY_HIP(hipStreamSynchronize(s));
+        if (rz0 < 0) rz0 = h[0];
+        if (h[1] <= rtol * rtol * rz0) {
+          ++it;
+          break;
+        }
       }
     }
+    return MM_OK;
+  };
+  if (rtol > 0) {
+    MM_TRY(body(S(stream)));
+  } else {
+    // a fixed iteration count: the whole solve is captured into the plan's cached graph, like
+    // mm_solve's schedule (replayed when called again with the same buffers and count)
+    const std::vector<double> key = {2.0, (double)(uintptr_t)d, (double)(uintptr_t)rhs_map, (double)(uintptr_t)m0,
+                                     (double)(uintptr_t)m_out, (double)(uintptr_t)chi2_hist_dev,
+                                     (double)(uintptr_t)rzh, (double)maxiter};
+    MM_TRY(run_graph(plan, key, stream, body));
+    it = maxiter;
   }
   if (iters_done) *iters_done = it;
   return MM_OK;

@@ -1095,7 +1095,7 @@ __device__ __forceinline__ uint64_t entry_psi_raw(int pk, const LaneEntries& e, 
 // in pixel-sorted order, scattered to their staging positions in LDS and written out along the
 // sub-batch's time-contiguous segments (coalesced within each segment).  Composite pointing:
 // each component's weighted projection goes to its half of the buffer (entry index).
-template <typename T, int NC, int PK>
+template <typename T, int NC, int PK, bool CP>
 __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt, const BinLds<T>& L, int& sbn,
                              T* __restrict__ pm_out) {
   constexpr int SPW = kSubBatch / kBinBlock;
@@ -1124,7 +1124,7 @@ __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt,
               v += c * mt[l * 3 + 1] + sn * mt[l * 3 + 2];
             }
             const int q = entry_u16(en.pmw, i);
-            if (P.composite) v *= q < S.na ? P.wa : P.wb;
+            if (CP) v *= q < S.na ? P.wa : P.wb;
             L.stage[q] = (T)v;
           }
         }
@@ -1145,7 +1145,8 @@ __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt,
   }
 }
 
-template <typename T, int NC>
+// CP: composite pointing (the component weights; compiled out of the single-beam kernels)
+template <typename T, int NC, bool CP>
 __global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* __restrict__ m,
                                                        T* __restrict__ pm_out) {
   extern __shared__ double smem_d[];
@@ -1162,14 +1163,15 @@ __global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* 
       for (int q = 0; q < NC; ++q) mt[l * NC + q] = m[q * P.npix + p];
     }
     __syncthreads();
-    tile_project<T, NC, -1>(P, tl, mt, L, sbn, pm_out);
+    tile_project<T, NC, -1, CP>(P, tl, mt, L, sbn, pm_out);
   }
 }
 
 // FP32 iteration binning: at most 128 VGPRs, so that four workgroups (36 KB of LDS each) share a CU
 // PK: the angle kind fixed at compile time (1 float64, 2 float32, 3 uint16 table index), or -1
 // (read from the plan)
-template <typename T, int NV, int PK>
+// CP: composite pointing (per-entry component weights; compiled out of the single-beam kernels)
+template <typename T, int NV, int PK, bool CP>
 __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) void k_bin(DevPlan P, int bsrc, const T* __restrict__ src, int epi,
                                                    const double* __restrict__ m_in, double* __restrict__ out,
                                                    double* __restrict__ w_out, int32_t* __restrict__ hits_out,
@@ -1269,7 +1271,7 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
               y = stage[pr];
               if (kScaleAtUse && bsrc == BSRC_DATA_OVER_TAU) y *= P.chunks[schunk[gpr]].inv_tau;
             }
-            if (P.composite) {
+            if constexpr (CP) {
               // the entry's component weight w; the weight blocks take w^2 / (tau / 2) (T_A = T_B = T/2)
               const double w = pr < S.na ? P.wa : P.wb;
               y *= PLAN ? 2.0 * w * w : w;
@@ -1420,7 +1422,7 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
     }
     __syncthreads();
     if (!PLAN && pm_out && (epi == EPI_UPDATE || epi == EPI_REPLACE || epi == EPI_MAPSIZED))
-      tile_project<T, (NV == 3 ? 3 : 1), PK>(P, tl, acc, L, sbn, pm_out);
+      tile_project<T, (NV == 3 ? 3 : 1), PK, CP>(P, tl, acc, L, sbn, pm_out);
   }
 }
 
@@ -1876,9 +1878,14 @@ static hipError_t launch_bin_t(const DevPlan& P, int bsrc, const void* src, int 
                                double* w_out, int32_t* hits_out, uint8_t* sol_out, hipStream_t s, void* pm_out) {
   constexpr bool plan = NV == 2 || NV == 7;
   const size_t lds = bin_lds_bytes<NV, T>(plan, P.max_tile_pix, plan || bsrc == BSRC_DATA_OVER_TAU);
-#define MM_BIN(PKV)                                                                                   \
-  hipLaunchKernelGGL((k_bin<T, NV, PKV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, bsrc, \
-                     (const T*)src, epi, m_in, out, w_out, hits_out, sol_out, (T*)pm_out)
+#define MM_BIN_CP(PKV, CPV)                                                                              \
+  hipLaunchKernelGGL((k_bin<T, NV, PKV, CPV>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, \
+                     bsrc, (const T*)src, epi, m_in, out, w_out, hits_out, sol_out, (T*)pm_out)
+#define MM_BIN(PKV)             \
+  if (P.composite)              \
+    MM_BIN_CP(PKV, true);       \
+  else                          \
+    MM_BIN_CP(PKV, false)
   // the I/Q/U iteration kernels take the angle kind at compile time
   if constexpr (NV != 3) {
     MM_BIN(-1);
@@ -1890,6 +1897,7 @@ static hipError_t launch_bin_t(const DevPlan& P, int bsrc, const void* src, int 
     }
   }
 #undef MM_BIN
+#undef MM_BIN_CP
   return hipGetLastError();
 }
 
@@ -2102,26 +2110,32 @@ hipError_t launch_interleave(const DevPlan& P, const double* m, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int NC>
+static void launch_project_t(const DevPlan& P, const double* m, T* pm_out, size_t lds, hipStream_t s) {
+  if (P.composite)
+    hipLaunchKernelGGL((k_project<T, NC, true>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
+                       pm_out);
+  else
+    hipLaunchKernelGGL((k_project<T, NC, false>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
+                       pm_out);
+}
+
 hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipStream_t s) {
   const bool f64 = P.precision == 0;
   if (P.ncomp == 1) {
     const size_t lds = f64 ? bin_lds_bytes<1, double>(false, P.max_tile_pix, false)
                            : bin_lds_bytes<1, float>(false, P.max_tile_pix, false);
     if (f64)
-      hipLaunchKernelGGL((k_project<double, 1>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
-                         (double*)pm_out);
+      launch_project_t<double, 1>(P, m, (double*)pm_out, lds, s);
     else
-      hipLaunchKernelGGL((k_project<float, 1>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
-                         (float*)pm_out);
+      launch_project_t<float, 1>(P, m, (float*)pm_out, lds, s);
   } else {
     const size_t lds = f64 ? bin_lds_bytes<3, double>(false, P.max_tile_pix, false)
                            : bin_lds_bytes<3, float>(false, P.max_tile_pix, false);
     if (f64)
-      hipLaunchKernelGGL((k_project<double, 3>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
-                         (double*)pm_out);
+      launch_project_t<double, 3>(P, m, (double*)pm_out, lds, s);
     else
-      hipLaunchKernelGGL((k_project<float, 3>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
-                         (float*)pm_out);
+      launch_project_t<float, 3>(P, m, (float*)pm_out, lds, s);
   }
   return hipGetLastError();
 }
