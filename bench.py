@@ -140,7 +140,7 @@ def write_traffic(args, form: str, fetch_dir: str, write_dir: str) -> None:
 
 
 def summarize_counters(run_dirs: list) -> None:
-    """Markdown table of per-kernel shader counters (rocprofv3 --pmc runs of SQ_ counters), mean per
+    """Markdown table of per-kernel shader counters (rocprofv3 --pmc runs of SQ_ counters, and of TA_ / TD_ / TCP_ counters for a memory-pipeline table), mean per
     dispatch over the workload's dispatches (those after the plan's precompute binning launch)."""
     per = {}
     for d in run_dirs:
@@ -169,6 +169,20 @@ def summarize_counters(run_dirs: list) -> None:
         print(f"| {k} | {w:.0f} | {f('SQ_INSTS_VALU', 1 / w)} | {f('SQ_INSTS_LDS', 1 / w)} | "
               f"{f('SQ_LDS_BANK_CONFLICT', 1 / w)} | {f('SQ_WAIT_ANY', 1 / cyc, '{:.2f}')} | "
               f"{f('SQ_ACTIVE_INST_VALU', 1 / cyc, '{:.2f}')} |")
+    mem = {k: c for k, c in per.items() if "TCP_TCC_READ_REQ_sum" in c}
+    if mem:
+        # memory pipeline: vector L1 -> L2 read requests, their mean latency, and how much of the
+        # texture-data unit's busy time is spent stalled on the cache
+        print()
+        print("| kernel | L1->L2 read requests / dispatch | mean L2 read latency (cycles) | "
+              "TD stalled on TC (share of TD busy) | TA address stalled on TC (cycles, sum) |")
+        print("|---|---|---|---|---|")
+        for k, c in sorted(mem.items(), key=lambda kv: -kv[1]["TCP_TCC_READ_REQ_sum"]):
+            req = c["TCP_TCC_READ_REQ_sum"] or 1.0
+            lat = c.get("TCP_TCC_READ_REQ_LATENCY_sum", 0.0) / req
+            td = c.get("TD_TC_STALL_sum", 0.0) / (c.get("TD_TD_BUSY_sum", 0.0) or 1.0)
+            ta = c.get("TA_ADDR_STALLED_BY_TC_CYCLES_sum", 0.0)
+            print(f"| {k} | {req:.3g} | {lat:.0f} | {td:.2f} | {ta:.3g} |")
 
 
 def summarize_trace(trace_dir: str) -> None:
