@@ -48,6 +48,28 @@ __device__ __forceinline__ cx<T> omega2M(const DevPlan& P, const DevClass& cl, i
   return cmul(tw[cl.twhi + (q >> cl.lb)], tw[cl.twlo + (q & ((1 << cl.lb) - 1))]);
 }
 
+// omega_{2M}^(q0 + u dq) for u = 0..U-1, with 0 <= q0, dq < 2M: one table lookup pair for the
+// start and one for the step instead of a lookup pair per element, the step's powers by
+// balanced products (s^u = (s^(u/2))^2 or s^(u-1) s), so that the rounding grows like log2 u
+// ulps.  Used by the FP32 transforms, where the lookups' memory round trips cost more than the
+// products; the FP64 form keeps its per-element lookups (it has no registers to spare).
+template <typename T, int U>
+__device__ __forceinline__ void omega2M_run(const DevPlan& P, const DevClass& cl, int q0, int dq, cx<T>* w) {
+  const cx<T> w0 = omega2M<T>(P, cl, q0);
+  w[0] = w0;
+  if constexpr (U > 1) {
+    const cx<T> st = omega2M<T>(P, cl, dq);
+    cx<T> pw[U];
+    pw[1] = st;
+    w[1] = cmul(w0, st);
+#pragma unroll
+    for (int u = 2; u < U; ++u) {
+      pw[u] = (u % 2 == 0) ? cmul(pw[u / 2], pw[u / 2]) : cmul(pw[u - 1], st);
+      w[u] = cmul(w0, pw[u]);
+    }
+  }
+}
+
 template <typename C>
 __device__ __forceinline__ C conjc(C a) {
   a.y = -a.y;
@@ -486,21 +508,33 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_a(DevPlan P, const ItemAC* _
     __syncthreads();
     lds_transform<T, false, true, kBlock, P2>(lds, M2, B, lgB, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
     cx<T>* Xc = X + uni64(ch.xoff);
-    // the four-step twiddles omega_2M^(2 j1 k2): the table offsets read once, then the two
-    // table reads of half of a thread's elements issued together, twice (elements outside the
-    // item read the q = 0 entries and store nothing)
-    const cx<T>* tw = twtab<T>(P);
-    const int64_t twhi = uni64(cl.twhi), twlo = uni64(cl.twlo);
-    const int lb = uni(cl.lb);
+    // the four-step twiddles omega_2M^(2 j1 k2).  kBlock is a multiple of the block width, so a
+    // thread keeps its column b and its elements step k2 by S = kBlock / B: along each half of
+    // them the twiddles form a geometric run (elements outside the item take the q = 0 start
+    // and store nothing)
+    const int bq = threadIdx.x & (B - 1), k20 = threadIdx.x >> lgB, S = kBlock >> lgB;
+    const int jj = j10 + bq;
+    const int dq = (S < M2 && bq < nbv) ? 2 * jj * S : 0;
 #pragma unroll 1
     for (int h = 0; h < E; h += E / 2) {
+      const int k2h = k20 + h * S;
       cx<T> w[E / 2];
+      if constexpr (X2 || sizeof(T) == 8) {
+        // the two-stream variants and the FP64 form keep one lookup pair per element (the runs
+        // would spill the former's registers and measured slower in the latter): the table
+        // offsets read once, the lookups issued together
+        const cx<T>* tw = twtab<T>(P);
+        const int64_t twhi = uni64(cl.twhi), twlo = uni64(cl.twlo);
+        const int lb = uni(cl.lb);
 #pragma unroll
-      for (int u = 0; u < E / 2; ++u) {
-        const int e = threadIdx.x + (h + u) * kBlock;
-        const int b = e & (B - 1), k2 = e >> lgB;
-        const int q = (e < ntot && b < nbv) ? 2 * (j10 + b) * k2 : 0;
-        w[u] = cmul(tw[twhi + (q >> lb)], tw[twlo + (q & ((1 << lb) - 1))]);
+        for (int u = 0; u < E / 2; ++u) {
+          const int e = threadIdx.x + (h + u) * kBlock;
+          const int b = e & (B - 1), k2 = e >> lgB;
+          const int q = (e < ntot && b < nbv) ? 2 * (j10 + b) * k2 : 0;
+          w[u] = cmul(tw[twhi + (q >> lb)], tw[twlo + (q & ((1 << lb) - 1))]);
+        }
+      } else {
+        omega2M_run<T, E / 2>(P, cl, (k2h < M2 && bq < nbv) ? 2 * jj * k2h : 0, dq, w);
       }
 #pragma unroll
       for (int u = 0; u < E / 2; ++u) {
@@ -640,12 +674,15 @@ __device__ __forceinline__ void row_load(cx<T>* lds, const cx<T>* __restrict__ X
 }
 
 // the inverse row transforms' output, times the conjugate column twiddle, back to the work buffer;
-// FP32: the twiddle-table reads of every element are issued together (slots past the row end or
-// the item's rows read the q = 0 entries and store nothing)
+// FP32: each row's twiddles from a geometric run, formed before the stores (slots past the row
+// end or the item's rows take the q = 0 run and store nothing)
 template <typename T, int NR>
 __device__ __forceinline__ void row_store(const cx<T>* lds, cx<T>* __restrict__ Xc, const DevPlan& P,
                                           const DevClass& cl, const int* rws, int nrow, int M1) {
   constexpr int U = Ept<T>::v / NR;
+  // along a row r, a thread's elements j1 = t + u kBlockB have the twiddles omega_2M^(2 r j1):
+  // a geometric run from omega^(2 r t) in steps of omega^(2 r kBlockB)
+  // (the FP64 form keeps a lookup pair per element)
   if constexpr (sizeof(T) == 8) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -658,12 +695,16 @@ __device__ __forceinline__ void row_store(const cx<T>* lds, cx<T>* __restrict__ 
     }
     return;
   }
+  const bool tok = (int)threadIdx.x < M1;
+  const int dstep = (tok && kBlockB < M1) ? 2 * kBlockB : 0;
   cx<T> w[U][NR];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int j1 = threadIdx.x + u * kBlockB;
+  for (int r = 0; r < NR; ++r) {
+    const bool ok = r < nrow && tok;
+    cx<T> wr[U];
+    omega2M_run<T, U>(P, cl, ok ? 2 * (int)threadIdx.x * rws[r] : 0, ok ? dstep * rws[r] : 0, wr);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) w[u][r] = omega2M<T>(P, cl, (j1 < M1 && r < nrow) ? 2 * j1 * rws[r] : 0);
+    for (int u = 0; u < U; ++u) w[u][r] = wr[u];
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -734,12 +775,24 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
         // thread's bins go out first
         constexpr int U = Ept<T>::v / 2;
         cx<T> wk[U];
+        if (M1 == U * kBlockB || (rc > 0 && 2 * M1 == U * kBlockB)) {
+          // one row of U elements per thread, or two rows of U/2: bins k = r + M2 (t + u kBlockB)
+          // along each row, a geometric run in steps of omega_2M^(M2 kBlockB)
+          const int dq = M2 * kBlockB;
+          if (M1 == U * kBlockB) {
+            omega2M_run<T, U>(P, cl, ra + M2 * (int)threadIdx.x, dq, wk);
+          } else {
+            omega2M_run<T, U / 2>(P, cl, ra + M2 * (int)threadIdx.x, dq, wk);
+            omega2M_run<T, U / 2>(P, cl, rc + M2 * (int)threadIdx.x, dq, wk + U / 2);
+          }
+        } else {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int t = threadIdx.x + u * kBlockB;
-          const int q = t >= M1 ? 1 : 0;
-          const int k1 = t - q * M1;
-          wk[u] = omega2M<T>(P, cl, t < nt ? (q ? rc : ra) + M2 * k1 : 0);
+          for (int u = 0; u < U; ++u) {
+            const int t = threadIdx.x + u * kBlockB;
+            const int q = t >= M1 ? 1 : 0;
+            const int k1 = t - q * M1;
+            wk[u] = omega2M<T>(P, cl, t < nt ? (q ? rc : ra) + M2 * k1 : 0);
+          }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
