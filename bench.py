@@ -314,7 +314,8 @@ def run_form(mm, torch, P, form, args, log):
                       map_access={"auto": mm.MM_MAP_AUTO, "gather": mm.MM_MAP_GATHER,
                                   "projected": mm.MM_MAP_PROJECTED}[args.map_access],
                       tune=mm.MM_TUNE_MEASURE if args.tune == "measure" else mm.MM_TUNE_STATIC,
-                      binning=mm.MM_BIN_ATOMIC if args.binning == "atomic" else mm.MM_BIN_SORTED)
+                      binning=mm.MM_BIN_ATOMIC if args.binning == "atomic" else mm.MM_BIN_SORTED,
+                      tile_pixels=args.tile_pixels)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     stats = mm.mm_plan_binning_stats(plan)
@@ -645,6 +646,8 @@ def main():
     ap.add_argument("--no-chi2", action="store_true", help="skip the time-to-chi2-target comparison")
     ap.add_argument("--chi2-tail", type=int, default=60, help="lambda = 1 iterations after the schedule")
     ap.add_argument("--cg-max", type=int, default=150)
+    ap.add_argument("--tile-pixels", type=int, default=0,
+                    help="pixels per binning tile (0: the plan's choice from the map size)")
     ap.add_argument("--map-access", choices=["auto", "gather", "projected"], default="auto",
                     help="how the time-domain sweeps read P m (the plan's rule by default)")
     ap.add_argument("--binning", choices=["sorted", "atomic"], default="sorted",
