@@ -108,7 +108,12 @@ enum { MM_BIN_SORTED = 0, MM_BIN_ATOMIC = 1 };                            /* bin
  *               n/2-point complex transform, column-block width, radix order):
  *               MM_TUNE_MEASURE times the candidate layouts on the GPU at plan
  *               time for chunks of n/2 >= 16384 and keeps the fastest (cached per
- *               process and length); MM_TUNE_STATIC takes the first candidate of
+ *               process and length; with the environment variable MM_TUNE_CACHE
+ *               naming a file, also persisted there, keyed by the device
+ *               architecture, the HIP runtime version and the library build, and
+ *               read back by later processes instead of timing again; the file
+ *               is replaced by a rename, and a file that cannot be read or
+ *               written only disables the persistence); MM_TUNE_STATIC takes the first candidate of
  *               a fixed rule.  Layouts differ only in rounding; MM_TUNE_STATIC
  *               gives bitwise identical results across processes.
  *               MM_TUNE_PICK0 + i takes candidate i of the rule's order for every

@@ -7,16 +7,29 @@
 // each candidate on copies of the chunk length and keeps the fastest.
 #include <hip/hip_runtime.h>
 
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "plan.h"
+
+// identifies the library build in the persisted tuner choices (the build script passes a hash
+// of the sources)
+#ifndef MM_BUILD_ID
+#define MM_BUILD_ID "unversioned"
+#endif
 
 namespace mm {
 
@@ -190,7 +203,56 @@ void append_row_items(int32_t c, const DevChunk& ch, std::vector<ItemB>& itemsB,
 namespace {
 
 std::mutex g_tune_mu;
-std::map<std::pair<int64_t, int>, int> g_tune_cache;  // (M, precision) -> candidate index
+// (persisted cache file or "", M, precision) -> candidate index
+std::map<std::tuple<std::string, int64_t, int>, int> g_tune_cache;
+
+// Persisted choices.  With the environment variable MM_TUNE_CACHE naming a file, every measured
+// choice is also written there, one line per choice: the device architecture, the HIP runtime
+// version, the library build, the chunk half-length M, the precision and the candidate count,
+// then the chosen index.  A process with the same device, runtime and build reads the choice
+// back instead of timing the candidates again.  Lines of other keys are kept; lines that do not
+// parse are dropped when the file is next written (a temporary file renamed over it).
+std::string persisted_key(int64_t M, bool f64, int ncand) {
+  int dev = 0, rt = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+  if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
+  std::ostringstream k;
+  k << prop.gcnArchName << ' ' << rt << ' ' << MM_BUILD_ID << ' ' << M << ' ' << (f64 ? "f64" : "f32") << ' '
+    << ncand;
+  return k.str();
+}
+
+std::map<std::string, int> read_persisted(const std::string& path) {
+  std::map<std::string, int> out;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::vector<std::string> tok;
+    std::string t;
+    while (ls >> t) tok.push_back(t);
+    if (tok.size() != 7) continue;
+    char* end = nullptr;
+    const long v = std::strtol(tok[6].c_str(), &end, 10);
+    if (!end || *end || v < 0 || v >= (long)kTuneMaxCandidates) continue;
+    out[tok[0] + ' ' + tok[1] + ' ' + tok[2] + ' ' + tok[3] + ' ' + tok[4] + ' ' + tok[5]] = (int)v;
+  }
+  return out;
+}
+
+void write_persisted(const std::string& path, const std::string& key, int value) {
+  std::map<std::string, int> all = read_persisted(path);
+  all[key] = value;
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  {
+    std::ofstream o(tmp, std::ios::trunc);
+    if (!o) return;
+    for (const auto& kv : all) o << kv.first << ' ' << kv.second << '\n';
+    if (!o) return;
+  }
+  if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
+}
 
 // Passes A-C (filter on) over K copies of a length-2M chunk under one layout: the device
 // tables and work lists (carved from the tuner's scratch), kept for repeated timing.
@@ -329,13 +391,25 @@ size_t tune_scratch_bytes(int64_t M, bool f64, const std::vector<Layout>& cands)
 int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream_t s, void* scratch,
                 size_t scratch_bytes) {
   if (!tune_wanted(M, cands.size())) return 0;
-  const std::pair<int64_t, int> key(M, f64 ? 0 : 1);
+  const char* env = std::getenv("MM_TUNE_CACHE");
+  const std::string path = env ? env : "";
+  const auto key = std::make_tuple(path, M, f64 ? 0 : 1);
+  const int ncand = (int)std::min<size_t>(cands.size(), kTuneMaxCandidates);
+  std::string pkey;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) return it->second;
+    if (!path.empty()) {
+      pkey = persisted_key(M, f64, ncand);
+      const std::map<std::string, int> saved = read_persisted(path);
+      auto ps = pkey.empty() ? saved.end() : saved.find(pkey);
+      if (ps != saved.end() && ps->second < ncand) {
+        g_tune_cache[key] = ps->second;
+        return ps->second;
+      }
+    }
   }
-  const int ncand = (int)std::min<size_t>(cands.size(), kTuneMaxCandidates);
   int64_t K;
   size_t bb;
   tune_shape(M, f64, &K, &bb);
@@ -383,6 +457,7 @@ int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream
   }
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tune_cache[key] = best;
+  if (ok && !pkey.empty()) write_persisted(path, pkey, best);
   return best;
 }
 

@@ -146,3 +146,29 @@ def test_tuner_picks_a_valid_layout(dev):
     mm.mm_messenger_iter(plan, torch.from_numpy(t.d).to(dev), 4.0, torch.from_numpy(m0).to(dev), mo)
     torch.cuda.synchronize()
     assert rel(mo.cpu().numpy(), messenger_step(S, t.d, m0, 4.0)) < F64_TOL
+
+
+def test_tuner_choice_persisted(dev, tmp_path, monkeypatch):
+    """MM_TUNE_CACHE: a measured choice is written to the file, one line per key ending with the
+    chosen index, and a later plan reading a file (a new path, so the in-process cache misses)
+    takes the index it finds there instead of timing the candidates."""
+    t = tiny_problem(83, ncomp=3, lengths=(2 * 3 * 5 * 2 ** 11,), nx=16)
+    first = tmp_path / "tune_a.txt"
+    monkeypatch.setenv("MM_TUNE_CACHE", str(first))
+    lay = mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_MEASURE), 0)
+    say(f"[tune cache] measured: {lay}")
+    assert lay["ncand"] > 1
+    lines = first.read_text().splitlines()
+    assert len(lines) == 1
+    tok = lines[0].split()
+    assert len(tok) == 7 and int(tok[6]) == lay["pick"]
+    # the key: device, runtime, build, M, precision and the number of candidates timed
+    ntimed = int(tok[5])
+    assert int(tok[3]) == 2 * 3 * 5 * 2 ** 10 and tok[4] == "f64" and 1 < ntimed <= lay["ncand"]
+    other = (lay["pick"] + 1) % ntimed
+    second = tmp_path / "tune_b.txt"
+    second.write_text("not a choice\n" + " ".join(tok[:6] + [str(other)]) + "\n")
+    monkeypatch.setenv("MM_TUNE_CACHE", str(second))
+    lay2 = mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_MEASURE), 0)
+    say(f"[tune cache] read back: {lay2}")
+    assert lay2["pick"] == other
