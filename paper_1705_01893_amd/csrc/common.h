@@ -131,7 +131,7 @@ struct DevPlan {
   int32_t ncomp, psi_kind, precision;
   int32_t all_pow2;          // every chunk length is a power of two (radix 8/4/2 transforms)
   int32_t max_tile_pix;      // pixels of the largest binning tile (LDS accumulators)
-  int32_t col_wave;          // inverse column pass: wave-local classes 0 none, 1 all, 2 some
+  int32_t col_wave;          // inverse column pass: wave-local classes 0 none, 1 all, 2 some, 3 all (register transforms)
   int64_t npix, nxm;         // pixels, map row length used by the tiles
   int64_t nsamp;
   int32_t nchunk, ntiles;

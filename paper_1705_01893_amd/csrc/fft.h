@@ -641,6 +641,85 @@ __device__ __forceinline__ void wave_fft(cx<T>* cols, int L, int Lc, int nw, con
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Register-resident transform of 1024 FP32 points held by one wave, lane l holding elements
+// l + 64 i (i < 16) in v[i]: a 16-point DFT over each lane's values, the twiddles
+// omega_1024^(l k1), then a 64-point decimation-in-frequency transform across the lanes, one
+// radix-2 level per lane bit, the partners exchanged by lane shuffles (DPP for lane xor 1 and 2,
+// ds_swizzle for xor 4, 8 and 16, v_permlane32_swap for xor 32) instead of LDS round trips.
+// On return lane l, register k1 holds X[k1 + 16 rev6(l)] (rev6: the reversal of l's six bits).
+// tw: omega_1024^q, q < 1024.
+
+// x of lane (lane xor h); h a compile-time constant after unrolling
+__device__ __forceinline__ float lane_xor(float x, int h) {
+  const int xi = __float_as_int(x);
+  int r;
+  if (h == 1) {
+    r = __builtin_amdgcn_mov_dpp(xi, 0xB1, 0xF, 0xF, false);  // quad_perm [1, 0, 3, 2]
+  } else if (h == 2) {
+    r = __builtin_amdgcn_mov_dpp(xi, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+  } else if (h == 4) {
+    r = __builtin_amdgcn_ds_swizzle(xi, 0x101F);  // bit mode: and mask 0x1f, xor mask h
+  } else if (h == 8) {
+    r = __builtin_amdgcn_ds_swizzle(xi, 0x201F);
+  } else if (h == 16) {
+    r = __builtin_amdgcn_ds_swizzle(xi, 0x401F);
+  } else {
+    // v_permlane32_swap: the upper half of the first operand trades places with the lower half
+    // of the second, so lane l >= 32 finds lane l - 32 in the first, lane l < 32 lane l + 32 in
+    // the second
+    const auto pr = __builtin_amdgcn_permlane32_swap((unsigned)xi, (unsigned)xi, false, false);
+    r = (threadIdx.x & 32) ? (int)pr[0] : (int)pr[1];
+  }
+  return __int_as_float(r);
+}
+
+template <bool INV>
+__device__ __forceinline__ void wave_fft1024_regs(cx<float>* v, const cx<float>* __restrict__ tw) {
+  const int lane = (int)(threadIdx.x & 63);
+  cx<float> wl = tw[lane];
+  if (INV) wl.y = -wl.y;
+  Dft<float, 16, INV>::run(v);
+  twiddle_powers<float, 16>(v, wl);
+  // the lane pair (l, l + h) of a level: a + b stays low, (a - b) omega_2h^(l mod h) goes high
+  cx<float> lw[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int h = 32 >> s;
+    lw[s] = tw[(lane & h) ? 16 * (lane & (h - 1)) * (32 / h) : 0];
+    if (INV) lw[s].y = -lw[s].y;
+  }
+  // the registers' 64-point transforms are independent: one register's six levels at a time
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int h = 32 >> s;
+      const bool hi = (lane & h) != 0;
+      const float sg = hi ? -1.0f : 1.0f;
+      cx<float> t;
+      t.x = fmaf(sg, v[i].x, lane_xor(v[i].x, h));
+      t.y = fmaf(sg, v[i].y, lane_xor(v[i].y, h));
+      v[i] = hi ? cmul(t, lw[s]) : t;
+    }
+  }
+}
+
+// The transform of one 1024-point column in LDS (element i at pad8(i), natural order in and
+// out) by the calling wave.  Inlined into a kernel variant that makes no other transform calls
+// (a call would make it save the callee-saved registers it uses to scratch, every item).
+template <bool INV>
+__device__ __forceinline__ void wave_col1024_regs(cx<float>* col, const cx<float>* __restrict__ tw) {
+  const int lane = (int)(threadIdx.x & 63);
+  cx<float> v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = col[pad8(lane + 64 * i)];
+  wave_fft1024_regs<INV>(v, tw);
+  const int br = (int)(__builtin_bitreverse32((uint32_t)lane) >> 26);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) col[pad8(i + 16 * br)] = v[i];
+}
+
 template <typename T, bool INV, bool BFAST, int NT, bool P2>
 __device__ __forceinline__ void lds_transform(cx<T>* lds, int L, int nb, int lg_nb, const int8_t* rad, int ns,
                                               const cx<T>* __restrict__ tw) {

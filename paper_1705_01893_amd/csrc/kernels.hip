@@ -854,7 +854,8 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
 // pass C: inverse column transforms -> filtered TOD in time order (in place)
 
 // WL: the LDS layout of the plan's classes: 0 interleaved (every class), 1 wave-local (every
-// class), 2 each class's own (eligible ones wave-local).  At most 128 VGPRs: two 512-thread
+// class), 2 each class's own (eligible ones wave-local), 3 wave-local with every class a
+// 1024-point FP32 column per wave, transformed in registers.  At most 128 VGPRs: two 512-thread
 // workgroups per CU.
 template <typename T, bool P2, int WL>
 __global__ __launch_bounds__(kBlock, 4) void k_pass_c(DevPlan P, const ItemAC* __restrict__ items, int nitems,
@@ -872,7 +873,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_c(DevPlan P, const ItemAC* _
     const int ntot = B * M2;
     // per transform class: the wave-local layout where it is eligible (never with the inlined
     // power-of-two stages)
-    const bool wl = !P2 && (WL == 1 || (WL == 2 && wave_cols(M2, B, (int)sizeof(cx<T>))));
+    const bool wl = !P2 && (WL == 1 || WL == 3 || (WL == 2 && wave_cols(M2, B, (int)sizeof(cx<T>))));
     const int Lc = wl ? wave_col_stride(M2, B, (int)sizeof(cx<T>)) : 0;
     cx<T>* Xc = X + ch.xoff + j10;
     {
@@ -893,15 +894,25 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_c(DevPlan P, const ItemAC* _
     }
     __syncthreads();
     if (wl) {
-      const int nw = B / kColWaves;
-      wave_fft<T, true>(lds + (int)(threadIdx.x >> 6) * nw * Lc, M2, Lc, nw, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+      if constexpr (WL == 3 && sizeof(T) == 4) {
+        // every class: one 1024-point column per wave, transformed in registers (lane shuffles
+        // between its radix-2 levels), back to the column in natural order
+        wave_col1024_regs<true>(lds + (int)(threadIdx.x >> 6) * Lc, twtab<T>(P) + cl.tw2);
+      } else {
+        const int nw = B / kColWaves;
+        wave_fft<T, true>(lds + (int)(threadIdx.x >> 6) * nw * Lc, M2, Lc, nw, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
+      }
       __syncthreads();
     } else {
       lds_transform<T, true, true, kBlock, P2>(lds, M2, B, lgB, cl.rad2, cl.nr2, twtab<T>(P) + cl.tw2);
     }
+    // the store addresses are formed here, not ahead of the transform calls (where they would
+    // have to survive the calls in registers)
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
 #pragma unroll
     for (int u = 0; u < E; ++u) {
-      const int e = threadIdx.x + u * kBlock;
+      const int e = tid + u * kBlock;
       const int b = e & (B - 1), j2 = e >> lgB;
       if (e < ntot && b < nbv) Xc[(int64_t)M1 * j2 + b] = lds[wl ? b * Lc + pad8(j2) : e];
     }
@@ -1904,6 +1915,8 @@ static void launch_pass_c_t(const DevPlan& P, const ItemAC* items, int nitems, v
   const dim3 g(col_grid(nitems)), b(kBlock);
   if (P2 || P.col_wave == 0)
     hipLaunchKernelGGL((k_pass_c<T, P2, 0>), g, b, lds, s, P, items, nitems, (cx<T>*)work);
+  else if (P.col_wave == 3 && sizeof(T) == 4)
+    hipLaunchKernelGGL((k_pass_c<float, false, 3>), g, b, lds, s, P, items, nitems, (float2*)work);
   else if (P.col_wave == 1)
     hipLaunchKernelGGL((k_pass_c<T, false, 1>), g, b, lds, s, P, items, nitems, (cx<T>*)work);
   else

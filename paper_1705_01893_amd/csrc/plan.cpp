@@ -789,7 +789,10 @@ mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStr
   Pd.ncomp = D.ncomp;
   Pd.all_pow2 = all_pow2 ? 1 : 0;
   Pd.max_tile_pix = (int32_t)(P.tw * P.th);
-  Pd.col_wave = nwave == 0 ? 0 : (nwave == (int)classes.size() ? 1 : 2);
+  // every class a 1024-point FP32 column per wave: the register-transform variant
+  bool reg_cols = !f64 && !classes.empty() && nwave == (int)classes.size();
+  for (size_t i = 0; i < classes.size(); ++i) reg_cols = reg_cols && classes[i].M2 == 1024 && class_cb[i] == kColWaves;
+  Pd.col_wave = reg_cols ? 3 : (nwave == 0 ? 0 : (nwave == (int)classes.size() ? 1 : 2));
   Pd.psi_kind = pl->psi_kind;
   Pd.precision = D.precision;
   Pd.npix = D.npix;

@@ -345,7 +345,7 @@ struct LayoutRun {
     P.spec = spec;
     const size_t csz = f64 ? sizeof(double2) : sizeof(float2);
     const bool wl = !(f64 && P.all_pow2) && wave_cols(L.M2, L.cb, (int)csz);
-    P.col_wave = wl ? 1 : 0;
+    P.col_wave = wl ? ((!f64 && L.M2 == 1024 && L.cb == kColWaves) ? 3 : 1) : 0;
     lds_ac = (size_t)col_tile_elems(L.M2, L.cb, (int)csz, false) * csz;
     lds_c = (size_t)col_tile_elems(L.M2, L.cb, (int)csz, wl) * csz;
     lds_b = (size_t)(row_fuse(L.M1, f64) ? 4 : 2) * L.M1 * csz;

@@ -88,8 +88,9 @@ def test_every_layout_fp64(dev, shape):
         assert kinds == {True, False}
 
 
-def test_every_layout_mixed(dev):
-    t = tiny_problem(78, ncomp=3, lengths=LENGTHS["mixed"], nx=16, psi_dtype=np.float32, tod_dtype=np.float32)
+@pytest.mark.parametrize("shape", list(LENGTHS))
+def test_every_layout_mixed(dev, shape):
+    t = tiny_problem(78, ncomp=3, lengths=LENGTHS[shape], nx=16, psi_dtype=np.float32, tod_dtype=np.float32)
     S = make_setup(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, t.npix, 3)
     m0 = random_map(8, 3, t.npix)
     m0[:, ~S.solvable] = 0
@@ -106,7 +107,39 @@ def test_every_layout_mixed(dev):
         mm.mm_messenger_iter(plan, d, 1.0, mi, mo)
         torch.cuda.synchronize()
         assert rel(mo.cpu().numpy(), ref) < MIX_TOL, pick
-    assert kinds == {True, False}
+    if shape == "mixed":
+        assert kinds == {True, False}
+
+
+def test_register_column_transform_mixed(dev):
+    """A 2^21-sample chunk under its 1024 x 1024 split with 8-column blocks, whose inverse column
+    pass transforms each 1024-point column in one wave's registers (lane shuffles between the
+    radix-2 levels); FP32-mixed iterations at lambda = 1 and 37.5 and chi^2 against the FP64
+    oracle."""
+    t = tiny_problem(84, ncomp=3, lengths=(2 ** 21, 2 ** 15), nx=16, psi_dtype=np.float32, tod_dtype=np.float32,
+                     walk=False)
+    S = make_setup(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, t.npix, 3)
+    ncand = mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_STATIC, mm.MM_MIXED), 0)["ncand"]
+    plan = None
+    for pick in range(ncand):
+        cand = plan_for(t, dev, mm.MM_TUNE_PICK0 + pick, mm.MM_MIXED)
+        lay = mm.mm_plan_chunk_layout(cand, 0)
+        if (lay["M2"], lay["cb"]) == (1024, 8):
+            plan = cand
+            break
+    say(f"[register columns] {lay}")
+    assert plan is not None
+    m0 = random_map(11, 3, t.npix)
+    m0[:, ~S.solvable] = 0
+    d64 = t.d.astype(np.float64)
+    d = torch.from_numpy(t.d).to(dev)
+    for lam in (1.0, 37.5):
+        mo = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+        c2 = torch.zeros(1, dtype=torch.float64, device=dev)
+        mm.mm_messenger_iter(plan, d, lam, torch.from_numpy(m0).to(dev), mo, c2)
+        torch.cuda.synchronize()
+        assert rel(mo.cpu().numpy(), messenger_step(S, d64, m0, lam)) < MIX_TOL, lam
+        assert c2.item() == pytest.approx(chi2(S, d64, m0), rel=1e-6)
 
 
 def test_inverse_pass_layout_per_class(dev):
