@@ -10,7 +10,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle.messenger import chi2, make_setup, messenger_step  # noqa: E402
+from oracle.messenger import chi2, chi2_of_residual, make_setup, messenger_step  # noqa: E402
 from paper_1705_01893_amd import mm  # noqa: E402
 from tests.tiny_inputs import random_map, tiny_problem  # noqa: E402
 
@@ -205,3 +205,35 @@ def test_tuner_choice_persisted(dev, tmp_path, monkeypatch):
     lay2 = mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_MEASURE), 0)
     say(f"[tune cache] read back: {lay2}")
     assert lay2["pick"] == other
+
+
+def test_long_chunks_mixed(dev):
+    """Two 2^22-sample chunks (the large workload's chunk length) under its 2048 x 1024 split with
+    8-column blocks: FP32-mixed iterations at lambda = 1 and 37.5 and chi^2 with the iteration
+    and on its own (per chunk, lambda = 5) against the FP64 oracle.  (At these lengths the FP32
+    transforms' rounding, carried by the 1/f power the filter passes at large lambda, puts one
+    iteration from a random map at 1.6e-6 relative at lambda = 1 and 8.8e-6 at 37.5.)"""
+    t = tiny_problem(85, ncomp=3, lengths=(2 ** 22, 2 ** 22), nx=16, psi_dtype=np.float32, tod_dtype=np.float32,
+                     walk=False)
+    S = make_setup(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, t.npix, 3)
+    plan = plan_for(t, dev, mm.MM_TUNE_STATIC, mm.MM_MIXED)
+    lay = [mm.mm_plan_chunk_layout(plan, c) for c in range(plan.nchunk)]
+    say(f"[long chunks] {lay}")
+    assert all((l["M1"], l["M2"], l["cb"]) == (2048, 1024, 8) for l in lay)
+    m0 = random_map(12, 3, t.npix)
+    m0[:, ~S.solvable] = 0
+    d64 = t.d.astype(np.float64)
+    d = torch.from_numpy(t.d).to(dev)
+    mi = torch.from_numpy(m0).to(dev)
+    for lam in (1.0, 37.5):
+        mo = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+        c2 = torch.zeros(1, dtype=torch.float64, device=dev)
+        mm.mm_messenger_iter(plan, d, lam, mi, mo, c2)
+        torch.cuda.synchronize()
+        assert rel(mo.cpu().numpy(), messenger_step(S, d64, m0, lam)) < MIX_TOL, lam
+        assert c2.item() == pytest.approx(chi2(S, d64, m0), rel=1e-6)
+    per = torch.zeros(plan.nchunk, dtype=torch.float64, device=dev)
+    v = mm.mm_chi2(plan, d, mi, 5.0, per)
+    ref = chi2_of_residual(S, d64 - S.pointing.project(m0), 5.0, per_chunk=True)
+    assert v == pytest.approx(float(np.sum(ref)), rel=1e-6)
+    assert np.allclose(per.cpu().numpy(), ref, rtol=1e-6, atol=0)
