@@ -150,6 +150,8 @@ struct DevPlan {
   const uint16_t* perm;      // sorted order -> stage position
   const uint16_t* lp;        // sorted order -> local pixel
   const void* psi_sorted;    // angles in sorted order (type psi_kind)
+  const uint16_t* lp_stage;  // local pixels and angles in stage order (time order within each
+  const void* psi_stage;     // sub-batch's segments), for the projection walk; null without P m
   const double* spec;        // FP64 form: sigma^2 (f_k / fknee)^alpha per chunk bin (f_0 -> f_1)
   const double* winv;        // [nw][npix], nw = 1 or 6 (00 01 02 11 12 22)
   const uint8_t* solvable;   // [npix]
@@ -211,6 +213,8 @@ struct SortOut {
   uint16_t* perm;
   uint16_t* lp;
   uint8_t* psi_sorted;
+  uint16_t* lp_stage;   // the same local pixels and angles in stage order (projecting plans; else null)
+  uint8_t* psi_stage;
   int64_t cap_sb, cap_seg, cap_sort;
   int64_t* totals;      // [3]: sub-batches, segments, sorted entries
 };

@@ -1155,62 +1155,71 @@ __device__ __forceinline__ uint64_t entry_psi_raw(int pk, const LaneEntries& e, 
 }
 
 // P m for every on-map sample of one tile, written to a TOD-sized buffer in time order.
-// mt: the tile's map values in LDS, [local pixel][NC].  For each sub-batch the values are formed
-// in pixel-sorted order, scattered to their staging positions in LDS and written out along the
-// sub-batch's time-contiguous segments (coalesced within each segment).  Composite pointing:
-// each component's weighted projection goes to its half of the buffer (entry index).
+// mt: the tile's map values in LDS, [local pixel][NC].  For each sub-batch, thread q of the
+// stage positions reads its sample's local pixel and angle from the plan's stage-order copies,
+// forms P m and writes it along the sub-batch's time-contiguous segments (coalesced within each
+// segment).  Composite pointing: each component's weighted projection goes to its half of the
+// buffer (the segments' entry indices).
 template <typename T, int NC, int PK, bool CP>
 __device__ void tile_project(const DevPlan& P, const Tile& tl, const double* mt, const BinLds<T>& L, int& sbn,
                              T* __restrict__ pm_out) {
   constexpr int SPW = kSubBatch / kBinBlock;
+  // entries in flight per thread: all of them for the FP32 I/Q/U kernels with 16-bit angle
+  // indices (their registers allow it), half at a time for the others
+  constexpr int kRounds = (NC == 3 && sizeof(T) == 4 && PK == 3) ? 1 : 2, kPer = SPW / kRounds;
+  const int pk = PK >= 0 ? PK : P.psi_kind;
+  const int esz = pk == 1 ? 8 : (pk == 2 ? 4 : 2);
   for (int sb = tl.sb_begin; sb < tl.sb_end; ++sb, ++sbn) {
     const SubBatch S = P.sbs[sb];
     const int cnt = S.count;
-    {
-      // the binning pass's split of the pixel-sorted order: a stripe per wave, kPerLane
-      // consecutive entries per lane; P m of each entry goes to its staging position
-      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-      const int stripe = (((cnt + kWaves - 1) / kWaves) + 63) & ~63;
-      const int k0 = wave * stripe, k1 = min(cnt, k0 + stripe);
-      const int kl = k0 + kPerLane * lane;
-      if (kl < k1) {
-        LaneEntries en;
-        load_lane_entries<NC == 3>(P, PK >= 0 ? PK : P.psi_kind, S.sorted_begin + kl, en);
+    load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), false, false, true);
+    SegIndex si;
+#pragma unroll 1
+    for (int h = 0; h < kRounds; ++h) {
+      // the round's stage entries go out together (the first round's before the segment table
+      // is needed)
+      int lq[kPer];
+      uint64_t rq[kPer];
 #pragma unroll
-        for (int i = 0; i < kPerLane; ++i) {
-          if (kl + i < k1) {
-            const int l = entry_u16(en.lpw, i);
-            double v = mt[l * NC];
-            if (NC == 3) {
-              double c, sn;
-              const int pk = PK >= 0 ? PK : P.psi_kind;
-              weights_from_raw<T>(P, pk, entry_psi_raw(pk, en, i), c, sn);
-              v += c * mt[l * 3 + 1] + sn * mt[l * 3 + 2];
-            }
-            const int q = entry_u16(en.pmw, i);
-            if (CP) v *= q < S.na ? P.wa : P.wb;
-            L.stage[q] = (T)v;
-          }
+      for (int u = 0; u < kPer; ++u) {
+        const int q = threadIdx.x + (h * kPer + u) * kBinBlock;
+        const int64_t e = S.sorted_begin + (q < cnt ? q : 0);
+        lq[u] = P.lp_stage[e];
+        rq[u] = 0;
+        if constexpr (NC == 3) {
+          const uint8_t* ps = (const uint8_t*)P.psi_stage + e * esz;
+          rq[u] = esz == 8 ? *(const uint64_t*)ps : (esz == 4 ? *(const uint32_t*)ps : *(const uint16_t*)ps);
         }
       }
-    }
-    load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), false, false, true);
-    __syncthreads();
-    const SegIndex si = seg_index(L.smask + (sbn & 1) * (kSubBatch / 64));
-    // the other bitmap was last read before the previous sub-batch's final barrier
-    if (threadIdx.x < kSubBatch / 64) L.smask[((sbn + 1) & 1) * (kSubBatch / 64) + threadIdx.x] = 0ull;
-#pragma unroll 4
-    for (int u = 0; u < SPW; ++u) {
-      const int q = threadIdx.x + u * kBinBlock;
-      const int g = seg_lookup(si, q);  // lane reads with every lane active
-      if (q < cnt) pm_out[L.sstart[g] + (q - (int)L.spos[g])] = L.stage[q];
+      if (h == 0) {
+        __syncthreads();
+        si = seg_index(L.smask + (sbn & 1) * (kSubBatch / 64));
+        // the other bitmap was last read before the previous sub-batch's final barrier
+        if (threadIdx.x < kSubBatch / 64) L.smask[((sbn + 1) & 1) * (kSubBatch / 64) + threadIdx.x] = 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int q = threadIdx.x + (h * kPer + u) * kBinBlock;
+        const int g = seg_lookup(si, q);  // lane reads with every lane active
+        if (q < cnt) {
+          const int l = lq[u];
+          double v = mt[l * NC];
+          if constexpr (NC == 3) {
+            double c, sn;
+            weights_from_raw<T>(P, pk, rq[u], c, sn);
+            v += c * mt[l * 3 + 1] + sn * mt[l * 3 + 2];
+          }
+          if (CP) v *= q < S.na ? P.wa : P.wb;
+          pm_out[L.sstart[g] + (q - (int)L.spos[g])] = (T)v;
+        }
+      }
     }
     __syncthreads();
   }
 }
 
-// CP: composite pointing (the component weights; compiled out of the single-beam kernels)
-template <typename T, int NC, bool CP>
+// PK: the angle kind fixed at compile time (as in the binning kernels; 0 for temperature-only maps)
+template <typename T, int NC, int PK, bool CP>
 __global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* __restrict__ m,
                                                        T* __restrict__ pm_out) {
   extern __shared__ double smem_d[];
@@ -1227,7 +1236,7 @@ __global__ __launch_bounds__(kBinBlock) void k_project(DevPlan P, const double* 
       for (int q = 0; q < NC; ++q) mt[l * NC + q] = m[q * P.npix + p];
     }
     __syncthreads();
-    tile_project<T, NC, -1, CP>(P, tl, mt, L, sbn, pm_out);
+    tile_project<T, NC, PK, CP>(P, tl, mt, L, sbn, pm_out);
   }
 }
 
@@ -2178,12 +2187,25 @@ hipError_t launch_interleave(const DevPlan& P, const double* m, hipStream_t s) {
 
 template <typename T, int NC>
 static void launch_project_t(const DevPlan& P, const double* m, T* pm_out, size_t lds, hipStream_t s) {
-  if (P.composite)
-    hipLaunchKernelGGL((k_project<T, NC, true>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
-                       pm_out);
-  else
-    hipLaunchKernelGGL((k_project<T, NC, false>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, s, P, m,
-                       pm_out);
+#define MM_PROJ(PKV)                                                                                              \
+  do {                                                                                                            \
+    if (P.composite)                                                                                              \
+      hipLaunchKernelGGL((k_project<T, NC, PKV, true>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock), lds, \
+                         s, P, m, pm_out);                                                                        \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_project<T, NC, PKV, false>), dim3(grid_for(P.ntiles, kGridCap)), dim3(kBinBlock),     \
+                         lds, s, P, m, pm_out);                                                                   \
+  } while (0)
+  if constexpr (NC == 1) {
+    MM_PROJ(0);
+  } else {
+    switch (P.psi_kind) {
+      case 1: MM_PROJ(1); break;
+      case 2: MM_PROJ(2); break;
+      default: MM_PROJ(3); break;
+    }
+  }
+#undef MM_PROJ
 }
 
 hipError_t launch_project(const DevPlan& P, const double* m, void* pm_out, hipStream_t s) {

@@ -365,6 +365,8 @@ struct Bufs {
   uint16_t* perm = nullptr;
   uint16_t* lp = nullptr;
   uint8_t* psis = nullptr;
+  uint16_t* lpq = nullptr;  // stage-order copies for the projection walk (projecting plans)
+  uint8_t* psiq = nullptr;
   double* winv = nullptr;
   uint8_t* sol = nullptr;
   int32_t* hits = nullptr;
@@ -416,6 +418,8 @@ bool carve(Arena& a, const mm_plan_desc& D, const Prep& P, Bufs& B) {
        take(a, (size_t)P.cap_seg, &B.segs) && take(a, (size_t)P.cap_sort, &B.perm) &&
        take(a, (size_t)P.cap_sort, &B.lp);
   if (ok && P.pes) ok = take(a, (size_t)P.cap_sort * P.pes, &B.psis);
+  if (ok && P.pm_mode) ok = take(a, (size_t)P.cap_sort, &B.lpq);
+  if (ok && P.pm_mode && P.pes) ok = take(a, (size_t)P.cap_sort * P.pes, &B.psiq);
   ok = ok && take(a, (size_t)P.nw * npix, &B.winv) && take(a, (size_t)npix, &B.sol) && take(a, (size_t)npix, &B.hits);
   if (ok && P.f64) ok = take(a, (size_t)P.spec_total, &B.spec);
   ok = ok && take(a, std::max<size_t>(P.capB, 3 * P.capG), &B.chi2part) && take(a, 64, &B.scal) &&
@@ -616,6 +620,8 @@ mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStr
   O.perm = B.perm;
   O.lp = B.lp;
   O.psi_sorted = B.psis;
+  O.lp_stage = B.lpq;
+  O.psi_stage = B.psiq;
   O.cap_sb = P.cap_sb;
   O.cap_seg = P.cap_seg;
   O.cap_sort = P.cap_sort;
@@ -815,6 +821,8 @@ mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStr
   Pd.perm = B.perm;
   Pd.lp = B.lp;
   Pd.psi_sorted = B.psis;
+  Pd.lp_stage = B.lpq;
+  Pd.psi_stage = B.psiq;
   Pd.spec = B.spec;
   Pd.winv = B.winv;
   Pd.solvable = B.sol;

@@ -405,7 +405,9 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pixels(PixSrc pix, const vo
                                                             const SubBatch* __restrict__ sbs,
                                                             const Segment* __restrict__ segs,
                                                             uint16_t* __restrict__ perm, uint16_t* __restrict__ lp,
-                                                            uint8_t* __restrict__ psi_sorted) {
+                                                            uint8_t* __restrict__ psi_sorted,
+                                                            uint16_t* __restrict__ lp_stage,
+                                                            uint8_t* __restrict__ psi_stage) {
   __shared__ uint32_t key[kSubBatch];
   __shared__ int64_t jq[kSubBatch];
   __shared__ int64_t sstart[kMaxSegs];
@@ -441,6 +443,22 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pixels(PixSrc pix, const vo
           jq[q] = j;
         } else {
           key[q] = 0xffffffffu;
+        }
+      }
+      if (lp_stage) {
+        // stage order (the padding past count left as it is: never read)
+        for (int q = threadIdx.x; q < cnt; q += kSortBlock) {
+          const int64_t j = jq[q];
+          lp_stage[S.sorted_begin + q] = (uint16_t)(key[q] >> 12);
+          if (psi_esz) {
+            uint8_t* dst = psi_stage + (S.sorted_begin + q) * psi_esz;
+            if (psi_esz == 8)
+              *(uint64_t*)dst = psi_at<uint64_t>(psi, psi_b, pix.na, j);
+            else if (psi_esz == 4)
+              *(uint32_t*)dst = psi_at<uint32_t>(psi, psi_b, pix.na, j);
+            else
+              *(uint16_t*)dst = psi_at<uint16_t>(psi, psi_b, pix.na, j);
+          }
         }
       }
       __syncthreads();
@@ -544,7 +562,7 @@ hipError_t launch_sort_pixels(const SlabWalk& w, const void* psi, const void* ps
                               const SortOut& O, hipStream_t s) {
   const int grid = g.ntiles < 65536 ? g.ntiles : 65536;
   hipLaunchKernelGGL(k_sort_pixels, dim3(grid > 0 ? grid : 1), dim3(kSortBlock), 0, s, pix_src(w), psi, psi_b,
-                     psi_esz, g, O.tiles, O.sbs, O.segs, O.perm, O.lp, O.psi_sorted);
+                     psi_esz, g, O.tiles, O.sbs, O.segs, O.perm, O.lp, O.psi_sorted, O.lp_stage, O.psi_stage);
   return hipGetLastError();
 }
 
