@@ -509,6 +509,50 @@ __device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, const int8_t* rad,
   }
 }
 
+// One Stockham stage of NB consecutive rows of length L, every size known at compile time
+// (p = P, the product of the radices applied before): the sequence and position of each
+// butterfly, the quotient k / P and the LDS strides fold into shifts and immediate offsets.
+template <typename T, int R, bool INV, int L, int NB, int P, int NT>
+__device__ __attribute__((noinline)) void row_stage_ct(cx<T>* lds_generic, const cx<T>* __restrict__ tw_generic) {
+  const lds_v2<T> lds = (lds_v2<T>)lds_generic;
+  const glob_v2<T> tw = (glob_v2<T>)tw_generic;
+  constexpr int NBF = L / R, TOTAL = NBF * NB, STEP = L / (P * R), K = TOTAL / NT;
+  static_assert(TOTAL % NT == 0 && (NBF & (NBF - 1)) == 0 && (P & (P - 1)) == 0, "power-of-two stage");
+  cx<T> v[K][R];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int f = (int)threadIdx.x + u * NT;
+    const int b = f / NBF, k = f % NBF;
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[u][m] = to_cx<T>(lds[b * L + k + m * NBF]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int f = (int)threadIdx.x + u * NT;
+    const int b = f / NBF, k = f % NBF;
+    const int kq = k / P, j = k % P;
+    if (P > 1 && j != 0) {
+      cx<T> w = to_cx<T>(tw[j * STEP]);
+      if (INV) w.y = -w.y;
+      twiddle_powers<T, R>(v[u], w);
+    }
+    Dft<T, R, INV>::run(v[u]);
+#pragma unroll
+    for (int m = 0; m < R; ++m) lds[b * L + kq * P * R + j + m * P] = to_v2<T>(v[u][m]);
+  }
+  __syncthreads();
+}
+
+// The 2048-point transforms of two rows with the radix schedule 8, 16, 16 (the first of the
+// candidate orders for 2048-point FP32 rows), every stage specialised at compile time.
+template <typename T, bool INV, int NT>
+__device__ __forceinline__ void row_fft2048_8_16_16(cx<T>* lds, const cx<T>* __restrict__ tw) {
+  row_stage_ct<T, 8, INV, 2048, 2, 1, NT>(lds, tw);
+  row_stage_ct<T, 16, INV, 2048, 2, 8, NT>(lds, tw);
+  row_stage_ct<T, 16, INV, 2048, 2, 128, NT>(lds, tw);
+}
+
 // The same transform for power-of-two lengths (radices 8, 4 and 2 only), with the stages
 // inlined: no call boundaries, so loads the caller has in flight stay in flight.
 template <typename T, bool INV, bool BFAST, int NT>
