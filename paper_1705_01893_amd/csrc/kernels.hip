@@ -739,12 +739,11 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
       row_load<T, 2>(lds, Xc, rws, nrow, M1);
     __syncthreads();
     const cx<T>* tw1 = twtab<T>(P) + cl.tw1;
-    // FP32 pairs of 2048-point rows under the radix schedule 8, 16, 16: stages specialised at
+    // pairs of rows under the precision's compiled-in radix schedule: stages specialised at
     // compile time
-    const bool ct2048 = sizeof(T) == 4 && M1 == 2048 && nrow == 2 && cl.nr1 == 3 && cl.rad1[0] == 8 &&
-                        cl.rad1[1] == 16 && cl.rad1[2] == 16;
-    if (ct2048)
-      row_fft2048_8_16_16<T, false, kBlockB>(lds, tw1);
+    const bool ct = row_ct_ok<T>(M1, nrow, cl.nr1, cl.rad1);
+    if (ct)
+      row_fft_ct<T, false, kBlockB>(lds, tw1);
     else
       lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
     double chi = 0.0;
@@ -847,8 +846,8 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     }
     if (ops & B_FILTER) {
       __syncthreads();
-      if (ct2048)
-        row_fft2048_8_16_16<T, true, kBlockB>(lds, tw1);
+      if (ct)
+        row_fft_ct<T, true, kBlockB>(lds, tw1);
       else
         lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
       if (rc > 0)
