@@ -766,12 +766,21 @@ __device__ __forceinline__ void wave_fft1024_regs(cx<float>* v, const cx<float>*
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int h = 32 >> s;
-      const bool hi = (lane & h) != 0;
-      const float sg = hi ? -1.0f : 1.0f;
+      const float sg = (lane & h) ? -1.0f : 1.0f;
       cx<float> t;
-      t.x = fmaf(sg, v[i].x, lane_xor(v[i].x, h));
-      t.y = fmaf(sg, v[i].y, lane_xor(v[i].y, h));
-      v[i] = hi ? cmul(t, lw[s]) : t;
+      if (h == 32) {
+        // one swap per component hands every lane both values of its pair: lane l finds
+        // x[l mod 32] in the first result and x[(l mod 32) + 32] in the second
+        const auto px = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i].x), __float_as_uint(v[i].x), false, false);
+        const auto py = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i].y), __float_as_uint(v[i].y), false, false);
+        t.x = fmaf(sg, __uint_as_float(px[1]), __uint_as_float(px[0]));
+        t.y = fmaf(sg, __uint_as_float(py[1]), __uint_as_float(py[0]));
+      } else {
+        t.x = fmaf(sg, v[i].x, lane_xor(v[i].x, h));
+        t.y = fmaf(sg, v[i].y, lane_xor(v[i].y, h));
+      }
+      // the low lane of a pair holds omega^0 = (1, 0): the product returns t unchanged there
+      v[i] = cmul(t, lw[s]);
     }
   }
 }
