@@ -41,11 +41,16 @@ __device__ __forceinline__ const float2* twtab<float>(const DevPlan& P) { return
 template <>
 __device__ __forceinline__ const double2* twtab<double>(const DevPlan& P) { return P.tw64; }
 
-// omega_{2M}^q = exp(-2 pi i q / (2M)), 0 <= q < 2M, from the two-level table
+// omega_{2M}^q = exp(-2 pi i q / (2M)), 0 <= q < 2M, from the two-level table: tw + twhi holds
+// omega_2M^(h 2^lb), tw + twlo omega_2M^rem (rem < 2^lb)
+template <typename T>
+__device__ __forceinline__ cx<T> omega2M_tab(const cx<T>* tw, int64_t twhi, int64_t twlo, int lb, int q) {
+  return cmul(tw[twhi + (q >> lb)], tw[twlo + (q & ((1 << lb) - 1))]);
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> omega2M(const DevPlan& P, const DevClass& cl, int q) {
-  const cx<T>* tw = twtab<T>(P);
-  return cmul(tw[cl.twhi + (q >> cl.lb)], tw[cl.twlo + (q & ((1 << cl.lb) - 1))]);
+  return omega2M_tab<T>(twtab<T>(P), cl.twhi, cl.twlo, cl.lb, q);
 }
 
 // omega_{2M}^(q0 + u dq) for u = 0..U-1, with 0 <= q0, dq < 2M: one table lookup pair for the
@@ -54,11 +59,12 @@ __device__ __forceinline__ cx<T> omega2M(const DevPlan& P, const DevClass& cl, i
 // ulps.  Used by the FP32 transforms, where the lookups' memory round trips cost more than the
 // products; the FP64 form keeps its per-element lookups (it has no registers to spare).
 template <typename T, int U>
-__device__ __forceinline__ void omega2M_run(const DevPlan& P, const DevClass& cl, int q0, int dq, cx<T>* w) {
-  const cx<T> w0 = omega2M<T>(P, cl, q0);
+__device__ __forceinline__ void omega2M_run_tab(const cx<T>* tw, int64_t twhi, int64_t twlo, int lb, int q0, int dq,
+                                                cx<T>* w) {
+  const cx<T> w0 = omega2M_tab<T>(tw, twhi, twlo, lb, q0);
   w[0] = w0;
   if constexpr (U > 1) {
-    const cx<T> st = omega2M<T>(P, cl, dq);
+    const cx<T> st = omega2M_tab<T>(tw, twhi, twlo, lb, dq);
     cx<T> pw[U];
     pw[1] = st;
     w[1] = cmul(w0, st);
@@ -68,6 +74,11 @@ __device__ __forceinline__ void omega2M_run(const DevPlan& P, const DevClass& cl
       w[u] = cmul(w0, pw[u]);
     }
   }
+}
+
+template <typename T, int U>
+__device__ __forceinline__ void omega2M_run(const DevPlan& P, const DevClass& cl, int q0, int dq, cx<T>* w) {
+  omega2M_run_tab<T, U>(twtab<T>(P), cl.twhi, cl.twlo, cl.lb, q0, dq, w);
 }
 
 template <typename C>
@@ -715,6 +726,66 @@ __device__ __forceinline__ void row_store(const cx<T>* lds, cx<T>* __restrict__ 
   }
 }
 
+// The FP32 pairs of 2048-point rows (radices 8, 16, 16) touch the work buffer from their first
+// and last stages directly, without the row load's and the row store's passes through LDS.
+//
+// First forward stage (radix 8, p = 1): butterfly k of row b takes elements k + 256 m (m < 8) of
+// work row b, the elements the row load would have put in its LDS inputs, and writes its outputs
+// to LDS as the LDS stage does.
+template <typename T>
+__device__ __attribute__((noinline)) void row2048_first_from_work(cx<T>* lds_generic, const cx<T>* x0_generic,
+                                                                  const cx<T>* x1_generic) {
+  constexpr int L = 2048, R = 8, NBF = L / R;
+  static_assert(NBF == kBlockB, "one butterfly of each row per thread");
+  const lds_v2<T> lds = (lds_v2<T>)lds_generic;
+  const glob_v2<T> x0 = (glob_v2<T>)x0_generic, x1 = (glob_v2<T>)x1_generic;
+  const int k = (int)threadIdx.x;
+  cx<T> v[2][R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    v[0][m] = to_cx<T>(x0[k + m * NBF]);
+    v[1][m] = to_cx<T>(x1[k + m * NBF]);
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    Dft<T, R, false>::run(v[b]);
+#pragma unroll
+    for (int m = 0; m < R; ++m) lds[b * L + k * R + m] = to_v2<T>(v[b][m]);
+  }
+  __syncthreads();
+}
+
+// Last inverse stage (radix 16, p = 128): thread t takes butterfly j = t mod 128 of row
+// b = t / 128, whose outputs are the row's elements j1 = j + 128 m; each goes to work row r_b
+// times the conjugate column twiddle omega_2M^(-2 r_b j1) (a geometric run in m), as the row
+// store would have written it.  No LDS writes follow, so no barrier.
+template <typename T>
+__device__ __attribute__((noinline)) void row2048_last_to_work(const cx<T>* lds_generic, cx<T>* x0_generic,
+                                                               cx<T>* x1_generic, int r0, int r1,
+                                                               const cx<T>* __restrict__ tw1, const cx<T>* tw,
+                                                               int64_t twhi, int64_t twlo, int lb) {
+  constexpr int L = 2048, R = 16, P = 128, NBF = L / R;
+  static_assert(2 * NBF == kBlockB && NBF == P, "one butterfly per thread, outputs j + P m");
+  const lds_v2<T> lds = (lds_v2<T>)lds_generic;
+  const int b = (int)threadIdx.x / NBF, j = (int)threadIdx.x % NBF;
+  cx<T> v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = to_cx<T>(lds[b * L + j + m * NBF]);
+  if (j != 0) {
+    cx<T> w = to_cx<T>(((glob_v2<T>)tw1)[j]);  // omega_L^(j L / (P R)) with L / (P R) = 1
+    w.y = -w.y;
+    twiddle_powers<T, R>(v, w);
+  }
+  Dft<T, R, true>::run(v);
+  const int r = b ? r1 : r0;
+  cx<T> wr[R];
+  omega2M_run_tab<T, R>(tw, twhi, twlo, lb, 2 * j * r, 2 * P * r, wr);
+  using globw_v2 = __attribute__((address_space(1))) vec2<T>*;
+  const globw_v2 x = (globw_v2)(b ? x1_generic : x0_generic);
+#pragma unroll
+  for (int m = 0; m < R; ++m) x[j + m * P] = to_v2<T>(cmul(v[m], conjc(wr[m])));
+}
+
 // at most 128 VGPRs, so that four 256-thread workgroups share a CU
 template <typename T>
 __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* __restrict__ items, int nitems,
@@ -733,19 +804,28 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     const int nrow = rc > 0 ? 4 : ((ra == rb) ? 1 : 2);
     cx<T>* Xc = X + ch.xoff;
     const int rws[4] = {ra, rb, rc, M2 - rc};
-    if (rc > 0)
-      row_load<T, 4>(lds, Xc, rws, 4, M1);
-    else
-      row_load<T, 2>(lds, Xc, rws, nrow, M1);
-    __syncthreads();
     const cx<T>* tw1 = twtab<T>(P) + cl.tw1;
     // pairs of rows under the precision's compiled-in radix schedule: stages specialised at
-    // compile time
+    // compile time; in FP32 the first and last of them read and write the work buffer
     const bool ct = row_ct_ok<T>(M1, nrow, cl.nr1, cl.rad1);
-    if (ct)
-      row_fft_ct<T, false, kBlockB>(lds, tw1);
-    else
-      lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
+    const bool fused = sizeof(T) == 4 && ct;
+    if (fused) {
+      if constexpr (sizeof(T) == 4) {
+        row2048_first_from_work<T>(lds, Xc + (int64_t)ra * M1, Xc + (int64_t)rb * M1);
+        row_stage_ct<T, 16, false, 2048, 2, 8, kBlockB>(lds, tw1);
+        row_stage_ct<T, 16, false, 2048, 2, 128, kBlockB>(lds, tw1);
+      }
+    } else {
+      if (rc > 0)
+        row_load<T, 4>(lds, Xc, rws, 4, M1);
+      else
+        row_load<T, 2>(lds, Xc, rws, nrow, M1);
+      __syncthreads();
+      if (ct)
+        row_fft_ct<T, false, kBlockB>(lds, tw1);
+      else
+        lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
+    }
     double chi = 0.0;
     const bool self_a = (ra == 0) || (2 * ra == M2);
     if (!self_a) {
@@ -846,14 +926,23 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     }
     if (ops & B_FILTER) {
       __syncthreads();
-      if (ct)
-        row_fft_ct<T, true, kBlockB>(lds, tw1);
-      else
-        lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
-      if (rc > 0)
-        row_store<T, 4>(lds, Xc, P, cl, rws, 4, M1);
-      else
-        row_store<T, 2>(lds, Xc, P, cl, rws, nrow, M1);
+      if (fused) {
+        if constexpr (sizeof(T) == 4) {
+          row_stage_ct<T, 8, true, 2048, 2, 1, kBlockB>(lds, tw1);
+          row_stage_ct<T, 16, true, 2048, 2, 8, kBlockB>(lds, tw1);
+          row2048_last_to_work<T>(lds, Xc + (int64_t)ra * M1, Xc + (int64_t)rb * M1, ra, rb, tw1, twtab<T>(P),
+                                  cl.twhi, cl.twlo, cl.lb);
+        }
+      } else {
+        if (ct)
+          row_fft_ct<T, true, kBlockB>(lds, tw1);
+        else
+          lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
+        if (rc > 0)
+          row_store<T, 4>(lds, Xc, P, cl, rws, 4, M1);
+        else
+          row_store<T, 2>(lds, Xc, P, cl, rws, nrow, M1);
+      }
     }
     __syncthreads();
   }
