@@ -544,25 +544,6 @@ __device__ __attribute__((noinline)) void row_stage_ct(cx<T>* lds_generic, const
   __syncthreads();
 }
 
-// The 2048-point transforms of two rows with the radix schedule 8, 16, 16 (the first of the
-// candidate orders for 2048-point FP32 rows), every stage specialised at compile time.
-template <typename T, bool INV, int NT>
-__device__ __forceinline__ void row_fft2048_8_16_16(cx<T>* lds, const cx<T>* __restrict__ tw) {
-  row_stage_ct<T, 8, INV, 2048, 2, 1, NT>(lds, tw);
-  row_stage_ct<T, 16, INV, 2048, 2, 8, NT>(lds, tw);
-  row_stage_ct<T, 16, INV, 2048, 2, 128, NT>(lds, tw);
-}
-
-// The 1024-point transforms of two rows with the radix schedule 4, 4, 8, 8 (the first of the
-// candidate orders for 1024-point FP64 rows), every stage specialised at compile time.
-template <typename T, bool INV, int NT>
-__device__ __forceinline__ void row_fft1024_4_4_8_8(cx<T>* lds, const cx<T>* __restrict__ tw) {
-  row_stage_ct<T, 4, INV, 1024, 2, 1, NT>(lds, tw);
-  row_stage_ct<T, 4, INV, 1024, 2, 4, NT>(lds, tw);
-  row_stage_ct<T, 8, INV, 1024, 2, 16, NT>(lds, tw);
-  row_stage_ct<T, 8, INV, 1024, 2, 128, NT>(lds, tw);
-}
-
 // Whether a row item runs the precision's compiled-in schedule: two rows of 2048 points under
 // radices 8, 16, 16 in FP32, of 1024 points under 4, 4, 8, 8 in FP64.
 template <typename T>
@@ -572,15 +553,7 @@ __device__ __forceinline__ bool row_ct_ok(int M1, int nrow, int nr, const int8_t
   return M1 == 1024 && nr == 4 && rad[0] == 4 && rad[1] == 4 && rad[2] == 8 && rad[3] == 8;
 }
 
-template <typename T, bool INV, int NT>
-__device__ __forceinline__ void row_fft_ct(cx<T>* lds, const cx<T>* __restrict__ tw) {
-  if constexpr (sizeof(T) == 4)
-    row_fft2048_8_16_16<T, INV, NT>(lds, tw);
-  else
-    row_fft1024_4_4_8_8<T, INV, NT>(lds, tw);
-}
-
-// The same transform for power-of-two lengths (radices 8, 4 and 2 only), with the stages
+// The transform of lds_fft for power-of-two lengths (radices 8, 4 and 2 only), with the stages
 // inlined: no call boundaries, so loads the caller has in flight stay in flight.
 template <typename T, bool INV, bool BFAST, int NT>
 __device__ __forceinline__ void lds_fft_pow2(cx<T>* lds, int L, int nb, int lg_nb, const int8_t* rad, int ns,

@@ -726,16 +726,17 @@ __device__ __forceinline__ void row_store(const cx<T>* lds, cx<T>* __restrict__ 
   }
 }
 
-// The FP32 pairs of 2048-point rows (radices 8, 16, 16) touch the work buffer from their first
-// and last stages directly, without the row load's and the row store's passes through LDS.
+// Pairs of rows under the precision's compiled-in schedule (FP32: 2048 points, radices 8, 16, 16;
+// FP64: 1024 points, radices 4, 4, 8, 8) touch the work buffer from their first and last stages
+// directly, without the row load's and the row store's passes through LDS.
 //
-// First forward stage (radix 8, p = 1): butterfly k of row b takes elements k + 256 m (m < 8) of
-// work row b, the elements the row load would have put in its LDS inputs, and writes its outputs
-// to LDS as the LDS stage does.
-template <typename T>
-__device__ __attribute__((noinline)) void row2048_first_from_work(cx<T>* lds_generic, const cx<T>* x0_generic,
-                                                                  const cx<T>* x1_generic) {
-  constexpr int L = 2048, R = 8, NBF = L / R;
+// First forward stage (radix R, p = 1, L / R butterflies per row, one per thread): butterfly k
+// of row b takes elements k + (L / R) m (m < R) of work row b, the elements the row load would
+// have put in its LDS inputs, and writes its outputs to LDS as the LDS stage does.
+template <typename T, int L, int R>
+__device__ __attribute__((noinline)) void row_first_from_work(cx<T>* lds_generic, const cx<T>* x0_generic,
+                                                              const cx<T>* x1_generic) {
+  constexpr int NBF = L / R;
   static_assert(NBF == kBlockB, "one butterfly of each row per thread");
   const lds_v2<T> lds = (lds_v2<T>)lds_generic;
   const glob_v2<T> x0 = (glob_v2<T>)x0_generic, x1 = (glob_v2<T>)x1_generic;
@@ -755,35 +756,69 @@ __device__ __attribute__((noinline)) void row2048_first_from_work(cx<T>* lds_gen
   __syncthreads();
 }
 
-// Last inverse stage (radix 16, p = 128): thread t takes butterfly j = t mod 128 of row
-// b = t / 128, whose outputs are the row's elements j1 = j + 128 m; each goes to work row r_b
-// times the conjugate column twiddle omega_2M^(-2 r_b j1) (a geometric run in m), as the row
-// store would have written it.  No LDS writes follow, so no barrier.
-template <typename T>
-__device__ __attribute__((noinline)) void row2048_last_to_work(const cx<T>* lds_generic, cx<T>* x0_generic,
-                                                               cx<T>* x1_generic, int r0, int r1,
-                                                               const cx<T>* __restrict__ tw1, const cx<T>* tw,
-                                                               int64_t twhi, int64_t twlo, int lb) {
-  constexpr int L = 2048, R = 16, P = 128, NBF = L / R;
-  static_assert(2 * NBF == kBlockB && NBF == P, "one butterfly per thread, outputs j + P m");
+// Last inverse stage (radix R, p = P = L / R, so that its twiddle step L / (P R) is 1): thread t
+// takes butterfly j = t mod P of row b = t / P, whose outputs are the row's elements
+// j1 = j + P m; each goes to work row r_b times the conjugate column twiddle omega_2M^(-2 r_b j1)
+// (a geometric run in m, in FP64 too: a lookup pair per element needs registers this stage does
+// not have), as the row store would have written it.  No LDS writes follow, so no barrier.
+template <typename T, int L, int R>
+__device__ __attribute__((noinline)) void row_last_to_work(const cx<T>* lds_generic, cx<T>* x0_generic,
+                                                           cx<T>* x1_generic, int r0, int r1,
+                                                           const cx<T>* __restrict__ tw1, const cx<T>* tw,
+                                                           int64_t twhi, int64_t twlo, int lb) {
+  constexpr int P = L / R, NBF = L / R;
+  static_assert(2 * NBF == kBlockB, "one butterfly per thread");
   const lds_v2<T> lds = (lds_v2<T>)lds_generic;
   const int b = (int)threadIdx.x / NBF, j = (int)threadIdx.x % NBF;
   cx<T> v[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) v[m] = to_cx<T>(lds[b * L + j + m * NBF]);
   if (j != 0) {
-    cx<T> w = to_cx<T>(((glob_v2<T>)tw1)[j]);  // omega_L^(j L / (P R)) with L / (P R) = 1
+    cx<T> w = to_cx<T>(((glob_v2<T>)tw1)[j]);
     w.y = -w.y;
     twiddle_powers<T, R>(v, w);
   }
   Dft<T, R, true>::run(v);
   const int r = b ? r1 : r0;
-  cx<T> wr[R];
-  omega2M_run_tab<T, R>(tw, twhi, twlo, lb, 2 * j * r, 2 * P * r, wr);
   using globw_v2 = __attribute__((address_space(1))) vec2<T>*;
   const globw_v2 x = (globw_v2)(b ? x1_generic : x0_generic);
+  cx<T> wr[R];
+  omega2M_run_tab<T, R>(tw, twhi, twlo, lb, 2 * j * r, 2 * P * r, wr);
 #pragma unroll
   for (int m = 0; m < R; ++m) x[j + m * P] = to_v2<T>(cmul(v[m], conjc(wr[m])));
+}
+
+// the compiled-in schedules, forward from the work buffer into LDS and inverse from LDS into the
+// work buffer
+template <typename T>
+__device__ __forceinline__ void row_ct_forward_from_work(cx<T>* lds, const cx<T>* x0, const cx<T>* x1,
+                                                         const cx<T>* __restrict__ tw1) {
+  if constexpr (sizeof(T) == 4) {
+    row_first_from_work<T, 2048, 8>(lds, x0, x1);
+    row_stage_ct<T, 16, false, 2048, 2, 8, kBlockB>(lds, tw1);
+    row_stage_ct<T, 16, false, 2048, 2, 128, kBlockB>(lds, tw1);
+  } else {
+    row_first_from_work<T, 1024, 4>(lds, x0, x1);
+    row_stage_ct<T, 4, false, 1024, 2, 4, kBlockB>(lds, tw1);
+    row_stage_ct<T, 8, false, 1024, 2, 16, kBlockB>(lds, tw1);
+    row_stage_ct<T, 8, false, 1024, 2, 128, kBlockB>(lds, tw1);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void row_ct_inverse_to_work(cx<T>* lds, cx<T>* x0, cx<T>* x1, int r0, int r1,
+                                                       const cx<T>* __restrict__ tw1, const cx<T>* tw,
+                                                       int64_t twhi, int64_t twlo, int lb) {
+  if constexpr (sizeof(T) == 4) {
+    row_stage_ct<T, 8, true, 2048, 2, 1, kBlockB>(lds, tw1);
+    row_stage_ct<T, 16, true, 2048, 2, 8, kBlockB>(lds, tw1);
+    row_last_to_work<T, 2048, 16>(lds, x0, x1, r0, r1, tw1, tw, twhi, twlo, lb);
+  } else {
+    row_stage_ct<T, 4, true, 1024, 2, 1, kBlockB>(lds, tw1);
+    row_stage_ct<T, 4, true, 1024, 2, 4, kBlockB>(lds, tw1);
+    row_stage_ct<T, 8, true, 1024, 2, 16, kBlockB>(lds, tw1);
+    row_last_to_work<T, 1024, 8>(lds, x0, x1, r0, r1, tw1, tw, twhi, twlo, lb);
+  }
 }
 
 // at most 128 VGPRs, so that four 256-thread workgroups share a CU
@@ -806,25 +841,17 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     const int rws[4] = {ra, rb, rc, M2 - rc};
     const cx<T>* tw1 = twtab<T>(P) + cl.tw1;
     // pairs of rows under the precision's compiled-in radix schedule: stages specialised at
-    // compile time; in FP32 the first and last of them read and write the work buffer
+    // compile time, the first and last of them reading and writing the work buffer
     const bool ct = row_ct_ok<T>(M1, nrow, cl.nr1, cl.rad1);
-    const bool fused = sizeof(T) == 4 && ct;
-    if (fused) {
-      if constexpr (sizeof(T) == 4) {
-        row2048_first_from_work<T>(lds, Xc + (int64_t)ra * M1, Xc + (int64_t)rb * M1);
-        row_stage_ct<T, 16, false, 2048, 2, 8, kBlockB>(lds, tw1);
-        row_stage_ct<T, 16, false, 2048, 2, 128, kBlockB>(lds, tw1);
-      }
+    if (ct) {
+      row_ct_forward_from_work<T>(lds, Xc + (int64_t)ra * M1, Xc + (int64_t)rb * M1, tw1);
     } else {
       if (rc > 0)
         row_load<T, 4>(lds, Xc, rws, 4, M1);
       else
         row_load<T, 2>(lds, Xc, rws, nrow, M1);
       __syncthreads();
-      if (ct)
-        row_fft_ct<T, false, kBlockB>(lds, tw1);
-      else
-        lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
+      lds_fft<T, false, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
     }
     double chi = 0.0;
     const bool self_a = (ra == 0) || (2 * ra == M2);
@@ -926,18 +953,11 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
     }
     if (ops & B_FILTER) {
       __syncthreads();
-      if (fused) {
-        if constexpr (sizeof(T) == 4) {
-          row_stage_ct<T, 8, true, 2048, 2, 1, kBlockB>(lds, tw1);
-          row_stage_ct<T, 16, true, 2048, 2, 8, kBlockB>(lds, tw1);
-          row2048_last_to_work<T>(lds, Xc + (int64_t)ra * M1, Xc + (int64_t)rb * M1, ra, rb, tw1, twtab<T>(P),
+      if (ct) {
+        row_ct_inverse_to_work<T>(lds, Xc + (int64_t)ra * M1, Xc + (int64_t)rb * M1, ra, rb, tw1, twtab<T>(P),
                                   cl.twhi, cl.twlo, cl.lb);
-        }
       } else {
-        if (ct)
-          row_fft_ct<T, true, kBlockB>(lds, tw1);
-        else
-          lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
+        lds_fft<T, true, false, kBlockB>(lds, M1, nrow, 0, cl.rad1, cl.nr1, tw1);
         if (rc > 0)
           row_store<T, 4>(lds, Xc, P, cl, rws, 4, M1);
         else
