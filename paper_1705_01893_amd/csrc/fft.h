@@ -509,28 +509,32 @@ __device__ void lds_fft(cx<T>* lds, int L, int nb, int lg_nb, const int8_t* rad,
   }
 }
 
-// One Stockham stage of NB consecutive rows of length L, every size known at compile time
-// (p = P, the product of the radices applied before): the sequence and position of each
-// butterfly, the quotient k / P and the LDS strides fold into shifts and immediate offsets.
-template <typename T, int R, bool INV, int L, int NB, int P, int NT>
-__device__ __attribute__((noinline)) void row_stage_ct(cx<T>* lds_generic, const cx<T>* __restrict__ tw_generic) {
+// One Stockham stage of NB sequences of length L, every size known at compile time (p = P, the
+// product of the radices applied before): the sequence and position of each butterfly, the
+// quotient k / P and the LDS strides fold into shifts and immediate offsets.  Element i of
+// sequence b sits at b L + i (consecutive rows; butterfly f in sequence f / (L / R)) or, with
+// BFAST, at i NB + b (interleaved columns; butterfly f in sequence f mod NB).
+template <typename T, int R, bool INV, int L, int NB, int P, int NT, bool BFAST = false>
+__device__ __attribute__((noinline)) void stage_ct(cx<T>* lds_generic, const cx<T>* __restrict__ tw_generic) {
   const lds_v2<T> lds = (lds_v2<T>)lds_generic;
   const glob_v2<T> tw = (glob_v2<T>)tw_generic;
   constexpr int NBF = L / R, TOTAL = NBF * NB, STEP = L / (P * R), K = TOTAL / NT;
-  static_assert(TOTAL % NT == 0 && (NBF & (NBF - 1)) == 0 && (P & (P - 1)) == 0, "power-of-two stage");
+  constexpr int SI = BFAST ? NB : 1, SB = BFAST ? 1 : L;
+  static_assert(TOTAL % NT == 0 && (NBF & (NBF - 1)) == 0 && (P & (P - 1)) == 0 && (NB & (NB - 1)) == 0,
+                "power-of-two stage");
   cx<T> v[K][R];
 #pragma unroll
   for (int u = 0; u < K; ++u) {
     const int f = (int)threadIdx.x + u * NT;
-    const int b = f / NBF, k = f % NBF;
+    const int b = BFAST ? f % NB : f / NBF, k = BFAST ? f / NB : f % NBF;
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[u][m] = to_cx<T>(lds[b * L + k + m * NBF]);
+    for (int m = 0; m < R; ++m) v[u][m] = to_cx<T>(lds[b * SB + (k + m * NBF) * SI]);
   }
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < K; ++u) {
     const int f = (int)threadIdx.x + u * NT;
-    const int b = f / NBF, k = f % NBF;
+    const int b = BFAST ? f % NB : f / NBF, k = BFAST ? f / NB : f % NBF;
     const int kq = k / P, j = k % P;
     if (P > 1 && j != 0) {
       cx<T> w = to_cx<T>(tw[j * STEP]);
@@ -539,7 +543,7 @@ __device__ __attribute__((noinline)) void row_stage_ct(cx<T>* lds_generic, const
     }
     Dft<T, R, INV>::run(v[u]);
 #pragma unroll
-    for (int m = 0; m < R; ++m) lds[b * L + kq * P * R + j + m * P] = to_v2<T>(v[u][m]);
+    for (int m = 0; m < R; ++m) lds[b * SB + (kq * P * R + j + m * P) * SI] = to_v2<T>(v[u][m]);
   }
   __syncthreads();
 }

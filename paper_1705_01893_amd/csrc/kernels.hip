@@ -795,13 +795,13 @@ __device__ __forceinline__ void row_ct_forward_from_work(cx<T>* lds, const cx<T>
                                                          const cx<T>* __restrict__ tw1) {
   if constexpr (sizeof(T) == 4) {
     row_first_from_work<T, 2048, 8>(lds, x0, x1);
-    row_stage_ct<T, 16, false, 2048, 2, 8, kBlockB>(lds, tw1);
-    row_stage_ct<T, 16, false, 2048, 2, 128, kBlockB>(lds, tw1);
+    stage_ct<T, 16, false, 2048, 2, 8, kBlockB>(lds, tw1);
+    stage_ct<T, 16, false, 2048, 2, 128, kBlockB>(lds, tw1);
   } else {
     row_first_from_work<T, 1024, 4>(lds, x0, x1);
-    row_stage_ct<T, 4, false, 1024, 2, 4, kBlockB>(lds, tw1);
-    row_stage_ct<T, 8, false, 1024, 2, 16, kBlockB>(lds, tw1);
-    row_stage_ct<T, 8, false, 1024, 2, 128, kBlockB>(lds, tw1);
+    stage_ct<T, 4, false, 1024, 2, 4, kBlockB>(lds, tw1);
+    stage_ct<T, 8, false, 1024, 2, 16, kBlockB>(lds, tw1);
+    stage_ct<T, 8, false, 1024, 2, 128, kBlockB>(lds, tw1);
   }
 }
 
@@ -810,13 +810,13 @@ __device__ __forceinline__ void row_ct_inverse_to_work(cx<T>* lds, cx<T>* x0, cx
                                                        const cx<T>* __restrict__ tw1, const cx<T>* tw,
                                                        int64_t twhi, int64_t twlo, int lb) {
   if constexpr (sizeof(T) == 4) {
-    row_stage_ct<T, 8, true, 2048, 2, 1, kBlockB>(lds, tw1);
-    row_stage_ct<T, 16, true, 2048, 2, 8, kBlockB>(lds, tw1);
+    stage_ct<T, 8, true, 2048, 2, 1, kBlockB>(lds, tw1);
+    stage_ct<T, 16, true, 2048, 2, 8, kBlockB>(lds, tw1);
     row_last_to_work<T, 2048, 16>(lds, x0, x1, r0, r1, tw1, tw, twhi, twlo, lb);
   } else {
-    row_stage_ct<T, 4, true, 1024, 2, 1, kBlockB>(lds, tw1);
-    row_stage_ct<T, 4, true, 1024, 2, 4, kBlockB>(lds, tw1);
-    row_stage_ct<T, 8, true, 1024, 2, 16, kBlockB>(lds, tw1);
+    stage_ct<T, 4, true, 1024, 2, 1, kBlockB>(lds, tw1);
+    stage_ct<T, 4, true, 1024, 2, 4, kBlockB>(lds, tw1);
+    stage_ct<T, 8, true, 1024, 2, 16, kBlockB>(lds, tw1);
     row_last_to_work<T, 1024, 8>(lds, x0, x1, r0, r1, tw1, tw, twhi, twlo, lb);
   }
 }
@@ -971,6 +971,63 @@ __global__ __launch_bounds__(kBlockB, 4) void k_pass_b(DevPlan P, const ItemB* _
 // ---------------------------------------------------------------------------------------------
 // pass C: inverse column transforms -> filtered TOD in time order (in place)
 
+// Blocks of NB interleaved FP64 columns of 2048 points under the radix schedule 4, 8, 8, 8 (the
+// first candidate order for 2048-point FP64 columns): the stages specialised at compile time, the
+// first reading the work buffer and the last writing it, without the load's and the store's
+// passes through LDS.  Column b of the block is work column j10 + b (xc points at its row 0);
+// element i sits at LDS slot i NB + b.
+template <typename T, int L, int R, int NB>
+__device__ __attribute__((noinline)) void col_first_from_work(cx<T>* lds_generic, const cx<T>* xc_generic, int M1) {
+  constexpr int NBF = L / R, K = NBF * NB / kBlock;
+  static_assert(NBF * NB == K * kBlock, "whole butterflies per thread");
+  const lds_v2<T> lds = (lds_v2<T>)lds_generic;
+  const glob_v2<T> x = (glob_v2<T>)xc_generic;
+  cx<T> v[K][R];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int f = (int)threadIdx.x + u * kBlock, b = f % NB, k = f / NB;
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[u][m] = to_cx<T>(x[(int64_t)(k + m * NBF) * M1 + b]);
+  }
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int f = (int)threadIdx.x + u * kBlock, b = f % NB, k = f / NB;
+    Dft<T, R, true>::run(v[u]);
+#pragma unroll
+    for (int m = 0; m < R; ++m) lds[(k * R + m) * NB + b] = to_v2<T>(v[u][m]);
+  }
+  __syncthreads();
+}
+
+// the last stage (p = L / R, twiddle step 1): butterfly j of column b writes elements j + p m
+template <typename T, int L, int R, int NB>
+__device__ __attribute__((noinline)) void col_last_to_work(const cx<T>* lds_generic, cx<T>* xc_generic, int M1,
+                                                           const cx<T>* __restrict__ tw2) {
+  constexpr int P = L / R, NBF = L / R;
+  static_assert(NBF * NB == kBlock, "one butterfly per thread");
+  const lds_v2<T> lds = (lds_v2<T>)lds_generic;
+  using globw_v2 = __attribute__((address_space(1))) vec2<T>*;
+  const globw_v2 x = (globw_v2)xc_generic;
+  const int b = (int)threadIdx.x % NB, j = (int)threadIdx.x / NB;
+  cx<T> v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = to_cx<T>(lds[(j + m * NBF) * NB + b]);
+  if (j != 0) {
+    cx<T> w = to_cx<T>(((glob_v2<T>)tw2)[j]);
+    w.y = -w.y;
+    twiddle_powers<T, R>(v, w);
+  }
+  Dft<T, R, true>::run(v);
+#pragma unroll
+  for (int m = 0; m < R; ++m) x[(int64_t)(j + m * P) * M1 + b] = to_v2<T>(v[m]);
+}
+
+template <typename T>
+__device__ __forceinline__ bool col_ct_ok(int M2, int B, int nbv, int nr, const int8_t* rad) {
+  return sizeof(T) == 8 && M2 == 2048 && B == 2 && nbv == B && nr == 4 && rad[0] == 4 && rad[1] == 8 &&
+         rad[2] == 8 && rad[3] == 8;
+}
+
 // WL: the LDS layout of the plan's classes: 0 interleaved (every class), 1 wave-local (every
 // class), 2 each class's own (eligible ones wave-local), 3 wave-local with every class a
 // 1024-point FP32 column per wave, transformed in registers.  At most 128 VGPRs: two 512-thread
@@ -994,6 +1051,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_pass_c(DevPlan P, const ItemAC* _
     const bool wl = !P2 && (WL == 1 || WL == 3 || (WL == 2 && wave_cols(M2, B, (int)sizeof(cx<T>))));
     const int Lc = wl ? wave_col_stride(M2, B, (int)sizeof(cx<T>)) : 0;
     cx<T>* Xc = X + ch.xoff + j10;
+    if constexpr (sizeof(T) == 8) {
+      if (!wl && col_ct_ok<T>(M2, B, nbv, cl.nr2, cl.rad2)) {
+        const cx<T>* tw2 = twtab<T>(P) + cl.tw2;
+        col_first_from_work<T, 2048, 4, 2>(lds, Xc, M1);
+        stage_ct<T, 8, true, 2048, 2, 4, kBlock, true>(lds, tw2);
+        stage_ct<T, 8, true, 2048, 2, 32, kBlock, true>(lds, tw2);
+        col_last_to_work<T, 2048, 8, 2>(lds, Xc, M1, tw2);
+        __syncthreads();
+        continue;
+      }
+    }
     {
       cx<T> v[E];
 #pragma unroll

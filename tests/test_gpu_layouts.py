@@ -237,3 +237,27 @@ def test_long_chunks_mixed(dev):
     ref = chi2_of_residual(S, d64 - S.pointing.project(m0), 5.0, per_chunk=True)
     assert v == pytest.approx(float(np.sum(ref)), rel=1e-6)
     assert np.allclose(per.cpu().numpy(), ref, rtol=1e-6, atol=0)
+
+
+def test_long_chunks_fp64(dev):
+    """Two 2^22-sample chunks under the FP64 split of that length (1024-point rows in pairs,
+    2048-point columns in blocks of two: the compiled-in radix schedules, whose first and last
+    stages read and write the work buffer): FP64 iterations at lambda = 1 and 37.5 and chi^2
+    against the FP64 oracle."""
+    t = tiny_problem(86, ncomp=3, lengths=(2 ** 22, 2 ** 22), nx=16, walk=False)
+    S = make_setup(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, t.psi, t.npix, 3)
+    plan = plan_for(t, dev, mm.MM_TUNE_STATIC)
+    lay = [mm.mm_plan_chunk_layout(plan, c) for c in range(plan.nchunk)]
+    say(f"[long chunks fp64] {lay}")
+    assert all((l["M1"], l["M2"], l["cb"]) == (1024, 2048, 2) for l in lay)
+    m0 = random_map(13, 3, t.npix)
+    m0[:, ~S.solvable] = 0
+    d = torch.from_numpy(t.d).to(dev)
+    mi = torch.from_numpy(m0).to(dev)
+    for lam in (1.0, 37.5):
+        mo = torch.zeros((3, t.npix), dtype=torch.float64, device=dev)
+        c2 = torch.zeros(1, dtype=torch.float64, device=dev)
+        mm.mm_messenger_iter(plan, d, lam, mi, mo, c2)
+        torch.cuda.synchronize()
+        assert rel(mo.cpu().numpy(), messenger_step(S, t.d, m0, lam)) < F64_TOL, lam
+        assert c2.item() == pytest.approx(chi2(S, t.d, m0), rel=F64_TOL)
