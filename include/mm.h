@@ -107,8 +107,11 @@ enum { MM_BIN_SORTED = 0, MM_BIN_ATOMIC = 1 };                            /* bin
  *  tune         layout of each chunk length's transforms (split M = M1 M2 of the
  *               n/2-point complex transform, column-block width, radix order):
  *               MM_TUNE_MEASURE times the candidate layouts on the GPU at plan
- *               time for chunks of n/2 >= 16384 and keeps the fastest (cached per
- *               process and length; with the environment variable MM_TUNE_CACHE
+ *               time for chunks of n/2 >= 16384 and keeps the fastest (the timing
+ *               reads the TOD streams the plan's column pass reads: d, and P m
+ *               under projected access, both halves of it with composite
+ *               pointing; cached per process, length and stream count; with the
+ *               environment variable MM_TUNE_CACHE
  *               naming a file, also persisted there, keyed by the device
  *               architecture, the HIP runtime version and the library build, and
  *               read back by later processes instead of timing again; the file

@@ -130,6 +130,7 @@ struct Prep {
   int64_t xwork = 0, spec_total = 0;
   size_t capAC = 0, capB = 0, capG = 0, capTW = 0;
   size_t tune_bytes = 0;
+  int tune_streams = 1;  // TOD-sized streams pass A reads (what the tuner's timing reads)
   bool pm_mode = false, adjoint = false, bin_atomic = false, mapi = false, gapfill = false;
   // tiles and counts
   int64_t nxm = 0, nym = 0, tw = 0, th = 0, ntx = 0, nty = 0, ntiles = 0;
@@ -190,10 +191,6 @@ void prep_transforms(const mm_plan_desc& D, Prep& P) {
     P.xwork += (M + kWorkAlign - 1) / kWorkAlign * kWorkAlign;
     P.spec_total += M + 1;
   }
-  for (const ClassInfo& ci : P.classes) {
-    P.capTW += ci.tw;
-    if (D.tune == MM_TUNE_MEASURE) P.tune_bytes = std::max(P.tune_bytes, tune_scratch_bytes(ci.M, P.f64, ci.cands));
-  }
   P.adjoint = D.with_adjoint != 0;
   P.bin_atomic = D.binning == MM_BIN_ATOMIC;
   // maps larger than the L2 of one XCD (4 MB) are gathered badly by the strided column pass:
@@ -202,6 +199,12 @@ void prep_transforms(const mm_plan_desc& D, Prep& P) {
   P.pm_mode = D.map_access == MM_MAP_PROJECTED || P.composite || P.gapfill ||
               (D.map_access == MM_MAP_AUTO && P.mapn * (int64_t)sizeof(double) > ((int64_t)4 << 20));
   P.mapi = !P.pm_mode && D.ncomp == 3;
+  P.tune_streams = !P.pm_mode ? 1 : (P.composite ? 3 : 2);
+  for (const ClassInfo& ci : P.classes) {
+    P.capTW += ci.tw;
+    if (D.tune == MM_TUNE_MEASURE)
+      P.tune_bytes = std::max(P.tune_bytes, tune_scratch_bytes(ci.M, P.f64, ci.cands, P.tune_streams));
+  }
 }
 
 // Tile shape: about `target` pixels, tw a power of two, shaped by the scan.  A sample moving
@@ -665,7 +668,7 @@ mm_status build_plan(const mm_plan_desc* desc, void* ws, size_t ws_bytes, hipStr
     if (ci.cands.empty()) return fail(MM_E_LEN, "a chunk length has no transform split that fits the LDS budget");
     int pick = 0;
     if (D.tune == MM_TUNE_MEASURE)
-      pick = tune_layout(ci.M, f64, ci.cands, s, B.transient, B.transient_bytes);
+      pick = tune_layout(ci.M, f64, ci.cands, P.tune_streams, s, B.transient, B.transient_bytes);
     else if (D.tune >= MM_TUNE_PICK0)
       pick = std::min<int>(D.tune - MM_TUNE_PICK0, (int)ci.cands.size() - 1);
     const Layout& L = ci.cands[pick];

@@ -126,12 +126,14 @@ void make_class(int64_t M, const Layout& L, std::vector<double2>& tw, DevClass& 
 bool row_fuse(int M1, bool f64);
 void append_col_items(int32_t c, const DevChunk& ch, std::vector<ItemAC>& itemsAC);
 void append_row_items(int32_t c, const DevChunk& ch, std::vector<ItemB>& itemsB, bool fuse);
-// whether a length with ncand candidates is timed, and the device scratch the timing takes
+// whether a length with ncand candidates is timed, and the device scratch the timing takes.
+// a_streams: the TOD-sized streams the plan's column pass A reads (1: d, its gathers aside;
+// 2: d and P m; 3: d and the two halves of a composite plan's P m), which the timing reads too
 bool tune_wanted(int64_t M, size_t ncand);
-size_t tune_scratch_bytes(int64_t M, bool f64, const std::vector<Layout>& cands);
+size_t tune_scratch_bytes(int64_t M, bool f64, const std::vector<Layout>& cands, int a_streams);
 // index of the fastest candidate, timed on the GPU in the given scratch (0 for short chunks or
-// on any failure); cached per process by (M, precision)
-int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream_t s, void* scratch,
+// on any failure); cached per process by (M, precision, a_streams)
+int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, int a_streams, hipStream_t s, void* scratch,
                 size_t scratch_bytes);
 
 // device bytes a plan of this description needs; `scratch` (device, scratch_bytes) serves the

@@ -203,8 +203,8 @@ void append_row_items(int32_t c, const DevChunk& ch, std::vector<ItemB>& itemsB,
 namespace {
 
 std::mutex g_tune_mu;
-// (persisted cache file or "", M, precision) -> candidate index
-std::map<std::tuple<std::string, int64_t, int>, int> g_tune_cache;
+// (persisted cache file or "", M, precision, streams pass A reads) -> candidate index
+std::map<std::tuple<std::string, int64_t, int, int>, int> g_tune_cache;
 
 // Persisted choices.  With the environment variable MM_TUNE_CACHE naming a file, every measured
 // choice is also written there, one line per choice: the device architecture, the HIP runtime
@@ -212,14 +212,14 @@ std::map<std::tuple<std::string, int64_t, int>, int> g_tune_cache;
 // then the chosen index.  A process with the same device, runtime and build reads the choice
 // back instead of timing the candidates again.  Lines of other keys are kept; lines that do not
 // parse are dropped when the file is next written (a temporary file renamed over it).
-std::string persisted_key(int64_t M, bool f64, int ncand) {
+std::string persisted_key(int64_t M, bool f64, int a_streams, int ncand) {
   int dev = 0, rt = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
   if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
   std::ostringstream k;
-  k << prop.gcnArchName << ' ' << rt << ' ' << MM_BUILD_ID << ' ' << M << ' ' << (f64 ? "f64" : "f32") << ' '
-    << ncand;
+  k << prop.gcnArchName << ' ' << rt << ' ' << MM_BUILD_ID << ' ' << M << ' ' << (f64 ? "f64" : "f32") << " a"
+    << a_streams << ' ' << ncand;
   return k.str();
 }
 
@@ -232,11 +232,14 @@ std::map<std::string, int> read_persisted(const std::string& path) {
     std::vector<std::string> tok;
     std::string t;
     while (ls >> t) tok.push_back(t);
-    if (tok.size() != 7) continue;
+    // the key's fields, then the chosen index
+    if (tok.size() < 2) continue;
     char* end = nullptr;
-    const long v = std::strtol(tok[6].c_str(), &end, 10);
+    const long v = std::strtol(tok.back().c_str(), &end, 10);
     if (!end || *end || v < 0 || v >= (long)kTuneMaxCandidates) continue;
-    out[tok[0] + ' ' + tok[1] + ' ' + tok[2] + ' ' + tok[3] + ' ' + tok[4] + ' ' + tok[5]] = (int)v;
+    std::string k = tok[0];
+    for (size_t i = 1; i + 1 < tok.size(); ++i) k += ' ' + tok[i];
+    out[k] = (int)v;
   }
   return out;
 }
@@ -352,8 +355,10 @@ struct LayoutRun {
     return true;
   }
 
-  bool run(void* din, void* dwork, hipStream_t s) const {
-    return launch_pass_a(P, dac, nac, din, nullptr, SRC_D, dwork, lds_ac, s) == hipSuccess &&
+  // pm: null for a pass A that reads d alone, else P m (and its second half with pmb_off set)
+  bool run(void* din, void* dwork, const void* pm, hipStream_t s) const {
+    return launch_pass_a(P, dac, nac, din, nullptr, pm ? SRC_D_MINUS_PMBUF : SRC_D, dwork, lds_ac, s, pm) ==
+               hipSuccess &&
            launch_pass_b(P, db, nb, dwork, B_FILTER, GAIN_MESSENGER, 1.0, 1.0, nullptr, lds_b, s) == hipSuccess &&
            launch_pass_c(P, dac, nac, dwork, lds_c, s) == hipSuccess;
   }
@@ -370,7 +375,7 @@ void tune_shape(int64_t M, bool f64, int64_t* K, size_t* buf_bytes) {
 
 bool tune_wanted(int64_t M, size_t ncand) { return ncand > 1 && M >= kTuneMinM; }
 
-size_t tune_scratch_bytes(int64_t M, bool f64, const std::vector<Layout>& cands) {
+size_t tune_scratch_bytes(int64_t M, bool f64, const std::vector<Layout>& cands, int a_streams) {
   if (!tune_wanted(M, cands.size())) return 0;
   int64_t K;
   size_t bb;
@@ -378,6 +383,7 @@ size_t tune_scratch_bytes(int64_t M, bool f64, const std::vector<Layout>& cands)
   Arena a;
   a.take(bb);
   a.take(bb);
+  if (a_streams > 1) a.take((size_t)(a_streams - 1) * bb);
   if (f64) a.take((size_t)K * (M + 1) * sizeof(double));
   const int ncand = (int)std::min<size_t>(cands.size(), kTuneMaxCandidates);
   size_t t = a.used;
@@ -388,12 +394,13 @@ size_t tune_scratch_bytes(int64_t M, bool f64, const std::vector<Layout>& cands)
   return t + 256;
 }
 
-int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream_t s, void* scratch,
+int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, int a_streams, hipStream_t s, void* scratch,
                 size_t scratch_bytes) {
   if (!tune_wanted(M, cands.size())) return 0;
+  a_streams = std::min(std::max(a_streams, 1), 3);
   const char* env = std::getenv("MM_TUNE_CACHE");
   const std::string path = env ? env : "";
-  const auto key = std::make_tuple(path, M, f64 ? 0 : 1);
+  const auto key = std::make_tuple(path, M, f64 ? 0 : 1, a_streams);
   const int ncand = (int)std::min<size_t>(cands.size(), kTuneMaxCandidates);
   std::string pkey;
   {
@@ -401,7 +408,7 @@ int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) return it->second;
     if (!path.empty()) {
-      pkey = persisted_key(M, f64, ncand);
+      pkey = persisted_key(M, f64, a_streams, ncand);
       const std::map<std::string, int> saved = read_persisted(path);
       auto ps = pkey.empty() ? saved.end() : saved.find(pkey);
       if (ps != saved.end() && ps->second < ncand) {
@@ -418,27 +425,33 @@ int tune_layout(int64_t M, bool f64, const std::vector<Layout>& cands, hipStream
   ar.cap = scratch_bytes;
   void* din = ar.take(bb);
   void* dwork = ar.take(bb);
+  void* pm = a_streams > 1 ? ar.take((size_t)(a_streams - 1) * bb) : nullptr;
   double* spec = nullptr;
   if (f64) spec = (double*)ar.take((size_t)K * (M + 1) * sizeof(double));
-  if (!din || !dwork || (f64 && !spec)) return 0;
+  if (!din || !dwork || (a_streams > 1 && !pm) || (f64 && !spec)) return 0;
   int best = 0;
   // every candidate prepared and warmed up, then timed round-robin (best of kTuneReps each), so
   // that clock and cache drift during the plan affects all of them alike
   std::vector<std::unique_ptr<LayoutRun>> runs;
   std::vector<double> t(ncand, -1.0);
   bool ok = launch_fill_i64((int64_t*)din, (int64_t)(bb / sizeof(int64_t)), 0, s) == hipSuccess;
+  if (ok && pm)
+    ok = launch_fill_i64((int64_t*)pm, (int64_t)((size_t)(a_streams - 1) * bb / sizeof(int64_t)), 0, s) ==
+         hipSuccess;
   for (int i = 0; ok && i < ncand; ++i) {
     runs.emplace_back(new LayoutRun);
     ok = runs[i]->prepare(M, f64, cands[i], K, spec, ar, s);
+    // a composite plan's P_B m half follows the P_A m half (offsets in complex pairs)
+    if (ok && a_streams == 3) runs[i]->P.pmb_off = K * M;
     if (ok && f64 && i == 0) ok = launch_spectrum(runs[0]->P, spec, s) == hipSuccess;
-    ok = ok && runs[i]->run(din, dwork, s);
+    ok = ok && runs[i]->run(din, dwork, pm, s);
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
   for (int rep = 0; ok && rep < kTuneReps; ++rep)
     for (int i = 0; ok && i < ncand; ++i) {
       float ms = 0.f;
-      ok = hipEventRecord(e0, s) == hipSuccess && runs[i]->run(din, dwork, s) &&
+      ok = hipEventRecord(e0, s) == hipSuccess && runs[i]->run(din, dwork, pm, s) &&
            hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
            hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
       if (ok && (t[i] < 0 || ms < t[i])) t[i] = ms;

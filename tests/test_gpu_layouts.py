@@ -194,13 +194,15 @@ def test_tuner_choice_persisted(dev, tmp_path, monkeypatch):
     lines = first.read_text().splitlines()
     assert len(lines) == 1
     tok = lines[0].split()
-    assert len(tok) == 7 and int(tok[6]) == lay["pick"]
-    # the key: device, runtime, build, M, precision and the number of candidates timed
-    ntimed = int(tok[5])
-    assert int(tok[3]) == 2 * 3 * 5 * 2 ** 10 and tok[4] == "f64" and 1 < ntimed <= lay["ncand"]
+    assert len(tok) == 8 and int(tok[7]) == lay["pick"]
+    # the key: device, runtime, build, M, precision, the TOD streams pass A reads (this small map
+    # is gathered: d alone) and the number of candidates timed
+    ntimed = int(tok[6])
+    assert int(tok[3]) == 2 * 3 * 5 * 2 ** 10 and tok[4] == "f64" and tok[5] == "a1"
+    assert 1 < ntimed <= lay["ncand"]
     other = (lay["pick"] + 1) % ntimed
     second = tmp_path / "tune_b.txt"
-    second.write_text("not a choice\n" + " ".join(tok[:6] + [str(other)]) + "\n")
+    second.write_text("not a choice\n" + " ".join(tok[:7] + [str(other)]) + "\n")
     monkeypatch.setenv("MM_TUNE_CACHE", str(second))
     lay2 = mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_MEASURE), 0)
     say(f"[tune cache] read back: {lay2}")
