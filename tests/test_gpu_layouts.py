@@ -207,6 +207,17 @@ def test_tuner_choice_persisted(dev, tmp_path, monkeypatch):
     lay2 = mm.mm_plan_chunk_layout(plan_for(t, dev, mm.MM_TUNE_MEASURE), 0)
     say(f"[tune cache] read back: {lay2}")
     assert lay2["pick"] == other
+    # projected map access: pass A reads d and P m, so the timing does too, under a key of its own
+    third = tmp_path / "tune_c.txt"
+    monkeypatch.setenv("MM_TUNE_CACHE", str(third))
+    psi = torch.from_numpy(np.ascontiguousarray(t.psi)).to(dev)
+    plan3 = mm.mm_plan(ncomp=3, npix=t.npix, nx=t.nx, chunk_off=t.chunk_off, fsample=t.fsample, sigma=t.sigma,
+                       fknee=t.fknee, alpha=t.alpha, pix=torch.from_numpy(t.pix).to(dev), psi=psi,
+                       precision=mm.MM_FP64, tune=mm.MM_TUNE_MEASURE, map_access=mm.MM_MAP_PROJECTED)
+    lay3 = mm.mm_plan_chunk_layout(plan3, 0)
+    tok3 = third.read_text().split()
+    say(f"[tune cache] projected: {lay3} {tok3}")
+    assert len(tok3) == 8 and tok3[5] == "a2" and tok3[:5] == tok[:5] and int(tok3[7]) == lay3["pick"]
 
 
 def test_long_chunks_mixed(dev):
