@@ -150,6 +150,11 @@ struct DevPlan {
   const uint16_t* perm;      // sorted order -> stage position
   const uint16_t* lp;        // sorted order -> local pixel
   const void* psi_sorted;    // angles in sorted order (type psi_kind)
+  // the pixel-sorted entries packed into 32 bits, in place of perm, lp and psi_sorted, when a
+  // 16-bit angle index fits beside them: stage position (12 bits) | local pixel << 12 | angle
+  // index << (12 + pk_lp_bits); else null
+  const uint32_t* packed;
+  int32_t pk_lp_bits;
   const uint16_t* lp_stage;  // local pixels and angles in stage order (time order within each
   const void* psi_stage;     // sub-batch's segments), for the projection walk; null without P m
   const double* spec;        // FP64 form: sigma^2 (f_k / fknee)^alpha per chunk bin (f_0 -> f_1)
@@ -213,6 +218,8 @@ struct SortOut {
   uint16_t* perm;
   uint16_t* lp;
   uint8_t* psi_sorted;
+  uint32_t* packed;     // the packed entries in place of the three above (or null)
+  int lp_bits;
   uint16_t* lp_stage;   // the same local pixels and angles in stage order (projecting plans; else null)
   uint8_t* psi_stage;
   int64_t cap_sb, cap_seg, cap_sort;

@@ -1308,10 +1308,17 @@ __device__ __forceinline__ void load_segments(const DevPlan& P, const SubBatch& 
 struct LaneEntries {
   uint4 lpw[2], pmw[2];
   uint4 psw[kPerLane / 2];  // raw angles: up to 16 x 8 bytes
+  uint4 pkw[kPerLane / 4];  // packed entries (stage position, local pixel, angle index)
 };
 
-template <bool POL>
+template <bool POL, bool PACKED = false>
 __device__ __forceinline__ void load_lane_entries(const DevPlan& P, int pk, int64_t g0, LaneEntries& e) {
+  if constexpr (PACKED) {
+    const uint4* pp = reinterpret_cast<const uint4*>(P.packed + g0);
+#pragma unroll
+    for (int w = 0; w < kPerLane / 4; ++w) e.pkw[w] = pp[w];
+    return;
+  }
   const uint4* lpp = reinterpret_cast<const uint4*>(P.lp + g0);
   const uint4* pmp = reinterpret_cast<const uint4*>(P.perm + g0);
   e.lpw[0] = lpp[0];
@@ -1331,6 +1338,11 @@ __device__ __forceinline__ void load_lane_entries(const DevPlan& P, int pk, int6
 __device__ __forceinline__ int entry_u16(const uint4* w, int i) {
   const uint32_t x = (i < 8) ? ((const uint32_t*)&w[0])[i / 2] : ((const uint32_t*)&w[1])[(i - 8) / 2];
   return (int)((x >> (16 * (i & 1))) & 0xffffu);
+}
+
+// entry i of a lane's packed entries: stage position, local pixel, angle index
+__device__ __forceinline__ uint32_t entry_packed(const LaneEntries& e, int i) {
+  return ((const uint32_t*)e.pkw)[i];
 }
 
 __device__ __forceinline__ uint64_t entry_psi_raw(int pk, const LaneEntries& e, int i) {
@@ -1440,7 +1452,11 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
   constexpr int SPW = kSubBatch / kBinBlock;  // staged samples per thread
   // the stage holds TOD values in the TOD precision: an FP32 stage cannot hold d / tau exactly
   constexpr bool kScaleAtUse = sizeof(T) < sizeof(double);
-  const int pk = PK >= 0 ? PK : P.psi_kind;
+  // PK 4: 16-bit table indices, the sorted entries packed (the plan's packed array)
+  constexpr bool PACKED = PK == 4;
+  const int pk = PACKED ? 3 : (PK >= 0 ? PK : P.psi_kind);
+  const int lpb = PACKED ? P.pk_lp_bits : 0;
+  const uint32_t lpm = PACKED ? (1u << lpb) - 1u : 0u;
   extern __shared__ double smem_d[];
   const BinLds<T> L = bin_lds<NV, T>(smem_d, PLAN, P.max_tile_pix);
   T* stage = L.stage;
@@ -1468,7 +1484,7 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
       const int kl = k0 + kPerLane * lane;
       const bool active = kl < k1;
       LaneEntries en = {};
-      if (active) load_lane_entries<POL>(P, pk, S.sorted_begin + kl, en);  // kl: a multiple of kSortAlign
+      if (active) load_lane_entries<POL, PACKED>(P, pk, S.sorted_begin + kl, en);  // kl: a multiple of kSortAlign
       load_segments(P, S, L, L.smask + (sbn & 1) * (kSubBatch / 64), PLAN || bsrc == BSRC_DATA_OVER_TAU,
                     bsrc == BSRC_WORK);
       if (lane == 0) clp[wave] = -1;
@@ -1510,7 +1526,8 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
         __syncthreads();
       }
       if (k0 < k1) {
-        const int first_lp = __shfl((int)(en.lpw[0].x & 0xffffu), 0);  // lane 0 is active
+        // lane 0 is active
+        const int first_lp = __shfl(PACKED ? (int)((en.pkw[0].x >> 12) & lpm) : (int)(en.lpw[0].x & 0xffffu), 0);
         // sequential reduce-by-key over this lane's entries
         int cur_lp = -1, h_lp = -1, nruns = 0;
         double cur[NV], hv[NV];
@@ -1518,11 +1535,11 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
         for (int q = 0; q < NV; ++q) cur[q] = hv[q] = 0.0;
 #pragma unroll
         for (int i = 0; i < kPerLane; ++i) {
-          const int pr = entry_u16(en.pmw, i);
+          const int pr = PACKED ? (int)(entry_packed(en, i) & 0xfffu) : entry_u16(en.pmw, i);
           // lane reads with every lane of the wave active
           const int gpr = (PLAN || (kScaleAtUse && bsrc == BSRC_DATA_OVER_TAU)) ? seg_lookup(si, pr) : 0;
           if (kl + i < k1) {
-            const int lp = entry_u16(en.lpw, i);
+            const int lp = PACKED ? (int)((entry_packed(en, i) >> 12) & lpm) : entry_u16(en.lpw, i);
             double y;
             if (PLAN) {
               y = P.chunks[schunk[gpr]].inv_tau;
@@ -1536,7 +1553,9 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
               y *= PLAN ? 2.0 * w * w : w;
             }
             double c = 0.0, sn = 0.0;
-            if (POL) weights_from_raw<T>(P, pk, entry_psi_raw(pk, en, i), c, sn);
+            if (POL)
+              weights_from_raw<T>(P, pk, PACKED ? (uint64_t)(entry_packed(en, i) >> (12 + lpb)) : entry_psi_raw(pk, en, i),
+                                  c, sn);
             double v[NV];
             contrib<T, NV>(P, y, c, sn, v);
             if (lp != cur_lp) {
@@ -1681,7 +1700,7 @@ __global__ __launch_bounds__(kBinBlock, (sizeof(T) == 4 && NV == 3) ? 4 : 1) voi
     }
     __syncthreads();
     if (!PLAN && pm_out && (epi == EPI_UPDATE || epi == EPI_REPLACE || epi == EPI_MAPSIZED))
-      tile_project<T, (NV == 3 ? 3 : 1), PK, CP>(P, tl, acc, L, sbn, pm_out);
+      tile_project<T, (NV == 3 ? 3 : 1), (PACKED ? 3 : PK), CP>(P, tl, acc, L, sbn, pm_out);
   }
 }
 
@@ -2147,7 +2166,14 @@ static hipError_t launch_bin_t(const DevPlan& P, int bsrc, const void* src, int 
     MM_BIN_CP(PKV, true);       \
   else                          \
     MM_BIN_CP(PKV, false)
-  // the I/Q/U iteration kernels take the angle kind at compile time
+  // the I/Q/U iteration kernels take the angle kind at compile time; packed sorted entries (I/Q/U
+  // plans with 16-bit angle indices that fit) take the packed variant, the plan pass's too
+  if constexpr (NV == 3 || NV == 7) {
+    if (P.packed) {
+      MM_BIN(4);
+      return hipGetLastError();
+    }
+  }
   if constexpr (NV != 3) {
     MM_BIN(-1);
   } else {

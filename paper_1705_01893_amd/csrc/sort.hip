@@ -406,6 +406,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pixels(PixSrc pix, const vo
                                                             const Segment* __restrict__ segs,
                                                             uint16_t* __restrict__ perm, uint16_t* __restrict__ lp,
                                                             uint8_t* __restrict__ psi_sorted,
+                                                            uint32_t* __restrict__ packed, int lp_bits,
                                                             uint16_t* __restrict__ lp_stage,
                                                             uint8_t* __restrict__ psi_stage) {
   __shared__ uint32_t key[kSubBatch];
@@ -488,6 +489,12 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pixels(PixSrc pix, const vo
           q = (uint16_t)(k & 0xfffu);
           l = (uint16_t)(k >> 12);
         }
+        if (packed) {
+          // the key already holds the stage position and the local pixel; the angle index above
+          packed[base + i] = i < cnt ? key[i] | ((uint32_t)psi_at<uint16_t>(psi, psi_b, pix.na, jq[q]) << (12 + lp_bits))
+                                     : 0u;
+          continue;
+        }
         perm[base + i] = q;
         lp[base + i] = l;
         if (psi_esz) {
@@ -562,7 +569,8 @@ hipError_t launch_sort_pixels(const SlabWalk& w, const void* psi, const void* ps
                               const SortOut& O, hipStream_t s) {
   const int grid = g.ntiles < 65536 ? g.ntiles : 65536;
   hipLaunchKernelGGL(k_sort_pixels, dim3(grid > 0 ? grid : 1), dim3(kSortBlock), 0, s, pix_src(w), psi, psi_b,
-                     psi_esz, g, O.tiles, O.sbs, O.segs, O.perm, O.lp, O.psi_sorted, O.lp_stage, O.psi_stage);
+                     psi_esz, g, O.tiles, O.sbs, O.segs, O.perm, O.lp, O.psi_sorted, O.packed, O.lp_bits, O.lp_stage,
+                     O.psi_stage);
   return hipGetLastError();
 }
 

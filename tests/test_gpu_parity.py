@@ -390,21 +390,24 @@ def test_unbiased_noise_free(dev):
     assert np.abs(m.cpu().numpy() - m_true).max() < 1e-11 * np.abs(m_true).max()
 
 
+@pytest.mark.parametrize("table_len", [48, 3000])
 @pytest.mark.parametrize("precision", [mm.MM_FP64, mm.MM_MIXED])
-def test_angle_table_indices(dev, precision):
+def test_angle_table_indices(dev, precision, table_len):
     """Angles stored as uint16 indices into a float32 table (MM_PSI_U16): the oracle takes the
-    identical table values promoted to float64."""
-    say(f"[psi u16] precision={precision}")
-    t = tiny_problem(919, ncomp=3, **SHAPES["mixed_radix"])
+    identical table values promoted to float64.  With 512-pixel tiles a sorted entry's local
+    pixel takes 9 bits, so a 48-entry table's indices are packed beside it and the stage
+    position (one 32-bit word per entry) and a 3000-entry table's are not (above 2^11)."""
+    say(f"[psi u16] precision={precision} table={table_len}")
+    t = tiny_problem(919, ncomp=3, lengths=SHAPES["mixed_radix"]["lengths"], nx=32)
     rng = np.random.default_rng(3)
-    table = np.linspace(0.0, np.pi, 48, endpoint=False).astype(np.float32)
+    table = np.linspace(0.0, np.pi, table_len, endpoint=False).astype(np.float32)
     idx = rng.integers(0, table.size, size=t.nsamp).astype(np.uint16)
     t.psi = table[idx].astype(np.float64)
     S = oracle_setup(t)
     plan = mm.mm_plan(ncomp=3, npix=t.npix, nx=t.nx, chunk_off=t.chunk_off, fsample=t.fsample, sigma=t.sigma,
                       fknee=t.fknee, alpha=t.alpha, pix=torch.from_numpy(t.pix).to(dev),
                       psi=torch.from_numpy(idx.view(np.int16)).to(dev).view(torch.uint16), psi_table=table,
-                      precision=precision)
+                      precision=precision, tile_pixels=512)
     mask = torch.zeros(t.npix, dtype=torch.uint8, device=dev)
     mm.mm_plan_solvable(plan, mask)
     m0 = random_map(4, 3, t.npix)
