@@ -153,6 +153,43 @@ def test_one_iteration(dev, name, precision, lam):
     assert c2.item() == pytest.approx(chi2(c.S, d_used, m0), rel=ctol)
 
 
+@pytest.mark.parametrize("precision", [mm.MM_FP64, mm.MM_MIXED])
+def test_one_iteration_angle_table(dev, precision):
+    """Composite I/Q/U pointing with both beams' angles stored as uint16 indices into a float32
+    table: the plan packs its pixel-sorted entries (the index beside the stage position and the
+    local pixel, both beams' entries); the oracle takes the table values promoted to float64."""
+    say(f"[composite iter, angle table] precision={precision}")
+    b_mode, ncomp, w, lengths, nx, _ = TINY["diff_IQU_f32psi"]
+    t, pb, _, w = tiny_composite(403, b_mode=b_mode, lengths=lengths, nx=nx, ncomp=ncomp, weights=w,
+                                 psi_dtype=np.float64)
+    rng = np.random.default_rng(7)
+    table = np.linspace(0.0, np.pi, 64, endpoint=False).astype(np.float32)
+    ia = rng.integers(0, table.size, size=len(t.pix)).astype(np.uint16)
+    ib = rng.integers(0, table.size, size=len(t.pix)).astype(np.uint16)
+    c = Case(t.chunk_off, t.fsample, t.sigma, t.fknee, t.alpha, t.pix, table[ia].astype(np.float64), pb,
+             table[ib].astype(np.float64), t.d, t.npix, nx, ncomp, w, dev)
+    u16 = lambda a: torch.from_numpy(a.view(np.int16)).to(dev).view(torch.uint16)
+    plan = mm.mm_plan(ncomp=ncomp, npix=c.npix, nx=nx, chunk_off=c.chunk_off, fsample=c.fsample, sigma=c.sigma,
+                      fknee=c.fknee, alpha=c.alpha, pix=c.dpix, psi=u16(ia), pix_b=c.dpix_b, psi_b=u16(ib),
+                      psi_table=table, weights=c.weights, precision=precision)
+    mask = torch.zeros(c.npix, dtype=torch.uint8, device=dev)
+    mm.mm_plan_solvable(plan, mask)
+    m0 = c.start_map(6)
+    d = c.tod(precision)
+    mi = torch.from_numpy(m0).to(dev)
+    mo = torch.zeros_like(mi)
+    c2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    mm.mm_messenger_iter(plan, d, 23.0, mi, mo, c2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(mask.cpu().numpy().astype(bool), c.S.solvable)
+    d_used = d.cpu().numpy().astype(np.float64)
+    tol, ctol = (F64_TOL, F64_TOL) if precision == mm.MM_FP64 else (MIX_TOL, MIX_CHI2)
+    e = rel(mo.cpu().numpy(), messenger_step(c.S, d_used, m0, 23.0))
+    say(f"  map rel {e:.2e}")
+    assert e < tol
+    assert c2.item() == pytest.approx(chi2(c.S, d_used, m0), rel=ctol)
+
+
 @pytest.mark.parametrize("name, ndet, nsamp, nx, sep", [("diff256", 4, 1 << 15, 96, 4.0),
                                                       ("diff512", 6, 1 << 15, 80, 5.0)])
 @pytest.mark.parametrize("precision", [mm.MM_FP64, mm.MM_MIXED])
